@@ -1,0 +1,235 @@
+/*
+ * tds.h - C ABI of the trajectory distance-threshold search library (libtds.so)
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Gowanlock & Casanova, arXiv:1410.2698, Sec. 3.1): a database D of
+ * 4-D entry line segments (x, y, z, t start point; end point; segment id;
+ * trajectory id) is indexed once and kept resident in GPU memory (Sec. 3.1,
+ * in-memory database); a set Q of query segments is then searched against it:
+ * for every query segment q and every entry segment l that overlap in time,
+ * the library reports the time interval during which the two linearly moving
+ * points are within Euclidean distance d (Sec. 4.1) of each other, as a
+ * record (q, l, [t_lo, t_hi]) (the result set of Sec. 3.1).
+ *
+ * Semantics fixed by this library where the paper is silent:
+ *   - time overlap is strict after clipping to the search window
+ *     [t_start, t_end] (the search interval of Sec. 1): pairs that only touch
+ *     at one instant are not results;
+ *   - "within d" is inclusive; a tangent pair gives t_lo == t_hi;
+ *   - one record per (query segment, entry segment) pair; intervals are not
+ *     merged across consecutive segments; each record carries both
+ *     trajectory ids;
+ *   - membership and endpoints follow one fixed FP64 evaluation order (no
+ *     fused multiply-add), so the result set is reproducible bit for bit.
+ *
+ * Conventions for every entry point:
+ *   - return value: a TDS_* status code; TDS_OK is 0;
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream);
+ *     work is ordered on it; calls that return counts wait for it;
+ *   - pointers flagged as device memory must be allocated on the device that
+ *     was current when the index was built;
+ *   - no entry point keeps a caller pointer after it returns.
+ */
+#ifndef TDS_H
+#define TDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDS_ABI_VERSION 1u
+
+/* Status codes. */
+enum {
+    TDS_OK = 0,
+    TDS_E_INVALID = 1,  /* bad argument or input value (NaN, t_end <= t_start, ...) */
+    TDS_E_OVERFLOW = 2, /* more results than the output capacity; *n_out holds the total */
+    TDS_E_NOMEM = 3,    /* device or host allocation failed */
+    TDS_E_DEVICE = 4,   /* a HIP call failed */
+    TDS_E_BUSY = 5      /* admission refused (serving, non-blocking submit) */
+};
+
+/* Arithmetic of the candidate filter inside the distance kernel. */
+enum {
+    /* Library default (currently TDS_PREC_FP32_RECHECK). */
+    TDS_PREC_DEFAULT = 0,
+    /* Plain form: every candidate pair is evaluated with the canonical FP64
+       predicate. */
+    TDS_PREC_FP64 = 1,
+    /* FP32 bulk test with a rigorous error margin around d (a pair is dropped
+       only when it provably has no result); the surviving pairs are decided,
+       and their endpoints computed, by the canonical FP64 evaluation.  Result
+       set and endpoints are identical to TDS_PREC_FP64. */
+    TDS_PREC_FP32_RECHECK = 2
+};
+
+/*
+ * A set of segments in structure-of-arrays form.  Segment k runs from
+ * (xs[k], ys[k], zs[k]) at time ts[k] to (xe[k], ye[k], ze[k]) at time te[k]
+ * (Sec. 3.1).  The segment id is the array position k.  traj_id may be NULL
+ * (every id 0).  All arrays hold n elements and live in host memory
+ * (on_device = 0) or device memory (on_device = 1).  Borrowed for the call.
+ * Requirements: every value finite, te[k] > ts[k], n < 2^32.
+ */
+typedef struct tds_segments {
+    const double* xs;
+    const double* ys;
+    const double* zs;
+    const double* ts;
+    const double* xe;
+    const double* ye;
+    const double* ze;
+    const double* te;
+    const uint32_t* traj_id;
+    uint64_t n;
+    int32_t on_device;
+    int32_t reserved;
+} tds_segments;
+
+/* Index parameters; a NULL pointer or 0 fields select defaults. */
+typedef struct tds_build_params {
+    /* Number m of temporal bins (Sec. 4.2.1).  0 = auto: the full temporal
+       extent divided by the mean segment duration, rounded, clamped to
+       [1, 65535]. */
+    uint32_t num_bins;
+    uint32_t reserved[7];
+} tds_build_params;
+
+/* One result record (32 bytes): the interaction of query segment q_seg with
+   entry segment e_seg is within d during [t_lo, t_hi] (Sec. 3.1). */
+typedef struct tds_result {
+    uint32_t q_seg;  /* query segment id (position in the request's Q) */
+    uint32_t e_seg;  /* entry segment id (position in the D given to build) */
+    uint32_t q_traj; /* trajectory id of the query segment */
+    uint32_t e_traj; /* trajectory id of the entry segment */
+    double t_lo;
+    double t_hi;
+} tds_result;
+
+/* Search parameters; a NULL pointer or 0 fields select defaults. */
+typedef struct tds_search_params {
+    int32_t precision;     /* TDS_PREC_* */
+    int32_t out_on_device; /* 1: `out` is device memory, else host memory */
+    uint32_t chunk;        /* candidates per work item; 0 = auto */
+    uint32_t grid_waves;   /* waves of the persistent distance kernel; 0 = auto */
+    /* Host output only: size, in records, of the device result buffer
+       (the paper's fixed result buffer, Sec. 5.2).  When the results exceed
+       it, the search is re-run in increments that each fit (Sec. 3.2).
+       0 = min(capacity, 2^24). */
+    uint64_t device_capacity;
+    uint64_t reserved[4];
+} tds_search_params;
+
+/* Counters of the last search (tests and benchmarks). */
+typedef struct tds_stats {
+    uint64_t query_segments;  /* query segments given */
+    uint64_t active_segments; /* with a non-empty window and candidate range */
+    uint64_t work_items;      /* (query group, candidate chunk) items */
+    uint64_t candidate_tests; /* (query, entry) pairs tested by the distance kernel */
+    uint64_t fp64_evals;      /* pairs evaluated by the canonical FP64 code */
+    uint64_t results;         /* result records found (may exceed the capacity) */
+    uint32_t passes;          /* distance-kernel launches (> 1: incremental) */
+    uint32_t reserved;
+    double kernel_ms;         /* distance kernel(s), measured with HIP events */
+    double total_ms;          /* whole call, host wall clock */
+} tds_stats;
+
+/* Index description. */
+typedef struct tds_index_info {
+    uint64_t n;         /* entry segments */
+    uint32_t num_bins;  /* m */
+    uint32_t device;    /* HIP device ordinal */
+    double t_min;       /* min t_start over D */
+    double t_max;       /* max t_end over D */
+    double bin_width;   /* (t_max - t_min) / m */
+    uint64_t device_bytes;
+} tds_index_info;
+
+typedef struct tds_index tds_index;
+
+/* ABI version (TDS_ABI_VERSION of the built library).  Never fails. */
+uint32_t tds_abi_version(void);
+
+/* Static string naming a status code.  Never fails. */
+const char* tds_status_str(int status);
+
+/*
+ * Build the temporal index of D on the current HIP device (Sec. 4.2.1): sort
+ * the entries by t_start (ties keep input order), assign them to m bins of
+ * equal width over [t_min, t_max], and record per bin the first sorted entry
+ * and the data extents used to compute candidate ranges.  The entries are
+ * copied; the index owns all its device memory until tds_index_destroy.
+ * Waits for `stream` before returning.
+ * Errors: TDS_E_INVALID (NULL pointers, n == 0, n >= 2^32 - 1, a non-finite
+ * value or te <= ts in D), TDS_E_NOMEM, TDS_E_DEVICE.
+ */
+int tds_build_index(const tds_segments* D, const tds_build_params* params,
+                    void* stream, tds_index** out);
+
+/* Free the index and its device memory.  NULL is accepted.  The caller must
+   ensure no search on it is still running. */
+int tds_index_destroy(tds_index* index);
+
+/* Describe the index.  Errors: TDS_E_INVALID (NULL pointers). */
+int tds_index_info_get(const tds_index* index, tds_index_info* info);
+
+/*
+ * Copy index tables to host memory (for inspection and tests); any output
+ * may be NULL.  order[n]: input position of the i-th entry in t_start order.
+ * bin_first[m + 1]: sorted position of the first entry of bin j
+ * (bin_first[m] = n; bin j holds [bin_first[j], bin_first[j+1])).
+ * min_ts[m], max_te[m]: data extents of bin j (+inf / -inf when empty).
+ * cmax_te[m]: running maximum of max_te over bins 0..j.
+ * Errors: TDS_E_INVALID, TDS_E_DEVICE.
+ */
+int tds_index_export(const tds_index* index, uint32_t* order, uint32_t* bin_first,
+                     double* min_ts, double* max_te, double* cmax_te);
+
+/*
+ * Candidate range (the schedule S of Sec. 4.2.2) of each query segment: the
+ * contiguous span [lo[k], hi[k]) of sorted entry positions from the first
+ * entry of the first bin whose running max t_end exceeds a_q to the last
+ * entry with t_start < b_q, where [a_q, b_q] is the query segment clipped to
+ * [t_start, t_end].  Every entry that strictly overlaps the clipped query in
+ * time lies in the span.  Empty windows or spans give lo = hi = 0.  lo and hi
+ * are host arrays of Q->n elements.  Waits for `stream`.
+ * Errors: TDS_E_INVALID (bad pointers or Q values, t_start >= t_end or NaN),
+ * TDS_E_NOMEM, TDS_E_DEVICE.
+ */
+int tds_schedule(const tds_index* index, const tds_segments* Q, double t_start,
+                 double t_end, uint32_t* lo, uint32_t* hi, void* stream);
+
+/*
+ * Distance threshold search of Q against the index (Sec. 3.1, Sec. 4.2.2).
+ * Records go to `out` (host or device memory per params->out_on_device) in
+ * unspecified order; *n_out is always set to the total number of results.
+ * d finite and >= 0; t_start < t_end (either may be infinite).  Waits for `stream`.
+ *   TDS_OK          all *n_out records are in out[0 .. *n_out).
+ *   TDS_E_OVERFLOW  *n_out > capacity: out holds an unspecified subset of at
+ *                   most `capacity` records; call again with a larger buffer.
+ * Host output larger than params->device_capacity is produced in several
+ * distance-kernel passes, each writing a slice that fits the device buffer.
+ * stats may be NULL.
+ * Errors: TDS_E_INVALID (bad pointers, d < 0 or NaN, t_start >= t_end, a
+ * non-finite value or te <= ts in Q), TDS_E_NOMEM, TDS_E_DEVICE.
+ */
+int tds_search(const tds_index* index, const tds_segments* Q, double d,
+               double t_start, double t_end, tds_result* out, uint64_t capacity,
+               uint64_t* n_out, const tds_search_params* params, void* stream,
+               tds_stats* stats);
+
+/* Fill *p with the defaults (TDS_PREC_FP32_RECHECK, host output, auto sizes). */
+void tds_search_params_default(tds_search_params* p);
+
+/* Counters of the last tds_search on this index (any thread).  Errors:
+   TDS_E_INVALID. */
+int tds_last_stats(const tds_index* index, tds_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDS_H */

@@ -1,0 +1,104 @@
+"""ctypes declarations of the C ABI in include/tds.h (argument marshalling only).
+
+The library is built in-tree (``paper_1410_2698_amd/libtds.so``); loading
+fails loudly when it is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtds.so")
+
+TDS_OK, TDS_E_INVALID, TDS_E_OVERFLOW, TDS_E_NOMEM, TDS_E_DEVICE, TDS_E_BUSY = range(6)
+TDS_PREC_DEFAULT, TDS_PREC_FP64, TDS_PREC_FP32_RECHECK = 0, 1, 2
+
+c_dbl_p = ctypes.POINTER(ctypes.c_double)
+c_u32_p = ctypes.POINTER(ctypes.c_uint32)
+c_u64_p = ctypes.POINTER(ctypes.c_uint64)
+
+
+class tds_segments(ctypes.Structure):
+    _fields_ = [("xs", ctypes.c_void_p), ("ys", ctypes.c_void_p), ("zs", ctypes.c_void_p),
+                ("ts", ctypes.c_void_p), ("xe", ctypes.c_void_p), ("ye", ctypes.c_void_p),
+                ("ze", ctypes.c_void_p), ("te", ctypes.c_void_p), ("traj_id", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("on_device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class tds_build_params(ctypes.Structure):
+    _fields_ = [("num_bins", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
+
+
+class tds_search_params(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("out_on_device", ctypes.c_int32),
+                ("chunk", ctypes.c_uint32), ("grid_waves", ctypes.c_uint32),
+                ("device_capacity", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 4)]
+
+
+class tds_stats(ctypes.Structure):
+    _fields_ = [("query_segments", ctypes.c_uint64), ("active_segments", ctypes.c_uint64),
+                ("work_items", ctypes.c_uint64), ("candidate_tests", ctypes.c_uint64),
+                ("fp64_evals", ctypes.c_uint64), ("results", ctypes.c_uint64),
+                ("passes", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class tds_index_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("num_bins", ctypes.c_uint32), ("device", ctypes.c_uint32),
+                ("t_min", ctypes.c_double), ("t_max", ctypes.c_double),
+                ("bin_width", ctypes.c_double), ("device_bytes", ctypes.c_uint64)]
+
+
+# exported name -> (restype, argtypes)
+SIGNATURES = {
+    "tds_abi_version": (ctypes.c_uint32, []),
+    "tds_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "tds_build_index": (ctypes.c_int, [ctypes.POINTER(tds_segments), ctypes.POINTER(tds_build_params),
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "tds_index_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "tds_index_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_index_info)]),
+    "tds_index_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tds_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments), ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tds_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments), ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_uint64,
+                                  c_u64_p, ctypes.POINTER(tds_search_params), ctypes.c_void_p,
+                                  ctypes.POINTER(tds_stats)]),
+    "tds_search_params_default": (None, [ctypes.POINTER(tds_search_params)]),
+    "tds_last_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_stats)]),
+}
+
+_lib = None
+
+
+class TdsError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = load().tds_status_str(status).decode() if _lib is not None else f"status {status}"
+        super().__init__(f"{what}: {msg}" if what else msg)
+
+
+def load():
+    """Load libtds.so and declare every entry point; raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
+                               "python paper_1410_2698_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(status: int, what: str = ""):
+    if status != TDS_OK:
+        raise TdsError(status, what)

@@ -1,0 +1,173 @@
+// Stable LSD radix sort of (u64 key, u32 value) pairs with 8-bit digits.
+//
+// Used by the index build to order the entry segments by t_start (Sec. 4.2.1
+// sorts D by ascending start time and renumbers it); stability keeps equal
+// start times in input order, which makes the renumbering deterministic.
+//
+// One pass per digit, three kernels per pass:
+//   rs_hist    each block counts the digits of its 2048-key tile in LDS;
+//   rs_scan    one block turns the digit-major count table into exclusive
+//              offsets (digit d of block b starts after every smaller digit
+//              and after digit d of the blocks before b);
+//   rs_scatter each block re-reads its tile and writes every key to its
+//              offset; the rank of a key among equal digits of its tile comes
+//              from wave ballots (wave-local) plus per-wave digit counts in
+//              LDS, processed in tile order, so the pass is stable.
+#include "tds_internal.hpp"
+
+namespace tds {
+
+namespace {
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr int kRadix = 256;
+constexpr int kRsWaves = kRsThreads / kWave;
+
+__global__ __launch_bounds__(kRsThreads) void rs_hist(const uint64_t* __restrict__ keys, uint32_t n,
+                                                      int shift, uint32_t* __restrict__ hist,
+                                                      uint32_t nblocks) {
+    __shared__ uint32_t h[kRadix];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+    for (int k = 0; k < kRsItems; ++k) {
+        uint64_t i = base + (uint64_t)k * kRsThreads + tid;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)tid * nblocks + blockIdx.x] = h[tid];
+}
+
+// Exclusive scan of `len` u32 values in place with one block of 1024 threads:
+// every thread owns a contiguous run.
+__global__ __launch_bounds__(1024) void rs_scan(uint32_t* __restrict__ v, uint32_t len) {
+    __shared__ uint32_t part[1024];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (len + 1023) / 1024;
+    const uint32_t b = tid * per;
+    const uint32_t e = min(len, b + per);
+    uint32_t s = 0;
+    for (uint32_t i = b; i < e; ++i) s += v[i];
+    part[tid] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 1024 partial sums
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        uint32_t t = (tid >= off) ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += t;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - s;
+    for (uint32_t i = b; i < e; ++i) {
+        uint32_t x = v[i];
+        v[i] = run;
+        run += x;
+    }
+}
+
+__device__ inline uint64_t lanemask_lt() {
+    const uint32_t lane = __lane_id();
+    return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+__global__ __launch_bounds__(kRsThreads) void rs_scatter(const uint64_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin,
+                                                         uint64_t* __restrict__ kout,
+                                                         uint32_t* __restrict__ vout, uint32_t n,
+                                                         int shift,
+                                                         const uint32_t* __restrict__ offs,
+                                                         uint32_t nblocks) {
+    __shared__ uint32_t base[kRadix];
+    __shared__ uint32_t wcnt[kRsWaves][kRadix];
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    base[tid] = offs[(uint64_t)tid * nblocks + blockIdx.x];
+    for (int w = 0; w < kRsWaves; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t tile = (uint64_t)blockIdx.x * kRsTile;
+    for (int k = 0; k < kRsItems; ++k) {
+        const uint64_t i = tile + (uint64_t)k * kRsThreads + tid;
+        const bool valid = i < n;
+        uint64_t key = valid ? kin[i] : 0ull;
+        uint32_t val = valid ? vin[i] : 0u;
+        // 9-bit class: digits 0..255, 256 for lanes without a key
+        const uint32_t digit = valid ? ((uint32_t)(key >> shift) & (kRadix - 1)) : (uint32_t)kRadix;
+        uint64_t same = __ballot(1);
+        for (int bit = 0; bit < 9; ++bit) {
+            const bool set = (digit >> bit) & 1u;
+            const uint64_t m = __ballot(set);
+            same &= set ? m : ~m;
+        }
+        const uint32_t rank = __popcll(same & lanemask_lt());
+        const bool leader = rank == 0;
+        if (valid && leader) wcnt[wave][digit] = __popcll(same);
+        __syncthreads();
+        // per digit: exclusive offsets over the waves of this round
+        {
+            uint32_t run = 0;
+            for (int w = 0; w < kRsWaves; ++w) {
+                uint32_t c = wcnt[w][tid];
+                wcnt[w][tid] = run;
+                run += c;
+            }
+            // run = total of digit tid in this round; add after the scatter
+            __syncthreads();
+            if (valid) {
+                const uint32_t pos = base[digit] + wcnt[wave][digit] + rank;
+                kout[pos] = key;
+                vout[pos] = val;
+            }
+            __syncthreads();
+            base[tid] += run;
+            for (int w = 0; w < kRsWaves; ++w) wcnt[w][tid] = 0;
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace
+
+int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                   uint32_t n, int key_bits, hipStream_t stream) {
+    if (n <= 1) return TDS_OK;
+    const uint32_t nblocks = ceil_div(n, kRsTile);
+    const uint64_t hlen = (uint64_t)kRadix * nblocks;
+    if (hlen >= (1ull << 32)) return TDS_E_INVALID;
+    uint32_t* hist = nullptr;
+    TDS_TRY(dmalloc(&hist, hlen));
+    int passes = (key_bits + 7) / 8;
+    uint64_t* ka = keys;
+    uint32_t* va = vals;
+    uint64_t* kb = keys_alt;
+    uint32_t* vb = vals_alt;
+    int status = TDS_OK;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(rs_hist, dim3(nblocks), dim3(kRsThreads), 0, stream, ka, n, shift, hist,
+                           nblocks);
+        hipLaunchKernelGGL(rs_scan, dim3(1), dim3(1024), 0, stream, hist, (uint32_t)hlen);
+        hipLaunchKernelGGL(rs_scatter, dim3(nblocks), dim3(kRsThreads), 0, stream, ka, va, kb, vb,
+                           n, shift, hist, nblocks);
+        if (hipGetLastError() != hipSuccess) {
+            status = TDS_E_DEVICE;
+            break;
+        }
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (status == TDS_OK && ka != keys) {
+        if (hipMemcpyAsync(keys, ka, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(vals, va, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, stream) !=
+                hipSuccess)
+            status = TDS_E_DEVICE;
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) status = TDS_E_DEVICE;
+    dfree(hist);
+    return status;
+}
+
+}  // namespace tds

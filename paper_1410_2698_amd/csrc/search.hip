@@ -1,0 +1,1050 @@
+// Distance threshold search on the GPU (Sec. 3.1 problem, Sec. 4.2.2 search).
+//
+// Per search, on one stream:
+//   k_zero       clear the header, bucket tables and request counters;
+//   k_qprep      one thread per query segment: validate, velocity, clip to the
+//                window, candidate range [lo, hi) by bisection of the bin
+//                tables (the schedule S of Sec. 4.2.2, computed on the GPU),
+//                FP32 filter sphere, bucket key = (first bin, bin span);
+//   k_bucket_scan  one block: bucket offsets, 64-segment groups per bucket,
+//                candidate chunks per bucket and the work-item table;
+//   k_scatter    order the query segments by bucket;
+//   k_distance   persistent waves pull work items (64 query segments of one
+//                bucket x one chunk of their common candidate range).  Each
+//                lane holds one query segment in registers; the candidates
+//                are streamed through wave-uniform scalar loads, so one load
+//                feeds 64 pair tests.  Pairs that pass the filter are queued
+//                in LDS and evaluated 64 at a time by the canonical FP64 code,
+//                and results are appended with one atomic per request per
+//                64 evaluations.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "tds_internal.hpp"
+
+namespace tds {
+
+namespace {
+
+constexpr uint32_t kInactive = 0xFFFFFFFFu;
+
+// Entry records are read through the constant address space with a
+// wave-uniform index, so the compiler fetches them with scalar loads into
+// SGPRs: one load serves the 64 lanes (query segments) of the wave.
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) f32x8* ConstE32;
+typedef const __attribute__((address_space(4))) f64x4* ConstE64;
+
+struct IndexView {
+    const EntryF64* e64;
+    const EntryF32* e32;
+    const uint32_t* seg_id;
+    const uint32_t* traj;
+    const uint32_t* bin_first;
+    const double* cmax_te;
+    const double* lo_ts;
+    uint32_t n, m;
+};
+
+struct QueryView {
+    const double* a[8];  // xs, ys, zs, ts, xe, ye, ze, te
+    const uint32_t* traj;
+    uint64_t n;
+};
+
+IndexView view_of(const tds_index* idx) {
+    IndexView v;
+    v.e64 = idx->e64;
+    v.e32 = idx->e32;
+    v.seg_id = idx->seg_id;
+    v.traj = idx->traj;
+    v.bin_first = idx->bin_first;
+    v.cmax_te = idx->cmax_te;
+    v.lo_ts = idx->lo_ts;
+    v.n = (uint32_t)idx->n;
+    v.m = idx->m;
+    return v;
+}
+
+__device__ inline double dmax(double a, double b) { return a > b ? a : b; }
+__device__ inline double dmin(double a, double b) { return a < b ? a : b; }
+
+__device__ inline uint64_t lanemask_lt() {
+    const uint32_t lane = __lane_id();
+    return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Keeps LDS traffic of one wave in program order around cross-lane exchange.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------ canonical FP64
+
+// Query side of the canonical evaluation.  aq = max(ts_q, t_start) and
+// bq = min(te_q, t_end) are exact, so max(aq, ts_l) is the common start of
+// the pair whatever order the maxima are taken in.
+struct QCanon {
+    double x, y, z, vx, vy, vz, ts, aq, bq, d;
+};
+
+// Membership and interval of one (query, entry) pair in the fixed FP64
+// operation order: positions at the ends of the common extent, squared
+// distances minus d^2 there (C0, C1), relative velocity W, A = |W|^2,
+// B = D(a).W; member iff C0 <= 0, C1 <= 0 or the vertex of the convex
+// quadratic lies strictly inside with a non-negative discriminant; the roots
+// in cancellation-free form (Higham, Accuracy and Stability of Numerical
+// Algorithms, Sec. 1.8).  Compiled without FP contraction.
+template <bool kInterval>
+__device__ __forceinline__ bool canon_eval(const QCanon& q, double lx, double ly, double lz,
+                                           double lvx, double lvy, double lvz, double lts,
+                                           double lte, double* t_lo, double* t_hi) {
+    const double a = dmax(q.aq, lts);
+    const double b = dmin(q.bq, lte);
+    if (!(a < b)) return false;
+    const double T = b - a;
+    const double dqa = a - q.ts, dla = a - lts;
+    const double dqb = b - q.ts, dlb = b - lts;
+    const double dax = (q.x + q.vx * dqa) - (lx + lvx * dla);
+    const double day = (q.y + q.vy * dqa) - (ly + lvy * dla);
+    const double daz = (q.z + q.vz * dqa) - (lz + lvz * dla);
+    const double dbx = (q.x + q.vx * dqb) - (lx + lvx * dlb);
+    const double dby = (q.y + q.vy * dqb) - (ly + lvy * dlb);
+    const double dbz = (q.z + q.vz * dqb) - (lz + lvz * dlb);
+    const double wx = q.vx - lvx, wy = q.vy - lvy, wz = q.vz - lvz;
+    const double dd = q.d * q.d;
+    const double C0 = ((dax * dax + day * day) + daz * daz) - dd;
+    const double C1 = ((dbx * dbx + dby * dby) + dbz * dbz) - dd;
+    const double A = (wx * wx + wy * wy) + wz * wz;
+    const double B = (dax * wx + day * wy) + daz * wz;
+    const bool member = (C0 <= 0.0) || (C1 <= 0.0) ||
+                        (A > 0.0 && B < 0.0 && -B < A * T && B * B - A * C0 >= 0.0);
+    if (!kInterval || !member) return member;
+    if (A == 0.0) {
+        *t_lo = a;
+        *t_hi = b;
+        return true;
+    }
+    const double disc = B * B - A * C0;
+    const double s = sqrt(dmax(disc, 0.0));
+    const double qq = (B >= 0.0) ? (-B - s) : (-B + s);
+    const double r1 = qq / A;
+    const double r2 = (qq != 0.0) ? C0 / qq : 0.0;
+    double lo = (C0 <= 0.0) ? a : a + dmin(dmax(dmin(r1, r2), 0.0), T);
+    double hi = (C1 <= 0.0) ? b : a + dmin(dmax(dmax(r1, r2), 0.0), T);
+    if (lo > hi) {
+        const double tv = a + dmin(dmax(-B / A, 0.0), T);
+        lo = tv;
+        hi = tv;
+    }
+    *t_lo = lo;
+    *t_hi = hi;
+    return true;
+}
+
+// ------------------------------------------------------------ schedule
+
+// Candidate range of a clipped query [aq, bq): lo = first position of the
+// first bin whose running max t_end exceeds aq; hi = number of entries with
+// t_start < bq.  Also returns the first and last bins of the span.
+__device__ inline void cand_range(const IndexView& I, double aq, double bq, uint32_t* lo,
+                                  uint32_t* hi, uint32_t* j0o, uint32_t* j1o) {
+    // j0 = first j with cmax_te[j] > aq (m if none)
+    uint32_t l = 0, h = I.m;
+    while (l < h) {
+        uint32_t mid = (l + h) >> 1;
+        if (I.cmax_te[mid] > aq) h = mid;
+        else l = mid + 1;
+    }
+    const uint32_t j0 = l;
+    // number of bins whose first t_start is < bq
+    l = 0;
+    h = I.m;
+    while (l < h) {
+        uint32_t mid = (l + h) >> 1;
+        if (I.lo_ts[mid] < bq) l = mid + 1;
+        else h = mid;
+    }
+    uint32_t hiv = 0, j1 = 0;
+    if (l > 0) {
+        j1 = l - 1;
+        uint32_t a = I.bin_first[j1], b = I.bin_first[j1 + 1];
+        while (a < b) {  // first position in bin j1 with ts >= bq
+            uint32_t mid = (a + b) >> 1;
+            if (I.e64[mid].ts < bq) a = mid + 1;
+            else b = mid;
+        }
+        hiv = a;
+    }
+    const uint32_t lov = (j0 < I.m) ? I.bin_first[j0] : I.n;
+    *lo = lov;
+    *hi = hiv;
+    *j0o = j0;
+    *j1o = j1;
+}
+
+__device__ inline bool finite(double v) { return isfinite(v); }
+
+// Request of query segment k: requests hold contiguous, ascending slices.
+__device__ inline uint32_t request_of(const Request* req, uint32_t nreq, uint64_t k) {
+    uint32_t l = 0, h = nreq;
+    while (h - l > 1) {
+        uint32_t mid = (l + h) >> 1;
+        if (req[mid].q_begin <= k) l = mid;
+        else h = mid;
+    }
+    return l;
+}
+
+// ------------------------------------------------------------ kernels
+
+__global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_count,
+                                                 uint32_t* b_lo, uint32_t* b_hi, uint32_t nb,
+                                                 ReqCounter* rc, uint32_t nreq) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) {
+        SearchHeader h = {};
+        *hdr = h;
+    }
+    if (i < nb) {
+        b_count[i] = 0;
+        b_lo[i] = 0xFFFFFFFFu;
+        b_hi[i] = 0;
+    }
+    if (i < nreq) {
+        rc[i].count = 0;
+        rc[i].pad = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const Request* __restrict__ req,
+                                                  uint32_t nreq, IndexView I,
+                                                  QPrep* __restrict__ qp,
+                                                  uint32_t* __restrict__ qkey,
+                                                  uint32_t* __restrict__ qslot, uint32_t* b_count,
+                                                  uint32_t* b_lo, uint32_t* b_hi, uint32_t shift,
+                                                  SearchHeader* hdr) {
+    const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool active = false;
+    if (k < Q.n) {
+        const uint32_t r = request_of(req, nreq, k);
+        const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k], ts = Q.a[3][k];
+        const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k], te = Q.a[7][k];
+        const bool ok = finite(xs) && finite(ys) && finite(zs) && finite(ts) && finite(xe) &&
+                        finite(ye) && finite(ze) && finite(te) && te > ts;
+        qslot[k] = kInactive;
+        if (!ok) {
+            atomicOr(&hdr->err, 1u);
+        } else {
+            const double d = req[r].d;
+            const double dt = te - ts;
+            QPrep p;
+            p.x = xs;
+            p.y = ys;
+            p.z = zs;
+            p.vx = (xe - xs) / dt;
+            p.vy = (ye - ys) / dt;
+            p.vz = (ze - zs) / dt;
+            p.ts = ts;
+            p.aq = dmax(ts, req[r].t_start);
+            p.bq = dmin(te, req[r].t_end);
+            p.d = d;
+            p.qid = (uint32_t)(k - req[r].q_begin);
+            p.traj = Q.traj ? Q.traj[k] : 0u;
+            p.req = r;
+            p.pad = 0;
+            if (p.aq < p.bq) {
+                uint32_t lo, hi, j0, j1;
+                cand_range(I, p.aq, p.bq, &lo, &hi, &j0, &j1);
+                if (lo < hi) {
+                    const double pax = p.x + p.vx * (p.aq - ts), pay = p.y + p.vy * (p.aq - ts),
+                                 paz = p.z + p.vz * (p.aq - ts);
+                    const double pbx = p.x + p.vx * (p.bq - ts), pby = p.y + p.vy * (p.bq - ts),
+                                 pbz = p.z + p.vz * (p.bq - ts);
+                    sphere32(pax, pay, paz, pbx, pby, pbz, d, p.cx, p.cy, p.cz, p.R);
+                    p.a32 = __double2float_rd(p.aq);
+                    p.b32 = __double2float_ru(p.bq);
+                    p.lo = lo;
+                    p.hi = hi;
+                    const uint32_t span = min(j1 - j0, kSpanClasses - 1);
+                    const uint32_t key = (j0 * kSpanClasses + span) >> shift;
+                    qkey[k] = key;
+                    qslot[k] = atomicAdd(&b_count[key], 1u);
+                    atomicMin(&b_lo[key], lo);
+                    atomicMax(&b_hi[key], hi);
+                    qp[k] = p;
+                    active = true;
+                }
+            }
+        }
+    }
+    const uint64_t am = __ballot(active);
+    if (__lane_id() == 0 && am) atomicAdd(&hdr->active, (uint32_t)__popcll(am));
+}
+
+// Schedule only (tds_schedule): candidate range per query segment.
+__global__ __launch_bounds__(kBlock) void k_schedule(QueryView Q, double t_start, double t_end,
+                                                     IndexView I, uint32_t* __restrict__ lo_out,
+                                                     uint32_t* __restrict__ hi_out,
+                                                     uint32_t* err) {
+    const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= Q.n) return;
+    bool ok = true;
+    for (int c = 0; c < 8; ++c) ok = ok && finite(Q.a[c][k]);
+    const double ts = Q.a[3][k], te = Q.a[7][k];
+    ok = ok && te > ts;
+    uint32_t lo = 0, hi = 0;
+    if (!ok) {
+        atomicOr(err, 1u);
+    } else {
+        const double aq = dmax(ts, t_start), bq = dmin(te, t_end);
+        if (aq < bq) {
+            uint32_t j0, j1;
+            cand_range(I, aq, bq, &lo, &hi, &j0, &j1);
+            if (lo >= hi) lo = hi = 0;
+        }
+    }
+    lo_out[k] = lo;
+    hi_out[k] = hi;
+}
+
+// Bucket offsets, groups and the work-item table, one block.
+__global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict__ b_count,
+                                                      const uint32_t* __restrict__ b_lo,
+                                                      const uint32_t* __restrict__ b_hi,
+                                                      uint32_t nb, uint32_t chunk,
+                                                      uint32_t* __restrict__ b_start,
+                                                      uint32_t* __restrict__ b_item,
+                                                      uint32_t* __restrict__ b_nch,
+                                                      uint32_t* __restrict__ b_clen,
+                                                      SearchHeader* hdr) {
+    __shared__ uint32_t pc[1024], pi[1024];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (nb + 1023) / 1024;
+    const uint32_t b0 = tid * per, b1 = min(nb, b0 + per);
+    uint32_t sc = 0, si = 0;
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint32_t cnt = b_count[b];
+        uint32_t nch = 0, clen = 0;
+        if (cnt) {
+            // balanced chunks of at most `chunk` candidates, none empty
+            const uint32_t len = b_hi[b] - b_lo[b];
+            const uint32_t n0 = (len + chunk - 1) / chunk;
+            clen = (len + n0 - 1) / n0;
+            nch = (len + clen - 1) / clen;
+        }
+        b_nch[b] = nch;
+        b_clen[b] = clen;
+        sc += cnt;
+        si += ((cnt + kWave - 1) / kWave) * nch;
+    }
+    pc[tid] = sc;
+    pi[tid] = si;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const uint32_t tc = (tid >= off) ? pc[tid - off] : 0u;
+        const uint32_t ti = (tid >= off) ? pi[tid - off] : 0u;
+        __syncthreads();
+        pc[tid] += tc;
+        pi[tid] += ti;
+        __syncthreads();
+    }
+    uint32_t rc = pc[tid] - sc, ri = pi[tid] - si;
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint32_t cnt = b_count[b];
+        b_start[b] = rc;
+        b_item[b] = ri;
+        rc += cnt;
+        ri += ((cnt + kWave - 1) / kWave) * b_nch[b];
+    }
+    if (tid == 1023) {
+        b_item[nb] = pi[1023];
+        hdr->n_items = pi[1023];
+        hdr->n_buckets = nb;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(uint64_t nq, const uint32_t* __restrict__ qkey,
+                                                    const uint32_t* __restrict__ qslot,
+                                                    const uint32_t* __restrict__ b_start,
+                                                    uint32_t* __restrict__ qsorted) {
+    const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= nq) return;
+    const uint32_t s = qslot[k];
+    if (s != kInactive) qsorted[b_start[qkey[k]] + s] = (uint32_t)k;
+}
+
+// Resets the per-pass counters of the distance kernel.
+__global__ void k_reset_pass(SearchHeader* hdr, ReqCounter* rc, uint32_t nreq) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) hdr->work_ctr = 0;
+    if (i < nreq) rc[i].count = 0;
+}
+
+struct DistArgs {
+    IndexView I;
+    const QPrep* qp;
+    const uint32_t* qsorted;
+    const uint32_t* b_start;
+    const uint32_t* b_count;
+    const uint32_t* b_lo;
+    const uint32_t* b_hi;
+    const uint32_t* b_nch;
+    const uint32_t* b_clen;
+    const uint32_t* b_item;
+    uint32_t nb;
+    SearchHeader* hdr;
+    const Request* req;
+    ReqCounter* rc;
+    tds_result* out;
+    uint64_t win_lo;        // first request-local result position kept
+    uint32_t item_begin;    // work items [item_begin, item_end)
+    uint32_t item_end;      // 0xFFFFFFFF: up to the header's item count
+    uint32_t* item_count;   // results per work item, or nullptr
+};
+
+struct WaveLDS {
+    uint32_t queue[5 * kWave];  // < 64 left over + 4 candidates x 64 lanes
+    double qx[kWave], qy[kWave], qz[kWave], qvx[kWave], qvy[kWave], qvz[kWave];
+    double qts[kWave], qaq[kWave], qbq[kWave], qd[kWave];
+    uint32_t qid[kWave], qtraj[kWave], qreq[kWave];
+};
+
+// Evaluates `cnt` <= 64 queued pairs from position `head` (one per lane) with
+// the canonical FP64 code and appends the results.  Returns the number of
+// results.
+__device__ __forceinline__ uint32_t drain(WaveLDS& L, uint32_t head, uint32_t cnt, uint32_t c0,
+                                          const DistArgs& A) {
+    const uint32_t lane = __lane_id();
+    const bool act = lane < cnt;
+    const uint32_t pk = act ? L.queue[head + lane] : 0u;
+    const uint32_t ql = pk & (kWave - 1);
+    const uint32_t i = c0 + (pk >> 6);
+    double t_lo = 0.0, t_hi = 0.0;
+    bool hit = false;
+    uint32_t myreq = 0;
+    if (act) {
+        QCanon q;
+        q.x = L.qx[ql];
+        q.y = L.qy[ql];
+        q.z = L.qz[ql];
+        q.vx = L.qvx[ql];
+        q.vy = L.qvy[ql];
+        q.vz = L.qvz[ql];
+        q.ts = L.qts[ql];
+        q.aq = L.qaq[ql];
+        q.bq = L.qbq[ql];
+        q.d = L.qd[ql];
+        const EntryF64 e = A.I.e64[i];
+        hit = canon_eval<true>(q, e.x, e.y, e.z, e.vx, e.vy, e.vz, e.ts, e.te, &t_lo, &t_hi);
+        myreq = L.qreq[ql];
+    }
+    uint64_t hm = ballot(hit);
+    const uint32_t nhit = (uint32_t)__popcll(hm);
+    while (hm) {
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)hm) - 1u;
+        const uint32_t r = __shfl(myreq, leader);
+        const uint64_t mm = ballot(hit && myreq == r);
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(&A.rc[r].count, (unsigned long long)__popcll(mm));
+        base = __shfl(base, leader);
+        if (hit && myreq == r) {
+            const uint64_t pos = base + (uint64_t)__popcll(mm & lanemask_lt());
+            const Request& R = A.req[r];
+            if (pos >= A.win_lo && pos - A.win_lo < R.out_capacity) {
+                tds_result rec;
+                rec.q_seg = L.qid[ql];
+                rec.e_seg = A.I.seg_id[i];
+                rec.q_traj = L.qtraj[ql];
+                rec.e_traj = A.I.traj[i];
+                rec.t_lo = t_lo;
+                rec.t_hi = t_hi;
+                A.out[R.out_offset + (pos - A.win_lo)] = rec;
+            }
+        }
+        hm &= ~mm;
+    }
+    return nhit;
+}
+
+// Appends the lanes of mask m (candidate i) to the wave's pair queue.
+__device__ __forceinline__ void enqueue(WaveLDS& L, uint64_t m, bool pass, uint32_t i, uint32_t c0,
+                                        uint32_t& qn) {
+    if (pass) L.queue[qn + (uint32_t)__popcll(m & lanemask_lt())] = ((i - c0) << 6) | __lane_id();
+    qn += (uint32_t)__popcll(m);
+}
+
+// Evaluates full batches of 64 queued pairs; keeps the remainder queued.
+__device__ __forceinline__ void drain_full(WaveLDS& L, uint32_t c0, uint32_t& qn, uint32_t& evals,
+                                           uint32_t& found, const DistArgs& A) {
+    const uint32_t lane = __lane_id();
+    uint32_t head = 0;
+    wave_sync();
+    while (qn - head >= kWave) {
+        found += drain(L, head, kWave, c0, A);
+        evals += kWave;
+        head += kWave;
+    }
+    if (head) {
+        const uint32_t rest = qn - head;  // < 64
+        wave_sync();
+        uint32_t v = 0;
+        if (lane < rest) v = L.queue[head + lane];
+        wave_sync();
+        if (lane < rest) L.queue[lane] = v;
+        qn = rest;
+    }
+    wave_sync();
+}
+
+// FP32 filter of one candidate record (cx, cy, cz, r, ts, te): the pair can
+// only be a result if the two bounding spheres come within d (the margins
+// are folded into R and r) and the outward-rounded time extents overlap.
+__device__ __forceinline__ bool filter32(const f32x8& e, float qcx, float qcy, float qcz, float qR,
+                                         float qa, float qb) {
+    const float dx = e[0] - qcx, dy = e[1] - qcy, dz = e[2] - qcz;
+    const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float R = qR + e[3];
+    return (s <= R * R) & (qa < e[5]) & (e[4] < qb);
+}
+
+template <int kPrec, bool kUniform>
+__device__ __forceinline__ void scan_chunk(WaveLDS& L, const DistArgs& A, uint32_t c0,
+                                           uint32_t c1, bool has, const QPrep& p,
+                                           uint32_t& qn, uint32_t& evals, uint32_t& found) {
+    const uint32_t qlo = p.lo, qhi = p.hi;
+    if (kPrec == TDS_PREC_FP32_RECHECK) {
+        ConstE32 ce = (ConstE32)(A.I.e32);
+        const float qcx = p.cx, qcy = p.cy, qcz = p.cz, qR = has ? p.R : -1.0f;
+        // lanes without a query get an empty time window
+        const float qa = has ? p.a32 : 1.0f, qb = has ? p.b32 : -1.0f;
+        uint32_t i = c0;
+        for (; i + 4 <= c1; i += 4) {
+            const f32x8 e0 = ce[i], e1 = ce[i + 1], e2 = ce[i + 2], e3 = ce[i + 3];
+            bool p0 = filter32(e0, qcx, qcy, qcz, qR, qa, qb);
+            bool p1 = filter32(e1, qcx, qcy, qcz, qR, qa, qb);
+            bool p2 = filter32(e2, qcx, qcy, qcz, qR, qa, qb);
+            bool p3 = filter32(e3, qcx, qcy, qcz, qR, qa, qb);
+            if (!kUniform) {
+                p0 = p0 & (i >= qlo) & (i < qhi);
+                p1 = p1 & (i + 1 >= qlo) & (i + 1 < qhi);
+                p2 = p2 & (i + 2 >= qlo) & (i + 2 < qhi);
+                p3 = p3 & (i + 3 >= qlo) & (i + 3 < qhi);
+            }
+            const uint64_t m0 = ballot(p0), m1 = ballot(p1), m2 = ballot(p2), m3 = ballot(p3);
+            if ((m0 | m1 | m2 | m3) == 0) continue;
+            enqueue(L, m0, p0, i, c0, qn);
+            enqueue(L, m1, p1, i + 1, c0, qn);
+            enqueue(L, m2, p2, i + 2, c0, qn);
+            enqueue(L, m3, p3, i + 3, c0, qn);
+            if (qn >= kWave) drain_full(L, c0, qn, evals, found, A);
+        }
+        for (; i < c1; ++i) {
+            const f32x8 e0 = ce[i];
+            bool p0 = filter32(e0, qcx, qcy, qcz, qR, qa, qb);
+            if (!kUniform) p0 = p0 & (i >= qlo) & (i < qhi);
+            const uint64_t m0 = ballot(p0);
+            if (!m0) continue;
+            enqueue(L, m0, p0, i, c0, qn);
+            if (qn >= kWave) drain_full(L, c0, qn, evals, found, A);
+        }
+    } else {
+        ConstE64 ce = (ConstE64)(A.I.e64);
+        QCanon q;
+        q.x = p.x;
+        q.y = p.y;
+        q.z = p.z;
+        q.vx = p.vx;
+        q.vy = p.vy;
+        q.vz = p.vz;
+        q.ts = p.ts;
+        q.aq = has ? p.aq : 1.0;
+        q.bq = has ? p.bq : 0.0;  // empty window: never a member
+        q.d = p.d;
+        for (uint32_t i = c0; i < c1; ++i) {
+            const f64x4 e0 = ce[2 * i], e1 = ce[2 * i + 1];  // x, y, z, vx | vy, vz, ts, te
+            bool pass = canon_eval<false>(q, e0[0], e0[1], e0[2], e0[3], e1[0], e1[1], e1[2], e1[3],
+                                          nullptr, nullptr);
+            if (!kUniform) pass = pass & (i >= qlo) & (i < qhi);
+            const uint64_t m = ballot(pass);
+            if (!m) continue;
+            enqueue(L, m, pass, i, c0, qn);
+            if (qn >= kWave) drain_full(L, c0, qn, evals, found, A);
+        }
+    }
+}
+
+template <int kPrec>
+__global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
+    __shared__ WaveLDS wl[kWavesPerBlock];
+    WaveLDS& L = wl[threadIdx.x / kWave];
+    const uint32_t lane = __lane_id();
+    const uint32_t item_end = (A.item_end == 0xFFFFFFFFu) ? A.hdr->n_items : A.item_end;
+    uint64_t tests = 0, evals_total = 0;
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(&A.hdr->work_ctr, 1u);
+        it = uniform(__shfl(it, 0)) + A.item_begin;
+        if (it >= item_end) break;
+        // bucket b: last b with b_item[b] <= it
+        uint32_t lo = 0, hi = A.nb;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (A.b_item[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t b = uniform(lo);
+        const uint32_t local = it - A.b_item[b];
+        const uint32_t nch = A.b_nch[b];
+        const uint32_t g = local / nch;
+        const uint32_t c = local - g * nch;
+        const uint32_t cnt = A.b_count[b];
+        const uint32_t nq = uniform(min((uint32_t)kWave, cnt - g * kWave));
+        const uint32_t clen = A.b_clen[b];
+        const uint32_t c0 = uniform(A.b_lo[b] + c * clen);
+        const uint32_t c1 = uniform(min(A.b_hi[b], c0 + clen));
+        const bool has = lane < nq;
+        QPrep p = {};
+        if (has) p = A.qp[A.qsorted[A.b_start[b] + g * kWave + lane]];
+        L.qx[lane] = p.x;
+        L.qy[lane] = p.y;
+        L.qz[lane] = p.z;
+        L.qvx[lane] = p.vx;
+        L.qvy[lane] = p.vy;
+        L.qvz[lane] = p.vz;
+        L.qts[lane] = p.ts;
+        L.qaq[lane] = p.aq;
+        L.qbq[lane] = p.bq;
+        L.qd[lane] = p.d;
+        L.qid[lane] = p.qid;
+        L.qtraj[lane] = p.traj;
+        L.qreq[lane] = p.req;
+        wave_sync();
+        const bool cover = !has || (p.lo <= c0 && p.hi >= c1);
+        const bool all_cover = ballot(cover) == ~0ull;
+        uint32_t qn = 0, evals = 0, found = 0;
+        if (all_cover) scan_chunk<kPrec, true>(L, A, c0, c1, has, p, qn, evals, found);
+        else scan_chunk<kPrec, false>(L, A, c0, c1, has, p, qn, evals, found);
+        if (qn) {
+            wave_sync();
+            found += drain(L, 0, qn, c0, A);
+            evals += qn;
+        }
+        wave_sync();
+        tests += (uint64_t)(c1 - c0) * nq;
+        evals_total += evals;
+        if (A.item_count && lane == 0) A.item_count[it] = found;
+    }
+    if (lane == 0) {
+        if (tests) atomicAdd((unsigned long long*)&A.hdr->tests, (unsigned long long)tests);
+        if (evals_total)
+            atomicAdd((unsigned long long*)&A.hdr->evals, (unsigned long long)evals_total);
+    }
+}
+
+// ------------------------------------------------------------ host side
+
+template <typename T>
+int grow(T** p, size_t* cap, size_t need) {
+    if (*cap >= need && *p) return TDS_OK;
+    dfree(*p);
+    *p = nullptr;
+    *cap = 0;
+    TDS_TRY(dmalloc(p, need));
+    *cap = need;
+    return TDS_OK;
+}
+
+struct WsCaps {
+    size_t q = 0, r = 0, items = 0, res = 0, stage = 0;
+};
+
+}  // namespace
+
+Workspace::~Workspace() {
+    dfree(qp);
+    dfree(qkey);
+    dfree(qslot);
+    dfree(qsorted);
+    dfree(qstage);
+    dfree(qtraj_stage);
+    dfree(req);
+    dfree(req_ctr);
+    dfree(b_count);
+    dfree(b_lo);
+    dfree(b_hi);
+    dfree(b_start);
+    dfree(b_item);
+    dfree(b_nch);
+    dfree(b_clen);
+    dfree(item_count);
+    dfree(res);
+    dfree(hdr);
+    if (hdr_host) (void)hipHostFree(hdr_host);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+}
+
+namespace {
+
+int ws_init(Workspace* w) {
+    TDS_TRY(dmalloc(&w->b_count, kMaxBuckets));
+    TDS_TRY(dmalloc(&w->b_lo, kMaxBuckets));
+    TDS_TRY(dmalloc(&w->b_hi, kMaxBuckets));
+    TDS_TRY(dmalloc(&w->b_start, kMaxBuckets));
+    TDS_TRY(dmalloc(&w->b_item, kMaxBuckets + 1));
+    TDS_TRY(dmalloc(&w->b_nch, kMaxBuckets));
+    TDS_TRY(dmalloc(&w->b_clen, kMaxBuckets));
+    TDS_TRY(dmalloc(&w->hdr, 1));
+    TDS_HIP(hipHostMalloc((void**)&w->hdr_host, sizeof(SearchHeader), hipHostMallocDefault));
+    TDS_HIP(hipEventCreate(&w->ev0));
+    TDS_HIP(hipEventCreate(&w->ev1));
+    return TDS_OK;
+}
+
+int ws_reserve(Workspace* w, size_t nq, size_t nreq) {
+    if (w->q_cap < nq || !w->qp) {
+        dfree(w->qp);
+        dfree(w->qkey);
+        dfree(w->qslot);
+        dfree(w->qsorted);
+        w->qp = nullptr;
+        w->qkey = w->qslot = w->qsorted = nullptr;
+        w->q_cap = 0;
+        TDS_TRY(dmalloc(&w->qp, nq));
+        TDS_TRY(dmalloc(&w->qkey, nq));
+        TDS_TRY(dmalloc(&w->qslot, nq));
+        TDS_TRY(dmalloc(&w->qsorted, nq));
+        w->q_cap = nq;
+    }
+    if (w->r_cap < nreq || !w->req) {
+        dfree(w->req);
+        dfree(w->req_ctr);
+        w->req = nullptr;
+        w->req_ctr = nullptr;
+        w->r_cap = 0;
+        TDS_TRY(dmalloc(&w->req, nreq));
+        TDS_TRY(dmalloc(&w->req_ctr, nreq));
+        w->r_cap = nreq;
+    }
+    return TDS_OK;
+}
+
+Workspace* acquire(tds_index* idx) {
+    {
+        std::lock_guard<std::mutex> g(idx->mu);
+        if (!idx->pool.empty()) {
+            Workspace* w = idx->pool.back();
+            idx->pool.pop_back();
+            return w;
+        }
+    }
+    Workspace* w = new (std::nothrow) Workspace();
+    if (!w) return nullptr;
+    w->device = idx->device;
+    if (ws_init(w) != TDS_OK) {
+        delete w;
+        return nullptr;
+    }
+    return w;
+}
+
+void release(tds_index* idx, Workspace* w) {
+    std::lock_guard<std::mutex> g(idx->mu);
+    idx->pool.push_back(w);
+}
+
+struct WsGuard {
+    tds_index* idx;
+    Workspace* w;
+    ~WsGuard() {
+        if (w) release(idx, w);
+    }
+};
+
+// Device view of the query arrays; host arrays are copied into the staging
+// buffers first.
+int stage_queries(const tds_segments* Q, QueryView* V, hipStream_t s, double** stage_buf,
+                  size_t* stage_cap, uint32_t** traj_buf, size_t* traj_cap) {
+    V->n = Q->n;
+    const double* src[8] = {Q->xs, Q->ys, Q->zs, Q->ts, Q->xe, Q->ye, Q->ze, Q->te};
+    if (Q->on_device) {
+        for (int k = 0; k < 8; ++k) V->a[k] = src[k];
+        V->traj = Q->traj_id;
+        return TDS_OK;
+    }
+    TDS_TRY(grow(stage_buf, stage_cap, 8 * (size_t)Q->n));
+    for (int k = 0; k < 8; ++k) {
+        TDS_HIP(hipMemcpyAsync(*stage_buf + k * Q->n, src[k], Q->n * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+        V->a[k] = *stage_buf + k * Q->n;
+    }
+    V->traj = nullptr;
+    if (Q->traj_id) {
+        TDS_TRY(grow(traj_buf, traj_cap, (size_t)Q->n));
+        TDS_HIP(hipMemcpyAsync(*traj_buf, Q->traj_id, Q->n * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, s));
+        V->traj = *traj_buf;
+    }
+    return TDS_OK;
+}
+
+uint32_t bucket_shift(uint32_t m) {
+    uint32_t shift = 0;
+    while ((((uint64_t)m * kSpanClasses - 1) >> shift) >= kMaxBuckets) ++shift;
+    return shift;
+}
+
+// Stage-1 launches: clear, prepare queries, bucket table, ordering.
+int enqueue_prepare(const tds_index* idx, Workspace* w, const QueryView& Q, uint32_t nreq,
+                    uint32_t chunk, hipStream_t s, uint32_t* nb_out) {
+    const IndexView I = view_of(idx);
+    const uint32_t shift = bucket_shift(idx->m);
+    const uint32_t nb = (uint32_t)((((uint64_t)idx->m * kSpanClasses - 1) >> shift) + 1);
+    const uint32_t zn = std::max(nb, nreq);
+    hipLaunchKernelGGL(k_zero, dim3(ceil_div(zn, kBlock)), dim3(kBlock), 0, s, w->hdr, w->b_count,
+                       w->b_lo, w->b_hi, nb, w->req_ctr, nreq);
+    if (Q.n) {
+        hipLaunchKernelGGL(k_qprep, dim3(ceil_div(Q.n, kBlock)), dim3(kBlock), 0, s, Q, w->req,
+                           nreq, I, w->qp, w->qkey, w->qslot, w->b_count, w->b_lo, w->b_hi, shift,
+                           w->hdr);
+    }
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_lo, w->b_hi, nb,
+                       chunk, w->b_start, w->b_item, w->b_nch, w->b_clen, w->hdr);
+    if (Q.n) {
+        hipLaunchKernelGGL(k_scatter, dim3(ceil_div(Q.n, kBlock)), dim3(kBlock), 0, s, Q.n,
+                           w->qkey, w->qslot, w->b_start, w->qsorted);
+    }
+    TDS_HIP(hipGetLastError());
+    *nb_out = nb;
+    return TDS_OK;
+}
+
+int enqueue_distance(const tds_index* idx, Workspace* w, int prec, uint32_t nb, uint32_t nreq,
+                     tds_result* out, uint64_t win_lo, uint32_t item_begin, uint32_t item_end,
+                     uint32_t* item_count, uint32_t grid_waves, hipStream_t s,
+                     hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr) {
+    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(nreq, 1u), 256)), dim3(256), 0, s,
+                       w->hdr, w->req_ctr, nreq);
+    if (ev_begin) TDS_HIP(hipEventRecord(ev_begin, s));
+    DistArgs A;
+    A.I = view_of(idx);
+    A.qp = w->qp;
+    A.qsorted = w->qsorted;
+    A.b_start = w->b_start;
+    A.b_count = w->b_count;
+    A.b_lo = w->b_lo;
+    A.b_hi = w->b_hi;
+    A.b_nch = w->b_nch;
+    A.b_clen = w->b_clen;
+    A.b_item = w->b_item;
+    A.nb = nb;
+    A.hdr = w->hdr;
+    A.req = w->req;
+    A.rc = w->req_ctr;
+    A.out = out;
+    A.win_lo = win_lo;
+    A.item_begin = item_begin;
+    A.item_end = item_end;
+    A.item_count = item_count;
+    const uint32_t blocks = std::max(1u, ceil_div(grid_waves, kWavesPerBlock));
+    if (prec == TDS_PREC_FP64)
+        hipLaunchKernelGGL(k_distance<TDS_PREC_FP64>, dim3(blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL(k_distance<TDS_PREC_FP32_RECHECK>, dim3(blocks), dim3(kBlock), 0, s, A);
+    TDS_HIP(hipGetLastError());
+    if (ev_end) TDS_HIP(hipEventRecord(ev_end, s));
+    return TDS_OK;
+}
+
+}  // namespace
+
+int schedule_impl(tds_index* idx, const tds_segments* Q, double t_start, double t_end,
+                  uint32_t* lo, uint32_t* hi, hipStream_t s) {
+    if (!idx || !lo || !hi) return TDS_E_INVALID;
+    TDS_TRY(validate_segments_args(Q));
+    if (!(t_start < t_end)) return TDS_E_INVALID;
+    const uint64_t nq = Q->n;
+    double* stage = nullptr;
+    size_t scap = 0;
+    uint32_t* tstage = nullptr;
+    size_t tcap = 0;
+    uint32_t *dlo = nullptr, *dhi = nullptr, *err = nullptr;
+    int st = TDS_OK;
+    QueryView V{};
+    do {
+        if ((st = stage_queries(Q, &V, s, &stage, &scap, &tstage, &tcap))) break;
+        if ((st = dmalloc(&dlo, nq))) break;
+        if ((st = dmalloc(&dhi, nq))) break;
+        if ((st = dmalloc(&err, 1))) break;
+        if (hipMemsetAsync(err, 0, sizeof(uint32_t), s) != hipSuccess) { st = TDS_E_DEVICE; break; }
+        hipLaunchKernelGGL(k_schedule, dim3(ceil_div(nq, kBlock)), dim3(kBlock), 0, s, V, t_start,
+                           t_end, view_of(idx), dlo, dhi, err);
+        uint32_t herr = 0;
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(lo, dlo, nq * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(hi, dhi, nq * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&herr, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            st = TDS_E_DEVICE;
+            break;
+        }
+        if (herr) st = TDS_E_INVALID;
+    } while (0);
+    dfree(stage);
+    dfree(tstage);
+    dfree(dlo);
+    dfree(dhi);
+    dfree(err);
+    return st;
+}
+
+int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start, double t_end,
+                tds_result* out, uint64_t capacity, uint64_t* n_out,
+                const tds_search_params* params, hipStream_t s, tds_stats* stats) {
+    const auto t_begin = std::chrono::steady_clock::now();
+    if (!idx || !n_out) return TDS_E_INVALID;
+    *n_out = 0;
+    TDS_TRY(validate_segments_args(Q));
+    if (!(d >= 0.0) || std::isinf(d)) return TDS_E_INVALID;
+    if (!(t_start < t_end)) return TDS_E_INVALID;
+    if (capacity > 0 && !out) return TDS_E_INVALID;
+    tds_search_params P;
+    tds_search_params_default(&P);
+    if (params) P = *params;
+    int prec = P.precision == TDS_PREC_DEFAULT ? TDS_PREC_FP32_RECHECK : P.precision;
+    if (prec != TDS_PREC_FP64 && prec != TDS_PREC_FP32_RECHECK) return TDS_E_INVALID;
+    const uint32_t chunk = P.chunk ? std::max(P.chunk, 64u) : (prec == TDS_PREC_FP64 ? 512u : 1024u);
+    const bool dev_out = P.out_on_device != 0;
+
+    Workspace* w = acquire(idx);
+    if (!w) return TDS_E_NOMEM;
+    WsGuard guard{idx, w};
+    TDS_TRY(ws_reserve(w, Q->n, 1));
+    QueryView V{};
+    TDS_TRY(stage_queries(Q, &V, s, &w->qstage, &w->stage_cap, &w->qtraj_stage, &w->traj_cap));
+
+    // result buffer
+    uint64_t dev_cap;
+    tds_result* res;
+    if (dev_out) {
+        dev_cap = capacity;
+        res = out;
+    } else {
+        dev_cap = P.device_capacity ? P.device_capacity
+                                    : std::min<uint64_t>(std::max<uint64_t>(capacity, 1), kDefaultDevCap);
+        TDS_TRY(grow(&w->res, &w->res_cap, (size_t)std::max<uint64_t>(dev_cap, 1)));
+        res = w->res;
+    }
+    Request R{};
+    R.q_begin = 0;
+    R.q_count = Q->n;
+    R.d = d;
+    R.t_start = t_start;
+    R.t_end = t_end;
+    R.out_offset = 0;
+    R.out_capacity = dev_cap;
+    TDS_HIP(hipMemcpyAsync(w->req, &R, sizeof(Request), hipMemcpyHostToDevice, s));
+    uint32_t nb = 0;
+    TDS_TRY(enqueue_prepare(idx, w, V, 1, chunk, s, &nb));
+    TDS_HIP(hipMemcpyAsync(w->hdr_host, w->hdr, sizeof(SearchHeader), hipMemcpyDeviceToHost, s));
+    TDS_HIP(hipStreamSynchronize(s));
+    const SearchHeader h1 = *w->hdr_host;
+    if (h1.err) return TDS_E_INVALID;
+    const uint32_t n_items = h1.n_items;
+    uint32_t grid_waves = P.grid_waves ? P.grid_waves : 256u * 16u;
+    grid_waves = std::max(1u, std::min(grid_waves, n_items));
+    TDS_TRY(grow(&w->item_count, &w->item_cap, std::max<size_t>(n_items, 1)));
+
+    tds_stats st{};
+    st.query_segments = Q->n;
+    st.active_segments = h1.active;
+    st.work_items = n_items;
+    float ms = 0.f;
+    uint64_t total = 0;
+    // pass 1: everything, result window [0, dev_cap)
+    TDS_TRY(enqueue_distance(idx, w, prec, nb, 1, res, 0, 0, n_items, w->item_count, grid_waves, s,
+                             w->ev0, w->ev1));
+    ReqCounter rc{};
+    TDS_HIP(hipMemcpyAsync(&rc, w->req_ctr, sizeof(ReqCounter), hipMemcpyDeviceToHost, s));
+    TDS_HIP(hipMemcpyAsync(w->hdr_host, w->hdr, sizeof(SearchHeader), hipMemcpyDeviceToHost, s));
+    TDS_HIP(hipStreamSynchronize(s));
+    TDS_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+    st.kernel_ms += ms;
+    st.passes = 1;
+    total = rc.count;
+    st.candidate_tests = w->hdr_host->tests;
+    st.fp64_evals = w->hdr_host->evals;
+    int status = TDS_OK;
+    if (dev_out) {
+        status = (total > capacity) ? TDS_E_OVERFLOW : TDS_OK;
+    } else if (total <= dev_cap) {
+        const uint64_t k = std::min(total, capacity);
+        if (k) TDS_HIP(hipMemcpyAsync(out, res, k * sizeof(tds_result), hipMemcpyDeviceToHost, s));
+        TDS_HIP(hipStreamSynchronize(s));
+        status = (total > capacity) ? TDS_E_OVERFLOW : TDS_OK;
+    } else if (total > capacity) {
+        const uint64_t k = std::min(dev_cap, capacity);
+        if (k) TDS_HIP(hipMemcpyAsync(out, res, k * sizeof(tds_result), hipMemcpyDeviceToHost, s));
+        TDS_HIP(hipStreamSynchronize(s));
+        status = TDS_E_OVERFLOW;
+    } else {
+        // incremental processing: re-run consecutive work items whose results
+        // fit the device buffer; an item larger than the buffer is re-run
+        // alone with a sliding window (one wave processes an item, in a fixed
+        // order, so its result order is the same on every run)
+        std::vector<uint32_t> cnt(n_items);
+        TDS_HIP(hipMemcpyAsync(cnt.data(), w->item_count, n_items * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s));
+        TDS_HIP(hipStreamSynchronize(s));
+        uint64_t written = 0;
+        uint32_t i0 = 0;
+        while (i0 < n_items) {
+            uint32_t i1 = i0;
+            uint64_t sum = 0;
+            while (i1 < n_items && sum + cnt[i1] <= dev_cap) sum += cnt[i1++];
+            std::vector<std::pair<uint64_t, uint64_t>> windows;  // (win_lo, expected)
+            if (i1 == i0) {
+                // single oversized item
+                i1 = i0 + 1;
+                for (uint64_t wl = 0; wl < cnt[i0]; wl += dev_cap)
+                    windows.push_back({wl, std::min<uint64_t>(dev_cap, cnt[i0] - wl)});
+            } else {
+                windows.push_back({0, sum});
+            }
+            for (auto& win : windows) {
+                if (win.second == 0) continue;
+                TDS_TRY(enqueue_distance(idx, w, prec, nb, 1, res, win.first, i0, i1, nullptr,
+                                         std::min(grid_waves, i1 - i0), s, w->ev0, w->ev1));
+                TDS_HIP(hipMemcpyAsync(out + written, res, win.second * sizeof(tds_result),
+                                       hipMemcpyDeviceToHost, s));
+                TDS_HIP(hipStreamSynchronize(s));
+                TDS_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+                st.kernel_ms += ms;
+                st.passes += 1;
+                written += win.second;
+            }
+            i0 = i1;
+        }
+        if (written != total) return TDS_E_DEVICE;
+    }
+    *n_out = total;
+    st.results = total;
+    st.total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
+    if (stats) *stats = st;
+    {
+        std::lock_guard<std::mutex> g(idx->mu);
+        idx->last = st;
+    }
+    return status;
+}
+
+}  // namespace tds

@@ -1,0 +1,232 @@
+// Internal types of libtds: device record layouts, the index object, the
+// per-search workspace and the launch helpers shared by the HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "tds.h"
+
+namespace tds {
+
+// ---------------------------------------------------------------- constants
+
+constexpr int kWave = 64;               // CDNA wavefront width
+constexpr int kBlock = 256;             // threads per block of the search kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr uint32_t kMaxBins = 65535;
+constexpr uint32_t kMaxBuckets = 65536; // query buckets of one search
+constexpr uint32_t kSpanClasses = 4;    // bin-span classes per first bin
+constexpr uint64_t kDefaultDevCap = 1ull << 24;
+
+// ---------------------------------------------------------------- records
+
+// Canonical FP64 entry record, one per indexed segment in t_start order.
+// 64 bytes so that one wave-uniform scalar load brings a whole record.
+struct alignas(64) EntryF64 {
+    double x, y, z;     // start point
+    double vx, vy, vz;  // velocity (P_end - P_start) / (t_end - t_start)
+    double ts, te;
+};
+static_assert(sizeof(EntryF64) == 64, "EntryF64 layout");
+
+// FP32 filter record: bounding sphere of the segment (centre rounded to
+// nearest, radius inflated and rounded up) and the time extent rounded
+// outwards.  32 bytes: one scalar load.
+struct alignas(32) EntryF32 {
+    float cx, cy, cz, r;
+    float ts, te;       // ts rounded down, te rounded up
+    float pad0, pad1;
+};
+static_assert(sizeof(EntryF32) == 32, "EntryF32 layout");
+
+// Prepared query segment (one per query segment of a search).
+struct alignas(16) QPrep {
+    // canonical FP64 data
+    double x, y, z, vx, vy, vz;
+    double ts;          // original t_start (positions are relative to it)
+    double aq, bq;      // segment clipped to the window: max(ts, t_start), min(te, t_end)
+    double d;
+    // FP32 filter data
+    float cx, cy, cz, R; // sphere of the clipped segment; R >= r + d + margins
+    float a32, b32;      // aq rounded down, bq rounded up
+    uint32_t lo, hi;     // candidate range [lo, hi) in sorted entry positions
+    uint32_t qid;        // query segment id reported in records (request-local)
+    uint32_t traj;
+    uint32_t req;        // request of the segment
+    uint32_t pad;
+};
+static_assert(sizeof(QPrep) % 16 == 0, "QPrep layout");
+
+// One request of a batch: a contiguous slice of the batch's query segments
+// with its own distance and window, and its own slice of the result buffer.
+struct Request {
+    uint64_t q_begin, q_count;
+    double d, t_start, t_end;
+    uint64_t out_offset, out_capacity;  // slice of the result buffer
+    uint64_t pad;
+};
+
+// Device-side header of one search; zeroed before every search.
+struct alignas(64) SearchHeader {
+    uint32_t work_ctr;      // persistent-kernel work counter
+    uint32_t n_items;       // total work items
+    uint32_t err;           // input validation failure flag
+    uint32_t active;        // active query segments
+    uint64_t tests;         // candidate tests executed
+    uint64_t evals;         // canonical FP64 evaluations
+    uint64_t results;       // total results (all requests)
+    uint32_t n_buckets;     // buckets in use
+    uint32_t pad;
+};
+
+// Per-request device counters.
+struct alignas(16) ReqCounter {
+    unsigned long long count;  // results of the request (keeps counting past capacity)
+    unsigned long long pad;
+};
+
+// ---------------------------------------------------------------- host objects
+
+struct Workspace {
+    int device = 0;
+    // query-side buffers, sized for `q_cap` query segments and `r_cap` requests
+    size_t q_cap = 0, r_cap = 0, item_cap = 0, res_cap = 0;
+    QPrep* qp = nullptr;
+    uint32_t* qkey = nullptr;
+    uint32_t* qslot = nullptr;
+    uint32_t* qsorted = nullptr;
+    double* qstage = nullptr;       // staging of host query arrays (8 * stage_cap doubles)
+    uint32_t* qtraj_stage = nullptr;
+    size_t stage_cap = 0, traj_cap = 0;
+    Request* req = nullptr;
+    ReqCounter* req_ctr = nullptr;
+    // bucket tables (kMaxBuckets each)
+    uint32_t* b_count = nullptr;
+    uint32_t* b_lo = nullptr;
+    uint32_t* b_hi = nullptr;
+    uint32_t* b_start = nullptr;
+    uint32_t* b_item = nullptr;     // kMaxBuckets + 1: first item of each bucket
+    uint32_t* b_nch = nullptr;
+    uint32_t* b_clen = nullptr;
+    uint32_t* item_count = nullptr; // results per work item (incremental mode)
+    tds_result* res = nullptr;      // device result buffer (host-output mode)
+    SearchHeader* hdr = nullptr;
+    SearchHeader* hdr_host = nullptr;  // pinned mirror
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    ~Workspace();
+};
+
+}  // namespace tds
+
+struct tds_index {
+    int device = 0;
+    uint64_t n = 0;
+    uint32_t m = 0;
+    double t_min = 0, t_max = 0, bw = 0;
+    tds::EntryF64* e64 = nullptr;
+    tds::EntryF32* e32 = nullptr;
+    uint32_t* seg_id = nullptr;    // sorted position -> input position
+    uint32_t* traj = nullptr;      // sorted position -> trajectory id
+    uint32_t* bin_first = nullptr; // m + 1
+    double* min_ts = nullptr;      // m
+    double* max_te = nullptr;      // m
+    double* cmax_te = nullptr;     // m
+    double* lo_ts = nullptr;       // m: t_start of the first entry of bins >= j
+    uint64_t device_bytes = 0;
+    std::mutex mu;
+    std::vector<tds::Workspace*> pool;
+    tds_stats last{};
+};
+
+namespace tds {
+
+// Error propagation for HIP calls inside functions returning a TDS status.
+#define TDS_HIP(call)                                        \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) {                              \
+            (void)hipGetLastError();                         \
+            return (e_ == hipErrorOutOfMemory) ? TDS_E_NOMEM \
+                                               : TDS_E_DEVICE; \
+        }                                                    \
+    } while (0)
+
+#define TDS_TRY(call)              \
+    do {                           \
+        int s_ = (call);           \
+        if (s_ != TDS_OK) return s_; \
+    } while (0)
+
+template <typename T>
+int dmalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return e == hipErrorOutOfMemory ? TDS_E_NOMEM : TDS_E_DEVICE;
+    }
+    return TDS_OK;
+}
+
+inline void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// FP32 bounding sphere of the segment from a to b (FP64 end points), used by
+// the FP32 candidate filter: centre rounded to nearest; radius
+// (r + extra)(1 + 8u) + 2u|c| + 1e-18 rounded up, u = 2^-24.  The margin
+// covers the rounding of both spheres' centres to FP32, the FP32 evaluation
+// of the squared centre distance and of (R_q + r_l)^2, and the FP64 rounding
+// of the canonical arithmetic, so a pair whose canonical evaluation is a
+// result always passes the filter.  Beyond 1e18 the radius is +inf (the pair
+// always passes).
+__device__ inline void sphere32(double ax, double ay, double az, double bx, double by, double bz,
+                                double extra, float& cx32, float& cy32, float& cz32, float& r32) {
+    const double u = 5.9604644775390625e-08;
+    const double cx = 0.5 * (ax + bx), cy = 0.5 * (ay + by), cz = 0.5 * (az + bz);
+    const double hx = 0.5 * (bx - ax), hy = 0.5 * (by - ay), hz = 0.5 * (bz - az);
+    const double rr = sqrt(hx * hx + hy * hy + hz * hz);
+    const double cn = sqrt(cx * cx + cy * cy + cz * cz);
+    const double R = (rr + extra) * (1.0 + 8.0 * u) + 2.0 * u * cn + 1e-18;
+    cx32 = __double2float_rn(cx);
+    cy32 = __double2float_rn(cy);
+    cz32 = __double2float_rn(cz);
+    r32 = (R < 1e18 && cn < 1e18) ? __double2float_ru(R) : __int_as_float(0x7f800000);
+}
+
+// Stable LSD radix sort of (key, value) pairs on `stream`; keys_bits is the
+// number of low key bits that may differ (passes of 8 bits).  Buffers *_alt
+// are scratch of the same size; the sorted data ends up in keys/vals.
+int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                   uint32_t n, int key_bits, hipStream_t stream);
+
+// Device segment staging: copies host arrays to the device when needed.
+struct SegView {
+    const double* a[8];     // xs, ys, zs, ts, xe, ye, ze, te (device)
+    const uint32_t* traj;   // device or nullptr
+    uint64_t n;
+};
+
+int validate_segments_args(const tds_segments* S);
+
+// Search implementation (search.hip).
+int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
+                double t_end, tds_result* out, uint64_t capacity, uint64_t* n_out,
+                const tds_search_params* params, hipStream_t stream, tds_stats* stats);
+int schedule_impl(tds_index* idx, const tds_segments* Q, double t_start, double t_end,
+                  uint32_t* lo, uint32_t* hi, hipStream_t stream);
+// Index build implementation (index_build.hip).
+int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t stream,
+               tds_index** out);
+void destroy_index(tds_index* idx);
+
+}  // namespace tds
