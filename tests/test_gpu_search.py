@@ -214,15 +214,15 @@ def test_swap_symmetry_on_gpu():
 def test_overflow_reports_total_and_incremental_passes_match():
     w = trajgen.dense(0.02, n_pts=31)
     idx = build(w.D)
-    want = oracle.search(w.Q, w.D, 3.0, *w.window)
+    want = oracle.search(w.Q, w.D, 6.0, *w.window)
     n = len(want)
     assert n > 500
     buf = np.empty(10, tds.RESULT_DTYPE)
-    st, total, _ = idx.search_raw(w.Q, 3.0, *w.window, out_ptr=buf.ctypes.data, capacity=10,
+    st, total, _ = idx.search_raw(w.Q, 6.0, *w.window, out_ptr=buf.ctypes.data, capacity=10,
                                   out_on_device=False)
     assert st == tds.TDS_E_OVERFLOW and total == n
     for dev_cap in (1, 7, 1000, n - 1, n):
-        got = idx.search(w.Q, 3.0, *w.window, capacity=n, device_capacity=dev_cap)
+        got = idx.search(w.Q, 6.0, *w.window, capacity=n, device_capacity=dev_cap)
         compare(got, want, f"device_capacity={dev_cap}")
         if dev_cap < n:
             assert idx.last_stats["passes"] > 1
@@ -232,17 +232,17 @@ def test_overflow_reports_total_and_incremental_passes_match():
 def test_device_output_buffer():
     w = trajgen.dense(0.02, n_pts=31)
     idx = build(w.D)
-    want = oracle.search(w.Q, w.D, 3.0, *w.window)
+    want = oracle.search(w.Q, w.D, 6.0, *w.window)
     cap = len(want) + 100
     out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
-    st, total, _ = idx.search_raw(w.Q, 3.0, *w.window, out_ptr=out.data_ptr(), capacity=cap,
+    st, total, _ = idx.search_raw(w.Q, 6.0, *w.window, out_ptr=out.data_ptr(), capacity=cap,
                                   out_on_device=True)
     assert st == tds.TDS_OK and total == len(want)
     torch.cuda.synchronize()
     got = np.frombuffer(out[: total * 32].cpu().numpy().tobytes(), dtype=tds.RESULT_DTYPE)
     compare(got, want, "device out")
     small = torch.empty(5 * 32, dtype=torch.uint8, device="cuda")
-    st, total2, _ = idx.search_raw(w.Q, 3.0, *w.window, out_ptr=small.data_ptr(), capacity=5,
+    st, total2, _ = idx.search_raw(w.Q, 6.0, *w.window, out_ptr=small.data_ptr(), capacity=5,
                                    out_on_device=True)
     assert st == tds.TDS_E_OVERFLOW and total2 == len(want)
     idx.close()
