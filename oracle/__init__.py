@@ -54,7 +54,7 @@ def _load():
         lib.orc_velocity.argtypes = [i64] + [P] * 11
         lib.orc_bins.argtypes = [i64, P, P, i64] + [P] * 10
         lib.orc_bins.restype = ctypes.c_int
-        lib.orc_schedule.argtypes = [i64, P, i64, P, P, i64, P, P, dbl, dbl, P, P]
+        lib.orc_schedule.argtypes = [i64, P, P, P, P, i64, P, P, dbl, dbl, P, P]
         _lib = lib
     return _lib
 
@@ -152,10 +152,9 @@ def schedule(ts, te, m: int, qts, qte, t_start=-np.inf, t_end=np.inf, tables: Op
     lib = _load()
     ts, te = _f64(ts), _f64(te)
     tb = tables if tables is not None else bins(ts, te, m)
-    sorted_ts = np.ascontiguousarray(ts[tb["order"]])
     qts, qte = _f64(qts), _f64(qte)
     nq = qts.shape[0]
     lo, hi = np.empty(nq, np.int64), np.empty(nq, np.int64)
-    lib.orc_schedule(ts.shape[0], _ptr(sorted_ts), m, _ptr(tb["first"]), _ptr(tb["cmax_te"]),
+    lib.orc_schedule(m, _ptr(tb["first"]), _ptr(tb["last"]), _ptr(tb["min_ts"]), _ptr(tb["cmax_te"]),
                      nq, _ptr(qts), _ptr(qte), float(t_start), float(t_end), _ptr(lo), _ptr(hi))
     return lo, hi

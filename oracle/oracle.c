@@ -48,9 +48,10 @@
  * positions of its first and last entry.
  *
  * Schedule (Sec. 4.2.2): for a query segment clipped to the window,
- * [a_q, b_q], the candidate range is the contiguous span of sorted entries
- * from the first entry of the first bin whose entries reach past a_q (running
- * maximum of te over bins > a_q) up to the last entry with ts < b_q.
+ * [a_q, b_q], the candidate range E_k = [B^first, B^last] spans the bins from
+ * the first bin whose entries reach past a_q (running maximum of te over
+ * bins > a_q) to the last non-empty bin whose first entry starts before b_q,
+ * taken as one contiguous span of sorted entries.
  */
 #include <math.h>
 #include <stdint.h>
@@ -293,27 +294,28 @@ int orc_bins(int64_t n, const double* ts, const double* te, int64_t m,
 }
 
 /*
- * Schedule of Sec. 4.2.2 for nq query segments: lo[k] = first sorted position
- * of the first bin whose running max te exceeds a_q; hi[k] = number of sorted
- * entries with ts < b_q (exclusive end).  a_q = max(qts, t_start),
- * b_q = min(qte, t_end).  An empty window or range gives lo = hi = 0.
- * sorted_ts holds the entries' t_start in sorted order.
+ * Schedule of Sec. 4.2.2 for nq query segments: lo[k] = B^first of the first
+ * bin whose running max te exceeds a_q; hi[k] = B^last + 1 of the last
+ * non-empty bin whose minimum ts is below b_q (exclusive end).
+ * a_q = max(qts, t_start), b_q = min(qte, t_end).  An empty window or range
+ * gives lo = hi = 0.
  */
-void orc_schedule(int64_t n, const double* sorted_ts, int64_t m, const int64_t* first,
-                  const double* cmax_te, int64_t nq, const double* qts,
-                  const double* qte, double t_start, double t_end,
-                  int64_t* lo, int64_t* hi) {
+void orc_schedule(int64_t m, const int64_t* first, const int64_t* last,
+                  const double* min_ts, const double* cmax_te, int64_t nq,
+                  const double* qts, const double* qte, double t_start,
+                  double t_end, int64_t* lo, int64_t* hi) {
     for (int64_t k = 0; k < nq; ++k) {
         double aq = dmax(qts[k], t_start), bq = dmin(qte[k], t_end);
-        int64_t l = n, h = 0;
+        int64_t l = 0, h = 0;
+        int found = 0;
         if (aq < bq) {
             for (int64_t j = 0; j < m; ++j) {
-                if (cmax_te[j] > aq) { l = first[j]; break; }
+                if (cmax_te[j] > aq) { l = first[j]; found = 1; break; }
             }
-            for (int64_t i = 0; i < n; ++i)
-                if (sorted_ts[i] < bq) h = i + 1;
+            for (int64_t j = 0; j < m; ++j)
+                if (last[j] >= first[j] && min_ts[j] < bq) h = last[j] + 1;
         }
-        if (l >= h) { l = 0; h = 0; }
+        if (!found || l >= h) { l = 0; h = 0; }
         lo[k] = l;
         hi[k] = h;
     }

@@ -319,12 +319,19 @@ def test_temporal_bins_reproduce_paper_example():
 
 def test_schedule_paper_example_noncontiguous_overlap():
     """A query on [7, 7.2] overlaps bins B0 (end 7.5) and B2 but not B1 (end
-    6.2); the candidate span still covers every overlapping entry."""
+    6.2); the candidate span E_k runs from B0^first = 0 to B2^last = 11 and
+    covers every overlapping entry."""
     segs, _ = _load_example()
     ts = np.array([s[1] for s in segs])
     te = np.array([s[2] for s in segs])
     lo, hi = oracle.schedule(ts, te, 4, np.array([7.0]), np.array([7.2]))
-    assert (lo[0], hi[0]) == (0, 11)
+    assert (lo[0], hi[0]) == (0, 12)
+    # a query inside B1's extent only: [B0^first, B1^last] (B0 reaches 7.5)
+    lo, hi = oracle.schedule(ts, te, 4, np.array([4.0]), np.array([4.5]))
+    assert (lo[0], hi[0]) == (0, 9)
+    # before every entry's end: nothing; after the last start: only B3
+    lo, hi = oracle.schedule(ts, te, 4, np.array([11.95]), np.array([12.5]))
+    assert (lo[0], hi[0]) == (12, 15)
     overl = [i for i in range(15) if max(ts[i], 7.0) < min(te[i], 7.2)]
     assert overl == [4, 9, 10]
 
@@ -377,3 +384,7 @@ def test_schedule_is_exact_on_aligned_unit_steps():
     for k in range(49):
         run = np.flatnonzero(sorted_ts == k)
         assert (lo[k], hi[k]) == (run[0], run[-1] + 1)
+    # a window ending inside a bin keeps that whole bin (bin granularity)
+    lo, hi = oracle.schedule(D.ts, D.te, m, np.array([3.0]), np.array([4.0]), 0.0, 3.5, tables=tb)
+    run = np.flatnonzero(sorted_ts == 3)
+    assert (lo[0], hi[0]) == (run[0], run[-1] + 1)
