@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--cpu-traj", type=int, default=8, help="query trajectories in the oracle sample")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--grid-waves", type=int, default=0)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -77,6 +79,13 @@ def main():
     import trajgen
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = trajgen.uniform1m()
     ds = w.ds
     t0, t1 = w.window

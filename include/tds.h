@@ -190,10 +190,10 @@ int tds_index_export(const tds_index* index, uint32_t* order, uint32_t* bin_firs
 
 /*
  * Candidate range (the schedule S of Sec. 4.2.2) of each query segment: the
- * contiguous span [lo[k], hi[k]) of sorted entry positions from the first
- * entry of the first bin whose running max t_end exceeds a_q to the last
- * entry with t_start < b_q, where [a_q, b_q] is the query segment clipped to
- * [t_start, t_end].  Every entry that strictly overlaps the clipped query in
+ * contiguous span E_k = [lo[k], hi[k]) of sorted entry positions from the
+ * first entry of the first bin whose running max t_end exceeds a_q to the last
+ * entry of the last non-empty bin whose first entry has t_start < b_q, where
+ * [a_q, b_q] is the query segment clipped to [t_start, t_end].  Every entry that strictly overlaps the clipped query in
  * time lies in the span.  Empty windows or spans give lo = hi = 0.  lo and hi
  * are host arrays of Q->n elements.  Waits for `stream`.
  * Errors: TDS_E_INVALID (bad pointers or Q values, t_start >= t_end or NaN),

@@ -132,21 +132,30 @@ __global__ __launch_bounds__(kBT) void k_bin_stats(uint64_t n, const EntryF64* _
                                                    const uint32_t* __restrict__ bin_first,
                                                    double* __restrict__ min_ts,
                                                    double* __restrict__ max_te,
+                                                   double* __restrict__ min_te,
                                                    double* __restrict__ lo_ts) {
-    __shared__ double smax[kBT];
+    __shared__ double smax[kBT], smin[kBT];
     const uint32_t j = blockIdx.x;
     const uint32_t f = bin_first[j], e = bin_first[j + 1];
-    double mx = -INFINITY;
-    for (uint32_t i = f + threadIdx.x; i < e; i += kBT) mx = fmax(mx, e64[i].te);
+    double mx = -INFINITY, mn = INFINITY;
+    for (uint32_t i = f + threadIdx.x; i < e; i += kBT) {
+        mx = fmax(mx, e64[i].te);
+        mn = fmin(mn, e64[i].te);
+    }
     smax[threadIdx.x] = mx;
+    smin[threadIdx.x] = mn;
     __syncthreads();
     for (uint32_t off = kBT / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+        if (threadIdx.x < off) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + off]);
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         min_ts[j] = (f < e) ? e64[f].ts : INFINITY;
         max_te[j] = smax[0];
+        min_te[j] = smin[0];
         lo_ts[j] = (f < n) ? e64[f].ts : INFINITY;
     }
 }
@@ -206,6 +215,7 @@ void destroy_index(tds_index* idx) {
     dfree(idx->bin_first);
     dfree(idx->min_ts);
     dfree(idx->max_te);
+    dfree(idx->min_te);
     dfree(idx->cmax_te);
     dfree(idx->lo_ts);
     (void)hipSetDevice(cur);
@@ -321,6 +331,7 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
         if ((st = dmalloc(&idx->bin_first, (size_t)m + 1))) break;
         if ((st = dmalloc(&idx->min_ts, m))) break;
         if ((st = dmalloc(&idx->max_te, m))) break;
+        if ((st = dmalloc(&idx->min_te, m))) break;
         if ((st = dmalloc(&idx->cmax_te, m))) break;
         if ((st = dmalloc(&idx->lo_ts, m))) break;
     } while (0);
@@ -328,13 +339,13 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
         destroy_index(idx);
         return st;
     }
-    idx->device_bytes = n * (sizeof(EntryF64) + sizeof(EntryF32) + 8) + (size_t)m * 36 + 4;
+    idx->device_bytes = n * (sizeof(EntryF64) + sizeof(EntryF32) + 8) + (size_t)m * 44 + 4;
     hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kBT), 0, stream, n, vals, tmp64, tmp32, S.traj,
                        idx->e64, idx->e32, idx->seg_id, idx->traj);
     hipLaunchKernelGGL(k_bin_first, dim3(nb), dim3(kBT), 0, stream, n, idx->e64, tmin, bw, m,
                        idx->bin_first);
     hipLaunchKernelGGL(k_bin_stats, dim3(m), dim3(kBT), 0, stream, n, idx->e64, idx->bin_first,
-                       idx->min_ts, idx->max_te, idx->lo_ts);
+                       idx->min_ts, idx->max_te, idx->min_te, idx->lo_ts);
     hipLaunchKernelGGL(k_bin_cummax, dim3(1), dim3(1024), 0, stream, idx->max_te, idx->cmax_te, m);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
         destroy_index(idx);

@@ -29,6 +29,12 @@ namespace {
 
 constexpr uint32_t kInactive = 0xFFFFFFFFu;
 
+// Candidates held per lane by the FP32 form: a wave works on tiles of
+// kCpl * 64 candidates, so each query record fetched by a scalar load feeds
+// kCpl * 64 pair tests.
+constexpr int kCpl = 4;
+constexpr uint32_t kTile = kCpl * kWave;
+
 // Entry records are read through the constant address space with a
 // wave-uniform index, so the compiler fetches them with scalar loads into
 // SGPRs: one load serves the 64 lanes (query segments) of the wave.
@@ -151,43 +157,34 @@ __device__ __forceinline__ bool canon_eval(const QCanon& q, double lx, double ly
 
 // ------------------------------------------------------------ schedule
 
-// Candidate range of a clipped query [aq, bq): lo = first position of the
-// first bin whose running max t_end exceeds aq; hi = number of entries with
-// t_start < bq.  Also returns the first and last bins of the span.
+// Candidate range E_k of a clipped query [aq, bq] (Sec. 4.2.2): from the
+// first entry of the first bin whose running max t_end exceeds aq (bin j0)
+// to the last entry of the last non-empty bin whose first t_start is below
+// bq (bin j1), as one contiguous span [lo, hi) of sorted positions.
 __device__ inline void cand_range(const IndexView& I, double aq, double bq, uint32_t* lo,
                                   uint32_t* hi, uint32_t* j0o, uint32_t* j1o) {
     // j0 = first j with cmax_te[j] > aq (m if none)
     uint32_t l = 0, h = I.m;
     while (l < h) {
-        uint32_t mid = (l + h) >> 1;
+        const uint32_t mid = (l + h) >> 1;
         if (I.cmax_te[mid] > aq) h = mid;
         else l = mid + 1;
     }
     const uint32_t j0 = l;
-    // number of bins whose first t_start is < bq
+    // L = number of bins j whose first entry at or after the bin start has
+    // t_start < bq (lo_ts is non-decreasing); entries before bin_first[L]
+    // are exactly those of bins < L
     l = 0;
     h = I.m;
     while (l < h) {
-        uint32_t mid = (l + h) >> 1;
+        const uint32_t mid = (l + h) >> 1;
         if (I.lo_ts[mid] < bq) l = mid + 1;
         else h = mid;
     }
-    uint32_t hiv = 0, j1 = 0;
-    if (l > 0) {
-        j1 = l - 1;
-        uint32_t a = I.bin_first[j1], b = I.bin_first[j1 + 1];
-        while (a < b) {  // first position in bin j1 with ts >= bq
-            uint32_t mid = (a + b) >> 1;
-            if (I.e64[mid].ts < bq) a = mid + 1;
-            else b = mid;
-        }
-        hiv = a;
-    }
-    const uint32_t lov = (j0 < I.m) ? I.bin_first[j0] : I.n;
-    *lo = lov;
-    *hi = hiv;
+    *lo = (j0 < I.m) ? I.bin_first[j0] : I.n;
+    *hi = I.bin_first[l];
     *j0o = j0;
-    *j1o = j1;
+    *j1o = (l > 0) ? l - 1 : 0;
 }
 
 __device__ inline bool finite(double v) { return isfinite(v); }
@@ -229,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const Request* __
                                                   QPrep* __restrict__ qp,
                                                   uint32_t* __restrict__ qkey,
                                                   uint32_t* __restrict__ qslot, uint32_t* b_count,
-                                                  uint32_t* b_lo, uint32_t* b_hi, uint32_t shift,
+                                                  uint32_t* b_hi, uint32_t shift,
                                                   SearchHeader* hdr) {
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     bool active = false;
@@ -277,8 +274,9 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const Request* __
                     const uint32_t key = (j0 * kSpanClasses + span) >> shift;
                     qkey[k] = key;
                     qslot[k] = atomicAdd(&b_count[key], 1u);
-                    atomicMin(&b_lo[key], lo);
-                    atomicMax(&b_hi[key], hi);
+                    // the bucket's range follows from its key unless it merges
+                    // several first bins or spans an open number of bins
+                    if (shift || span == kSpanClasses - 1) atomicMax(&b_hi[key], hi);
                     qp[k] = p;
                     active = true;
                 }
@@ -317,13 +315,18 @@ __global__ __launch_bounds__(kBlock) void k_schedule(QueryView Q, double t_start
 
 // Bucket offsets, groups and the work-item table, one block.
 __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict__ b_count,
-                                                      const uint32_t* __restrict__ b_lo,
-                                                      const uint32_t* __restrict__ b_hi,
+                                                      uint32_t* __restrict__ b_lo,
+                                                      uint32_t* __restrict__ b_hi,
+                                                      const uint32_t* __restrict__ bin_first,
+                                                      const double* __restrict__ min_te,
+                                                      const EntryF64* __restrict__ e64,
+                                                      uint32_t m, uint32_t shift,
                                                       uint32_t nb, uint32_t chunk,
                                                       uint32_t* __restrict__ b_start,
                                                       uint32_t* __restrict__ b_item,
                                                       uint32_t* __restrict__ b_nch,
                                                       uint32_t* __restrict__ b_clen,
+                                                      BucketInfo* __restrict__ binfo,
                                                       SearchHeader* hdr) {
     __shared__ uint32_t pc[1024], pi[1024];
     const uint32_t tid = threadIdx.x;
@@ -334,10 +337,22 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
         const uint32_t cnt = b_count[b];
         uint32_t nch = 0, clen = 0;
         if (cnt) {
-            // balanced chunks of at most `chunk` candidates, none empty
-            const uint32_t len = b_hi[b] - b_lo[b];
+            // range of the bucket: first entry of its smallest first bin to
+            // the end of its last bin (from the key, or the members' maximum)
+            const uint32_t code = b << shift;  // smallest (j0 * classes + span) of the bucket
+            const uint32_t j0 = code / kSpanClasses, span = code % kSpanClasses;
+            const uint32_t lo = bin_first[j0];
+            uint32_t hi = b_hi[b];
+            if (shift == 0 && span < kSpanClasses - 1) hi = bin_first[min(j0 + span + 1, m)];
+            b_lo[b] = lo;
+            b_hi[b] = hi;
+            // balanced chunks of at most `chunk` candidates, whole 64-candidate
+            // tiles where possible, none empty
+            const uint32_t len = hi - lo;
             const uint32_t n0 = (len + chunk - 1) / chunk;
             clen = (len + n0 - 1) / n0;
+            clen = (clen + kWave - 1) / kWave * kWave;
+            if (clen > 2 * kTile) clen = (clen + kTile - 1) / kTile * kTile;
             nch = (len + clen - 1) / clen;
         }
         b_nch[b] = nch;
@@ -361,6 +376,25 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
         const uint32_t cnt = b_count[b];
         b_start[b] = rc;
         b_item[b] = ri;
+        BucketInfo bi;
+        bi.tmin_te = -INFINITY;  // unknown: the kernel keeps the per-pair time test
+        bi.tmax_ts = INFINITY;
+        if (cnt && shift == 0 && (b % kSpanClasses) < kSpanClasses - 1) {
+            const uint32_t j0 = b / kSpanClasses, j1 = min(j0 + b % kSpanClasses, m - 1);
+            double mn = INFINITY;
+            for (uint32_t j = j0; j <= j1; ++j) mn = fmin(mn, min_te[j]);
+            bi.tmin_te = mn;
+            bi.tmax_ts = e64[b_hi[b] - 1].ts;  // entries are sorted by t_start
+        }
+        bi.lo = b_lo[b];
+        bi.hi = b_hi[b];
+        bi.nch = b_nch[b];
+        bi.clen = b_clen[b];
+        bi.count = cnt;
+        bi.start = rc;
+        bi.item0 = ri;
+        bi.pad = 0;
+        binfo[b] = bi;
         rc += cnt;
         ri += ((cnt + kWave - 1) / kWave) * b_nch[b];
     }
@@ -374,11 +408,35 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
 __global__ __launch_bounds__(kBlock) void k_scatter(uint64_t nq, const uint32_t* __restrict__ qkey,
                                                     const uint32_t* __restrict__ qslot,
                                                     const uint32_t* __restrict__ b_start,
-                                                    uint32_t* __restrict__ qsorted) {
+                                                    const QPrep* __restrict__ qp,
+                                                    uint32_t* __restrict__ qsorted,
+                                                    QF32* __restrict__ qf) {
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= nq) return;
     const uint32_t s = qslot[k];
-    if (s != kInactive) qsorted[b_start[qkey[k]] + s] = (uint32_t)k;
+    if (s == kInactive) return;
+    const uint32_t pos = b_start[qkey[k]] + s;
+    qsorted[pos] = (uint32_t)k;
+    const QPrep& p = qp[k];
+    QF32 f;
+    f.cx = p.cx;
+    f.cy = p.cy;
+    f.cz = p.cz;
+    f.R = p.R;
+    f.a32 = p.a32;
+    f.b32 = p.b32;
+    f.lo = p.lo;
+    f.hi = p.hi;
+    qf[pos] = f;
+}
+
+// item_bucket[i] = bucket of work item i; one block per bucket.
+__global__ __launch_bounds__(kBlock) void k_item_fill(const BucketInfo* __restrict__ binfo,
+                                                      uint32_t* __restrict__ item_bucket) {
+    const uint32_t b = blockIdx.x;
+    const BucketInfo bi = binfo[b];
+    const uint32_t n = ((bi.count + kWave - 1) / kWave) * bi.nch;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) item_bucket[bi.item0 + i] = b;
 }
 
 // Resets the per-pass counters of the distance kernel.
@@ -391,37 +449,29 @@ __global__ void k_reset_pass(SearchHeader* hdr, ReqCounter* rc, uint32_t nreq) {
 struct DistArgs {
     IndexView I;
     const QPrep* qp;
+    const QF32* qf;
     const uint32_t* qsorted;
-    const uint32_t* b_start;
-    const uint32_t* b_count;
-    const uint32_t* b_lo;
-    const uint32_t* b_hi;
-    const uint32_t* b_nch;
-    const uint32_t* b_clen;
-    const uint32_t* b_item;
-    uint32_t nb;
+    const BucketInfo* binfo;
+    const uint32_t* item_bucket;
     SearchHeader* hdr;
     const Request* req;
     ReqCounter* rc;
     tds_result* out;
     uint64_t win_lo;        // first request-local result position kept
     uint32_t item_begin;    // work items [item_begin, item_end)
-    uint32_t item_end;      // 0xFFFFFFFF: up to the header's item count
+    uint32_t item_end;
     uint32_t* item_count;   // results per work item, or nullptr
 };
 
 struct WaveLDS {
-    uint32_t queue[5 * kWave];  // < 64 left over + 4 candidates x 64 lanes
-    double qx[kWave], qy[kWave], qz[kWave], qvx[kWave], qvy[kWave], qvz[kWave];
-    double qts[kWave], qaq[kWave], qbq[kWave], qd[kWave];
-    uint32_t qid[kWave], qtraj[kWave], qreq[kWave];
+    uint32_t queue[2 * kWave];  // < 64 left over + one pair per lane
 };
 
 // Evaluates `cnt` <= 64 queued pairs from position `head` (one per lane) with
 // the canonical FP64 code and appends the results.  Returns the number of
 // results.
 __device__ __forceinline__ uint32_t drain(WaveLDS& L, uint32_t head, uint32_t cnt, uint32_t c0,
-                                          const DistArgs& A) {
+                                          uint32_t qbase, const DistArgs& A) {
     const uint32_t lane = __lane_id();
     const bool act = lane < cnt;
     const uint32_t pk = act ? L.queue[head + lane] : 0u;
@@ -429,22 +479,25 @@ __device__ __forceinline__ uint32_t drain(WaveLDS& L, uint32_t head, uint32_t cn
     const uint32_t i = c0 + (pk >> 6);
     double t_lo = 0.0, t_hi = 0.0;
     bool hit = false;
-    uint32_t myreq = 0;
+    uint32_t myreq = 0, qid = 0, qtraj = 0;
     if (act) {
+        const QPrep& p = A.qp[A.qsorted[qbase + ql]];
         QCanon q;
-        q.x = L.qx[ql];
-        q.y = L.qy[ql];
-        q.z = L.qz[ql];
-        q.vx = L.qvx[ql];
-        q.vy = L.qvy[ql];
-        q.vz = L.qvz[ql];
-        q.ts = L.qts[ql];
-        q.aq = L.qaq[ql];
-        q.bq = L.qbq[ql];
-        q.d = L.qd[ql];
+        q.x = p.x;
+        q.y = p.y;
+        q.z = p.z;
+        q.vx = p.vx;
+        q.vy = p.vy;
+        q.vz = p.vz;
+        q.ts = p.ts;
+        q.aq = p.aq;
+        q.bq = p.bq;
+        q.d = p.d;
+        myreq = p.req;
+        qid = p.qid;
+        qtraj = p.traj;
         const EntryF64 e = A.I.e64[i];
         hit = canon_eval<true>(q, e.x, e.y, e.z, e.vx, e.vy, e.vz, e.ts, e.te, &t_lo, &t_hi);
-        myreq = L.qreq[ql];
     }
     uint64_t hm = ballot(hit);
     const uint32_t nhit = (uint32_t)__popcll(hm);
@@ -460,9 +513,9 @@ __device__ __forceinline__ uint32_t drain(WaveLDS& L, uint32_t head, uint32_t cn
             const Request& R = A.req[r];
             if (pos >= A.win_lo && pos - A.win_lo < R.out_capacity) {
                 tds_result rec;
-                rec.q_seg = L.qid[ql];
+                rec.q_seg = qid;
                 rec.e_seg = A.I.seg_id[i];
-                rec.q_traj = L.qtraj[ql];
+                rec.q_traj = qtraj;
                 rec.e_traj = A.I.traj[i];
                 rec.t_lo = t_lo;
                 rec.t_hi = t_hi;
@@ -482,13 +535,13 @@ __device__ __forceinline__ void enqueue(WaveLDS& L, uint64_t m, bool pass, uint3
 }
 
 // Evaluates full batches of 64 queued pairs; keeps the remainder queued.
-__device__ __forceinline__ void drain_full(WaveLDS& L, uint32_t c0, uint32_t& qn, uint32_t& evals,
-                                           uint32_t& found, const DistArgs& A) {
+__device__ __forceinline__ void drain_full(WaveLDS& L, uint32_t c0, uint32_t qbase, uint32_t& qn,
+                                           uint32_t& evals, uint32_t& found, const DistArgs& A) {
     const uint32_t lane = __lane_id();
     uint32_t head = 0;
     wave_sync();
     while (qn - head >= kWave) {
-        found += drain(L, head, kWave, c0, A);
+        found += drain(L, head, kWave, c0, qbase, A);
         evals += kWave;
         head += kWave;
     }
@@ -504,80 +557,203 @@ __device__ __forceinline__ void drain_full(WaveLDS& L, uint32_t c0, uint32_t& qn
     wave_sync();
 }
 
-// FP32 filter of one candidate record (cx, cy, cz, r, ts, te): the pair can
-// only be a result if the two bounding spheres come within d (the margins
-// are folded into R and r) and the outward-rounded time extents overlap.
-__device__ __forceinline__ bool filter32(const f32x8& e, float qcx, float qcy, float qcz, float qR,
-                                         float qa, float qb) {
-    const float dx = e[0] - qcx, dy = e[1] - qcy, dz = e[2] - qcz;
+// FP32 filter of one query against the wave's 64 candidates, as a lane mask.
+// The query record q comes from a scalar load (cx, cy, cz, R, a32, b32, lo,
+// hi), the candidate fields from the lane's registers.  A pair can only be a
+// result if the two bounding spheres come within d (the error margins are
+// folded into R and r) and the outward-rounded time extents overlap
+// strictly.  Each comparison is balloted on its own so that the masks combine
+// in scalar registers.  With kTime false the caller has established that
+// every pair of the tile overlaps in time.
+template <bool kTime>
+__device__ __forceinline__ uint64_t filter32(const f32x8& q, float ecx, float ecy, float ecz,
+                                             float er, float ets, float ete) {
+    const float dx = ecx - q[0], dy = ecy - q[1], dz = ecz - q[2];
     const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const float R = qR + e[3];
-    return (s <= R * R) & (qa < e[5]) & (e[4] < qb);
+    const float R = q[3] + er;
+    const uint64_t m = ballot(s <= R * R);
+    return kTime ? (m & ballot(q[4] < ete) & ballot(ets < q[5])) : m;
 }
 
-template <int kPrec, bool kUniform>
-__device__ __forceinline__ void scan_chunk(WaveLDS& L, const DistArgs& A, uint32_t c0,
-                                           uint32_t c1, bool has, const QPrep& p,
-                                           uint32_t& qn, uint32_t& evals, uint32_t& found) {
-    const uint32_t qlo = p.lo, qhi = p.hi;
-    if (kPrec == TDS_PREC_FP32_RECHECK) {
-        ConstE32 ce = (ConstE32)(A.I.e32);
-        const float qcx = p.cx, qcy = p.cy, qcz = p.cz, qR = has ? p.R : -1.0f;
-        // lanes without a query get an empty time window
-        const float qa = has ? p.a32 : 1.0f, qb = has ? p.b32 : -1.0f;
-        uint32_t i = c0;
-        for (; i + 4 <= c1; i += 4) {
-            const f32x8 e0 = ce[i], e1 = ce[i + 1], e2 = ce[i + 2], e3 = ce[i + 3];
-            bool p0 = filter32(e0, qcx, qcy, qcz, qR, qa, qb);
-            bool p1 = filter32(e1, qcx, qcy, qcz, qR, qa, qb);
-            bool p2 = filter32(e2, qcx, qcy, qcz, qR, qa, qb);
-            bool p3 = filter32(e3, qcx, qcy, qcz, qR, qa, qb);
-            if (!kUniform) {
-                p0 = p0 & (i >= qlo) & (i < qhi);
-                p1 = p1 & (i + 1 >= qlo) & (i + 1 < qhi);
-                p2 = p2 & (i + 2 >= qlo) & (i + 2 < qhi);
-                p3 = p3 & (i + 3 >= qlo) & (i + 3 < qhi);
+__device__ __forceinline__ uint64_t in_range(const f32x8& q, uint32_t cand) {
+    return ballot(cand >= __float_as_uint(q[6])) & ballot(cand < __float_as_uint(q[7]));
+}
+
+__device__ __forceinline__ void push(WaveLDS& L, uint64_t m, uint32_t code, uint32_t& qn) {
+    const uint32_t lane = __lane_id();
+    if ((m >> lane) & 1ull) L.queue[qn + (uint32_t)__popcll(m & lanemask_lt())] = code;
+    qn += (uint32_t)__popcll(m);
+}
+
+struct ItemState {
+    uint32_t c0, c1, qbase, nq;
+    uint32_t qn, evals, found;
+};
+
+// Pass test of one query against one candidate held in the lane.
+template <bool kUniform, bool kTime>
+__device__ __forceinline__ bool pass32(const f32x8& q, uint32_t cand, float ecx, float ecy,
+                                       float ecz, float er, float ets, float ete) {
+    const float dx = ecx - q[0], dy = ecy - q[1], dz = ecz - q[2];
+    const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float R = q[3] + er;
+    bool p = s <= R * R;
+    if (kTime) p = p & (q[4] < ete) & (ets < q[5]);
+    if (!kUniform)
+        p = p & (cand >= __float_as_uint(q[6])) & (cand < __float_as_uint(q[7]));
+    return p;
+}
+
+// Tests queries [j0, j1) (j1 - j0 <= 32) of the group against the tile held in
+// registers and records the outcome as one bit per (query, candidate) in the
+// lane: bit j - j0 of bits[k] for candidate slot k.  Queries are visited from
+// the top down and each outcome is shifted in at the bottom
+// (bits = 2 * bits + pass), so the loop is pure vector arithmetic.
+template <bool kUniform, bool kTime>
+__device__ __forceinline__ void test_queries(ConstE32 qf, uint32_t j0, uint32_t j1,
+                                             const uint32_t (&cand)[kCpl],
+                                             const float (&ecx)[kCpl], const float (&ecy)[kCpl],
+                                             const float (&ecz)[kCpl], const float (&er)[kCpl],
+                                             const float (&ets)[kCpl], const float (&ete)[kCpl],
+                                             uint32_t (&bits)[kCpl]) {
+#pragma unroll
+    for (int k = 0; k < kCpl; ++k) bits[k] = 0;
+    uint32_t j = j1;
+    for (; j >= j0 + 2; j -= 2) {
+        const f32x8 qa = qf[j - 1], qb = qf[j - 2];
+#pragma unroll
+        for (int k = 0; k < kCpl; ++k) {
+            bits[k] = 2u * bits[k] +
+                      (uint32_t)pass32<kUniform, kTime>(qa, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                                                        ets[k], ete[k]);
+            bits[k] = 2u * bits[k] +
+                      (uint32_t)pass32<kUniform, kTime>(qb, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                                                        ets[k], ete[k]);
+        }
+    }
+    if (j > j0) {
+        const f32x8 qa = qf[j - 1];
+#pragma unroll
+        for (int k = 0; k < kCpl; ++k)
+            bits[k] = 2u * bits[k] +
+                      (uint32_t)pass32<kUniform, kTime>(qa, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                                                        ets[k], ete[k]);
+    }
+}
+
+// Queues the pairs recorded in bits (query j0 + bit position, candidate slot
+// k), one pair per lane per round.
+__device__ __forceinline__ void push_bits(WaveLDS& L, const DistArgs& A, ItemState& S,
+                                          const uint32_t (&cand)[kCpl], uint32_t (&bits)[kCpl],
+                                          uint32_t j0) {
+#pragma unroll
+    for (int k = 0; k < kCpl; ++k) {
+        const uint32_t code = (cand[k] - S.c0) << 6;
+        uint32_t b = bits[k];
+        for (;;) {
+            const bool act = b != 0;
+            const uint64_t m = ballot(act);
+            if (!m) break;
+            if (act) {
+                const uint32_t j = j0 + (uint32_t)__builtin_ctz(b);
+                L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
+                b &= b - 1u;
             }
-            const uint64_t m0 = ballot(p0), m1 = ballot(p1), m2 = ballot(p2), m3 = ballot(p3);
-            if ((m0 | m1 | m2 | m3) == 0) continue;
-            enqueue(L, m0, p0, i, c0, qn);
-            enqueue(L, m1, p1, i + 1, c0, qn);
-            enqueue(L, m2, p2, i + 2, c0, qn);
-            enqueue(L, m3, p3, i + 3, c0, qn);
-            if (qn >= kWave) drain_full(L, c0, qn, evals, found, A);
+            S.qn += (uint32_t)__popcll(m);
+            if (S.qn >= kWave) drain_full(L, S.c0, S.qbase, S.qn, S.evals, S.found, A);
         }
-        for (; i < c1; ++i) {
-            const f32x8 e0 = ce[i];
-            bool p0 = filter32(e0, qcx, qcy, qcz, qR, qa, qb);
-            if (!kUniform) p0 = p0 & (i >= qlo) & (i < qhi);
-            const uint64_t m0 = ballot(p0);
-            if (!m0) continue;
-            enqueue(L, m0, p0, i, c0, qn);
-            if (qn >= kWave) drain_full(L, c0, qn, evals, found, A);
+    }
+}
+
+template <bool kUniform, bool kTime>
+__device__ __forceinline__ void tile_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
+                                          ConstE32 qf, const uint32_t (&cand)[kCpl],
+                                          const float (&ecx)[kCpl], const float (&ecy)[kCpl],
+                                          const float (&ecz)[kCpl], const float (&er)[kCpl],
+                                          const float (&ets)[kCpl], const float (&ete)[kCpl]) {
+    for (uint32_t j0 = 0; j0 < S.nq; j0 += 32) {
+        const uint32_t j1 = min(S.nq, j0 + 32);
+        uint32_t bits[kCpl];
+        test_queries<kUniform, kTime>(qf, j0, j1, cand, ecx, ecy, ecz, er, ets, ete, bits);
+        uint32_t any = 0;
+#pragma unroll
+        for (int k = 0; k < kCpl; ++k) any |= bits[k];
+        if (ballot(any != 0)) push_bits(L, A, S, cand, bits, j0);
+    }
+}
+
+// FP32 form: the wave takes the chunk kCpl * 64 candidates at a time (kCpl
+// per lane, coalesced vector loads) and streams the group's query records
+// through scalar loads (they stay in the scalar cache for the whole item).
+// When every candidate of the bucket overlaps every query of the group in
+// time, the per-pair time test is skipped: exact, since the outward-rounded
+// FP32 times then overlap as well.
+template <bool kUniform>
+__device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
+                                                const BucketInfo& bi) {
+    const uint32_t lane = __lane_id();
+    ConstE32 qf = (ConstE32)(A.qf + S.qbase);
+    float qa = -INFINITY, qb = INFINITY;
+    if (lane < S.nq) {
+        const QF32 f = A.qf[S.qbase + lane];
+        qa = f.a32;
+        qb = f.b32;
+    }
+    const bool all_overlap =
+        ballot(((double)qa < bi.tmin_te) && (bi.tmax_ts < (double)qb)) == ~0ull;
+    for (uint32_t tile = S.c0; tile < S.c1; tile += kTile) {
+        uint32_t cand[kCpl];
+        float ecx[kCpl], ecy[kCpl], ecz[kCpl], er[kCpl], ets[kCpl], ete[kCpl];
+        bool full = true;
+#pragma unroll
+        for (int k = 0; k < kCpl; ++k) {
+            cand[k] = tile + k * kWave + lane;
+            const bool valid = cand[k] < S.c1;
+            full = full && valid;
+            const EntryF32 e = A.I.e32[valid ? cand[k] : S.c1 - 1];
+            ecx[k] = e.cx;
+            ecy[k] = e.cy;
+            ecz[k] = e.cz;
+            er[k] = e.r;
+            // a slot past the chunk gets an empty time extent: it never passes
+            ets[k] = valid ? e.ts : INFINITY;
+            ete[k] = valid ? e.te : -INFINITY;
         }
-    } else {
-        ConstE64 ce = (ConstE64)(A.I.e64);
-        QCanon q;
-        q.x = p.x;
-        q.y = p.y;
-        q.z = p.z;
-        q.vx = p.vx;
-        q.vy = p.vy;
-        q.vz = p.vz;
-        q.ts = p.ts;
-        q.aq = has ? p.aq : 1.0;
-        q.bq = has ? p.bq : 0.0;  // empty window: never a member
-        q.d = p.d;
-        for (uint32_t i = c0; i < c1; ++i) {
-            const f64x4 e0 = ce[2 * i], e1 = ce[2 * i + 1];  // x, y, z, vx | vy, vz, ts, te
-            bool pass = canon_eval<false>(q, e0[0], e0[1], e0[2], e0[3], e1[0], e1[1], e1[2], e1[3],
-                                          nullptr, nullptr);
-            if (!kUniform) pass = pass & (i >= qlo) & (i < qhi);
-            const uint64_t m = ballot(pass);
-            if (!m) continue;
-            enqueue(L, m, pass, i, c0, qn);
-            if (qn >= kWave) drain_full(L, c0, qn, evals, found, A);
-        }
+        // the time test can be dropped only on full tiles
+        if (all_overlap && ballot(full) == ~0ull)
+            tile_fp32<kUniform, false>(L, A, S, qf, cand, ecx, ecy, ecz, er, ets, ete);
+        else
+            tile_fp32<kUniform, true>(L, A, S, qf, cand, ecx, ecy, ecz, er, ets, ete);
+    }
+}
+
+// Plain FP64 form: one query segment per lane, every candidate of the chunk
+// streamed through scalar loads and tested with the canonical predicate.
+template <bool kUniform>
+__device__ __forceinline__ void scan_chunk_fp64(WaveLDS& L, const DistArgs& A, ItemState& S,
+                                                bool has, const QPrep& p) {
+    const uint32_t qlo = p.lo, qhi = p.hi;
+    ConstE64 ce = (ConstE64)(A.I.e64);
+    QCanon q;
+    q.x = p.x;
+    q.y = p.y;
+    q.z = p.z;
+    q.vx = p.vx;
+    q.vy = p.vy;
+    q.vz = p.vz;
+    q.ts = p.ts;
+    q.aq = has ? p.aq : 1.0;
+    q.bq = has ? p.bq : 0.0;  // empty window: never a member
+    q.d = p.d;
+    for (uint32_t i = S.c0; i < S.c1; ++i) {
+        const f64x4 e0 = ce[2 * i], e1 = ce[2 * i + 1];  // x, y, z, vx | vy, vz, ts, te
+        bool pass = canon_eval<false>(q, e0[0], e0[1], e0[2], e0[3], e1[0], e1[1], e1[2], e1[3],
+                                      nullptr, nullptr);
+        if (!kUniform) pass = pass & (i >= qlo) & (i < qhi);
+        const uint64_t m = ballot(pass);
+        if (!m) continue;
+        enqueue(L, m, pass, i, S.c0, S.qn);
+        if (S.qn >= kWave) drain_full(L, S.c0, S.qbase, S.qn, S.evals, S.found, A);
     }
 }
 
@@ -586,61 +762,51 @@ __global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
     __shared__ WaveLDS wl[kWavesPerBlock];
     WaveLDS& L = wl[threadIdx.x / kWave];
     const uint32_t lane = __lane_id();
-    const uint32_t item_end = (A.item_end == 0xFFFFFFFFu) ? A.hdr->n_items : A.item_end;
     uint64_t tests = 0, evals_total = 0;
     for (;;) {
         uint32_t it = 0;
         if (lane == 0) it = atomicAdd(&A.hdr->work_ctr, 1u);
         it = uniform(__shfl(it, 0)) + A.item_begin;
-        if (it >= item_end) break;
-        // bucket b: last b with b_item[b] <= it
-        uint32_t lo = 0, hi = A.nb;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (A.b_item[mid] <= it) lo = mid;
-            else hi = mid;
+        if (it >= A.item_end) break;
+        const uint32_t b = uniform(A.item_bucket[it]);
+        const BucketInfo bi = A.binfo[b];
+        const uint32_t local = it - bi.item0;
+        const uint32_t g = local / bi.nch;
+        const uint32_t c = local - g * bi.nch;
+        ItemState S;
+        S.nq = uniform(min((uint32_t)kWave, bi.count - g * kWave));
+        S.c0 = uniform(bi.lo + c * bi.clen);
+        S.c1 = uniform(min(bi.hi, S.c0 + bi.clen));
+        S.qbase = uniform(bi.start + g * kWave);
+        S.qn = 0;
+        S.evals = 0;
+        S.found = 0;
+        // does every query of the group cover the whole chunk?
+        bool cover = true;
+        if (lane < S.nq) {
+            const QF32 f = A.qf[S.qbase + lane];
+            cover = f.lo <= S.c0 && f.hi >= S.c1;
         }
-        const uint32_t b = uniform(lo);
-        const uint32_t local = it - A.b_item[b];
-        const uint32_t nch = A.b_nch[b];
-        const uint32_t g = local / nch;
-        const uint32_t c = local - g * nch;
-        const uint32_t cnt = A.b_count[b];
-        const uint32_t nq = uniform(min((uint32_t)kWave, cnt - g * kWave));
-        const uint32_t clen = A.b_clen[b];
-        const uint32_t c0 = uniform(A.b_lo[b] + c * clen);
-        const uint32_t c1 = uniform(min(A.b_hi[b], c0 + clen));
-        const bool has = lane < nq;
-        QPrep p = {};
-        if (has) p = A.qp[A.qsorted[A.b_start[b] + g * kWave + lane]];
-        L.qx[lane] = p.x;
-        L.qy[lane] = p.y;
-        L.qz[lane] = p.z;
-        L.qvx[lane] = p.vx;
-        L.qvy[lane] = p.vy;
-        L.qvz[lane] = p.vz;
-        L.qts[lane] = p.ts;
-        L.qaq[lane] = p.aq;
-        L.qbq[lane] = p.bq;
-        L.qd[lane] = p.d;
-        L.qid[lane] = p.qid;
-        L.qtraj[lane] = p.traj;
-        L.qreq[lane] = p.req;
-        wave_sync();
-        const bool cover = !has || (p.lo <= c0 && p.hi >= c1);
         const bool all_cover = ballot(cover) == ~0ull;
-        uint32_t qn = 0, evals = 0, found = 0;
-        if (all_cover) scan_chunk<kPrec, true>(L, A, c0, c1, has, p, qn, evals, found);
-        else scan_chunk<kPrec, false>(L, A, c0, c1, has, p, qn, evals, found);
-        if (qn) {
+        if (kPrec == TDS_PREC_FP32_RECHECK) {
+            if (all_cover) scan_chunk_fp32<true>(L, A, S, bi);
+            else scan_chunk_fp32<false>(L, A, S, bi);
+        } else {
+            const bool has = lane < S.nq;
+            QPrep p = {};
+            if (has) p = A.qp[A.qsorted[S.qbase + lane]];
+            if (all_cover) scan_chunk_fp64<true>(L, A, S, has, p);
+            else scan_chunk_fp64<false>(L, A, S, has, p);
+        }
+        if (S.qn) {
             wave_sync();
-            found += drain(L, 0, qn, c0, A);
-            evals += qn;
+            S.found += drain(L, 0, S.qn, S.c0, S.qbase, A);
+            S.evals += S.qn;
         }
         wave_sync();
-        tests += (uint64_t)(c1 - c0) * nq;
-        evals_total += evals;
-        if (A.item_count && lane == 0) A.item_count[it] = found;
+        tests += (uint64_t)(S.c1 - S.c0) * S.nq;
+        evals_total += S.evals;
+        if (A.item_count && lane == 0) A.item_count[it] = S.found;
     }
     if (lane == 0) {
         if (tests) atomicAdd((unsigned long long*)&A.hdr->tests, (unsigned long long)tests);
@@ -673,6 +839,7 @@ Workspace::~Workspace() {
     dfree(qkey);
     dfree(qslot);
     dfree(qsorted);
+    dfree(qf);
     dfree(qstage);
     dfree(qtraj_stage);
     dfree(req);
@@ -684,6 +851,8 @@ Workspace::~Workspace() {
     dfree(b_item);
     dfree(b_nch);
     dfree(b_clen);
+    dfree(binfo);
+    dfree(item_bucket);
     dfree(item_count);
     dfree(res);
     dfree(hdr);
@@ -702,6 +871,7 @@ int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_item, kMaxBuckets + 1));
     TDS_TRY(dmalloc(&w->b_nch, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_clen, kMaxBuckets));
+    TDS_TRY(dmalloc(&w->binfo, kMaxBuckets));
     TDS_TRY(dmalloc(&w->hdr, 1));
     TDS_HIP(hipHostMalloc((void**)&w->hdr_host, sizeof(SearchHeader), hipHostMallocDefault));
     TDS_HIP(hipEventCreate(&w->ev0));
@@ -715,13 +885,16 @@ int ws_reserve(Workspace* w, size_t nq, size_t nreq) {
         dfree(w->qkey);
         dfree(w->qslot);
         dfree(w->qsorted);
+        dfree(w->qf);
         w->qp = nullptr;
+        w->qf = nullptr;
         w->qkey = w->qslot = w->qsorted = nullptr;
         w->q_cap = 0;
         TDS_TRY(dmalloc(&w->qp, nq));
         TDS_TRY(dmalloc(&w->qkey, nq));
         TDS_TRY(dmalloc(&w->qslot, nq));
         TDS_TRY(dmalloc(&w->qsorted, nq));
+        TDS_TRY(dmalloc(&w->qf, nq + kQfPad));
         w->q_cap = nq;
     }
     if (w->r_cap < nreq || !w->req) {
@@ -813,21 +986,21 @@ int enqueue_prepare(const tds_index* idx, Workspace* w, const QueryView& Q, uint
                        w->b_lo, w->b_hi, nb, w->req_ctr, nreq);
     if (Q.n) {
         hipLaunchKernelGGL(k_qprep, dim3(ceil_div(Q.n, kBlock)), dim3(kBlock), 0, s, Q, w->req,
-                           nreq, I, w->qp, w->qkey, w->qslot, w->b_count, w->b_lo, w->b_hi, shift,
-                           w->hdr);
+                           nreq, I, w->qp, w->qkey, w->qslot, w->b_count, w->b_hi, shift, w->hdr);
     }
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_lo, w->b_hi, nb,
-                       chunk, w->b_start, w->b_item, w->b_nch, w->b_clen, w->hdr);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_lo, w->b_hi,
+                       idx->bin_first, idx->min_te, idx->e64, idx->m, shift, nb, chunk, w->b_start, w->b_item, w->b_nch,
+                       w->b_clen, w->binfo, w->hdr);
     if (Q.n) {
         hipLaunchKernelGGL(k_scatter, dim3(ceil_div(Q.n, kBlock)), dim3(kBlock), 0, s, Q.n,
-                           w->qkey, w->qslot, w->b_start, w->qsorted);
+                           w->qkey, w->qslot, w->b_start, w->qp, w->qsorted, w->qf);
     }
     TDS_HIP(hipGetLastError());
     *nb_out = nb;
     return TDS_OK;
 }
 
-int enqueue_distance(const tds_index* idx, Workspace* w, int prec, uint32_t nb, uint32_t nreq,
+int enqueue_distance(const tds_index* idx, Workspace* w, int prec, uint32_t nreq,
                      tds_result* out, uint64_t win_lo, uint32_t item_begin, uint32_t item_end,
                      uint32_t* item_count, uint32_t grid_waves, hipStream_t s,
                      hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr) {
@@ -838,14 +1011,9 @@ int enqueue_distance(const tds_index* idx, Workspace* w, int prec, uint32_t nb, 
     A.I = view_of(idx);
     A.qp = w->qp;
     A.qsorted = w->qsorted;
-    A.b_start = w->b_start;
-    A.b_count = w->b_count;
-    A.b_lo = w->b_lo;
-    A.b_hi = w->b_hi;
-    A.b_nch = w->b_nch;
-    A.b_clen = w->b_clen;
-    A.b_item = w->b_item;
-    A.nb = nb;
+    A.qf = w->qf;
+    A.binfo = w->binfo;
+    A.item_bucket = w->item_bucket;
     A.hdr = w->hdr;
     A.req = w->req;
     A.rc = w->req_ctr;
@@ -962,6 +1130,9 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     uint32_t grid_waves = P.grid_waves ? P.grid_waves : 256u * 16u;
     grid_waves = std::max(1u, std::min(grid_waves, n_items));
     TDS_TRY(grow(&w->item_count, &w->item_cap, std::max<size_t>(n_items, 1)));
+    TDS_TRY(grow(&w->item_bucket, &w->item_bucket_cap, std::max<size_t>(n_items, 1)));
+    if (n_items)
+        hipLaunchKernelGGL(k_item_fill, dim3(nb), dim3(kBlock), 0, s, w->binfo, w->item_bucket);
 
     tds_stats st{};
     st.query_segments = Q->n;
@@ -970,7 +1141,7 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     float ms = 0.f;
     uint64_t total = 0;
     // pass 1: everything, result window [0, dev_cap)
-    TDS_TRY(enqueue_distance(idx, w, prec, nb, 1, res, 0, 0, n_items, w->item_count, grid_waves, s,
+    TDS_TRY(enqueue_distance(idx, w, prec, 1, res, 0, 0, n_items, w->item_count, grid_waves, s,
                              w->ev0, w->ev1));
     ReqCounter rc{};
     TDS_HIP(hipMemcpyAsync(&rc, w->req_ctr, sizeof(ReqCounter), hipMemcpyDeviceToHost, s));
@@ -1021,7 +1192,7 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
             }
             for (auto& win : windows) {
                 if (win.second == 0) continue;
-                TDS_TRY(enqueue_distance(idx, w, prec, nb, 1, res, win.first, i0, i1, nullptr,
+                TDS_TRY(enqueue_distance(idx, w, prec, 1, res, win.first, i0, i1, nullptr,
                                          std::min(grid_waves, i1 - i0), s, w->ev0, w->ev1));
                 TDS_HIP(hipMemcpyAsync(out + written, res, win.second * sizeof(tds_result),
                                        hipMemcpyDeviceToHost, s));

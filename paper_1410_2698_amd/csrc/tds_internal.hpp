@@ -22,6 +22,7 @@ constexpr uint32_t kMaxBins = 65535;
 constexpr uint32_t kMaxBuckets = 65536; // query buckets of one search
 constexpr uint32_t kSpanClasses = 4;    // bin-span classes per first bin
 constexpr uint64_t kDefaultDevCap = 1ull << 24;
+constexpr uint32_t kQfPad = 4;          // query records read past a group's end
 
 // ---------------------------------------------------------------- records
 
@@ -62,6 +63,30 @@ struct alignas(16) QPrep {
 };
 static_assert(sizeof(QPrep) % 16 == 0, "QPrep layout");
 
+// FP32 filter record of a query segment in bucket order (32 bytes: one
+// wave-uniform scalar load).
+struct alignas(32) QF32 {
+    float cx, cy, cz, R;  // sphere of the clipped segment, R >= r + d + margins
+    float a32, b32;       // clipped window rounded outwards
+    uint32_t lo, hi;      // candidate range
+};
+static_assert(sizeof(QF32) == 32, "QF32 layout");
+
+// Per-bucket work description, written by the bucket scan (64 bytes: one
+// scalar load in the distance kernel).
+struct alignas(64) BucketInfo {
+    uint32_t lo, hi;      // candidate range of the bucket
+    uint32_t nch, clen;   // chunks and chunk length
+    uint32_t count;       // query segments in the bucket
+    uint32_t start;       // their first position in bucket order
+    uint32_t item0;       // first work item of the bucket
+    uint32_t pad;
+    double tmin_te;       // min t_end over the candidate range (-inf: unknown)
+    double tmax_ts;       // max t_start over the candidate range (+inf: unknown)
+    double pad2[2];
+};
+static_assert(sizeof(BucketInfo) == 64, "BucketInfo layout");
+
 // One request of a batch: a contiguous slice of the batch's query segments
 // with its own distance and window, and its own slice of the result buffer.
 struct Request {
@@ -100,6 +125,7 @@ struct Workspace {
     uint32_t* qkey = nullptr;
     uint32_t* qslot = nullptr;
     uint32_t* qsorted = nullptr;
+    QF32* qf = nullptr;             // q_cap + kQfPad records
     double* qstage = nullptr;       // staging of host query arrays (8 * stage_cap doubles)
     uint32_t* qtraj_stage = nullptr;
     size_t stage_cap = 0, traj_cap = 0;
@@ -113,6 +139,9 @@ struct Workspace {
     uint32_t* b_item = nullptr;     // kMaxBuckets + 1: first item of each bucket
     uint32_t* b_nch = nullptr;
     uint32_t* b_clen = nullptr;
+    BucketInfo* binfo = nullptr;    // kMaxBuckets
+    uint32_t* item_bucket = nullptr; // bucket of every work item
+    size_t item_bucket_cap = 0;
     uint32_t* item_count = nullptr; // results per work item (incremental mode)
     tds_result* res = nullptr;      // device result buffer (host-output mode)
     SearchHeader* hdr = nullptr;
@@ -135,6 +164,7 @@ struct tds_index {
     uint32_t* bin_first = nullptr; // m + 1
     double* min_ts = nullptr;      // m
     double* max_te = nullptr;      // m
+    double* min_te = nullptr;      // m: min t_end per bin (+inf when empty)
     double* cmax_te = nullptr;     // m
     double* lo_ts = nullptr;       // m: t_start of the first entry of bins >= j
     uint64_t device_bytes = 0;
