@@ -1,30 +1,34 @@
 """Benchmark of the distance threshold search on one MI355X.
 
-Workload (one "step" = one pass of the whole search path over one batch):
-the random-uniform 1M database (2,500 trajectories x 401 timesteps =
+Headline workload (one "step" = one pass of the whole search path over one
+batch): the random-uniform 1M database (2,500 trajectories x 401 timesteps =
 1,000,000 segments, start U[0,1000]^3, per-step velocity U[-5,5]^3), the full
 query set of 500 query trajectories (200,000 query segments) over [0, 400],
 searched at d = 1, 5 and 25 (three searches per step), FP32 bulk filter with
 FP64 recheck, index and queries resident in HBM, results written to a device
-buffer.
+buffer.  Launch parameters (bin count, chunk, grid) come from the autotuner,
+run before the timed region.
 
 value = strictly time-overlapping (query, entry) segment pairs resolved per
-second (index independent: every such pair is decided exactly), over the
-timed steps.  Also reported: candidate tests per kernel-second, queries/s
-(one query = one query trajectory at one d), the plain form (FP64 canonical
-test of every candidate, one query trajectory per call, host memory in and
-out) with its p50/p99 latency, the roofline of the distance kernel, and the
-oracle timed on the host on a bounded sample.
+second (index independent: every such pair is decided exactly).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
+Also reported: candidate tests per kernel-second, queries/s (one query = one
+query trajectory at one d), the roofline of the distance kernel, the served
+form (open-loop replay of the request stream: Poisson arrivals at 5,000/s of
+query trajectories of 5-400 segments with random windows and d in [1, 25],
+through the serving loop) and the plain form (FP64 canonical test of every
+candidate, one request per call, host memory in and out) on the same stream,
+each with p50/p99 latency, and the oracle timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serve]
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -34,13 +38,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "segment-pair tests/s + queries/s at exact results; p50/p99 latency vs plain GPU"
 
-# MI355X: 256 CUs, 4 SIMD16 per CU (wave64 over 4 cycles), 2.4 GHz.  Packed
-# FP32 is not used, so one FP32 FMA per lane per cycle:
-# 256 * 64 lanes * 2 flops * 2.4e9 = 78.6 TFLOP/s.
-PEAK_FP32_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# MI355X published FP32 vector peak: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU
+# = 157.3 TFLOP/s.
+PEAK_FP32_TFLOPS = 256 * 256 * 2.4e9 / 1e12
 # FP operations of one FP32 filter test: 3 sub, 1 mul, 2 FMA (2 flops each),
 # 1 add, 1 mul, 3 compares (1 each) = 13.
 FLOPS_PER_TEST_FP32 = 13
+KERNEL = "k_distance<FP32_RECHECK>"
 
 
 def overlap_pairs(D, Q, t0, t1):
@@ -55,16 +59,89 @@ def overlap_pairs(D, Q, t0, t1):
     return int(n.sum())
 
 
+def pct(x, q):
+    return round(float(np.percentile(np.asarray(x), q)), 4)
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the distance kernel from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_distance_fp32_uniform1m_traffic.json")
+    src = os.path.join(ROOT, "paper_1410_2698_amd", "csrc", "search.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    return rec.get("bytes_per_launch") if rec.get("search_hip_sha256_16") == h else None
+
+
+def serve_leg(tds, idx, n_req, rate, warm):
+    import trajgen
+    reqs = trajgen.request_stream(n_req + warm, rate=rate)
+    srv = tds.Server(idx, max_batch_segments=1 << 17, max_batch_requests=2048, slots=2,
+                     result_capacity=1 << 21, default_reserve=512)
+    for r in reqs[:warm]:
+        srv.wait(srv.submit(r.Q, r.d, r.t_start, r.t_end))
+    reqs = reqs[warm:]
+    base = reqs[0].arrival
+    tickets = [None] * len(reqs)
+    t_start = time.perf_counter()
+
+    def submitter():
+        for i, r in enumerate(reqs):
+            dt = (r.arrival - base) - (time.perf_counter() - t_start)
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = srv.submit(r.Q, r.d, r.t_start, r.t_end)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, n_rec = [], 0
+    for i in range(len(reqs)):
+        while tickets[i] is None:
+            time.sleep(0.0002)
+        recs, ms = srv.wait(tickets[i])
+        lat.append(ms)
+        n_rec += recs.size
+    th.join()
+    elapsed = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    # plain form on the same requests: FP64, one request per call
+    plain = []
+    for r in reqs:
+        t0 = time.perf_counter()
+        idx.search(r.Q, r.d, r.t_start, r.t_end, precision="fp64", capacity=4096)
+        plain.append(1e3 * (time.perf_counter() - t0))
+    return {
+        "served_fp32": {"offered_rate": rate, "requests": len(reqs),
+                        "requests_per_s": round(len(reqs) / elapsed, 1),
+                        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "records": n_rec,
+                        "batches": st["batches"], "requeued": st["requeued"],
+                        "max_batch_requests": st["max_batch_requests_seen"]},
+        "plain_fp64": {"requests_per_s": round(len(plain) / (sum(plain) * 1e-3), 1),
+                       "p50_ms": pct(plain, 50), "p99_ms": pct(plain, 99),
+                       "note": "one request per call, back to back (service time, no queueing)"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-traj", type=int, default=8, help="query trajectories in the oracle sample")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--cpu-traj", type=int, default=500, help="query trajectories in the oracle sample")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--grid-waves", type=int, default=0)
+    ap.add_argument("--num-bins", type=int, default=0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -77,6 +154,7 @@ def main():
 
     import paper_1410_2698_amd as tds
     import trajgen
+    from paper_1410_2698_amd import autotune
 
     torch.cuda.set_device(0)
     if args.calib_copy_mb:
@@ -89,13 +167,18 @@ def main():
     w = trajgen.uniform1m()
     ds = w.ds
     t0, t1 = w.window
-    idx = tds.Index(w.D)
+    tuned = {"num_bins": args.num_bins, "chunk": args.chunk, "grid_waves": args.grid_waves}
+    if not args.no_tune and not (args.chunk or args.grid_waves or args.num_bins):
+        sl = w.query_traj_slices()
+        sample = w.Q.take(np.arange(sl[0][0], sl[99][1]))  # 100 of 500 query trajectories
+        best = autotune.tune(w.D, sample, ds, w.window, cache=None)
+        tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves")}
+    idx = tds.Index(w.D, num_bins=tuned["num_bins"])
     Qt = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in w.Q.arrays().items()
           if k != "traj"}
     Qt["traj"] = torch.from_numpy(w.Q.traj.astype(np.int32)).cuda()
     pairs = overlap_pairs(w.D, w.Q, t0, t1)
 
-    # size the device result buffer from one untimed search per d
     counts = {}
     for d in ds:
         _, n, _ = idx.search_raw(Qt, d, t0, t1, out_ptr=0, capacity=0, out_on_device=True)
@@ -103,21 +186,20 @@ def main():
     cap = max(counts.values()) + 1
     out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
 
-    kern_ms = 0.0
-    tests = 0
-    launches = 0
+    kern_ms, tests, evals, launches = 0.0, 0, 0, 0
 
     def step(record):
-        nonlocal kern_ms, tests, launches
+        nonlocal kern_ms, tests, evals, launches
         for d in ds:
             st, n, s = idx.search_raw(Qt, d, t0, t1, out_ptr=out.data_ptr(), capacity=cap,
-                                      out_on_device=True, chunk=args.chunk,
-                                      grid_waves=args.grid_waves)
+                                      out_on_device=True, chunk=tuned["chunk"],
+                                      grid_waves=tuned["grid_waves"])
             if st != tds.TDS_OK or n != counts[d]:
                 raise RuntimeError(f"search failed: status {st}, {n} vs {counts[d]}")
             if record:
                 kern_ms += s["kernel_ms"]
                 tests += s["candidate_tests"]
+                evals += s["fp64_evals"]
                 launches += s["passes"]
 
     for _ in range(args.warmup):
@@ -135,34 +217,22 @@ def main():
     avg_ms = kern_ms / max(launches, 1)
     tests_per_launch = tests / max(launches, 1)
     achieved = FLOPS_PER_TEST_FP32 * tests_per_launch / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3),
-                "peak": round(PEAK_FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4), "traffic": None,
-                "kernel": "k_distance<FP32_RECHECK>", "avg_launch_ms": round(avg_ms, 4),
-                "tests_per_launch": int(tests_per_launch)}
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic_from_profile(), "kernel": KERNEL,
+                "avg_launch_ms": round(avg_ms, 4), "tests_per_launch": int(tests_per_launch),
+                "flops_per_test": FLOPS_PER_TEST_FP32}
 
     extra = {"queries_per_s": round(n_queries * args.steps / elapsed, 1),
              "candidate_tests_per_kernel_s": round(tests / (kern_ms * 1e-3), 1) if kern_ms else None,
+             "fp64_recheck_fraction": round(evals / max(tests, 1), 8),
+             "fp32_endpoint_error": 0.0,
              "results_per_d": {str(d): counts[d] for d in ds},
-             "overlap_pairs_per_search": pairs}
+             "overlap_pairs_per_search": pairs, "tuned": tuned,
+             "batch_latency_ms": round(ms_per_step / len(ds), 4)}
 
-    # plain form: FP64 test of every candidate, one query trajectory per call,
-    # queries from host memory and results back to host memory
-    if not args.no_plain:
-        lat = []
-        sl = w.query_traj_slices()
-        d = 5.0
-        for i, (b, e) in enumerate(sl):
-            sub = w.Q.take(np.arange(b, e))
-            tq = time.perf_counter()
-            idx.search(sub, d, t0, t1, precision="fp64", capacity=4096)
-            lat.append(time.perf_counter() - tq)
-        lat = np.array(lat) * 1e3
-        extra["plain_fp64"] = {"queries_per_s": round(len(lat) / (lat.sum() * 1e-3), 1),
-                               "p50_ms": round(float(np.percentile(lat, 50)), 4),
-                               "p99_ms": round(float(np.percentile(lat, 99)), 4), "d": d}
-        extra["batched_fp32"] = {"queries_per_s": extra["queries_per_s"],
-                                 "batch_latency_ms": round(ms_per_step / len(ds), 4)}
+    if not args.no_serve:
+        extra.update(serve_leg(tds, idx, args.serve_requests, 5000.0, 200))
 
     cpu = None
     if not args.no_cpu:
@@ -177,7 +247,7 @@ def main():
         cpu = {"value": round(overlap_pairs(w.D, sub, t0, t1) / dt, 1), "unit": "pair tests/s",
                "cores": cores, "kind": "oracle",
                "sample": f"{k} of 500 query trajectories ({len(sub)} query segments) x 1,000,000 "
-                         f"entries at d=5, brute force; {dt:.2f} s"}
+                         f"entries at d=5, brute force over all pairs; {dt:.2f} s"}
 
     rec = {"metric": METRIC, "value": round(value, 1), "unit": "pair tests/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),

@@ -221,6 +221,123 @@ int tds_search(const tds_index* index, const tds_segments* Q, double d,
                uint64_t* n_out, const tds_search_params* params, void* stream,
                tds_stats* stats);
 
+/*
+ * One request of a batch: a slice of the batch's query segments searched with
+ * its own distance and window, writing into its own slice of the output.
+ * Requests of a batch must tile the query segments in order: the first
+ * starts at 0 and each starts where the previous one ends.  q_seg in the
+ * records of a request counts from its q_begin.
+ */
+typedef struct tds_request {
+    uint64_t q_begin, q_count;
+    double d, t_start, t_end;          /* as for tds_search */
+    uint64_t out_offset, out_capacity; /* output slice, in records */
+} tds_request;
+
+/*
+ * Batched search: all requests in one pass of the search kernels (their query
+ * segments share work items; each record goes to its request's slice).
+ * counts[r] (host, nreq entries) is set to the total results of request r;
+ * a request whose total exceeds its out_capacity keeps an unspecified subset
+ * and makes the call return TDS_E_OVERFLOW (the other requests are complete).
+ * `out` holds out_capacity records in host or device memory
+ * (params->out_on_device).  Waits for `stream`.
+ * Errors: TDS_E_INVALID (requests that do not tile Q, slices outside out,
+ * bad d or window, bad Q values), TDS_E_NOMEM, TDS_E_DEVICE.
+ */
+int tds_search_batch(const tds_index* index, const tds_segments* Q, const tds_request* reqs,
+                     uint32_t nreq, tds_result* out, uint64_t out_capacity, uint64_t* counts,
+                     const tds_search_params* params, void* stream, tds_stats* stats);
+
+/*
+ * Batcher: a reusable batched search with fixed capacities whose launch
+ * sequence is captured once in a hipGraph and replayed for every batch
+ * (sizes are read from device memory).  It owns its device buffers and
+ * pinned staging; `stream` (kept, not owned; NULL = a stream of its own) is
+ * where it works.  One batch at a time per batcher.
+ */
+typedef struct tds_batcher tds_batcher;
+
+/* Errors: TDS_E_INVALID (zero capacities, bad params), TDS_E_NOMEM, TDS_E_DEVICE. */
+int tds_batcher_create(const tds_index* index, uint64_t max_segments, uint32_t max_requests,
+                       uint64_t result_capacity, const tds_search_params* params, void* stream,
+                       tds_batcher** out);
+
+/*
+ * Run one batch (Q in host or device memory, at most max_segments; at most
+ * max_requests requests; output slices within result_capacity).  `out` is
+ * host memory of result_capacity records; counts as for tds_search_batch.
+ * Returns after the results are in `out`.  Same status codes as
+ * tds_search_batch.
+ */
+int tds_batcher_run(tds_batcher* b, const tds_segments* Q, const tds_request* reqs, uint32_t nreq,
+                    tds_result* out, uint64_t* counts, tds_stats* stats);
+
+/* Number of graph replays so far (0 until the first batch). */
+uint64_t tds_batcher_replays(const tds_batcher* b);
+
+int tds_batcher_destroy(tds_batcher* b);
+
+/*
+ * Serving loop over a resident index (the in-memory database of Sec. 3.1,
+ * queried many times).  Requests (one query trajectory each, host memory,
+ * with its own d and window) are admitted in arrival order into batches by
+ * free batch slots, query-segment capacity and result-memory reservations;
+ * batches run on `slots` streams at once (continuous batching: requests that
+ * arrive while batches run join the next batch to start).  A request whose
+ * results exceed its reservation is re-queued with the exact size, so every
+ * request completes with all its records.  Each request's records are the
+ * same as from tds_search on its own.
+ */
+typedef struct tds_server tds_server;
+
+typedef struct tds_server_params {
+    uint64_t max_batch_segments; /* query segments per batch (0 = 262144) */
+    uint32_t max_batch_requests; /* requests per batch (0 = 4096) */
+    uint32_t slots;              /* batches in flight (0 = 2) */
+    uint64_t result_capacity;    /* result records per batch (0 = 2^21) */
+    uint64_t default_reserve;    /* records reserved per request until known (0 = 1024) */
+    uint32_t max_pending;        /* queued requests before submit refuses (0 = 1 << 20) */
+    uint32_t reserved0;
+    tds_search_params search;    /* precision, chunk, grid (output fields ignored) */
+} tds_server_params;
+
+typedef struct tds_server_stats {
+    uint64_t submitted, completed, batches, requeued, failed;
+    uint64_t max_batch_requests_seen;
+} tds_server_stats;
+
+/* Errors: TDS_E_INVALID, TDS_E_NOMEM, TDS_E_DEVICE.  params may be NULL. */
+int tds_server_create(const tds_index* index, const tds_server_params* params, tds_server** out);
+
+/*
+ * Queue one request (Q in host memory, copied; at most max_batch_segments
+ * segments).  reserve = result records to reserve (0 = default).  When the
+ * queue is full: blocking != 0 waits, else TDS_E_BUSY.  *ticket identifies
+ * the request for tds_server_wait / tds_server_poll.
+ * Errors: TDS_E_INVALID (bad Q, d or window), TDS_E_BUSY.
+ */
+int tds_server_submit(tds_server* srv, const tds_segments* Q, double d, double t_start,
+                      double t_end, uint64_t reserve, int blocking, uint64_t* ticket);
+
+/* *done = 1 once the request has completed (or failed). */
+int tds_server_poll(tds_server* srv, uint64_t ticket, int* done);
+
+/*
+ * Wait for a request and copy its records (host memory).  *n_out = number of
+ * records, *latency_ms = time from submit to completion (either may be NULL).
+ * TDS_E_OVERFLOW: more than `capacity` records; nothing copied, the request
+ * stays available for another call.  On any other return the ticket is
+ * released.  Errors: TDS_E_INVALID (unknown ticket), or the request's failure.
+ */
+int tds_server_wait(tds_server* srv, uint64_t ticket, tds_result* out, uint64_t capacity,
+                    uint64_t* n_out, double* latency_ms);
+
+int tds_server_stats_get(tds_server* srv, tds_server_stats* stats);
+
+/* Finishes queued requests, stops the worker and frees everything. */
+int tds_server_destroy(tds_server* srv);
+
 /* Fill *p with the defaults (TDS_PREC_FP32_RECHECK, host output, auto sizes). */
 void tds_search_params_default(tds_search_params* p);
 

@@ -190,6 +190,190 @@ class Index:
             raise TdsError(status, "tds_search")
 
 
+    def search_batch(self, requests, *, precision: str = "fp32", chunk: int = 0,
+                     grid_waves: int = 0, capacity: Optional[int] = None):
+        """Batched search (tds_search_batch).  ``requests`` is a list of
+        (Q, d, t_start, t_end); returns one record array per request.  Output
+        slices start at ``capacity`` records each and grow on overflow."""
+        Qcat, reqs = _concat_requests(requests, 1 << 12 if capacity is None else capacity)
+        h = _segments(Qcat)
+        while True:
+            total = sum(r.out_capacity for r in reqs)
+            buf = np.empty(max(total, 1), RESULT_DTYPE)
+            counts = (ctypes.c_uint64 * len(reqs))()
+            p = _search_params(precision, chunk, grid_waves)
+            st = _lib.tds_stats()
+            status = self._lib.tds_search_batch(self._h, ctypes.byref(h.struct), reqs, len(reqs),
+                                                ctypes.c_void_p(buf.ctypes.data), total, counts,
+                                                ctypes.byref(p), _current_stream(), ctypes.byref(st))
+            self.last_stats = st.as_dict()
+            if status == TDS_OK:
+                return [buf[r.out_offset: r.out_offset + counts[i]].copy() for i, r in enumerate(reqs)]
+            if status == TDS_E_OVERFLOW and capacity is None:
+                _resize_slices(reqs, counts)
+                continue
+            raise TdsError(status, "tds_search_batch")
+
+
+def _search_params(precision="fp32", chunk=0, grid_waves=0):
+    lib = load()
+    p = _lib.tds_search_params()
+    lib.tds_search_params_default(ctypes.byref(p))
+    p.precision = PRECISIONS[precision]
+    p.chunk = int(chunk)
+    p.grid_waves = int(grid_waves)
+    return p
+
+
+def _concat_requests(requests, cap):
+    """Concatenate the requests' query segments; one output slice each."""
+    parts = [r[0] for r in requests]
+    Qcat = {k: np.concatenate([np.asarray(getattr(q, k) if not isinstance(q, dict) else q[k],
+                                          dtype=np.float64) for q in parts]) for k in _FIELDS}
+    Qcat["traj"] = np.concatenate([np.asarray(getattr(q, "traj") if not isinstance(q, dict) else q["traj"],
+                                              dtype=np.uint32) for q in parts])
+    reqs = (_lib.tds_request * len(requests))()
+    off = 0
+    for i, (q, d, t0, t1) in enumerate(requests):
+        n = len(np.asarray(getattr(q, "xs") if not isinstance(q, dict) else q["xs"]))
+        reqs[i].q_begin = off
+        reqs[i].q_count = n
+        reqs[i].d = float(d)
+        reqs[i].t_start = float(t0)
+        reqs[i].t_end = float(t1)
+        reqs[i].out_offset = i * cap
+        reqs[i].out_capacity = cap
+        off += n
+    return Qcat, reqs
+
+
+def _resize_slices(reqs, counts):
+    off = 0
+    for i in range(len(reqs)):
+        reqs[i].out_offset = off
+        reqs[i].out_capacity = max(int(counts[i]), int(reqs[i].out_capacity))
+        off += reqs[i].out_capacity
+
+
+class Batcher:
+    """Fixed-capacity batched search replayed from a captured hipGraph."""
+
+    def __init__(self, index: Index, max_segments: int, max_requests: int, result_capacity: int,
+                 *, precision: str = "fp32", chunk: int = 0, grid_waves: int = 0):
+        self._lib = load()
+        self.index = index
+        self.result_capacity = int(result_capacity)
+        p = _search_params(precision, chunk, grid_waves)
+        out = ctypes.c_void_p()
+        check(self._lib.tds_batcher_create(index.handle, int(max_segments), int(max_requests),
+                                           int(result_capacity), ctypes.byref(p), None,
+                                           ctypes.byref(out)), "tds_batcher_create")
+        self._h = out
+        self.last_stats: Optional[dict] = None
+
+    def run(self, requests, slice_capacity: Optional[int] = None):
+        """``requests``: list of (Q, d, t_start, t_end).  Returns (records per
+        request, status): every request gets an equal output slice."""
+        cap = slice_capacity or max(1, self.result_capacity // len(requests))
+        Qcat, reqs = _concat_requests(requests, cap)
+        h = _segments(Qcat)
+        buf = np.empty(self.result_capacity, RESULT_DTYPE)
+        counts = (ctypes.c_uint64 * len(reqs))()
+        st = _lib.tds_stats()
+        status = self._lib.tds_batcher_run(self._h, ctypes.byref(h.struct), reqs, len(reqs),
+                                           ctypes.c_void_p(buf.ctypes.data), counts, ctypes.byref(st))
+        if status not in (TDS_OK, TDS_E_OVERFLOW):
+            raise TdsError(status, "tds_batcher_run")
+        self.last_stats = st.as_dict()
+        out = [buf[r.out_offset: r.out_offset + min(counts[i], r.out_capacity)].copy()
+               for i, r in enumerate(reqs)]
+        return out, [int(c) for c in counts], status
+
+    @property
+    def replays(self) -> int:
+        return int(self._lib.tds_batcher_replays(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tds_batcher_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop with continuous batching over a resident index."""
+
+    def __init__(self, index: Index, *, max_batch_segments: int = 0, max_batch_requests: int = 0,
+                 slots: int = 0, result_capacity: int = 0, default_reserve: int = 0,
+                 max_pending: int = 0, precision: str = "fp32", chunk: int = 0, grid_waves: int = 0):
+        self._lib = load()
+        self.index = index
+        p = _lib.tds_server_params()
+        p.max_batch_segments = max_batch_segments
+        p.max_batch_requests = max_batch_requests
+        p.slots = slots
+        p.result_capacity = result_capacity
+        p.default_reserve = default_reserve
+        p.max_pending = max_pending
+        p.search = _search_params(precision, chunk, grid_waves)
+        out = ctypes.c_void_p()
+        check(self._lib.tds_server_create(index.handle, ctypes.byref(p), ctypes.byref(out)),
+              "tds_server_create")
+        self._h = out
+        self._keep = {}
+
+    def submit(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
+               reserve: int = 0, blocking: bool = True) -> int:
+        h = _segments(Q)
+        t = ctypes.c_uint64()
+        check(self._lib.tds_server_submit(self._h, ctypes.byref(h.struct), float(d), float(t_start),
+                                          float(t_end), int(reserve), 1 if blocking else 0,
+                                          ctypes.byref(t)), "tds_server_submit")
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        """Returns (records, latency_ms)."""
+        cap = 1024
+        while True:
+            buf = np.empty(cap, RESULT_DTYPE)
+            n = ctypes.c_uint64()
+            lat = ctypes.c_double()
+            st = self._lib.tds_server_wait(self._h, ticket, ctypes.c_void_p(buf.ctypes.data), cap,
+                                           ctypes.byref(n), ctypes.byref(lat))
+            if st == TDS_OK:
+                return buf[: n.value].copy(), lat.value
+            if st == TDS_E_OVERFLOW:
+                cap = int(n.value)
+                continue
+            raise TdsError(st, "tds_server_wait")
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int()
+        check(self._lib.tds_server_poll(self._h, ticket, ctypes.byref(done)), "tds_server_poll")
+        return bool(done.value)
+
+    def stats(self) -> dict:
+        s = _lib.tds_server_stats()
+        check(self._lib.tds_server_stats_get(self._h, ctypes.byref(s)), "tds_server_stats_get")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tds_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def abi_version() -> int:
     return int(load().tds_abi_version())
 

@@ -53,6 +53,28 @@ class tds_index_info(ctypes.Structure):
                 ("bin_width", ctypes.c_double), ("device_bytes", ctypes.c_uint64)]
 
 
+class tds_request(ctypes.Structure):
+    _fields_ = [("q_begin", ctypes.c_uint64), ("q_count", ctypes.c_uint64), ("d", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("out_offset", ctypes.c_uint64), ("out_capacity", ctypes.c_uint64)]
+
+
+class tds_server_params(ctypes.Structure):
+    _fields_ = [("max_batch_segments", ctypes.c_uint64), ("max_batch_requests", ctypes.c_uint32),
+                ("slots", ctypes.c_uint32), ("result_capacity", ctypes.c_uint64),
+                ("default_reserve", ctypes.c_uint64), ("max_pending", ctypes.c_uint32),
+                ("reserved0", ctypes.c_uint32), ("search", tds_search_params)]
+
+
+class tds_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("requeued", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("max_batch_requests_seen", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # exported name -> (restype, argtypes)
 SIGNATURES = {
     "tds_abi_version": (ctypes.c_uint32, []),
@@ -71,6 +93,28 @@ SIGNATURES = {
                                   ctypes.POINTER(tds_stats)]),
     "tds_search_params_default": (None, [ctypes.POINTER(tds_search_params)]),
     "tds_last_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_stats)]),
+    "tds_search_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments),
+                                        ctypes.POINTER(tds_request), ctypes.c_uint32, ctypes.c_void_p,
+                                        ctypes.c_uint64, c_u64_p, ctypes.POINTER(tds_search_params),
+                                        ctypes.c_void_p, ctypes.POINTER(tds_stats)]),
+    "tds_batcher_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_uint64, ctypes.POINTER(tds_search_params),
+                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "tds_batcher_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments),
+                                       ctypes.POINTER(tds_request), ctypes.c_uint32, ctypes.c_void_p,
+                                       c_u64_p, ctypes.POINTER(tds_stats)]),
+    "tds_batcher_replays": (ctypes.c_uint64, [ctypes.c_void_p]),
+    "tds_batcher_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "tds_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_server_params),
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "tds_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments), ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                         ctypes.c_int, c_u64_p]),
+    "tds_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
+    "tds_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                       ctypes.c_uint64, c_u64_p, ctypes.POINTER(ctypes.c_double)]),
+    "tds_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_server_stats)]),
+    "tds_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 _lib = None

@@ -4,29 +4,7 @@
 
 #include "tds_internal.hpp"
 
-namespace {
-
-// Makes the index's device current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) {
-            (void)hipGetLastError();
-            ok = false;
-            return;
-        }
-        if (prev != dev && hipSetDevice(dev) != hipSuccess) {
-            (void)hipGetLastError();
-            ok = false;
-        }
-    }
-    ~DeviceGuard() {
-        if (ok && prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-}  // namespace
+using tds::DeviceGuard;
 
 extern "C" {
 

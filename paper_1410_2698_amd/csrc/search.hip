@@ -205,6 +205,7 @@ __device__ inline uint32_t request_of(const Request* req, uint32_t nreq, uint64_
 __global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_count,
                                                  uint32_t* b_lo, uint32_t* b_hi, uint32_t nb,
                                                  ReqCounter* rc, uint32_t nreq) {
+    // nreq: capacity of the request counters (all of them are cleared)
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i == 0) {
         SearchHeader h = {};
@@ -221,8 +222,8 @@ __global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const Request* __restrict__ req,
-                                                  uint32_t nreq, IndexView I,
+__global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* __restrict__ desc,
+                                                  const Request* __restrict__ req, IndexView I,
                                                   QPrep* __restrict__ qp,
                                                   uint32_t* __restrict__ qkey,
                                                   uint32_t* __restrict__ qslot, uint32_t* b_count,
@@ -230,8 +231,8 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const Request* __
                                                   SearchHeader* hdr) {
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     bool active = false;
-    if (k < Q.n) {
-        const uint32_t r = request_of(req, nreq, k);
+    if (k < desc->nq) {
+        const uint32_t r = request_of(req, desc->nreq, k);
         const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k], ts = Q.a[3][k];
         const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k], te = Q.a[7][k];
         const bool ok = finite(xs) && finite(ys) && finite(zs) && finite(ts) && finite(xe) &&
@@ -405,14 +406,15 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(uint64_t nq, const uint32_t* __restrict__ qkey,
+__global__ __launch_bounds__(kBlock) void k_scatter(const BatchDesc* __restrict__ desc,
+                                                    const uint32_t* __restrict__ qkey,
                                                     const uint32_t* __restrict__ qslot,
                                                     const uint32_t* __restrict__ b_start,
                                                     const QPrep* __restrict__ qp,
                                                     uint32_t* __restrict__ qsorted,
                                                     QF32* __restrict__ qf) {
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= nq) return;
+    if (k >= desc->nq) return;
     const uint32_t s = qslot[k];
     if (s == kInactive) return;
     const uint32_t pos = b_start[qkey[k]] + s;
@@ -432,11 +434,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter(uint64_t nq, const uint32_t*
 
 // item_bucket[i] = bucket of work item i; one block per bucket.
 __global__ __launch_bounds__(kBlock) void k_item_fill(const BucketInfo* __restrict__ binfo,
-                                                      uint32_t* __restrict__ item_bucket) {
+                                                      const BatchDesc* __restrict__ desc,
+                                                      uint32_t* __restrict__ item_bucket,
+                                                      SearchHeader* hdr) {
     const uint32_t b = blockIdx.x;
     const BucketInfo bi = binfo[b];
     const uint32_t n = ((bi.count + kWave - 1) / kWave) * bi.nch;
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) item_bucket[bi.item0 + i] = b;
+    const uint32_t cap = desc->item_cap;
+    if (threadIdx.x == 0 && n && (uint64_t)bi.item0 + n > cap) atomicOr(&hdr->err, 2u);
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock)
+        if (bi.item0 + i < cap) item_bucket[bi.item0 + i] = b;
 }
 
 // Resets the per-pass counters of the distance kernel.
@@ -453,13 +460,14 @@ struct DistArgs {
     const uint32_t* qsorted;
     const BucketInfo* binfo;
     const uint32_t* item_bucket;
+    const BatchDesc* desc;
     SearchHeader* hdr;
     const Request* req;
     ReqCounter* rc;
     tds_result* out;
     uint64_t win_lo;        // first request-local result position kept
     uint32_t item_begin;    // work items [item_begin, item_end)
-    uint32_t item_end;
+    uint32_t item_end;      // 0xFFFFFFFF: every item of the search
     uint32_t* item_count;   // results per work item, or nullptr
 };
 
@@ -763,11 +771,15 @@ __global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
     WaveLDS& L = wl[threadIdx.x / kWave];
     const uint32_t lane = __lane_id();
     uint64_t tests = 0, evals_total = 0;
+    // all items of the search, unless a range is given (incremental passes)
+    const uint32_t item_end = (A.item_end == 0xFFFFFFFFu)
+                                  ? uniform(min(A.hdr->n_items, A.desc->item_cap))
+                                  : A.item_end;
     for (;;) {
         uint32_t it = 0;
         if (lane == 0) it = atomicAdd(&A.hdr->work_ctr, 1u);
         it = uniform(__shfl(it, 0)) + A.item_begin;
-        if (it >= A.item_end) break;
+        if (it >= item_end) break;
         const uint32_t b = uniform(A.item_bucket[it]);
         const BucketInfo bi = A.binfo[b];
         const uint32_t local = it - bi.item0;
@@ -828,40 +840,20 @@ int grow(T** p, size_t* cap, size_t need) {
     return TDS_OK;
 }
 
-struct WsCaps {
-    size_t q = 0, r = 0, items = 0, res = 0, stage = 0;
-};
-
 }  // namespace
 
 Workspace::~Workspace() {
-    dfree(qp);
-    dfree(qkey);
-    dfree(qslot);
-    dfree(qsorted);
-    dfree(qf);
-    dfree(qstage);
-    dfree(qtraj_stage);
-    dfree(req);
-    dfree(req_ctr);
-    dfree(b_count);
-    dfree(b_lo);
-    dfree(b_hi);
-    dfree(b_start);
-    dfree(b_item);
-    dfree(b_nch);
-    dfree(b_clen);
-    dfree(binfo);
-    dfree(item_bucket);
-    dfree(item_count);
-    dfree(res);
-    dfree(hdr);
+    for (void* p : {(void*)qp, (void*)qkey, (void*)qslot, (void*)qsorted, (void*)qf, (void*)qstage,
+                    (void*)qtraj_stage, (void*)req, (void*)req_ctr, (void*)b_count, (void*)b_lo,
+                    (void*)b_hi, (void*)b_start, (void*)b_item, (void*)b_nch, (void*)b_clen,
+                    (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res, (void*)hdr,
+                    (void*)desc})
+        dfree(p);
     if (hdr_host) (void)hipHostFree(hdr_host);
+    if (desc_host) (void)hipHostFree(desc_host);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
 }
-
-namespace {
 
 int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_count, kMaxBuckets));
@@ -873,7 +865,9 @@ int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_clen, kMaxBuckets));
     TDS_TRY(dmalloc(&w->binfo, kMaxBuckets));
     TDS_TRY(dmalloc(&w->hdr, 1));
+    TDS_TRY(dmalloc(&w->desc, 1));
     TDS_HIP(hipHostMalloc((void**)&w->hdr_host, sizeof(SearchHeader), hipHostMallocDefault));
+    TDS_HIP(hipHostMalloc((void**)&w->desc_host, sizeof(BatchDesc), hipHostMallocDefault));
     TDS_HIP(hipEventCreate(&w->ev0));
     TDS_HIP(hipEventCreate(&w->ev1));
     return TDS_OK;
@@ -881,11 +875,9 @@ int ws_init(Workspace* w) {
 
 int ws_reserve(Workspace* w, size_t nq, size_t nreq) {
     if (w->q_cap < nq || !w->qp) {
-        dfree(w->qp);
-        dfree(w->qkey);
-        dfree(w->qslot);
-        dfree(w->qsorted);
-        dfree(w->qf);
+        for (void* p : {(void*)w->qp, (void*)w->qkey, (void*)w->qslot, (void*)w->qsorted,
+                        (void*)w->qf})
+            dfree(p);
         w->qp = nullptr;
         w->qf = nullptr;
         w->qkey = w->qslot = w->qsorted = nullptr;
@@ -907,6 +899,147 @@ int ws_reserve(Workspace* w, size_t nq, size_t nreq) {
         TDS_TRY(dmalloc(&w->req_ctr, nreq));
         w->r_cap = nreq;
     }
+    return TDS_OK;
+}
+
+namespace {
+
+uint32_t bucket_shift(uint32_t m) {
+    uint32_t shift = 0;
+    while ((((uint64_t)m * kSpanClasses - 1) >> shift) >= kMaxBuckets) ++shift;
+    return shift;
+}
+
+uint32_t bucket_count(uint32_t m) {
+    return (uint32_t)((((uint64_t)m * kSpanClasses - 1) >> bucket_shift(m)) + 1);
+}
+
+// Upper bound of the work items of a batch of nq query segments: every
+// non-empty bucket contributes ceil(count / 64) groups, each split into at
+// most ceil(n / chunk) chunks.
+uint64_t item_bound(uint64_t nq, uint32_t nb, uint64_t n, uint32_t chunk) {
+    const uint64_t groups = (nq + kWave - 1) / kWave + std::min<uint64_t>(nq, nb);
+    const uint64_t nch = std::max<uint64_t>((n + chunk - 1) / chunk, 1);
+    return groups * nch;
+}
+
+constexpr uint64_t kMaxItemTable = 1ull << 26;  // entries (256 MiB) kept without an exact count
+
+uint32_t resolve_chunk(int prec, uint32_t chunk) {
+    if (chunk) return std::max(chunk, 64u);
+    return prec == TDS_PREC_FP64 ? 512u : 2048u;
+}
+
+uint32_t resolve_grid(uint32_t grid_waves) { return grid_waves ? grid_waves : 256u * 8u; }
+
+int resolve_prec(int p) {
+    if (p == TDS_PREC_DEFAULT) return TDS_PREC_FP32_RECHECK;
+    if (p != TDS_PREC_FP64 && p != TDS_PREC_FP32_RECHECK) return -1;
+    return p;
+}
+
+// Device view of the query arrays; host arrays are copied into the staging
+// buffers first.
+int stage_queries(const tds_segments* Q, QueryView* V, hipStream_t s, double** stage_buf,
+                  size_t* stage_cap, uint32_t** traj_buf, size_t* traj_cap, bool force_copy) {
+    V->n = Q->n;
+    const double* src[8] = {Q->xs, Q->ys, Q->zs, Q->ts, Q->xe, Q->ye, Q->ze, Q->te};
+    if (Q->on_device && !force_copy) {
+        for (int k = 0; k < 8; ++k) V->a[k] = src[k];
+        V->traj = Q->traj_id;
+        return TDS_OK;
+    }
+    const hipMemcpyKind kind = Q->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    TDS_TRY(grow(stage_buf, stage_cap, 8 * (size_t)Q->n));
+    for (int k = 0; k < 8; ++k) {
+        TDS_HIP(hipMemcpyAsync(*stage_buf + k * Q->n, src[k], Q->n * sizeof(double), kind, s));
+        V->a[k] = *stage_buf + k * Q->n;
+    }
+    V->traj = nullptr;
+    if (Q->traj_id) {
+        TDS_TRY(grow(traj_buf, traj_cap, (size_t)Q->n));
+        TDS_HIP(hipMemcpyAsync(*traj_buf, Q->traj_id, Q->n * sizeof(uint32_t), kind, s));
+        V->traj = *traj_buf;
+    }
+    return TDS_OK;
+}
+
+DistArgs dist_args(const tds_index* idx, const Workspace* w, tds_result* out, uint64_t win_lo,
+                   uint32_t item_begin, uint32_t item_end, uint32_t* item_count) {
+    DistArgs A;
+    A.I = view_of(idx);
+    A.qp = w->qp;
+    A.qsorted = w->qsorted;
+    A.qf = w->qf;
+    A.binfo = w->binfo;
+    A.item_bucket = w->item_bucket;
+    A.desc = w->desc;
+    A.hdr = w->hdr;
+    A.req = w->req;
+    A.rc = w->req_ctr;
+    A.out = out;
+    A.win_lo = win_lo;
+    A.item_begin = item_begin;
+    A.item_end = item_end;
+    A.item_count = item_count;
+    return A;
+}
+
+int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_t s) {
+    const uint32_t blocks = std::max(1u, ceil_div(grid_waves, kWavesPerBlock));
+    if (prec == TDS_PREC_FP64)
+        hipLaunchKernelGGL(k_distance<TDS_PREC_FP64>, dim3(blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL(k_distance<TDS_PREC_FP32_RECHECK>, dim3(blocks), dim3(kBlock), 0, s, A);
+    TDS_HIP(hipGetLastError());
+    return TDS_OK;
+}
+
+// The whole search for the batch described by w->desc / w->req, as a fixed
+// sequence of fixed-shape launches (capturable in a graph): clear, prepare
+// queries, bucket table, ordering, item table, distance kernel over every
+// item.  q_grid and r_cap are the capacities the launches are shaped for.
+int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, size_t q_grid,
+                     uint32_t r_cap, int prec, uint32_t chunk, uint32_t grid_waves,
+                     tds_result* out, uint32_t* item_count, hipStream_t s, hipEvent_t ev_begin,
+                     hipEvent_t ev_end) {
+    const IndexView I = view_of(idx);
+    const uint32_t shift = bucket_shift(idx->m);
+    const uint32_t nb = bucket_count(idx->m);
+    const uint32_t zn = std::max(nb, r_cap);
+    hipLaunchKernelGGL(k_zero, dim3(ceil_div(zn, kBlock)), dim3(kBlock), 0, s, w->hdr, w->b_count,
+                       w->b_lo, w->b_hi, nb, w->req_ctr, r_cap);
+    const uint32_t qblocks = std::max(1u, ceil_div(q_grid, kBlock));
+    hipLaunchKernelGGL(k_qprep, dim3(qblocks), dim3(kBlock), 0, s, Q, w->desc, w->req, I, w->qp,
+                       w->qkey, w->qslot, w->b_count, w->b_hi, shift, w->hdr);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_lo, w->b_hi,
+                       idx->bin_first, idx->min_te, idx->e64, idx->m, shift, nb, chunk, w->b_start,
+                       w->b_item, w->b_nch, w->b_clen, w->binfo, w->hdr);
+    hipLaunchKernelGGL(k_scatter, dim3(qblocks), dim3(kBlock), 0, s, w->desc, w->qkey, w->qslot,
+                       w->b_start, w->qp, w->qsorted, w->qf);
+    hipLaunchKernelGGL(k_item_fill, dim3(nb), dim3(kBlock), 0, s, w->binfo, w->desc,
+                       w->item_bucket, w->hdr);
+    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, 1u), 256)), dim3(256), 0, s,
+                       w->hdr, w->req_ctr, r_cap);
+    TDS_HIP(hipGetLastError());
+    if (ev_begin) TDS_HIP(hipEventRecord(ev_begin, s));
+    TDS_TRY(launch_distance(prec, dist_args(idx, w, out, 0, 0, 0xFFFFFFFFu, item_count), grid_waves,
+                            s));
+    if (ev_end) TDS_HIP(hipEventRecord(ev_end, s));
+    return TDS_OK;
+}
+
+// Re-runs the distance kernel over work items [i0, i1) keeping result
+// positions [win_lo, win_lo + capacity) (incremental processing).
+int enqueue_range(const tds_index* idx, Workspace* w, int prec, uint32_t r_cap, tds_result* out,
+                  uint64_t win_lo, uint32_t i0, uint32_t i1, uint32_t grid_waves, hipStream_t s,
+                  hipEvent_t ev_begin, hipEvent_t ev_end) {
+    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, 1u), 256)), dim3(256), 0, s,
+                       w->hdr, w->req_ctr, r_cap);
+    TDS_HIP(hipGetLastError());
+    if (ev_begin) TDS_HIP(hipEventRecord(ev_begin, s));
+    TDS_TRY(launch_distance(prec, dist_args(idx, w, out, win_lo, i0, i1, nullptr), grid_waves, s));
+    if (ev_end) TDS_HIP(hipEventRecord(ev_end, s));
     return TDS_OK;
 }
 
@@ -942,97 +1075,80 @@ struct WsGuard {
     }
 };
 
-// Device view of the query arrays; host arrays are copied into the staging
-// buffers first.
-int stage_queries(const tds_segments* Q, QueryView* V, hipStream_t s, double** stage_buf,
-                  size_t* stage_cap, uint32_t** traj_buf, size_t* traj_cap) {
-    V->n = Q->n;
-    const double* src[8] = {Q->xs, Q->ys, Q->zs, Q->ts, Q->xe, Q->ye, Q->ze, Q->te};
-    if (Q->on_device) {
-        for (int k = 0; k < 8; ++k) V->a[k] = src[k];
-        V->traj = Q->traj_id;
-        return TDS_OK;
-    }
-    TDS_TRY(grow(stage_buf, stage_cap, 8 * (size_t)Q->n));
-    for (int k = 0; k < 8; ++k) {
-        TDS_HIP(hipMemcpyAsync(*stage_buf + k * Q->n, src[k], Q->n * sizeof(double),
-                               hipMemcpyHostToDevice, s));
-        V->a[k] = *stage_buf + k * Q->n;
-    }
-    V->traj = nullptr;
-    if (Q->traj_id) {
-        TDS_TRY(grow(traj_buf, traj_cap, (size_t)Q->n));
-        TDS_HIP(hipMemcpyAsync(*traj_buf, Q->traj_id, Q->n * sizeof(uint32_t),
-                               hipMemcpyHostToDevice, s));
-        V->traj = *traj_buf;
-    }
+bool valid_window(double d, double t0, double t1) {
+    return d >= 0.0 && !std::isinf(d) && t0 < t1;
+}
+
+// Sizes the item table for the batch: from the bound when it is small enough,
+// else from the exact count after the preparation launches (one extra sync).
+int reserve_items(const tds_index* idx, Workspace* w, uint64_t nq, uint32_t chunk,
+                  uint64_t* cap_out) {
+    const uint64_t bound = item_bound(nq, bucket_count(idx->m), idx->n, chunk);
+    const uint64_t cap = std::min<uint64_t>(bound, kMaxItemTable);
+    TDS_TRY(grow(&w->item_bucket, &w->item_bucket_cap, std::max<size_t>(cap, 1)));
+    TDS_TRY(grow(&w->item_count, &w->item_cap, std::max<size_t>(cap, 1)));
+    *cap_out = cap;
     return TDS_OK;
 }
 
-uint32_t bucket_shift(uint32_t m) {
-    uint32_t shift = 0;
-    while ((((uint64_t)m * kSpanClasses - 1) >> shift) >= kMaxBuckets) ++shift;
-    return shift;
-}
-
-// Stage-1 launches: clear, prepare queries, bucket table, ordering.
-int enqueue_prepare(const tds_index* idx, Workspace* w, const QueryView& Q, uint32_t nreq,
-                    uint32_t chunk, hipStream_t s, uint32_t* nb_out) {
-    const IndexView I = view_of(idx);
-    const uint32_t shift = bucket_shift(idx->m);
-    const uint32_t nb = (uint32_t)((((uint64_t)idx->m * kSpanClasses - 1) >> shift) + 1);
-    const uint32_t zn = std::max(nb, nreq);
-    hipLaunchKernelGGL(k_zero, dim3(ceil_div(zn, kBlock)), dim3(kBlock), 0, s, w->hdr, w->b_count,
-                       w->b_lo, w->b_hi, nb, w->req_ctr, nreq);
-    if (Q.n) {
-        hipLaunchKernelGGL(k_qprep, dim3(ceil_div(Q.n, kBlock)), dim3(kBlock), 0, s, Q, w->req,
-                           nreq, I, w->qp, w->qkey, w->qslot, w->b_count, w->b_hi, shift, w->hdr);
+// Runs the pipeline once for the batch already described in w (desc, req),
+// growing the item table and re-running if the bound was too small.
+int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t nreq, int prec,
+              uint32_t chunk, uint32_t grid_waves, tds_result* out, hipStream_t s,
+              tds_stats* st, SearchHeader* h_out) {
+    uint64_t cap = 0;
+    TDS_TRY(reserve_items(idx, w, V.n, chunk, &cap));
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        w->desc_host->nq = V.n;
+        w->desc_host->nreq = nreq;
+        w->desc_host->item_cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
+        TDS_HIP(hipMemcpyAsync(w->desc, w->desc_host, sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+        TDS_TRY(enqueue_pipeline(idx, w, V, V.n, nreq, prec, chunk, grid_waves, out, w->item_count, s,
+                                 w->ev0, w->ev1));
+        TDS_HIP(hipMemcpyAsync(w->hdr_host, w->hdr, sizeof(SearchHeader), hipMemcpyDeviceToHost, s));
+        TDS_HIP(hipStreamSynchronize(s));
+        *h_out = *w->hdr_host;
+        float ms = 0.f;
+        TDS_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+        st->kernel_ms += ms;
+        st->passes += 1;
+        if (h_out->err & 1u) return TDS_E_INVALID;
+        if (!(h_out->err & 2u)) return TDS_OK;
+        // the item table was too small: size it exactly and run again
+        cap = h_out->n_items;
+        TDS_TRY(grow(&w->item_bucket, &w->item_bucket_cap, std::max<size_t>(cap, 1)));
+        TDS_TRY(grow(&w->item_count, &w->item_cap, std::max<size_t>(cap, 1)));
     }
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_lo, w->b_hi,
-                       idx->bin_first, idx->min_te, idx->e64, idx->m, shift, nb, chunk, w->b_start, w->b_item, w->b_nch,
-                       w->b_clen, w->binfo, w->hdr);
-    if (Q.n) {
-        hipLaunchKernelGGL(k_scatter, dim3(ceil_div(Q.n, kBlock)), dim3(kBlock), 0, s, Q.n,
-                           w->qkey, w->qslot, w->b_start, w->qp, w->qsorted, w->qf);
-    }
-    TDS_HIP(hipGetLastError());
-    *nb_out = nb;
-    return TDS_OK;
-}
-
-int enqueue_distance(const tds_index* idx, Workspace* w, int prec, uint32_t nreq,
-                     tds_result* out, uint64_t win_lo, uint32_t item_begin, uint32_t item_end,
-                     uint32_t* item_count, uint32_t grid_waves, hipStream_t s,
-                     hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr) {
-    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(nreq, 1u), 256)), dim3(256), 0, s,
-                       w->hdr, w->req_ctr, nreq);
-    if (ev_begin) TDS_HIP(hipEventRecord(ev_begin, s));
-    DistArgs A;
-    A.I = view_of(idx);
-    A.qp = w->qp;
-    A.qsorted = w->qsorted;
-    A.qf = w->qf;
-    A.binfo = w->binfo;
-    A.item_bucket = w->item_bucket;
-    A.hdr = w->hdr;
-    A.req = w->req;
-    A.rc = w->req_ctr;
-    A.out = out;
-    A.win_lo = win_lo;
-    A.item_begin = item_begin;
-    A.item_end = item_end;
-    A.item_count = item_count;
-    const uint32_t blocks = std::max(1u, ceil_div(grid_waves, kWavesPerBlock));
-    if (prec == TDS_PREC_FP64)
-        hipLaunchKernelGGL(k_distance<TDS_PREC_FP64>, dim3(blocks), dim3(kBlock), 0, s, A);
-    else
-        hipLaunchKernelGGL(k_distance<TDS_PREC_FP32_RECHECK>, dim3(blocks), dim3(kBlock), 0, s, A);
-    TDS_HIP(hipGetLastError());
-    if (ev_end) TDS_HIP(hipEventRecord(ev_end, s));
-    return TDS_OK;
+    return TDS_E_DEVICE;
 }
 
 }  // namespace
+
+int resolve_config(const tds_search_params* params, PipelineConfig* cfg) {
+    tds_search_params P;
+    tds_search_params_default(&P);
+    if (params) P = *params;
+    cfg->prec = resolve_prec(P.precision);
+    if (cfg->prec < 0) return TDS_E_INVALID;
+    cfg->chunk = resolve_chunk(cfg->prec, P.chunk);
+    cfg->grid_waves = resolve_grid(P.grid_waves);
+    return TDS_OK;
+}
+
+uint64_t item_table_bound(const tds_index* idx, uint64_t nq, uint32_t chunk) {
+    return item_bound(nq, bucket_count(idx->m), idx->n, chunk);
+}
+
+int enqueue_search(const tds_index* idx, Workspace* w, const double* const* qarrays,
+                   const uint32_t* qtraj, size_t q_grid, uint32_t r_cap,
+                   const PipelineConfig& cfg, tds_result* out, hipStream_t s) {
+    QueryView V{};
+    for (int k = 0; k < 8; ++k) V.a[k] = qarrays[k];
+    V.traj = qtraj;
+    V.n = q_grid;
+    return enqueue_pipeline(idx, w, V, q_grid, r_cap, cfg.prec, cfg.chunk, cfg.grid_waves, out,
+                            w->item_count, s, nullptr, nullptr);
+}
 
 int schedule_impl(tds_index* idx, const tds_segments* Q, double t_start, double t_end,
                   uint32_t* lo, uint32_t* hi, hipStream_t s) {
@@ -1048,7 +1164,7 @@ int schedule_impl(tds_index* idx, const tds_segments* Q, double t_start, double 
     int st = TDS_OK;
     QueryView V{};
     do {
-        if ((st = stage_queries(Q, &V, s, &stage, &scap, &tstage, &tcap))) break;
+        if ((st = stage_queries(Q, &V, s, &stage, &scap, &tstage, &tcap, false))) break;
         if ((st = dmalloc(&dlo, nq))) break;
         if ((st = dmalloc(&dhi, nq))) break;
         if ((st = dmalloc(&err, 1))) break;
@@ -1081,15 +1197,15 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     if (!idx || !n_out) return TDS_E_INVALID;
     *n_out = 0;
     TDS_TRY(validate_segments_args(Q));
-    if (!(d >= 0.0) || std::isinf(d)) return TDS_E_INVALID;
-    if (!(t_start < t_end)) return TDS_E_INVALID;
+    if (!valid_window(d, t_start, t_end)) return TDS_E_INVALID;
     if (capacity > 0 && !out) return TDS_E_INVALID;
     tds_search_params P;
     tds_search_params_default(&P);
     if (params) P = *params;
-    int prec = P.precision == TDS_PREC_DEFAULT ? TDS_PREC_FP32_RECHECK : P.precision;
-    if (prec != TDS_PREC_FP64 && prec != TDS_PREC_FP32_RECHECK) return TDS_E_INVALID;
-    const uint32_t chunk = P.chunk ? std::max(P.chunk, 64u) : (prec == TDS_PREC_FP64 ? 512u : 1024u);
+    const int prec = resolve_prec(P.precision);
+    if (prec < 0) return TDS_E_INVALID;
+    const uint32_t chunk = resolve_chunk(prec, P.chunk);
+    const uint32_t grid_waves = resolve_grid(P.grid_waves);
     const bool dev_out = P.out_on_device != 0;
 
     Workspace* w = acquire(idx);
@@ -1097,7 +1213,7 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     WsGuard guard{idx, w};
     TDS_TRY(ws_reserve(w, Q->n, 1));
     QueryView V{};
-    TDS_TRY(stage_queries(Q, &V, s, &w->qstage, &w->stage_cap, &w->qtraj_stage, &w->traj_cap));
+    TDS_TRY(stage_queries(Q, &V, s, &w->qstage, &w->stage_cap, &w->qtraj_stage, &w->traj_cap, false));
 
     // result buffer
     uint64_t dev_cap;
@@ -1120,39 +1236,21 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     R.out_offset = 0;
     R.out_capacity = dev_cap;
     TDS_HIP(hipMemcpyAsync(w->req, &R, sizeof(Request), hipMemcpyHostToDevice, s));
-    uint32_t nb = 0;
-    TDS_TRY(enqueue_prepare(idx, w, V, 1, chunk, s, &nb));
-    TDS_HIP(hipMemcpyAsync(w->hdr_host, w->hdr, sizeof(SearchHeader), hipMemcpyDeviceToHost, s));
-    TDS_HIP(hipStreamSynchronize(s));
-    const SearchHeader h1 = *w->hdr_host;
-    if (h1.err) return TDS_E_INVALID;
-    const uint32_t n_items = h1.n_items;
-    uint32_t grid_waves = P.grid_waves ? P.grid_waves : 256u * 16u;
-    grid_waves = std::max(1u, std::min(grid_waves, n_items));
-    TDS_TRY(grow(&w->item_count, &w->item_cap, std::max<size_t>(n_items, 1)));
-    TDS_TRY(grow(&w->item_bucket, &w->item_bucket_cap, std::max<size_t>(n_items, 1)));
-    if (n_items)
-        hipLaunchKernelGGL(k_item_fill, dim3(nb), dim3(kBlock), 0, s, w->binfo, w->item_bucket);
 
     tds_stats st{};
     st.query_segments = Q->n;
-    st.active_segments = h1.active;
-    st.work_items = n_items;
-    float ms = 0.f;
-    uint64_t total = 0;
-    // pass 1: everything, result window [0, dev_cap)
-    TDS_TRY(enqueue_distance(idx, w, prec, 1, res, 0, 0, n_items, w->item_count, grid_waves, s,
-                             w->ev0, w->ev1));
+    SearchHeader h{};
+    // pass 1: every item, result window [0, dev_cap)
+    TDS_TRY(run_batch(idx, w, V, 1, prec, chunk, grid_waves, res, s, &st, &h));
     ReqCounter rc{};
-    TDS_HIP(hipMemcpyAsync(&rc, w->req_ctr, sizeof(ReqCounter), hipMemcpyDeviceToHost, s));
-    TDS_HIP(hipMemcpyAsync(w->hdr_host, w->hdr, sizeof(SearchHeader), hipMemcpyDeviceToHost, s));
-    TDS_HIP(hipStreamSynchronize(s));
-    TDS_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-    st.kernel_ms += ms;
-    st.passes = 1;
-    total = rc.count;
-    st.candidate_tests = w->hdr_host->tests;
-    st.fp64_evals = w->hdr_host->evals;
+    TDS_HIP(hipMemcpy(&rc, w->req_ctr, sizeof(ReqCounter), hipMemcpyDeviceToHost));
+    const uint32_t n_items = h.n_items;
+    st.active_segments = h.active;
+    st.work_items = n_items;
+    st.candidate_tests = h.tests;
+    st.fp64_evals = h.evals;
+    const uint64_t total = rc.count;
+    float ms = 0.f;
     int status = TDS_OK;
     if (dev_out) {
         status = (total > capacity) ? TDS_E_OVERFLOW : TDS_OK;
@@ -1183,7 +1281,6 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
             while (i1 < n_items && sum + cnt[i1] <= dev_cap) sum += cnt[i1++];
             std::vector<std::pair<uint64_t, uint64_t>> windows;  // (win_lo, expected)
             if (i1 == i0) {
-                // single oversized item
                 i1 = i0 + 1;
                 for (uint64_t wl = 0; wl < cnt[i0]; wl += dev_cap)
                     windows.push_back({wl, std::min<uint64_t>(dev_cap, cnt[i0] - wl)});
@@ -1192,8 +1289,8 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
             }
             for (auto& win : windows) {
                 if (win.second == 0) continue;
-                TDS_TRY(enqueue_distance(idx, w, prec, 1, res, win.first, i0, i1, nullptr,
-                                         std::min(grid_waves, i1 - i0), s, w->ev0, w->ev1));
+                TDS_TRY(enqueue_range(idx, w, prec, 1, res, win.first, i0, i1,
+                                      std::min(grid_waves, i1 - i0), s, w->ev0, w->ev1));
                 TDS_HIP(hipMemcpyAsync(out + written, res, win.second * sizeof(tds_result),
                                        hipMemcpyDeviceToHost, s));
                 TDS_HIP(hipStreamSynchronize(s));
@@ -1207,6 +1304,94 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
         if (written != total) return TDS_E_DEVICE;
     }
     *n_out = total;
+    st.results = total;
+    st.total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
+    if (stats) *stats = st;
+    {
+        std::lock_guard<std::mutex> g(idx->mu);
+        idx->last = st;
+    }
+    return status;
+}
+
+// Checks that the requests tile [0, nq) in order and their output slices fit.
+int validate_requests(const tds_request* reqs, uint32_t nreq, uint64_t nq, uint64_t out_cap) {
+    if (!reqs || nreq == 0) return TDS_E_INVALID;
+    uint64_t next = 0;
+    for (uint32_t r = 0; r < nreq; ++r) {
+        const tds_request& q = reqs[r];
+        if (q.q_begin != next || q.q_count == 0) return TDS_E_INVALID;
+        next += q.q_count;
+        if (!valid_window(q.d, q.t_start, q.t_end)) return TDS_E_INVALID;
+        if (q.out_offset > out_cap || q.out_capacity > out_cap - q.out_offset) return TDS_E_INVALID;
+    }
+    return next == nq ? TDS_OK : TDS_E_INVALID;
+}
+
+int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, uint32_t nreq,
+               tds_result* out, uint64_t out_capacity, uint64_t* counts,
+               const tds_search_params* params, hipStream_t s, tds_stats* stats) {
+    const auto t_begin = std::chrono::steady_clock::now();
+    if (!idx || !counts || (out_capacity && !out)) return TDS_E_INVALID;
+    TDS_TRY(validate_segments_args(Q));
+    TDS_TRY(validate_requests(reqs, nreq, Q->n, out_capacity));
+    tds_search_params P;
+    tds_search_params_default(&P);
+    if (params) P = *params;
+    const int prec = resolve_prec(P.precision);
+    if (prec < 0) return TDS_E_INVALID;
+    const uint32_t chunk = resolve_chunk(prec, P.chunk);
+    const uint32_t grid_waves = resolve_grid(P.grid_waves);
+    const bool dev_out = P.out_on_device != 0;
+
+    Workspace* w = acquire(idx);
+    if (!w) return TDS_E_NOMEM;
+    WsGuard guard{idx, w};
+    TDS_TRY(ws_reserve(w, Q->n, nreq));
+    QueryView V{};
+    TDS_TRY(stage_queries(Q, &V, s, &w->qstage, &w->stage_cap, &w->qtraj_stage, &w->traj_cap, false));
+    tds_result* res = out;
+    if (!dev_out) {
+        TDS_TRY(grow(&w->res, &w->res_cap, (size_t)std::max<uint64_t>(out_capacity, 1)));
+        res = w->res;
+    }
+    std::vector<Request> R(nreq);
+    for (uint32_t r = 0; r < nreq; ++r) {
+        R[r].q_begin = reqs[r].q_begin;
+        R[r].q_count = reqs[r].q_count;
+        R[r].d = reqs[r].d;
+        R[r].t_start = reqs[r].t_start;
+        R[r].t_end = reqs[r].t_end;
+        R[r].out_offset = reqs[r].out_offset;
+        R[r].out_capacity = reqs[r].out_capacity;
+        R[r].pad = 0;
+    }
+    TDS_HIP(hipMemcpyAsync(w->req, R.data(), nreq * sizeof(Request), hipMemcpyHostToDevice, s));
+    tds_stats st{};
+    st.query_segments = Q->n;
+    SearchHeader h{};
+    TDS_TRY(run_batch(idx, w, V, nreq, prec, chunk, grid_waves, res, s, &st, &h));
+    std::vector<ReqCounter> rc(nreq);
+    TDS_HIP(hipMemcpy(rc.data(), w->req_ctr, nreq * sizeof(ReqCounter), hipMemcpyDeviceToHost));
+    int status = TDS_OK;
+    uint64_t total = 0;
+    for (uint32_t r = 0; r < nreq; ++r) {
+        counts[r] = rc[r].count;
+        total += rc[r].count;
+        if (rc[r].count > reqs[r].out_capacity) status = TDS_E_OVERFLOW;
+        if (!dev_out) {
+            const uint64_t k = std::min<uint64_t>(rc[r].count, reqs[r].out_capacity);
+            if (k)
+                TDS_HIP(hipMemcpyAsync(out + reqs[r].out_offset, res + reqs[r].out_offset,
+                                       k * sizeof(tds_result), hipMemcpyDeviceToHost, s));
+        }
+    }
+    TDS_HIP(hipStreamSynchronize(s));
+    st.active_segments = h.active;
+    st.work_items = h.n_items;
+    st.candidate_tests = h.tests;
+    st.fp64_evals = h.evals;
     st.results = total;
     st.total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_begin).count();

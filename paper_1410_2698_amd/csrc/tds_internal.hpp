@@ -96,6 +96,15 @@ struct Request {
     uint64_t pad;
 };
 
+// Sizes of the current batch, in device memory so that a captured graph can
+// be replayed for batches of any size up to the workspace capacities.
+struct alignas(64) BatchDesc {
+    uint64_t nq;        // query segments
+    uint32_t nreq;      // requests
+    uint32_t item_cap;  // capacity of the work-item table
+    uint64_t pad[6];
+};
+
 // Device-side header of one search; zeroed before every search.
 struct alignas(64) SearchHeader {
     uint32_t work_ctr;      // persistent-kernel work counter
@@ -146,6 +155,8 @@ struct Workspace {
     tds_result* res = nullptr;      // device result buffer (host-output mode)
     SearchHeader* hdr = nullptr;
     SearchHeader* hdr_host = nullptr;  // pinned mirror
+    BatchDesc* desc = nullptr;
+    BatchDesc* desc_host = nullptr;    // pinned staging of the descriptor
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     ~Workspace();
 };
@@ -174,6 +185,26 @@ struct tds_index {
 };
 
 namespace tds {
+
+// Makes a device current for the duration of a call (restores the caller's).
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            (void)hipGetLastError();
+            ok = false;
+            return;
+        }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) {
+            (void)hipGetLastError();
+            ok = false;
+        }
+    }
+    ~DeviceGuard() {
+        if (ok && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 // Error propagation for HIP calls inside functions returning a TDS status.
 #define TDS_HIP(call)                                        \
@@ -247,6 +278,32 @@ struct SegView {
 };
 
 int validate_segments_args(const tds_segments* S);
+
+// Workspace set-up and growth (search.hip).
+int ws_init(Workspace* w);
+int ws_reserve(Workspace* w, size_t nq, size_t nreq);
+
+// Batched search and the graph-replaying batcher (search.hip, batch.hip).
+int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, uint32_t nreq,
+               tds_result* out, uint64_t out_capacity, uint64_t* counts,
+               const tds_search_params* params, hipStream_t s, tds_stats* stats);
+int validate_requests(const tds_request* reqs, uint32_t nreq, uint64_t nq, uint64_t out_cap);
+
+// Pieces of the search pipeline used by the batcher (search.hip).
+struct PipelineConfig {
+    int prec;
+    uint32_t chunk;
+    uint32_t grid_waves;
+};
+int resolve_config(const tds_search_params* params, PipelineConfig* cfg);
+uint64_t item_table_bound(const tds_index* idx, uint64_t nq, uint32_t chunk);
+// Enqueues the fixed-shape launch sequence for the batch described by the
+// workspace's descriptor and requests; query arrays at qarrays[0..7] (stride
+// q_grid doubles apart is not required: any device pointers), traj may be
+// nullptr.
+int enqueue_search(const tds_index* idx, Workspace* w, const double* const* qarrays,
+                   const uint32_t* qtraj, size_t q_grid, uint32_t r_cap,
+                   const PipelineConfig& cfg, tds_result* out, hipStream_t s);
 
 // Search implementation (search.hip).
 int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,

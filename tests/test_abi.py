@@ -76,7 +76,8 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {
         "tds_segments": _lib.tds_segments, "tds_build_params": _lib.tds_build_params,
         "tds_search_params": _lib.tds_search_params, "tds_stats": _lib.tds_stats,
-        "tds_index_info": _lib.tds_index_info,
+        "tds_index_info": _lib.tds_index_info, "tds_request": _lib.tds_request,
+        "tds_server_params": _lib.tds_server_params, "tds_server_stats": _lib.tds_server_stats,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tds.h"', "int main(void){"]
     for name, cls in structs.items():

@@ -1,0 +1,119 @@
+"""GPU tests of the batched forms: tds_search_batch, the graph-replaying
+batcher and the serving loop.  Every request's records must equal the
+oracle's for that request (same set, endpoints within 1e-9 relative) and be
+bit-identical to the same request searched on its own."""
+import numpy as np
+import pytest
+
+import oracle
+import trajgen
+
+torch = pytest.importorskip("torch")
+import paper_1410_2698_amd as tds  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    w = trajgen.uniform1m(0.05, n_pts=81)
+    idx = tds.Index(w.D)
+    stream = trajgen.request_stream(48, n_pts=81, seed=77)
+    # distances scaled up for the thinner database (125 trajectories)
+    reqs = [(r.Q, r.d * 6.0, r.t_start, r.t_end) for r in stream]
+    yield w, idx, reqs
+    idx.close()
+
+
+def key_sorted(r):
+    return tds.sort_records(r).tobytes()
+
+
+def check_oracle(got, Q, D, d, t0, t1):
+    want = oracle.sort_results(oracle.search(Q, D, d, t0, t1))
+    got = tds.sort_records(got)
+    assert got.size == want.size
+    for f in ("q_seg", "e_seg", "q_traj", "e_traj"):
+        assert np.array_equal(got[f], want[f])
+    for f in ("t_lo", "t_hi"):
+        assert np.all(np.abs(got[f] - want[f]) <= 1e-9 * np.maximum(1.0, np.abs(want[f])))
+    return want.size
+
+
+def test_batch_matches_oracle_and_alone(setup):
+    w, idx, reqs = setup
+    out = idx.search_batch(reqs)
+    assert len(out) == len(reqs)
+    total = 0
+    for (Q, d, t0, t1), got in zip(reqs, out):
+        total += check_oracle(got, Q, w.D, d, t0, t1)
+        alone = idx.search(Q, d, t0, t1)
+        assert key_sorted(alone) == key_sorted(got)
+    assert total > 100
+    # the FP64 form gives the same records
+    out64 = idx.search_batch(reqs, precision="fp64")
+    for a, b in zip(out, out64):
+        assert key_sorted(a) == key_sorted(b)
+
+
+def test_batch_overflow_is_per_request(setup):
+    w, idx, reqs = setup
+    b = tds.Batcher(idx, max_segments=20000, max_requests=64, result_capacity=64 * 2)
+    recs, counts, status = b.run(reqs, slice_capacity=2)
+    want = [len(oracle.search(Q, w.D, d, t0, t1)) for (Q, d, t0, t1) in reqs]
+    assert counts == want
+    assert (status == tds.TDS_E_OVERFLOW) == any(c > 2 for c in want)
+    for c, r in zip(counts, recs):
+        assert r.size == min(c, 2)
+    b.close()
+
+
+def test_batcher_graph_replays_match_eager(setup):
+    w, idx, reqs = setup
+    b = tds.Batcher(idx, max_segments=20000, max_requests=64, result_capacity=64 * 4096)
+    subsets = [reqs[:5], reqs[5:30], reqs[30:31], reqs[10:48], reqs[:48]]
+    for i, sub in enumerate(subsets):
+        eager = idx.search_batch(sub)
+        # unrelated eager work and a synchronisation between replays
+        x = torch.randn(1 << 16, device="cuda")
+        float(x.sum())
+        torch.cuda.synchronize()
+        got, counts, status = b.run(sub, slice_capacity=4096)
+        assert status == tds.TDS_OK
+        assert b.replays == i + 1
+        for e, g in zip(eager, got):
+            assert key_sorted(e) == key_sorted(g)
+    # fp64 batcher
+    b64 = tds.Batcher(idx, max_segments=20000, max_requests=64, result_capacity=64 * 4096,
+                      precision="fp64")
+    got, _, _ = b64.run(reqs[:20], slice_capacity=4096)
+    for e, g in zip(idx.search_batch(reqs[:20]), got):
+        assert key_sorted(e) == key_sorted(g)
+    b.close()
+    b64.close()
+
+
+def test_server_alone_vs_mix(setup):
+    w, idx, reqs = setup
+    srv = tds.Server(idx, max_batch_segments=20000, max_batch_requests=16, slots=2,
+                     result_capacity=1 << 16, default_reserve=4)
+    alone = []
+    for Q, d, t0, t1 in reqs:
+        t = srv.submit(Q, d, t0, t1)
+        recs, lat = srv.wait(t)
+        assert lat > 0
+        alone.append(recs)
+    tickets = [srv.submit(Q, d, t0, t1) for Q, d, t0, t1 in reqs]
+    mixed = [srv.wait(t)[0] for t in tickets]
+    st = srv.stats()
+    srv.close()
+    for (Q, d, t0, t1), a, m in zip(reqs, alone, mixed):
+        assert key_sorted(a) == key_sorted(m)
+    for i in range(0, len(reqs), 7):
+        Q, d, t0, t1 = reqs[i]
+        check_oracle(mixed[i], Q, w.D, d, t0, t1)
+    assert st["completed"] == 2 * len(reqs) and st["failed"] == 0
+    assert st["requeued"] > 0             # small reservations forced exact re-runs
+    assert st["max_batch_requests_seen"] > 1  # requests shared batches
+    assert st["batches"] < 2 * len(reqs) + st["requeued"]

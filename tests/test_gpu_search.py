@@ -373,3 +373,23 @@ def test_full_size_sampled(cfg, ds, n_traj):
         compare(got[mask], want, f"{cfg} d={d}")
         print(f"{cfg} d={d}: {got.size} records total, stats {idx.last_stats}")
     idx.close()
+
+
+def test_galaxy_full_database_sampled_queries():
+    """The merger-shaped database at full size (2 x 100,000 Plummer particles,
+    20 snapshots: 3.8M segments); a sample of the query particles against the
+    oracle, both forms."""
+    w = trajgen.galaxy()
+    assert len(w.D) == 3_800_000
+    idx = build(w.D)
+    sl = w.query_traj_slices()
+    pick = np.linspace(0, len(sl) - 1, 6).astype(int)
+    qsel = np.concatenate([np.arange(*sl[i]) for i in pick])
+    sub = w.Q.take(qsel)
+    want = oracle.search(sub, w.D, 0.5, *w.window)
+    assert len(want) > 1000
+    for prec in ("fp32", "fp64"):
+        got = idx.search(sub, 0.5, *w.window, precision=prec)
+        compare(got, want, f"galaxy {prec}")
+    print(f"galaxy sample: {len(want)} records, stats {idx.last_stats}")
+    idx.close()
