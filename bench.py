@@ -169,9 +169,7 @@ def main():
     t0, t1 = w.window
     tuned = {"num_bins": args.num_bins, "chunk": args.chunk, "grid_waves": args.grid_waves}
     if not args.no_tune and not (args.chunk or args.grid_waves or args.num_bins):
-        sl = w.query_traj_slices()
-        sample = w.Q.take(np.arange(sl[0][0], sl[99][1]))  # 100 of 500 query trajectories
-        best = autotune.tune(w.D, sample, ds, w.window, cache=None)
+        best = autotune.tune(w.D, w.Q, ds, w.window, cache=None)
         tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves")}
     idx = tds.Index(w.D, num_bins=tuned["num_bins"])
     Qt = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in w.Q.arrays().items()
