@@ -6,8 +6,9 @@ batch): the random-uniform 1M database (2,500 trajectories x 401 timesteps =
 query set of 500 query trajectories (200,000 query segments) over [0, 400],
 searched at d = 1, 5 and 25 (three searches per step), FP32 bulk filter with
 FP64 recheck, index and queries resident in HBM, results written to a device
-buffer.  Launch parameters (bin count, chunk, grid) come from the autotuner,
-run before the timed region.
+buffer.  Launch parameters (bin count, chunk, grid) are the library defaults
+(chosen by sweeps on this workload); --tune runs the autotuner on the full
+workload before the timed region instead.
 
 value = strictly time-overlapping (query, entry) segment pairs resolved per
 second (index independent: every such pair is decided exactly).
@@ -20,7 +21,7 @@ through the serving loop) and the plain form (FP64 canonical test of every
 candidate, one request per call, host memory in and out) on the same stream,
 each with p50/p99 latency, and the oracle timed on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serve]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serve] [--tune]
 """
 from __future__ import annotations
 
@@ -136,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="autotune before timing")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--cpu-traj", type=int, default=500, help="query trajectories in the oracle sample")
     ap.add_argument("--chunk", type=int, default=0)
@@ -168,7 +169,7 @@ def main():
     ds = w.ds
     t0, t1 = w.window
     tuned = {"num_bins": args.num_bins, "chunk": args.chunk, "grid_waves": args.grid_waves}
-    if not args.no_tune and not (args.chunk or args.grid_waves or args.num_bins):
+    if args.tune and not (args.chunk or args.grid_waves or args.num_bins):
         best = autotune.tune(w.D, w.Q, ds, w.window, cache=None)
         tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves")}
     idx = tds.Index(w.D, num_bins=tuned["num_bins"])
@@ -184,10 +185,10 @@ def main():
     cap = max(counts.values()) + 1
     out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
 
-    kern_ms, tests, evals, launches = 0.0, 0, 0, 0
+    kern_ms, tests, evals, launches, ftests, btests = 0.0, 0, 0, 0, 0, 0
 
     def step(record):
-        nonlocal kern_ms, tests, evals, launches
+        nonlocal kern_ms, tests, evals, launches, ftests, btests
         for d in ds:
             st, n, s = idx.search_raw(Qt, d, t0, t1, out_ptr=out.data_ptr(), capacity=cap,
                                       out_on_device=True, chunk=tuned["chunk"],
@@ -199,6 +200,8 @@ def main():
                 tests += s["candidate_tests"]
                 evals += s["fp64_evals"]
                 launches += s["passes"]
+                ftests += s["filter_tests"]
+                btests += s["block_tests"]
 
     for _ in range(args.warmup):
         step(False)
@@ -224,6 +227,9 @@ def main():
     extra = {"queries_per_s": round(n_queries * args.steps / elapsed, 1),
              "candidate_tests_per_kernel_s": round(tests / (kern_ms * 1e-3), 1) if kern_ms else None,
              "fp64_recheck_fraction": round(evals / max(tests, 1), 8),
+             "filter_tests_per_launch": int(ftests / max(launches, 1)),
+             "block_tests_per_launch": int(btests / max(launches, 1)),
+             "layout": {1: "temporal", 2: "spatial"}.get(idx.info()["layout"]),
              "fp32_endpoint_error": 0.0,
              "results_per_d": {str(d): counts[d] for d in ds},
              "overlap_pairs_per_search": pairs, "tuned": tuned,

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define TDS_ABI_VERSION 1u
+#define TDS_ABI_VERSION 2u
 
 /* Status codes. */
 enum {
@@ -89,13 +89,30 @@ typedef struct tds_segments {
     int32_t reserved;
 } tds_segments;
 
+/* Order of the entries inside each temporal bin. */
+enum {
+    /* Library default (currently TDS_LAYOUT_SPATIAL). */
+    TDS_LAYOUT_DEFAULT = 0,
+    /* Temporal index of Sec. 4.2.1 only: entries sorted by t_start. */
+    TDS_LAYOUT_TEMPORAL = 1,
+    /* Spatial subdivision of every temporal bin (the idea of the
+       spatiotemporal index, Sec. 4.3): inside a bin, entries are ordered by
+       the Morton code of their bounding-sphere centre on a 1024^3 grid over
+       the data's extent, and every aligned block of 64 entries carries a
+       bounding box, against which the FP32 form tests each query before it
+       tests the block's entries.  Bins, candidate ranges and results are
+       the same as with TDS_LAYOUT_TEMPORAL. */
+    TDS_LAYOUT_SPATIAL = 2
+};
+
 /* Index parameters; a NULL pointer or 0 fields select defaults. */
 typedef struct tds_build_params {
     /* Number m of temporal bins (Sec. 4.2.1).  0 = auto: the full temporal
        extent divided by the mean segment duration, rounded, clamped to
        [1, 65535]. */
     uint32_t num_bins;
-    uint32_t reserved[7];
+    uint32_t layout; /* TDS_LAYOUT_* */
+    uint32_t reserved[6];
 } tds_build_params;
 
 /* One result record (32 bytes): the interaction of query segment q_seg with
@@ -128,13 +145,16 @@ typedef struct tds_stats {
     uint64_t query_segments;  /* query segments given */
     uint64_t active_segments; /* with a non-empty window and candidate range */
     uint64_t work_items;      /* (query group, candidate chunk) items */
-    uint64_t candidate_tests; /* (query, entry) pairs tested by the distance kernel */
+    uint64_t candidate_tests; /* (query, entry) pairs in the candidate ranges */
     uint64_t fp64_evals;      /* pairs evaluated by the canonical FP64 code */
     uint64_t results;         /* result records found (may exceed the capacity) */
     uint32_t passes;          /* distance-kernel launches (> 1: incremental) */
     uint32_t reserved;
     double kernel_ms;         /* distance kernel(s), measured with HIP events */
     double total_ms;          /* whole call, host wall clock */
+    uint64_t filter_tests;    /* pairs put through the FP32 filter (FP32 form) or the
+                                 FP64 predicate (plain form) */
+    uint64_t block_tests;     /* (query, 64-entry block) bounding-box tests */
 } tds_stats;
 
 /* Index description. */
@@ -146,6 +166,8 @@ typedef struct tds_index_info {
     double t_max;       /* max t_end over D */
     double bin_width;   /* (t_max - t_min) / m */
     uint64_t device_bytes;
+    uint32_t layout;    /* TDS_LAYOUT_TEMPORAL or TDS_LAYOUT_SPATIAL */
+    uint32_t reserved;
 } tds_index_info;
 
 typedef struct tds_index tds_index;
@@ -157,10 +179,12 @@ uint32_t tds_abi_version(void);
 const char* tds_status_str(int status);
 
 /*
- * Build the temporal index of D on the current HIP device (Sec. 4.2.1): sort
- * the entries by t_start (ties keep input order), assign them to m bins of
- * equal width over [t_min, t_max], and record per bin the first sorted entry
- * and the data extents used to compute candidate ranges.  The entries are
+ * Build the temporal index of D on the current HIP device (Sec. 4.2.1): assign
+ * the entries to m bins of equal width over [t_min, t_max] by t_start, store
+ * them bin after bin (inside a bin by t_start, ties in input order, or, with
+ * the spatial layout, by spatial cell, ties in input order), and record per
+ * bin its first entry and the data extents used to compute candidate ranges.
+ * Errors also: TDS_E_INVALID for an unknown layout.  The entries are
  * copied; the index owns all its device memory until tds_index_destroy.
  * Waits for `stream` before returning.
  * Errors: TDS_E_INVALID (NULL pointers, n == 0, n >= 2^32 - 1, a non-finite
@@ -178,7 +202,7 @@ int tds_index_info_get(const tds_index* index, tds_index_info* info);
 
 /*
  * Copy index tables to host memory (for inspection and tests); any output
- * may be NULL.  order[n]: input position of the i-th entry in t_start order.
+ * may be NULL.  order[n]: input position of the i-th entry in index order.
  * bin_first[m + 1]: sorted position of the first entry of bin j
  * (bin_first[m] = n; bin j holds [bin_first[j], bin_first[j+1])).
  * min_ts[m], max_te[m]: data extents of bin j (+inf / -inf when empty).
@@ -192,7 +216,7 @@ int tds_index_export(const tds_index* index, uint32_t* order, uint32_t* bin_firs
  * Candidate range (the schedule S of Sec. 4.2.2) of each query segment: the
  * contiguous span E_k = [lo[k], hi[k]) of sorted entry positions from the
  * first entry of the first bin whose running max t_end exceeds a_q to the last
- * entry of the last non-empty bin whose first entry has t_start < b_q, where
+ * entry of the last non-empty bin whose smallest t_start is below b_q, where
  * [a_q, b_q] is the query segment clipped to [t_start, t_end].  Every entry that strictly overlaps the clipped query in
  * time lies in the span.  Empty windows or spans give lo = hi = 0.  lo and hi
  * are host arrays of Q->n elements.  Waits for `stream`.

@@ -90,14 +90,21 @@ def _segments(S) -> _SegHandle:
     return _SegHandle(st, keep)
 
 
-class Index:
-    """Temporal index of an entry-segment database, resident in HBM (Sec. 4.2.1)."""
+LAYOUTS = {"default": _lib.TDS_LAYOUT_DEFAULT, "temporal": _lib.TDS_LAYOUT_TEMPORAL,
+           "spatial": _lib.TDS_LAYOUT_SPATIAL}
 
-    def __init__(self, D, num_bins: int = 0):
+
+class Index:
+    """Temporal index of an entry-segment database, resident in HBM (Sec. 4.2.1);
+    layout "spatial" (the default) also orders every bin by space and keeps a
+    bounding box per 64-entry block (the subdivision idea of Sec. 4.3)."""
+
+    def __init__(self, D, num_bins: int = 0, layout: str = "default"):
         lib = load()
         h = _segments(D)
         p = _lib.tds_build_params()
         p.num_bins = int(num_bins)
+        p.layout = LAYOUTS[layout]
         out = ctypes.c_void_p()
         check(lib.tds_build_index(ctypes.byref(h.struct), ctypes.byref(p), _current_stream(),
                                   ctypes.byref(out)), "tds_build_index")

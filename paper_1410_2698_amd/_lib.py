@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libtds.so")
 
 TDS_OK, TDS_E_INVALID, TDS_E_OVERFLOW, TDS_E_NOMEM, TDS_E_DEVICE, TDS_E_BUSY = range(6)
 TDS_PREC_DEFAULT, TDS_PREC_FP64, TDS_PREC_FP32_RECHECK = 0, 1, 2
+TDS_LAYOUT_DEFAULT, TDS_LAYOUT_TEMPORAL, TDS_LAYOUT_SPATIAL = 0, 1, 2
 
 c_dbl_p = ctypes.POINTER(ctypes.c_double)
 c_u32_p = ctypes.POINTER(ctypes.c_uint32)
@@ -27,7 +28,8 @@ class tds_segments(ctypes.Structure):
 
 
 class tds_build_params(ctypes.Structure):
-    _fields_ = [("num_bins", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
+    _fields_ = [("num_bins", ctypes.c_uint32), ("layout", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 6)]
 
 
 class tds_search_params(ctypes.Structure):
@@ -41,7 +43,8 @@ class tds_stats(ctypes.Structure):
                 ("work_items", ctypes.c_uint64), ("candidate_tests", ctypes.c_uint64),
                 ("fp64_evals", ctypes.c_uint64), ("results", ctypes.c_uint64),
                 ("passes", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("filter_tests", ctypes.c_uint64), ("block_tests", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -50,7 +53,8 @@ class tds_stats(ctypes.Structure):
 class tds_index_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("num_bins", ctypes.c_uint32), ("device", ctypes.c_uint32),
                 ("t_min", ctypes.c_double), ("t_max", ctypes.c_double),
-                ("bin_width", ctypes.c_double), ("device_bytes", ctypes.c_uint64)]
+                ("bin_width", ctypes.c_double), ("device_bytes", ctypes.c_uint64),
+                ("layout", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class tds_request(ctypes.Structure):

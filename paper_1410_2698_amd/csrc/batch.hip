@@ -178,6 +178,8 @@ int Batcher::finish(uint64_t* counts, tds_stats* stats, bool* table_overflow) {
         st.active_segments = h.active;
         st.work_items = h.n_items;
         st.candidate_tests = h.tests;
+        st.filter_tests = h.ftests;
+        st.block_tests = h.btests;
         st.fp64_evals = h.evals;
         st.results = total;
         st.passes = 1;

@@ -52,6 +52,8 @@ int tds_index_info_get(const tds_index* index, tds_index_info* info) {
     info->t_max = index->t_max;
     info->bin_width = index->bw;
     info->device_bytes = index->device_bytes;
+    info->layout = index->layout;
+    info->reserved = 0;
     return TDS_OK;
 }
 

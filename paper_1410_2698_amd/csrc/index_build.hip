@@ -1,15 +1,22 @@
-// Index build on the GPU: the temporal index of Sec. 4.2.1.
+// Index build on the GPU: the temporal index of Sec. 4.2.1, optionally with
+// every temporal bin subdivided in space (the idea of Sec. 4.3).
 //
 //   k_seg_prep    validate every segment, compute its velocity (IEEE FP64
 //                 division), its FP32 bounding-sphere record, its sort key
 //                 (order-preserving bits of t_start) and per-block partial
-//                 min t_start / max t_end / sum of durations;
-//   radix sort    stable, by t_start (radix_sort.hip);
-//   k_gather      write the sorted AoS records, ids and trajectory ids;
-//   k_bin_first   first sorted position of every bin (boundary detection);
-//   k_bin_stats   per-bin data extents (min t_start, max t_end);
-//   k_bin_cummax  running maximum of max t_end over bins, which makes the
-//                 bins overlapping a query one contiguous, bisectable span.
+//                 min t_start / max t_end / sum of durations / extent of the
+//                 sphere centres;
+//   k_spatial_key (spatial layout) replace the key by (bin, Morton code of
+//                 the sphere centre on a 1024^3 grid over the centres' extent);
+//   radix sort    stable, by the key (radix_sort.hip);
+//   k_gather      write the ordered AoS records, ids and trajectory ids;
+//   k_bin_first   first position of every bin (boundary detection);
+//   k_bin_stats   per-bin data extents (min/max t_start, min/max t_end);
+//   k_bin_scan    running maximum of max t_end over bins, which makes the
+//                 bins overlapping a query one contiguous, bisectable span,
+//                 and the minimum t_start over the bins from j on;
+//   k_block_box   (spatial layout) bounding box of the spheres of every
+//                 aligned block of 64 entries.
 #include <cmath>
 #include <utility>
 
@@ -29,15 +36,20 @@ __device__ inline uint64_t order_key(double t) {
 
 __device__ inline bool finite(double v) { return isfinite(v); }
 
+// Per-block partials written by k_seg_prep: min t_start, max t_end, sum of
+// durations, then min and max of the sphere centres per axis.
+constexpr int kPart = 9;
+
 __global__ __launch_bounds__(kBT) void k_seg_prep(SegView S, EntryF64* __restrict__ tmp64,
                                                   EntryF32* __restrict__ tmp32,
                                                   uint64_t* __restrict__ keys,
                                                   uint32_t* __restrict__ vals,
                                                   double* __restrict__ part, uint32_t* err) {
-    __shared__ double smin[kBT], smax[kBT], ssum[kBT];
+    __shared__ double sp[kPart][kBT];
     const uint32_t tid = threadIdx.x;
     const uint64_t i = (uint64_t)blockIdx.x * kBT + tid;
-    double lmin = INFINITY, lmax = -INFINITY, lsum = 0.0;
+    double v[kPart] = {INFINITY, -INFINITY, 0.0, INFINITY, -INFINITY,
+                       INFINITY, -INFINITY, INFINITY, -INFINITY};
     if (i < S.n) {
         double xs = S.a[0][i], ys = S.a[1][i], zs = S.a[2][i], ts = S.a[3][i];
         double xe = S.a[4][i], ye = S.a[5][i], ze = S.a[6][i], te = S.a[7][i];
@@ -68,27 +80,28 @@ __global__ __launch_bounds__(kBT) void k_seg_prep(SegView S, EntryF64* __restric
         tmp32[i] = f;
         keys[i] = order_key(ts);
         vals[i] = (uint32_t)i;
-        lmin = ts;
-        lmax = te;
-        lsum = dt;
+        v[0] = ts;
+        v[1] = te;
+        v[2] = dt;
+        v[3] = v[4] = f.cx;
+        v[5] = v[6] = f.cy;
+        v[7] = v[8] = f.cz;
     }
-    smin[tid] = lmin;
-    smax[tid] = lmax;
-    ssum[tid] = lsum;
+    for (int k = 0; k < kPart; ++k) sp[k][tid] = v[k];
     __syncthreads();
     for (uint32_t off = kBT / 2; off > 0; off >>= 1) {
         if (tid < off) {
-            smin[tid] = fmin(smin[tid], smin[tid + off]);
-            smax[tid] = fmax(smax[tid], smax[tid + off]);
-            ssum[tid] = ssum[tid] + ssum[tid + off];
+            sp[0][tid] = fmin(sp[0][tid], sp[0][tid + off]);
+            sp[1][tid] = fmax(sp[1][tid], sp[1][tid + off]);
+            sp[2][tid] = sp[2][tid] + sp[2][tid + off];
+            for (int k = 3; k < kPart; k += 2) {
+                sp[k][tid] = fmin(sp[k][tid], sp[k][tid + off]);
+                sp[k + 1][tid] = fmax(sp[k + 1][tid], sp[k + 1][tid + off]);
+            }
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        part[3 * blockIdx.x + 0] = smin[0];
-        part[3 * blockIdx.x + 1] = smax[0];
-        part[3 * blockIdx.x + 2] = ssum[0];
-    }
+    if (tid < kPart) part[kPart * blockIdx.x + tid] = sp[tid][0];
 }
 
 // Bin of a t_start: floor((ts - t_min) / b) clamped to [0, m-1].
@@ -97,6 +110,40 @@ __device__ inline uint32_t bin_of(double ts, double tmin, double bw, uint32_t m)
     if (!(u > 0.0)) return 0u;
     if (u >= (double)(m - 1)) return m - 1;
     return (uint32_t)u;
+}
+
+// Spreads the low 10 bits of v to every third bit (Morton interleave).
+__device__ inline uint32_t spread3(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ inline uint32_t cell10(float c, float lo, float scale) {
+    const float u = (c - lo) * scale;
+    if (!(u > 0.f)) return 0u;
+    if (u >= 1023.f) return 1023u;
+    return (uint32_t)u;
+}
+
+// Spatial layout key: bin in the high bits, then the Morton code of the
+// sphere centre.  Only the order inside a bin depends on the cell, so the
+// bins, and every table derived from them, are those of the temporal layout.
+__global__ __launch_bounds__(kBT) void k_spatial_key(uint64_t n, const EntryF64* __restrict__ tmp64,
+                                                     const EntryF32* __restrict__ tmp32,
+                                                     double tmin, double bw, uint32_t m,
+                                                     float lx, float ly, float lz, float sx,
+                                                     float sy, float sz,
+                                                     uint64_t* __restrict__ keys) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBT + threadIdx.x;
+    if (i >= n) return;
+    const EntryF32 f = tmp32[i];
+    const uint32_t morton = spread3(cell10(f.cx, lx, sx)) | (spread3(cell10(f.cy, ly, sy)) << 1) |
+                            (spread3(cell10(f.cz, lz, sz)) << 2);
+    keys[i] = ((uint64_t)bin_of(tmp64[i].ts, tmin, bw, m) << 30) | morton;
 }
 
 __global__ __launch_bounds__(kBT) void k_gather(uint64_t n, const uint32_t* __restrict__ perm,
@@ -128,59 +175,104 @@ __global__ __launch_bounds__(kBT) void k_bin_first(uint64_t n, const EntryF64* _
         for (uint32_t k = j + 1; k <= m; ++k) bin_first[k] = (uint32_t)n;
 }
 
-__global__ __launch_bounds__(kBT) void k_bin_stats(uint64_t n, const EntryF64* __restrict__ e64,
+// Per-bin extents: min and max of t_start and of t_end over the bin's
+// entries (+inf / -inf when the bin is empty); one block per bin.
+__global__ __launch_bounds__(kBT) void k_bin_stats(const EntryF64* __restrict__ e64,
                                                    const uint32_t* __restrict__ bin_first,
                                                    double* __restrict__ min_ts,
-                                                   double* __restrict__ max_te,
+                                                   double* __restrict__ max_ts,
                                                    double* __restrict__ min_te,
-                                                   double* __restrict__ lo_ts) {
-    __shared__ double smax[kBT], smin[kBT];
+                                                   double* __restrict__ max_te) {
+    __shared__ double sp[4][kBT];
     const uint32_t j = blockIdx.x;
     const uint32_t f = bin_first[j], e = bin_first[j + 1];
-    double mx = -INFINITY, mn = INFINITY;
+    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
     for (uint32_t i = f + threadIdx.x; i < e; i += kBT) {
-        mx = fmax(mx, e64[i].te);
-        mn = fmin(mn, e64[i].te);
+        const double ts = e64[i].ts, te = e64[i].te;
+        v[0] = fmin(v[0], ts);
+        v[1] = fmax(v[1], ts);
+        v[2] = fmin(v[2], te);
+        v[3] = fmax(v[3], te);
     }
-    smax[threadIdx.x] = mx;
-    smin[threadIdx.x] = mn;
+    for (int k = 0; k < 4; ++k) sp[k][threadIdx.x] = v[k];
     __syncthreads();
     for (uint32_t off = kBT / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) {
-            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
-            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + off]);
+            for (int k = 0; k < 4; k += 2) {
+                sp[k][threadIdx.x] = fmin(sp[k][threadIdx.x], sp[k][threadIdx.x + off]);
+                sp[k + 1][threadIdx.x] = fmax(sp[k + 1][threadIdx.x], sp[k + 1][threadIdx.x + off]);
+            }
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        min_ts[j] = (f < e) ? e64[f].ts : INFINITY;
-        max_te[j] = smax[0];
-        min_te[j] = smin[0];
-        lo_ts[j] = (f < n) ? e64[f].ts : INFINITY;
+        min_ts[j] = sp[0][0];
+        max_ts[j] = sp[1][0];
+        min_te[j] = sp[2][0];
+        max_te[j] = sp[3][0];
     }
 }
 
-// Running maximum over m values with one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_bin_cummax(const double* __restrict__ v,
-                                                     double* __restrict__ out, uint32_t len) {
+// Running extreme over len values with one block of 1024 threads: the
+// maximum of v[0..i] (kMax, forward) or the minimum of v[i..len) (reverse).
+template <bool kMax>
+__global__ __launch_bounds__(1024) void k_bin_scan(const double* __restrict__ v,
+                                                   double* __restrict__ out, uint32_t len) {
     __shared__ double part[1024];
+    const double id = kMax ? -INFINITY : INFINITY;
+    auto op = [](double a, double b) { return kMax ? fmax(a, b) : fmin(a, b); };
+    // element k of the scan order: i = k (forward) or len - 1 - k (reverse)
+    auto at = [&](uint32_t k) { return kMax ? k : len - 1 - k; };
     const uint32_t tid = threadIdx.x;
     const uint32_t per = (len + 1023) / 1024;
     const uint32_t b = tid * per, e = min(len, b + per);
-    double mx = -INFINITY;
-    for (uint32_t i = b; i < e; ++i) mx = fmax(mx, v[i]);
-    part[tid] = mx;
+    double acc = id;
+    for (uint32_t k = b; k < e; ++k) acc = op(acc, v[at(k)]);
+    part[tid] = acc;
     __syncthreads();
     for (uint32_t off = 1; off < 1024; off <<= 1) {
-        double t = (tid >= off) ? part[tid - off] : -INFINITY;
+        const double t = (tid >= off) ? part[tid - off] : id;
         __syncthreads();
-        part[tid] = fmax(part[tid], t);
+        part[tid] = op(part[tid], t);
         __syncthreads();
     }
-    double run = (tid > 0) ? part[tid - 1] : -INFINITY;
-    for (uint32_t i = b; i < e; ++i) {
-        run = fmax(run, v[i]);
-        out[i] = run;
+    double run = (tid > 0) ? part[tid - 1] : id;
+    for (uint32_t k = b; k < e; ++k) {
+        run = op(run, v[at(k)]);
+        out[at(k)] = run;
+    }
+}
+
+// Bounding box of the FP32 spheres of each aligned block of 64 entries, one
+// wave per block (lanes past n contribute nothing).
+__global__ __launch_bounds__(kBT) void k_block_box(uint64_t n, const EntryF32* __restrict__ e32,
+                                                   BlockBox* __restrict__ box, uint32_t nblk) {
+    const uint32_t blk = blockIdx.x * (kBT / kWave) + threadIdx.x / kWave;
+    if (blk >= nblk) return;
+    const uint64_t i = ((uint64_t)blk << kBoxShift) + __lane_id();
+    float v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    if (i < n) {
+        const EntryF32 f = e32[i];
+        v[0] = v[3] = f.cx;
+        v[1] = v[4] = f.cy;
+        v[2] = v[5] = f.cz;
+        v[6] = f.r;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        for (int k = 0; k < 3; ++k) v[k] = fminf(v[k], __shfl_xor(v[k], off));
+        for (int k = 3; k < 7; ++k) v[k] = fmaxf(v[k], __shfl_xor(v[k], off));
+    }
+    if (__lane_id() == 0) {
+        BlockBox b;
+        b.lx = v[0];
+        b.ly = v[1];
+        b.lz = v[2];
+        b.hx = v[3];
+        b.hy = v[4];
+        b.hz = v[5];
+        b.rmax = v[6];
+        b.pad = 0.f;
+        box[blk] = b;
     }
 }
 
@@ -218,6 +310,8 @@ void destroy_index(tds_index* idx) {
     dfree(idx->min_te);
     dfree(idx->cmax_te);
     dfree(idx->lo_ts);
+    dfree(idx->max_ts);
+    dfree(idx->bbox);
     (void)hipSetDevice(cur);
     delete idx;
 }
@@ -230,6 +324,9 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
     const uint64_t n = D->n;
     const uint32_t req_bins = p ? p->num_bins : 0u;
     if (req_bins > kMaxBins) return TDS_E_INVALID;
+    uint32_t layout = p ? p->layout : (uint32_t)TDS_LAYOUT_DEFAULT;
+    if (layout == TDS_LAYOUT_DEFAULT) layout = TDS_LAYOUT_SPATIAL;
+    if (layout != TDS_LAYOUT_TEMPORAL && layout != TDS_LAYOUT_SPATIAL) return TDS_E_INVALID;
 
     int dev = 0;
     TDS_HIP(hipGetDevice(&dev));
@@ -279,7 +376,7 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
     sc.p[6] = vals;
     TDS_TRY(dmalloc(&vals2, n));
     sc.p[7] = vals2;
-    TDS_TRY(dmalloc(&part, 3 * (size_t)nb));
+    TDS_TRY(dmalloc(&part, kPart * (size_t)nb));
     sc.p[8] = part;
     TDS_TRY(dmalloc(&err, 1));
     sc.p[9] = err;
@@ -287,7 +384,7 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
     hipLaunchKernelGGL(k_seg_prep, dim3(nb), dim3(kBT), 0, stream, S, tmp64, tmp32, keys, vals,
                        part, err);
     TDS_HIP(hipGetLastError());
-    std::vector<double> hpart(3 * (size_t)nb);
+    std::vector<double> hpart(kPart * (size_t)nb);
     uint32_t herr = 0;
     TDS_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(double), hipMemcpyDeviceToHost,
                            stream));
@@ -295,10 +392,16 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
     TDS_HIP(hipStreamSynchronize(stream));
     if (herr) return TDS_E_INVALID;
     double tmin = INFINITY, tmax = -INFINITY, dsum = 0.0;
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t b = 0; b < nb; ++b) {
-        tmin = std::fmin(tmin, hpart[3 * b]);
-        tmax = std::fmax(tmax, hpart[3 * b + 1]);
-        dsum += hpart[3 * b + 2];
+        const double* q = &hpart[kPart * (size_t)b];
+        tmin = std::fmin(tmin, q[0]);
+        tmax = std::fmax(tmax, q[1]);
+        dsum += q[2];
+        for (int k = 0; k < 3; ++k) {
+            clo[k] = std::fmin(clo[k], q[3 + 2 * k]);
+            chi[k] = std::fmax(chi[k], q[4 + 2 * k]);
+        }
     }
     uint32_t m = req_bins;
     if (m == 0) {
@@ -310,8 +413,23 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
     }
     const double bw = (tmax - tmin) / (double)m;
 
-    // ---- sort by t_start
-    TDS_TRY(radix_sort_u64(keys, vals, keys2, vals2, (uint32_t)n, 64, stream));
+    // ---- sort: by t_start, or by (bin, spatial cell)
+    int key_bits = 64;
+    if (layout == TDS_LAYOUT_SPATIAL) {
+        float lo[3], sc[3];
+        for (int k = 0; k < 3; ++k) {
+            const double ext = chi[k] - clo[k];
+            lo[k] = (float)clo[k];
+            sc[k] = (ext > 0.0 && std::isfinite(ext)) ? (float)(1024.0 / ext) : 0.f;
+        }
+        hipLaunchKernelGGL(k_spatial_key, dim3(nb), dim3(kBT), 0, stream, n, tmp64, tmp32, tmin,
+                           bw, m, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], keys);
+        TDS_HIP(hipGetLastError());
+        int bin_bits = 0;
+        while ((1u << bin_bits) < m) ++bin_bits;
+        key_bits = 30 + bin_bits;
+    }
+    TDS_TRY(radix_sort_u64(keys, vals, keys2, vals2, (uint32_t)n, key_bits, stream));
 
     // ---- the index object
     tds_index* idx = new (std::nothrow) tds_index();
@@ -322,6 +440,8 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
     idx->t_min = tmin;
     idx->t_max = tmax;
     idx->bw = bw;
+    idx->layout = layout;
+    const uint32_t nblk = ceil_div(n, 1u << kBoxShift);
     int st = TDS_OK;
     do {
         if ((st = dmalloc(&idx->e64, n))) break;
@@ -334,19 +454,28 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
         if ((st = dmalloc(&idx->min_te, m))) break;
         if ((st = dmalloc(&idx->cmax_te, m))) break;
         if ((st = dmalloc(&idx->lo_ts, m))) break;
+        if ((st = dmalloc(&idx->max_ts, m))) break;
+        if (layout == TDS_LAYOUT_SPATIAL && (st = dmalloc(&idx->bbox, nblk))) break;
     } while (0);
     if (st != TDS_OK) {
         destroy_index(idx);
         return st;
     }
-    idx->device_bytes = n * (sizeof(EntryF64) + sizeof(EntryF32) + 8) + (size_t)m * 44 + 4;
+    idx->device_bytes = n * (sizeof(EntryF64) + sizeof(EntryF32) + 8) + (size_t)m * 52 + 4 +
+                        (idx->bbox ? (size_t)nblk * sizeof(BlockBox) : 0);
     hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kBT), 0, stream, n, vals, tmp64, tmp32, S.traj,
                        idx->e64, idx->e32, idx->seg_id, idx->traj);
     hipLaunchKernelGGL(k_bin_first, dim3(nb), dim3(kBT), 0, stream, n, idx->e64, tmin, bw, m,
                        idx->bin_first);
-    hipLaunchKernelGGL(k_bin_stats, dim3(m), dim3(kBT), 0, stream, n, idx->e64, idx->bin_first,
-                       idx->min_ts, idx->max_te, idx->min_te, idx->lo_ts);
-    hipLaunchKernelGGL(k_bin_cummax, dim3(1), dim3(1024), 0, stream, idx->max_te, idx->cmax_te, m);
+    hipLaunchKernelGGL(k_bin_stats, dim3(m), dim3(kBT), 0, stream, idx->e64, idx->bin_first,
+                       idx->min_ts, idx->max_ts, idx->min_te, idx->max_te);
+    hipLaunchKernelGGL(k_bin_scan<true>, dim3(1), dim3(1024), 0, stream, idx->max_te, idx->cmax_te,
+                       m);
+    hipLaunchKernelGGL(k_bin_scan<false>, dim3(1), dim3(1024), 0, stream, idx->min_ts, idx->lo_ts,
+                       m);
+    if (idx->bbox)
+        hipLaunchKernelGGL(k_block_box, dim3(ceil_div(nblk, kBT / kWave)), dim3(kBT), 0, stream, n,
+                           idx->e32, idx->bbox, nblk);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
         destroy_index(idx);
         return TDS_E_DEVICE;

@@ -51,6 +51,7 @@ struct IndexView {
     const uint32_t* bin_first;
     const double* cmax_te;
     const double* lo_ts;
+    const BlockBox* bbox;  // block boxes (spatial layout) or nullptr
     uint32_t n, m;
 };
 
@@ -69,6 +70,7 @@ IndexView view_of(const tds_index* idx) {
     v.bin_first = idx->bin_first;
     v.cmax_te = idx->cmax_te;
     v.lo_ts = idx->lo_ts;
+    v.bbox = idx->bbox;
     v.n = (uint32_t)idx->n;
     v.m = idx->m;
     return v;
@@ -159,8 +161,8 @@ __device__ __forceinline__ bool canon_eval(const QCanon& q, double lx, double ly
 
 // Candidate range E_k of a clipped query [aq, bq] (Sec. 4.2.2): from the
 // first entry of the first bin whose running max t_end exceeds aq (bin j0)
-// to the last entry of the last non-empty bin whose first t_start is below
-// bq (bin j1), as one contiguous span [lo, hi) of sorted positions.
+// to the last entry of the last non-empty bin whose smallest t_start is below
+// bq (bin j1), as one contiguous span [lo, hi) of index positions.
 __device__ inline void cand_range(const IndexView& I, double aq, double bq, uint32_t* lo,
                                   uint32_t* hi, uint32_t* j0o, uint32_t* j1o) {
     // j0 = first j with cmax_te[j] > aq (m if none)
@@ -171,9 +173,9 @@ __device__ inline void cand_range(const IndexView& I, double aq, double bq, uint
         else l = mid + 1;
     }
     const uint32_t j0 = l;
-    // L = number of bins j whose first entry at or after the bin start has
-    // t_start < bq (lo_ts is non-decreasing); entries before bin_first[L]
-    // are exactly those of bins < L
+    // L = number of bins j for which some entry of a bin >= j has
+    // t_start < bq (lo_ts, the minimum t_start over bins >= j, is
+    // non-decreasing); entries before bin_first[L] are those of bins < L
     l = 0;
     h = I.m;
     while (l < h) {
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
                                                       uint32_t* __restrict__ b_hi,
                                                       const uint32_t* __restrict__ bin_first,
                                                       const double* __restrict__ min_te,
-                                                      const EntryF64* __restrict__ e64,
+                                                      const double* __restrict__ max_ts,
                                                       uint32_t m, uint32_t shift,
                                                       uint32_t nb, uint32_t chunk,
                                                       uint32_t* __restrict__ b_start,
@@ -347,9 +349,11 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
             if (shift == 0 && span < kSpanClasses - 1) hi = bin_first[min(j0 + span + 1, m)];
             b_lo[b] = lo;
             b_hi[b] = hi;
-            // balanced chunks of at most `chunk` candidates, whole 64-candidate
-            // tiles where possible, none empty
-            const uint32_t len = hi - lo;
+            // balanced chunks of at most `chunk` candidates counted from the
+            // 64-entry block of lo (chunk c covers [base + c clen, base +
+            // (c + 1) clen) clipped to [lo, hi)), whole 64-candidate tiles
+            // where possible, none empty
+            const uint32_t len = hi - (lo & ~(uint32_t)(kWave - 1));
             const uint32_t n0 = (len + chunk - 1) / chunk;
             clen = (len + n0 - 1) / n0;
             clen = (clen + kWave - 1) / kWave * kWave;
@@ -382,10 +386,13 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
         bi.tmax_ts = INFINITY;
         if (cnt && shift == 0 && (b % kSpanClasses) < kSpanClasses - 1) {
             const uint32_t j0 = b / kSpanClasses, j1 = min(j0 + b % kSpanClasses, m - 1);
-            double mn = INFINITY;
-            for (uint32_t j = j0; j <= j1; ++j) mn = fmin(mn, min_te[j]);
+            double mn = INFINITY, mx = -INFINITY;
+            for (uint32_t j = j0; j <= j1; ++j) {
+                mn = fmin(mn, min_te[j]);
+                mx = fmax(mx, max_ts[j]);
+            }
             bi.tmin_te = mn;
-            bi.tmax_ts = e64[b_hi[b] - 1].ts;  // entries are sorted by t_start
+            bi.tmax_ts = mx;
         }
         bi.lo = b_lo[b];
         bi.hi = b_hi[b];
@@ -473,6 +480,7 @@ struct DistArgs {
 
 struct WaveLDS {
     uint32_t queue[2 * kWave];  // < 64 left over + one pair per lane
+    uint8_t sel[32];            // queries of the group being queued (push_set)
 };
 
 // Evaluates `cnt` <= 64 queued pairs from position `head` (one per lane) with
@@ -565,40 +573,19 @@ __device__ __forceinline__ void drain_full(WaveLDS& L, uint32_t c0, uint32_t qba
     wave_sync();
 }
 
-// FP32 filter of one query against the wave's 64 candidates, as a lane mask.
-// The query record q comes from a scalar load (cx, cy, cz, R, a32, b32, lo,
-// hi), the candidate fields from the lane's registers.  A pair can only be a
-// result if the two bounding spheres come within d (the error margins are
-// folded into R and r) and the outward-rounded time extents overlap
-// strictly.  Each comparison is balloted on its own so that the masks combine
-// in scalar registers.  With kTime false the caller has established that
-// every pair of the tile overlaps in time.
-template <bool kTime>
-__device__ __forceinline__ uint64_t filter32(const f32x8& q, float ecx, float ecy, float ecz,
-                                             float er, float ets, float ete) {
-    const float dx = ecx - q[0], dy = ecy - q[1], dz = ecz - q[2];
-    const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const float R = q[3] + er;
-    const uint64_t m = ballot(s <= R * R);
-    return kTime ? (m & ballot(q[4] < ete) & ballot(ets < q[5])) : m;
-}
-
-__device__ __forceinline__ uint64_t in_range(const f32x8& q, uint32_t cand) {
-    return ballot(cand >= __float_as_uint(q[6])) & ballot(cand < __float_as_uint(q[7]));
-}
-
-__device__ __forceinline__ void push(WaveLDS& L, uint64_t m, uint32_t code, uint32_t& qn) {
-    const uint32_t lane = __lane_id();
-    if ((m >> lane) & 1ull) L.queue[qn + (uint32_t)__popcll(m & lanemask_lt())] = code;
-    qn += (uint32_t)__popcll(m);
-}
-
 struct ItemState {
     uint32_t c0, c1, qbase, nq;
     uint32_t qn, evals, found;
+    uint64_t ftests, btests;
 };
 
-// Pass test of one query against one candidate held in the lane.
+// FP32 filter of one query against the candidate held in the lane.  The query
+// record q comes from a scalar load (cx, cy, cz, R, a32, b32, lo, hi), the
+// candidate fields from the lane's registers.  A pair can only be a result if
+// the two bounding spheres come within d (the error margins are folded into
+// R and r) and the outward-rounded time extents overlap strictly.  With kTime
+// false the caller has established that every pair of the slot overlaps in
+// time; with kUniform true, that every query's candidate range covers it.
 template <bool kUniform, bool kTime>
 __device__ __forceinline__ bool pass32(const f32x8& q, uint32_t cand, float ecx, float ecy,
                                        float ecz, float er, float ets, float ete) {
@@ -612,87 +599,98 @@ __device__ __forceinline__ bool pass32(const f32x8& q, uint32_t cand, float ecx,
     return p;
 }
 
-// Tests queries [j0, j1) (j1 - j0 <= 32) of the group against the tile held in
-// registers and records the outcome as one bit per (query, candidate) in the
-// lane: bit j - j0 of bits[k] for candidate slot k.  Queries are visited from
-// the top down and each outcome is shifted in at the bottom
-// (bits = 2 * bits + pass), so the loop is pure vector arithmetic.
+// Bounding-box test of a query sphere (cx, cy, cz, R) against the block box b
+// (lx, ly, lz, hx, hy, hz, rmax).  It is the filter's own arithmetic with the
+// centre distance replaced by the distance to the box: per axis the gap
+// fl(lo - c) or fl(c - hi) is at most the filter's |fl(c_l - c)| for every
+// centre c_l in the box (rounding to nearest is monotone and odd), squares,
+// FMAs and fl(R + r) are monotone in their operands, and r <= rmax; so
+// whenever the filter passes a pair of the block, this test passes.
+__device__ __forceinline__ bool box_pass(const f32x8& b, float cx, float cy, float cz, float R) {
+    const float gx = fmaxf(fmaxf(b[0] - cx, cx - b[3]), 0.f);
+    const float gy = fmaxf(fmaxf(b[1] - cy, cy - b[4]), 0.f);
+    const float gz = fmaxf(fmaxf(b[2] - cz, cz - b[5]), 0.f);
+    const float s = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+    const float Rr = R + b[6];
+    return s <= Rr * Rr;
+}
+
+// Tests the queries whose bits are set in gm (query 32 h + bit of the group)
+// against the candidate held in the lane.  Queries are taken from the highest
+// down and each outcome is shifted in at the bottom (bits = 2 bits + pass), so
+// bit p of the result belongs to the p-th lowest query of gm.  gm is wave
+// uniform: the walk over its bits and the query loads are scalar.
 template <bool kUniform, bool kTime>
-__device__ __forceinline__ void test_queries(ConstE32 qf, uint32_t j0, uint32_t j1,
-                                             const uint32_t (&cand)[kCpl],
-                                             const float (&ecx)[kCpl], const float (&ecy)[kCpl],
-                                             const float (&ecz)[kCpl], const float (&er)[kCpl],
-                                             const float (&ets)[kCpl], const float (&ete)[kCpl],
-                                             uint32_t (&bits)[kCpl]) {
-#pragma unroll
-    for (int k = 0; k < kCpl; ++k) bits[k] = 0;
-    uint32_t j = j1;
-    for (; j >= j0 + 2; j -= 2) {
-        const f32x8 qa = qf[j - 1], qb = qf[j - 2];
-#pragma unroll
-        for (int k = 0; k < kCpl; ++k) {
-            bits[k] = 2u * bits[k] +
-                      (uint32_t)pass32<kUniform, kTime>(qa, cand[k], ecx[k], ecy[k], ecz[k], er[k],
-                                                        ets[k], ete[k]);
-            bits[k] = 2u * bits[k] +
-                      (uint32_t)pass32<kUniform, kTime>(qb, cand[k], ecx[k], ecy[k], ecz[k], er[k],
-                                                        ets[k], ete[k]);
+__device__ __forceinline__ uint32_t test_set(ConstE32 qh, uint32_t gm, uint32_t cand, float ecx,
+                                             float ecy, float ecz, float er, float ets,
+                                             float ete) {
+    uint32_t bits = 0;
+    while (gm) {
+        const uint32_t ja = 31u - (uint32_t)__builtin_clz(gm);
+        gm ^= 1u << ja;
+        const f32x8 qa = qh[ja];
+        if (gm) {
+            const uint32_t jb = 31u - (uint32_t)__builtin_clz(gm);
+            gm ^= 1u << jb;
+            const f32x8 qb = qh[jb];
+            const uint32_t pa = pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
+            const uint32_t pb = pass32<kUniform, kTime>(qb, cand, ecx, ecy, ecz, er, ets, ete);
+            bits = 4u * bits + 2u * pa + pb;
+        } else {
+            bits = 2u * bits +
+                   (uint32_t)pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
         }
     }
-    if (j > j0) {
-        const f32x8 qa = qf[j - 1];
-#pragma unroll
-        for (int k = 0; k < kCpl; ++k)
-            bits[k] = 2u * bits[k] +
-                      (uint32_t)pass32<kUniform, kTime>(qa, cand[k], ecx[k], ecy[k], ecz[k], er[k],
-                                                        ets[k], ete[k]);
+    return bits;
+}
+
+// Queues the pairs recorded in bits (see test_set) for the candidate of the
+// lane, one pair per lane per round.
+__device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemState& S,
+                                         uint32_t cand, uint32_t bits, uint32_t gm, uint32_t h) {
+    const uint32_t lane = __lane_id();
+    // ascending list of the queries of gm
+    wave_sync();
+    if (lane < 32 && ((gm >> lane) & 1u))
+        L.sel[__popc(gm & ((1u << lane) - 1u))] = (uint8_t)(32u * h + lane);
+    wave_sync();
+    const uint32_t code = (cand - S.c0) << 6;
+    uint32_t b = bits;
+    for (;;) {
+        const bool act = b != 0;
+        const uint64_t m = ballot(act);
+        if (!m) break;
+        if (act) {
+            const uint32_t j = L.sel[__builtin_ctz(b)];
+            L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
+            b &= b - 1u;
+        }
+        S.qn += (uint32_t)__popcll(m);
+        if (S.qn >= kWave) drain_full(L, S.c0, S.qbase, S.qn, S.evals, S.found, A);
     }
 }
 
-// Queues the pairs recorded in bits (query j0 + bit position, candidate slot
-// k), one pair per lane per round.
-__device__ __forceinline__ void push_bits(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                          const uint32_t (&cand)[kCpl], uint32_t (&bits)[kCpl],
-                                          uint32_t j0) {
-#pragma unroll
-    for (int k = 0; k < kCpl; ++k) {
-        const uint32_t code = (cand[k] - S.c0) << 6;
-        uint32_t b = bits[k];
-        for (;;) {
-            const bool act = b != 0;
-            const uint64_t m = ballot(act);
-            if (!m) break;
-            if (act) {
-                const uint32_t j = j0 + (uint32_t)__builtin_ctz(b);
-                L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
-                b &= b - 1u;
-            }
-            S.qn += (uint32_t)__popcll(m);
-            if (S.qn >= kWave) drain_full(L, S.c0, S.qbase, S.qn, S.evals, S.found, A);
-        }
-    }
-}
-
+// One 64-candidate slot against the queries of mask mk, 32 at a time.
 template <bool kUniform, bool kTime>
-__device__ __forceinline__ void tile_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                          ConstE32 qf, const uint32_t (&cand)[kCpl],
-                                          const float (&ecx)[kCpl], const float (&ecy)[kCpl],
-                                          const float (&ecz)[kCpl], const float (&er)[kCpl],
-                                          const float (&ets)[kCpl], const float (&ete)[kCpl]) {
-    for (uint32_t j0 = 0; j0 < S.nq; j0 += 32) {
-        const uint32_t j1 = min(S.nq, j0 + 32);
-        uint32_t bits[kCpl];
-        test_queries<kUniform, kTime>(qf, j0, j1, cand, ecx, ecy, ecz, er, ets, ete, bits);
-        uint32_t any = 0;
+__device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
+                                          ConstE32 qf, uint64_t mk, uint32_t cand, float ecx,
+                                          float ecy, float ecz, float er, float ets, float ete) {
 #pragma unroll
-        for (int k = 0; k < kCpl; ++k) any |= bits[k];
-        if (ballot(any != 0)) push_bits(L, A, S, cand, bits, j0);
+    for (uint32_t h = 0; h < 2; ++h) {
+        const uint32_t gm = (uint32_t)(mk >> (32u * h));
+        if (!gm) continue;
+        const uint32_t bits =
+            test_set<kUniform, kTime>(qf + 32u * h, gm, cand, ecx, ecy, ecz, er, ets, ete);
+        if (ballot(bits != 0u)) push_set(L, A, S, cand, bits, gm, h);
     }
 }
 
 // FP32 form: the wave takes the chunk kCpl * 64 candidates at a time (kCpl
-// per lane, coalesced vector loads) and streams the group's query records
-// through scalar loads (they stay in the scalar cache for the whole item).
+// per lane, coalesced vector loads, tiles aligned to the 64-entry blocks) and
+// streams the group's query records through scalar loads (they stay in the
+// scalar cache for the whole item).  With the spatial layout, each query is
+// first tested against the bounding box of each block (one lane per query),
+// and only the queries that pass are tested against the block's entries.
 // When every candidate of the bucket overlaps every query of the group in
 // time, the per-pair time test is skipped: exact, since the outward-rounded
 // FP32 times then overlap as well.
@@ -701,37 +699,64 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
                                                 const BucketInfo& bi) {
     const uint32_t lane = __lane_id();
     ConstE32 qf = (ConstE32)(A.qf + S.qbase);
-    float qa = -INFINITY, qb = INFINITY;
-    if (lane < S.nq) {
+    const bool has = lane < S.nq;
+    float qa = -INFINITY, qb = INFINITY, qcx = 0.f, qcy = 0.f, qcz = 0.f, qR = 0.f;
+    uint32_t qlo = 0, qhi = 0;
+    if (has) {
         const QF32 f = A.qf[S.qbase + lane];
         qa = f.a32;
         qb = f.b32;
+        qcx = f.cx;
+        qcy = f.cy;
+        qcz = f.cz;
+        qR = f.R;
+        qlo = f.lo;
+        qhi = f.hi;
     }
     const bool all_overlap =
         ballot(((double)qa < bi.tmin_te) && (bi.tmax_ts < (double)qb)) == ~0ull;
-    for (uint32_t tile = S.c0; tile < S.c1; tile += kTile) {
+    const uint64_t has_mask = ballot(has);
+    const bool cull = A.I.bbox != nullptr;
+    const ConstE32 boxes = (ConstE32)A.I.bbox;
+    for (uint32_t tile = S.c0 & ~(uint32_t)(kWave - 1); tile < S.c1; tile += kTile) {
         uint32_t cand[kCpl];
         float ecx[kCpl], ecy[kCpl], ecz[kCpl], er[kCpl], ets[kCpl], ete[kCpl];
-        bool full = true;
+        bool valid[kCpl];
 #pragma unroll
         for (int k = 0; k < kCpl; ++k) {
             cand[k] = tile + k * kWave + lane;
-            const bool valid = cand[k] < S.c1;
-            full = full && valid;
-            const EntryF32 e = A.I.e32[valid ? cand[k] : S.c1 - 1];
+            valid[k] = cand[k] >= S.c0 && cand[k] < S.c1;
+            const EntryF32 e = A.I.e32[valid[k] ? cand[k] : S.c1 - 1];
             ecx[k] = e.cx;
             ecy[k] = e.cy;
             ecz[k] = e.cz;
             er[k] = e.r;
-            // a slot past the chunk gets an empty time extent: it never passes
-            ets[k] = valid ? e.ts : INFINITY;
-            ete[k] = valid ? e.te : -INFINITY;
+            // a slot outside the chunk gets an empty time extent: it never passes
+            ets[k] = valid[k] ? e.ts : INFINITY;
+            ete[k] = valid[k] ? e.te : -INFINITY;
         }
-        // the time test can be dropped only on full tiles
-        if (all_overlap && ballot(full) == ~0ull)
-            tile_fp32<kUniform, false>(L, A, S, qf, cand, ecx, ecy, ecz, er, ets, ete);
-        else
-            tile_fp32<kUniform, true>(L, A, S, qf, cand, ecx, ecy, ecz, er, ets, ete);
+#pragma unroll
+        for (int k = 0; k < kCpl; ++k) {
+            const uint32_t b0 = tile + k * kWave;  // first entry of the block
+            if (b0 >= S.c1) break;
+            uint64_t mk = has_mask;
+            if (!kUniform) mk &= ballot(qlo < b0 + kWave && qhi > b0);
+            if (cull && mk) {
+                const f32x8 box = boxes[b0 >> kBoxShift];
+                mk &= ballot(box_pass(box, qcx, qcy, qcz, qR));
+                S.btests += S.nq;
+            }
+            if (!mk) continue;
+            const uint64_t vm = ballot(valid[k]);
+            S.ftests += (uint64_t)__popcll(mk) * (uint64_t)__popcll(vm);
+            // the time test can be dropped only on full slots
+            if (all_overlap && vm == ~0ull)
+                slot_fp32<kUniform, false>(L, A, S, qf, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                                           ets[k], ete[k]);
+            else
+                slot_fp32<kUniform, true>(L, A, S, qf, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                                          ets[k], ete[k]);
+        }
     }
 }
 
@@ -770,7 +795,7 @@ __global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
     __shared__ WaveLDS wl[kWavesPerBlock];
     WaveLDS& L = wl[threadIdx.x / kWave];
     const uint32_t lane = __lane_id();
-    uint64_t tests = 0, evals_total = 0;
+    uint64_t tests = 0, evals_total = 0, ftests = 0, btests = 0;
     // all items of the search, unless a range is given (incremental passes)
     const uint32_t item_end = (A.item_end == 0xFFFFFFFFu)
                                   ? uniform(min(A.hdr->n_items, A.desc->item_cap))
@@ -787,12 +812,15 @@ __global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
         const uint32_t c = local - g * bi.nch;
         ItemState S;
         S.nq = uniform(min((uint32_t)kWave, bi.count - g * kWave));
-        S.c0 = uniform(bi.lo + c * bi.clen);
-        S.c1 = uniform(min(bi.hi, S.c0 + bi.clen));
+        const uint64_t base = (uint64_t)(bi.lo & ~(uint32_t)(kWave - 1)) + (uint64_t)c * bi.clen;
+        S.c0 = uniform((uint32_t)max((uint64_t)bi.lo, base));
+        S.c1 = uniform((uint32_t)min((uint64_t)bi.hi, base + bi.clen));
         S.qbase = uniform(bi.start + g * kWave);
         S.qn = 0;
         S.evals = 0;
         S.found = 0;
+        S.ftests = 0;
+        S.btests = 0;
         // does every query of the group cover the whole chunk?
         bool cover = true;
         if (lane < S.nq) {
@@ -817,6 +845,8 @@ __global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
         }
         wave_sync();
         tests += (uint64_t)(S.c1 - S.c0) * S.nq;
+        ftests += (kPrec == TDS_PREC_FP64) ? (uint64_t)(S.c1 - S.c0) * S.nq : S.ftests;
+        btests += S.btests;
         evals_total += S.evals;
         if (A.item_count && lane == 0) A.item_count[it] = S.found;
     }
@@ -824,6 +854,8 @@ __global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
         if (tests) atomicAdd((unsigned long long*)&A.hdr->tests, (unsigned long long)tests);
         if (evals_total)
             atomicAdd((unsigned long long*)&A.hdr->evals, (unsigned long long)evals_total);
+        if (ftests) atomicAdd((unsigned long long*)&A.hdr->ftests, (unsigned long long)ftests);
+        if (btests) atomicAdd((unsigned long long*)&A.hdr->btests, (unsigned long long)btests);
     }
 }
 
@@ -916,10 +948,10 @@ uint32_t bucket_count(uint32_t m) {
 
 // Upper bound of the work items of a batch of nq query segments: every
 // non-empty bucket contributes ceil(count / 64) groups, each split into at
-// most ceil(n / chunk) chunks.
+// most ceil((n + 63) / chunk) chunks (chunks count from a 64-entry block).
 uint64_t item_bound(uint64_t nq, uint32_t nb, uint64_t n, uint32_t chunk) {
     const uint64_t groups = (nq + kWave - 1) / kWave + std::min<uint64_t>(nq, nb);
-    const uint64_t nch = std::max<uint64_t>((n + chunk - 1) / chunk, 1);
+    const uint64_t nch = std::max<uint64_t>((n + kWave - 1 + chunk - 1) / chunk, 1);
     return groups * nch;
 }
 
@@ -1013,7 +1045,7 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
     hipLaunchKernelGGL(k_qprep, dim3(qblocks), dim3(kBlock), 0, s, Q, w->desc, w->req, I, w->qp,
                        w->qkey, w->qslot, w->b_count, w->b_hi, shift, w->hdr);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_lo, w->b_hi,
-                       idx->bin_first, idx->min_te, idx->e64, idx->m, shift, nb, chunk, w->b_start,
+                       idx->bin_first, idx->min_te, idx->max_ts, idx->m, shift, nb, chunk, w->b_start,
                        w->b_item, w->b_nch, w->b_clen, w->binfo, w->hdr);
     hipLaunchKernelGGL(k_scatter, dim3(qblocks), dim3(kBlock), 0, s, w->desc, w->qkey, w->qslot,
                        w->b_start, w->qp, w->qsorted, w->qf);
@@ -1248,6 +1280,8 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     st.active_segments = h.active;
     st.work_items = n_items;
     st.candidate_tests = h.tests;
+    st.filter_tests = h.ftests;
+    st.block_tests = h.btests;
     st.fp64_evals = h.evals;
     const uint64_t total = rc.count;
     float ms = 0.f;
@@ -1391,6 +1425,8 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
     st.active_segments = h.active;
     st.work_items = h.n_items;
     st.candidate_tests = h.tests;
+    st.filter_tests = h.ftests;
+    st.block_tests = h.btests;
     st.fp64_evals = h.evals;
     st.results = total;
     st.total_ms =

@@ -26,7 +26,7 @@ constexpr uint32_t kQfPad = 4;          // query records read past a group's end
 
 // ---------------------------------------------------------------- records
 
-// Canonical FP64 entry record, one per indexed segment in t_start order.
+// Canonical FP64 entry record, one per indexed segment in index order.
 // 64 bytes so that one wave-uniform scalar load brings a whole record.
 struct alignas(64) EntryF64 {
     double x, y, z;     // start point
@@ -44,6 +44,18 @@ struct alignas(32) EntryF32 {
     float pad0, pad1;
 };
 static_assert(sizeof(EntryF32) == 32, "EntryF32 layout");
+
+// Bounding box of the FP32 filter spheres of one aligned block of 64 index
+// entries (spatial layout): every centre lies in [lo, hi] and every radius is
+// at most rmax.  32 bytes: one scalar load.
+struct alignas(32) BlockBox {
+    float lx, ly, lz;
+    float hx, hy, hz;
+    float rmax;
+    float pad;
+};
+static_assert(sizeof(BlockBox) == 32, "BlockBox layout");
+constexpr uint32_t kBoxShift = 6;  // log2 of the entries per box (one wave)
 
 // Prepared query segment (one per query segment of a search).
 struct alignas(16) QPrep {
@@ -116,7 +128,10 @@ struct alignas(64) SearchHeader {
     uint64_t results;       // total results (all requests)
     uint32_t n_buckets;     // buckets in use
     uint32_t pad;
+    uint64_t ftests;        // pairs through the FP32 filter / FP64 predicate
+    uint64_t btests;        // (query, block) bounding-box tests
 };
+static_assert(sizeof(SearchHeader) == 64, "SearchHeader layout");
 
 // Per-request device counters.
 struct alignas(16) ReqCounter {
@@ -170,14 +185,17 @@ struct tds_index {
     double t_min = 0, t_max = 0, bw = 0;
     tds::EntryF64* e64 = nullptr;
     tds::EntryF32* e32 = nullptr;
-    uint32_t* seg_id = nullptr;    // sorted position -> input position
-    uint32_t* traj = nullptr;      // sorted position -> trajectory id
+    uint32_t* seg_id = nullptr;    // index position -> input position
+    uint32_t* traj = nullptr;      // index position -> trajectory id
     uint32_t* bin_first = nullptr; // m + 1
     double* min_ts = nullptr;      // m
     double* max_te = nullptr;      // m
     double* min_te = nullptr;      // m: min t_end per bin (+inf when empty)
     double* cmax_te = nullptr;     // m
-    double* lo_ts = nullptr;       // m: t_start of the first entry of bins >= j
+    double* lo_ts = nullptr;       // m: min t_start over bins >= j (+inf when none)
+    double* max_ts = nullptr;      // m: max t_start per bin (-inf when empty)
+    tds::BlockBox* bbox = nullptr; // ceil(n / 64) block boxes (spatial layout)
+    uint32_t layout = TDS_LAYOUT_TEMPORAL;
     uint64_t device_bytes = 0;
     std::mutex mu;
     std::vector<tds::Workspace*> pool;
@@ -248,8 +266,8 @@ inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1)
 // covers the rounding of both spheres' centres to FP32, the FP32 evaluation
 // of the squared centre distance and of (R_q + r_l)^2, and the FP64 rounding
 // of the canonical arithmetic, so a pair whose canonical evaluation is a
-// result always passes the filter.  Beyond 1e18 the radius is +inf (the pair
-// always passes).
+// result always passes the filter.  Beyond 1e18 the radius is +inf and the
+// centre 0 (the pair always passes).
 __device__ inline void sphere32(double ax, double ay, double az, double bx, double by, double bz,
                                 double extra, float& cx32, float& cy32, float& cz32, float& r32) {
     const double u = 5.9604644775390625e-08;
@@ -261,7 +279,14 @@ __device__ inline void sphere32(double ax, double ay, double az, double bx, doub
     cx32 = __double2float_rn(cx);
     cy32 = __double2float_rn(cy);
     cz32 = __double2float_rn(cz);
-    r32 = (R < 1e18 && cn < 1e18) ? __double2float_ru(R) : __int_as_float(0x7f800000);
+    if (R < 1e18 && cn < 1e18) {
+        r32 = __double2float_ru(R);
+    } else {
+        // infinite radius, centre at the origin: every distance test against
+        // it passes without forming inf - inf
+        cx32 = cy32 = cz32 = 0.f;
+        r32 = __int_as_float(0x7f800000);
+    }
 }
 
 // Stable LSD radix sort of (key, value) pairs on `stream`; keys_bits is the

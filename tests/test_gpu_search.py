@@ -42,27 +42,50 @@ def compare(got, want, label=""):
     return int(np.sum((got["t_lo"] == want["t_lo"]) & (got["t_hi"] == want["t_hi"])))
 
 
-def build(D, m=0):
-    return tds.Index(D, num_bins=m)
+def build(D, m=0, layout="default"):
+    return tds.Index(D, num_bins=m, layout=layout)
+
+
+def check_tables(ex, ob, n, layout):
+    """Bin tables equal the oracle's; the order equals the oracle's t_start
+    order (temporal layout) or holds the same entries bin by bin (spatial
+    layout, where only the order inside a bin differs)."""
+    assert np.array_equal(ex["bin_first"][:-1].astype(np.int64), ob["first"])
+    assert ex["bin_first"][-1] == n
+    assert np.array_equal(ex["min_ts"], ob["min_ts"])
+    assert np.array_equal(ex["max_te"], ob["max_te"])
+    assert np.array_equal(ex["cmax_te"], ob["cmax_te"])
+    order = ex["order"].astype(np.int64)
+    if layout == "temporal":
+        assert np.array_equal(order, ob["order"])
+    else:
+        assert np.array_equal(np.sort(order), np.arange(n))
+        f = ex["bin_first"].astype(np.int64)
+        for j in range(len(f) - 1):
+            assert np.array_equal(np.sort(order[f[j]:f[j + 1]]), np.sort(ob["order"][f[j]:f[j + 1]]))
 
 
 # ---------------------------------------------------------------- index build
 
+@pytest.mark.parametrize("layout", ["temporal", "spatial"])
 @pytest.mark.parametrize("m", [0, 1, 7, 49])
-def test_index_tables_match_oracle(m):
+def test_index_tables_match_oracle(m, layout):
     w = trajgen.tiny(scale=0.05)
-    idx = build(w.D, m)
-    mm = idx.info()["num_bins"]
+    idx = build(w.D, m, layout)
+    inf = idx.info()
+    mm = inf["num_bins"]
+    assert inf["layout"] == tds.LAYOUTS[layout]
     if m == 0:
         assert mm == 49  # span 49 / mean duration 1
-    ex = idx.export()
     ob = oracle.bins(w.D.ts, w.D.te, mm)
-    assert np.array_equal(ex["order"].astype(np.int64), ob["order"])
-    assert np.array_equal(ex["bin_first"][:-1].astype(np.int64), ob["first"])
-    assert ex["bin_first"][-1] == len(w.D)
-    assert np.array_equal(ex["min_ts"], ob["min_ts"])
-    assert np.array_equal(ex["max_te"], ob["max_te"])
-    assert np.array_equal(ex["cmax_te"], ob["cmax_te"])
+    check_tables(idx.export(), ob, len(w.D), layout)
+    idx.close()
+
+
+def test_default_layout_is_spatial():
+    w = trajgen.tiny(scale=0.01)
+    idx = build(w.D)
+    assert idx.info()["layout"] == tds.LAYOUTS["spatial"]
     idx.close()
 
 
@@ -77,13 +100,10 @@ def test_index_tables_irregular_times():
                          xe=rng.normal(size=n), ye=rng.normal(size=n), ze=rng.normal(size=n), te=te,
                          traj=np.arange(n, dtype=np.uint32))
     for m in (1, 13, 1000):
-        idx = build(D, m)
-        ex = idx.export()
-        ob = oracle.bins(ts, te, m)
-        assert np.array_equal(ex["order"].astype(np.int64), ob["order"])
-        assert np.array_equal(ex["bin_first"][:-1].astype(np.int64), ob["first"])
-        assert np.array_equal(ex["cmax_te"], ob["cmax_te"])
-        idx.close()
+        for layout in ("temporal", "spatial"):
+            idx = build(D, m, layout)
+            check_tables(idx.export(), oracle.bins(ts, te, m), n, layout)
+            idx.close()
 
 
 def test_paper_example_index_on_gpu():
@@ -161,6 +181,77 @@ def test_reduced_configs(cfg, scale, d, prec):
     compare(got, want, f"{cfg}/{prec}")
     print(f"{cfg} d={d} {prec}: {got.size} records, stats {idx.last_stats}")
     idx.close()
+
+
+@pytest.mark.parametrize("cfg,scale,d", [
+    ("uniform1m", 0.02, 25.0),
+    ("dense", 0.02, 2.0),
+    ("galaxy", 0.01, 0.5),
+])
+def test_spatial_and_temporal_layouts_same_results(cfg, scale, d):
+    """Subdividing the bins in space changes which pairs are tested, never the
+    result: both layouts give the oracle's set with identical bytes."""
+    kw = {"n_pts": 61} if cfg in ("uniform1m", "dense") else {}
+    w = trajgen.CONFIGS[cfg](scale, **kw)
+    want = oracle.search(w.Q, w.D, d, *w.window)
+    got, stats = {}, {}
+    for layout in ("temporal", "spatial"):
+        idx = build(w.D, 0, layout)
+        for prec in ("fp32", "fp64"):
+            r = idx.search(w.Q, d, *w.window, precision=prec)
+            compare(r, want, f"{cfg}/{layout}/{prec}")
+            got[layout, prec] = tds.sort_records(r).tobytes()
+            stats[layout, prec] = dict(idx.last_stats)
+        idx.close()
+    assert len(set(got.values())) == 1
+    t, s = stats["temporal", "fp32"], stats["spatial", "fp32"]
+    assert t["candidate_tests"] == s["candidate_tests"]
+    assert t["block_tests"] == 0 and s["block_tests"] > 0
+    assert t["filter_tests"] <= t["candidate_tests"]
+    assert s["filter_tests"] <= t["filter_tests"]
+    print(f"{cfg}: candidate {s['candidate_tests']}, filter temporal {t['filter_tests']}, "
+          f"spatial {s['filter_tests']} after {s['block_tests']} block tests")
+
+
+def test_spatial_layout_culls_pairs():
+    """With hundreds of entries per bin, the block boxes remove most pairs
+    before the filter; the result stays the oracle's."""
+    w = trajgen.uniform1m(0.2, n_pts=61)  # 500 trajectories: 500 entries per bin
+    sl = w.query_traj_slices()
+    Q = w.Q.take(np.arange(sl[0][0], sl[19][1]))
+    want = oracle.search(Q, w.D, 5.0, *w.window)
+    stats = {}
+    for layout in ("temporal", "spatial"):
+        idx = build(w.D, 0, layout)
+        compare(idx.search(Q, 5.0, *w.window), want, layout)
+        stats[layout] = dict(idx.last_stats)
+        idx.close()
+    t, s = stats["temporal"], stats["spatial"]
+    print(f"filter tests: temporal {t['filter_tests']}, spatial {s['filter_tests']}")
+    assert s["filter_tests"] < 0.7 * t["filter_tests"]
+
+
+def test_huge_coordinates():
+    """Positions near the top of the double range: FP32 spheres become
+    infinite and must pass every pair on to the FP64 code."""
+    rng = np.random.default_rng(8)
+    rows = []
+    for k in range(300):
+        big = 10.0 ** float(rng.choice([20, 100, 300, 307]))
+        p = rng.choice([-1.0, 1.0], 3) * big
+        q = p + rng.normal(size=3) * float(rng.choice([0.0, 1.0, big * 1e-3]))
+        t = float(rng.integers(0, 20))
+        rows.append([*p, t, *q, t + 1.0])
+    rows += [[0, 0, 0, 0, 1, 1, 1, 5], [1e308, 0, 0, 2, -1e308, 0, 0, 3]]
+    D = _seg(rows)
+    Q = _seg(rows[::3])
+    for layout in ("temporal", "spatial"):
+        idx = build(D, 0, layout)
+        for d in (0.0, 1.0, 1e300):
+            want = oracle.search(Q, D, d, -math.inf, math.inf)
+            for prec in ("fp32", "fp64"):
+                compare(idx.search(Q, d, precision=prec), want, f"huge {layout} d={d} {prec}")
+        idx.close()
 
 
 def test_fp32_and_fp64_forms_bit_identical():
