@@ -197,6 +197,27 @@ class Index:
             raise TdsError(status, "tds_search")
 
 
+    def search_batch_raw(self, Q, requests, *, out_ptr: int, out_capacity: int,
+                         out_on_device: bool, precision: str = "fp32", chunk: int = 0,
+                         grid_waves: int = 0):
+        """One call of tds_search_batch into caller memory.  ``requests`` holds
+        (q_begin, q_count, d, t_start, t_end, out_offset, out_capacity) tuples
+        that tile Q in order.  Returns (status, counts, stats)."""
+        h = _segments(Q)
+        reqs = (_lib.tds_request * len(requests))()
+        for r, (qb, qc, d, t0, t1, oo, oc) in zip(reqs, requests):
+            r.q_begin, r.q_count, r.d, r.t_start, r.t_end = int(qb), int(qc), float(d), float(t0), float(t1)
+            r.out_offset, r.out_capacity = int(oo), int(oc)
+        counts = (ctypes.c_uint64 * len(requests))()
+        p = _search_params(precision, chunk, grid_waves)
+        p.out_on_device = 1 if out_on_device else 0
+        st = _lib.tds_stats()
+        status = self._lib.tds_search_batch(self._h, ctypes.byref(h.struct), reqs, len(requests),
+                                            ctypes.c_void_p(out_ptr), int(out_capacity), counts,
+                                            ctypes.byref(p), _current_stream(), ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        return status, [int(c) for c in counts], self.last_stats
+
     def search_batch(self, requests, *, precision: str = "fp32", chunk: int = 0,
                      grid_waves: int = 0, capacity: Optional[int] = None):
         """Batched search (tds_search_batch).  ``requests`` is a list of

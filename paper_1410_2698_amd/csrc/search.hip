@@ -35,11 +35,12 @@ constexpr uint32_t kInactive = 0xFFFFFFFFu;
 constexpr int kCpl = 4;
 constexpr uint32_t kTile = kCpl * kWave;
 
-// Entry records are read through the constant address space with a
-// wave-uniform index, so the compiler fetches them with scalar loads into
-// SGPRs: one load serves the 64 lanes (query segments) of the wave.
-typedef float f32x8 __attribute__((ext_vector_type(8)));
+// Records read through the constant address space with a wave-uniform index
+// are fetched with scalar loads into SGPRs: one load serves the 64 lanes of
+// the wave (FP64 entry records in the plain form, FP32 query records in the
+// filter form).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef const __attribute__((address_space(4))) f32x8* ConstE32;
 typedef const __attribute__((address_space(4))) f64x4* ConstE64;
 
@@ -52,6 +53,7 @@ struct IndexView {
     const double* cmax_te;
     const double* lo_ts;
     const BlockBox* bbox;  // block boxes (spatial layout) or nullptr
+    double t_min, bw;      // bin origin and width (search starting points)
     uint32_t n, m;
 };
 
@@ -71,6 +73,8 @@ IndexView view_of(const tds_index* idx) {
     v.cmax_te = idx->cmax_te;
     v.lo_ts = idx->lo_ts;
     v.bbox = idx->bbox;
+    v.t_min = idx->t_min;
+    v.bw = idx->bw;
     v.n = (uint32_t)idx->n;
     v.m = idx->m;
     return v;
@@ -159,6 +163,75 @@ __device__ __forceinline__ bool canon_eval(const QCanon& q, double lx, double ly
 
 // ------------------------------------------------------------ schedule
 
+// Smallest j in [0, m] with pred(j), for a predicate that is monotone
+// (false ... false true ... true) with pred(m) true.  The bins have equal
+// widths, so the caller's guess g (the bin of the time searched for) is
+// usually within one of the answer: four neighbouring values are loaded at
+// once, and only if the answer lies outside them does the search gallop
+// away from g and bisect the bracket found.
+template <class Pred>
+__device__ inline uint32_t first_true(Pred pred, uint32_t m, uint32_t g) {
+    g = min(g, m);
+    const uint32_t a = (g > 0) ? g - 1 : 0;
+    bool w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = (a + k >= m) ? true : pred(a + k);
+    uint32_t l, h;  // the answer lies in [l, h] and pred(h) holds
+    if (w[0]) {
+        if (a == 0) return 0;
+        // answer <= a: gallop down from a
+        h = a;
+        uint32_t step = 1;
+        for (;;) {
+            if (h < step) {
+                l = 0;
+                break;
+            }
+            const uint32_t c = h - step;
+            if (!pred(c)) {
+                l = c + 1;
+                break;
+            }
+            h = c;
+            step *= 2;
+        }
+    } else {
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if (w[k] && !w[k - 1]) return a + k;
+        // answer > a + 3: gallop up
+        l = a + 4;
+        uint32_t step = 1;
+        for (;;) {
+            const uint32_t c = l - 1 + step;
+            if (c >= m) {
+                h = m;
+                break;
+            }
+            if (pred(c)) {
+                h = c;
+                break;
+            }
+            l = c + 1;
+            step *= 2;
+        }
+    }
+    while (l < h) {
+        const uint32_t mid = l + (h - l) / 2;
+        if (pred(mid)) h = mid;
+        else l = mid + 1;
+    }
+    return l;
+}
+
+// Bin of time t for a search starting point (any value is correct).
+__device__ inline uint32_t guess_bin(const IndexView& I, double t) {
+    const double u = floor((t - I.t_min) / I.bw);
+    if (!(u > 0.0)) return 0u;
+    if (u >= (double)I.m) return I.m;
+    return (uint32_t)u;
+}
+
 // Candidate range E_k of a clipped query [aq, bq] (Sec. 4.2.2): from the
 // first entry of the first bin whose running max t_end exceeds aq (bin j0)
 // to the last entry of the last non-empty bin whose smallest t_start is below
@@ -166,27 +239,18 @@ __device__ __forceinline__ bool canon_eval(const QCanon& q, double lx, double ly
 __device__ inline void cand_range(const IndexView& I, double aq, double bq, uint32_t* lo,
                                   uint32_t* hi, uint32_t* j0o, uint32_t* j1o) {
     // j0 = first j with cmax_te[j] > aq (m if none)
-    uint32_t l = 0, h = I.m;
-    while (l < h) {
-        const uint32_t mid = (l + h) >> 1;
-        if (I.cmax_te[mid] > aq) h = mid;
-        else l = mid + 1;
-    }
-    const uint32_t j0 = l;
+    const uint32_t j0 =
+        first_true([&](uint32_t j) { return I.cmax_te[j] > aq; }, I.m, guess_bin(I, aq));
     // L = number of bins j for which some entry of a bin >= j has
     // t_start < bq (lo_ts, the minimum t_start over bins >= j, is
-    // non-decreasing); entries before bin_first[L] are those of bins < L
-    l = 0;
-    h = I.m;
-    while (l < h) {
-        const uint32_t mid = (l + h) >> 1;
-        if (I.lo_ts[mid] < bq) l = mid + 1;
-        else h = mid;
-    }
+    // non-decreasing), i.e. the first j with lo_ts[j] >= bq; entries before
+    // bin_first[L] are those of bins < L
+    const uint32_t L =
+        first_true([&](uint32_t j) { return I.lo_ts[j] >= bq; }, I.m, guess_bin(I, bq) + 1u);
     *lo = (j0 < I.m) ? I.bin_first[j0] : I.n;
-    *hi = I.bin_first[l];
+    *hi = I.bin_first[L];
     *j0o = j0;
-    *j1o = (l > 0) ? l - 1 : 0;
+    *j1o = (L > 0) ? L - 1 : 0;
 }
 
 __device__ inline bool finite(double v) { return isfinite(v); }
@@ -232,7 +296,6 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                                                   uint32_t* b_hi, uint32_t shift,
                                                   SearchHeader* hdr) {
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool active = false;
     if (k < desc->nq) {
         const uint32_t r = request_of(req, desc->nreq, k);
         const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k], ts = Q.a[3][k];
@@ -281,13 +344,10 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                     // several first bins or spans an open number of bins
                     if (shift || span == kSpanClasses - 1) atomicMax(&b_hi[key], hi);
                     qp[k] = p;
-                    active = true;
                 }
             }
         }
     }
-    const uint64_t am = __ballot(active);
-    if (__lane_id() == 0 && am) atomicAdd(&hdr->active, (uint32_t)__popcll(am));
 }
 
 // Schedule only (tds_schedule): candidate range per query segment.
@@ -410,6 +470,7 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
         b_item[nb] = pi[1023];
         hdr->n_items = pi[1023];
         hdr->n_buckets = nb;
+        hdr->active = pc[1023];  // every active query segment has a bucket slot
     }
 }
 
@@ -454,10 +515,38 @@ __global__ __launch_bounds__(kBlock) void k_item_fill(const BucketInfo* __restri
 }
 
 // Resets the per-pass counters of the distance kernel.
-__global__ void k_reset_pass(SearchHeader* hdr, ReqCounter* rc, uint32_t nreq) {
+__global__ void k_reset_pass(WorkCtr* wctr, ReqCounter* rc, uint32_t nreq) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) hdr->work_ctr = 0;
+    if (i < kParts) wctr[i].v = 0;
     if (i < nreq) rc[i].count = 0;
+}
+
+// Adds the per-workgroup counters of one distance-kernel launch to the
+// header (one block).
+__global__ __launch_bounds__(256) void k_stats_fold(const BlockStats* __restrict__ bs, uint32_t nb,
+                                                    SearchHeader* hdr) {
+    __shared__ uint64_t red[4][256];
+    uint64_t v[4] = {0, 0, 0, 0};
+    for (uint32_t i = threadIdx.x; i < nb; i += 256) {
+        const BlockStats b = bs[i];
+        v[0] += b.tests;
+        v[1] += b.evals;
+        v[2] += b.ftests;
+        v[3] += b.btests;
+    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (uint32_t off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        hdr->tests += red[0][0];
+        hdr->evals += red[1][0];
+        hdr->ftests += red[2][0];
+        hdr->btests += red[3][0];
+    }
 }
 
 struct DistArgs {
@@ -469,6 +558,8 @@ struct DistArgs {
     const uint32_t* item_bucket;
     const BatchDesc* desc;
     SearchHeader* hdr;
+    WorkCtr* wctr;
+    BlockStats* bstats;
     const Request* req;
     ReqCounter* rc;
     tds_result* out;
@@ -579,13 +670,24 @@ struct ItemState {
     uint64_t ftests, btests;
 };
 
-// FP32 filter of one query against the candidate held in the lane.  The query
-// record q comes from a scalar load (cx, cy, cz, R, a32, b32, lo, hi), the
-// candidate fields from the lane's registers.  A pair can only be a result if
-// the two bounding spheres come within d (the error margins are folded into
-// R and r) and the outward-rounded time extents overlap strictly.  With kTime
-// false the caller has established that every pair of the slot overlaps in
-// time; with kUniform true, that every query's candidate range covers it.
+// FP32 filter record of the query segment held by a lane (its QF32 record).
+struct QReg {
+    float cx, cy, cz, R;  // sphere of the clipped segment
+    float a, b;           // clipped window rounded outwards
+    uint32_t lo, hi;      // candidate range
+};
+
+// Value of v in lane j (wave-uniform j): a register read, no memory access.
+__device__ __forceinline__ float lane_val(float v, uint32_t j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)j));
+}
+
+// FP32 filter of one query (its QF32 record q, from a scalar load) against
+// the candidate held in this lane.  A pair can only be a result if the two
+// bounding spheres come within d (the error margins are folded into R and r)
+// and the outward-rounded time extents overlap strictly.  With kTime false
+// the caller has established that every pair of the slot overlaps in time;
+// with kUniform true, that every query's candidate range covers it.
 template <bool kUniform, bool kTime>
 __device__ __forceinline__ bool pass32(const f32x8& q, uint32_t cand, float ecx, float ecy,
                                        float ecz, float er, float ets, float ete) {
@@ -594,19 +696,19 @@ __device__ __forceinline__ bool pass32(const f32x8& q, uint32_t cand, float ecx,
     const float R = q[3] + er;
     bool p = s <= R * R;
     if (kTime) p = p & (q[4] < ete) & (ets < q[5]);
-    if (!kUniform)
-        p = p & (cand >= __float_as_uint(q[6])) & (cand < __float_as_uint(q[7]));
+    if (!kUniform) p = p & (cand >= __float_as_uint(q[6])) & (cand < __float_as_uint(q[7]));
     return p;
 }
 
-// Bounding-box test of a query sphere (cx, cy, cz, R) against the block box b
+// Bounding-box test of a query sphere (cx, cy, cz, R) against a block box
 // (lx, ly, lz, hx, hy, hz, rmax).  It is the filter's own arithmetic with the
 // centre distance replaced by the distance to the box: per axis the gap
 // fl(lo - c) or fl(c - hi) is at most the filter's |fl(c_l - c)| for every
 // centre c_l in the box (rounding to nearest is monotone and odd), squares,
 // FMAs and fl(R + r) are monotone in their operands, and r <= rmax; so
 // whenever the filter passes a pair of the block, this test passes.
-__device__ __forceinline__ bool box_pass(const f32x8& b, float cx, float cy, float cz, float R) {
+__device__ __forceinline__ bool box_pass(const float (&b)[7], float cx, float cy, float cz,
+                                         float R) {
     const float gx = fmaxf(fmaxf(b[0] - cx, cx - b[3]), 0.f);
     const float gy = fmaxf(fmaxf(b[1] - cy, cy - b[4]), 0.f);
     const float gz = fmaxf(fmaxf(b[2] - cz, cz - b[5]), 0.f);
@@ -619,26 +721,26 @@ __device__ __forceinline__ bool box_pass(const f32x8& b, float cx, float cy, flo
 // against the candidate held in the lane.  Queries are taken from the highest
 // down and each outcome is shifted in at the bottom (bits = 2 bits + pass), so
 // bit p of the result belongs to the p-th lowest query of gm.  gm is wave
-// uniform: the walk over its bits and the query loads are scalar.
+// uniform: the walk over its bits and the loads of the group's query records
+// qg are scalar (the records stay in the scalar cache for the whole item).
 template <bool kUniform, bool kTime>
-__device__ __forceinline__ uint32_t test_set(ConstE32 qh, uint32_t gm, uint32_t cand, float ecx,
-                                             float ecy, float ecz, float er, float ets,
-                                             float ete) {
+__device__ __forceinline__ uint32_t test_set(ConstE32 qg, uint32_t h, uint32_t gm,
+                                             uint32_t cand, float ecx, float ecy, float ecz,
+                                             float er, float ets, float ete) {
     uint32_t bits = 0;
     while (gm) {
         const uint32_t ja = 31u - (uint32_t)__builtin_clz(gm);
         gm ^= 1u << ja;
-        const f32x8 qa = qh[ja];
+        const f32x8 qa = qg[32u * h + ja];
+        const uint32_t pa = pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
         if (gm) {
             const uint32_t jb = 31u - (uint32_t)__builtin_clz(gm);
             gm ^= 1u << jb;
-            const f32x8 qb = qh[jb];
-            const uint32_t pa = pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
+            const f32x8 qb = qg[32u * h + jb];
             const uint32_t pb = pass32<kUniform, kTime>(qb, cand, ecx, ecy, ecz, er, ets, ete);
             bits = 4u * bits + 2u * pa + pb;
         } else {
-            bits = 2u * bits +
-                   (uint32_t)pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
+            bits = 2u * bits + pa;
         }
     }
     return bits;
@@ -673,51 +775,54 @@ __device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemStat
 // One 64-candidate slot against the queries of mask mk, 32 at a time.
 template <bool kUniform, bool kTime>
 __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                          ConstE32 qf, uint64_t mk, uint32_t cand, float ecx,
+                                          ConstE32 qg, uint64_t mk, uint32_t cand, float ecx,
                                           float ecy, float ecz, float er, float ets, float ete) {
 #pragma unroll
     for (uint32_t h = 0; h < 2; ++h) {
         const uint32_t gm = (uint32_t)(mk >> (32u * h));
         if (!gm) continue;
         const uint32_t bits =
-            test_set<kUniform, kTime>(qf + 32u * h, gm, cand, ecx, ecy, ecz, er, ets, ete);
+            test_set<kUniform, kTime>(qg, h, gm, cand, ecx, ecy, ecz, er, ets, ete);
         if (ballot(bits != 0u)) push_set(L, A, S, cand, bits, gm, h);
     }
 }
 
 // FP32 form: the wave takes the chunk kCpl * 64 candidates at a time (kCpl
-// per lane, coalesced vector loads, tiles aligned to the 64-entry blocks) and
-// streams the group's query records through scalar loads (they stay in the
-// scalar cache for the whole item).  With the spatial layout, each query is
-// first tested against the bounding box of each block (one lane per query),
-// and only the queries that pass are tested against the block's entries.
-// When every candidate of the bucket overlaps every query of the group in
-// time, the per-pair time test is skipped: exact, since the outward-rounded
-// FP32 times then overlap as well.
+// per lane, coalesced vector loads, tiles aligned to the 64-entry blocks).
+// Lane j holds query j of the group and, with the spatial layout, the box of
+// one of the next 64 blocks (broadcast from its registers by readlane, so the
+// loop over blocks makes no memory access).  Each block's box is first tested
+// against every query (one lane per query), and only the queries that pass
+// are tested against the block's entries, their records coming from scalar
+// loads.  When every
+// candidate of the bucket overlaps every query of the group in time, the
+// per-pair time test is skipped: exact, since the outward-rounded FP32 times
+// then overlap as well.
 template <bool kUniform>
 __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
                                                 const BucketInfo& bi) {
     const uint32_t lane = __lane_id();
-    ConstE32 qf = (ConstE32)(A.qf + S.qbase);
+    const ConstE32 qg = (ConstE32)(A.qf + S.qbase);
     const bool has = lane < S.nq;
-    float qa = -INFINITY, qb = INFINITY, qcx = 0.f, qcy = 0.f, qcz = 0.f, qR = 0.f;
-    uint32_t qlo = 0, qhi = 0;
+    QReg q = {0.f, 0.f, 0.f, 0.f, -INFINITY, INFINITY, 0u, 0u};
     if (has) {
         const QF32 f = A.qf[S.qbase + lane];
-        qa = f.a32;
-        qb = f.b32;
-        qcx = f.cx;
-        qcy = f.cy;
-        qcz = f.cz;
-        qR = f.R;
-        qlo = f.lo;
-        qhi = f.hi;
+        q.cx = f.cx;
+        q.cy = f.cy;
+        q.cz = f.cz;
+        q.R = f.R;
+        q.a = f.a32;
+        q.b = f.b32;
+        q.lo = f.lo;
+        q.hi = f.hi;
     }
     const bool all_overlap =
-        ballot(((double)qa < bi.tmin_te) && (bi.tmax_ts < (double)qb)) == ~0ull;
+        ballot(((double)q.a < bi.tmin_te) && (bi.tmax_ts < (double)q.b)) == ~0ull;
     const uint64_t has_mask = ballot(has);
     const bool cull = A.I.bbox != nullptr;
-    const ConstE32 boxes = (ConstE32)A.I.bbox;
+    const uint32_t last_blk = (S.c1 - 1) >> kBoxShift;
+    uint32_t wb = 0xFFFFFFFFu;  // first block of the box window held in the lanes
+    float wbox[7];
     for (uint32_t tile = S.c0 & ~(uint32_t)(kWave - 1); tile < S.c1; tile += kTile) {
         uint32_t cand[kCpl];
         float ecx[kCpl], ecy[kCpl], ecz[kCpl], er[kCpl], ets[kCpl], ete[kCpl];
@@ -735,15 +840,32 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
             ets[k] = valid[k] ? e.ts : INFINITY;
             ete[k] = valid[k] ? e.te : -INFINITY;
         }
+        const uint32_t tb = tile >> kBoxShift;
+        if (cull && (wb == 0xFFFFFFFFu || tb + kCpl > wb + kWave)) {
+            // lane l takes the box of block wb + l (the last block of the
+            // chunk repeated past the end)
+            wb = tb;
+            const BlockBox bx = A.I.bbox[min(wb + lane, last_blk)];
+            wbox[0] = bx.lx;
+            wbox[1] = bx.ly;
+            wbox[2] = bx.lz;
+            wbox[3] = bx.hx;
+            wbox[4] = bx.hy;
+            wbox[5] = bx.hz;
+            wbox[6] = bx.rmax;
+        }
 #pragma unroll
         for (int k = 0; k < kCpl; ++k) {
             const uint32_t b0 = tile + k * kWave;  // first entry of the block
             if (b0 >= S.c1) break;
             uint64_t mk = has_mask;
-            if (!kUniform) mk &= ballot(qlo < b0 + kWave && qhi > b0);
+            if (!kUniform) mk &= ballot(q.lo < b0 + kWave && q.hi > b0);
             if (cull && mk) {
-                const f32x8 box = boxes[b0 >> kBoxShift];
-                mk &= ballot(box_pass(box, qcx, qcy, qcz, qR));
+                const uint32_t bl = tb + k - wb;
+                float box[7];
+#pragma unroll
+                for (int f = 0; f < 7; ++f) box[f] = lane_val(wbox[f], bl);
+                mk &= ballot(box_pass(box, q.cx, q.cy, q.cz, q.R));
                 S.btests += S.nq;
             }
             if (!mk) continue;
@@ -751,10 +873,10 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
             S.ftests += (uint64_t)__popcll(mk) * (uint64_t)__popcll(vm);
             // the time test can be dropped only on full slots
             if (all_overlap && vm == ~0ull)
-                slot_fp32<kUniform, false>(L, A, S, qf, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                slot_fp32<kUniform, false>(L, A, S, qg, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
                                            ets[k], ete[k]);
             else
-                slot_fp32<kUniform, true>(L, A, S, qf, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                slot_fp32<kUniform, true>(L, A, S, qg, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
                                           ets[k], ete[k]);
         }
     }
@@ -800,11 +922,32 @@ __global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
     const uint32_t item_end = (A.item_end == 0xFFFFFFFFu)
                                   ? uniform(min(A.hdr->n_items, A.desc->item_cap))
                                   : A.item_end;
+    // items [item_begin, item_end) in kParts contiguous parts; a workgroup
+    // starts on part blockIdx.x % kParts and moves on to the next part when
+    // its own is exhausted (an exhausted part is recognised by a plain atomic
+    // load, without a read-modify-write)
+    const uint64_t n_it = item_end > A.item_begin ? item_end - A.item_begin : 0u;
+    uint32_t part = blockIdx.x % kParts, tries = 0;
     for (;;) {
-        uint32_t it = 0;
-        if (lane == 0) it = atomicAdd(&A.hdr->work_ctr, 1u);
-        it = uniform(__shfl(it, 0)) + A.item_begin;
-        if (it >= item_end) break;
+        uint32_t it = 0xFFFFFFFFu;
+        while (tries < kParts) {
+            const uint32_t p0 = A.item_begin + (uint32_t)(n_it * part / kParts);
+            const uint32_t cnt = A.item_begin + (uint32_t)(n_it * (part + 1) / kParts) - p0;
+            uint32_t v = 0xFFFFFFFFu;
+            if (lane == 0 && cnt) {
+                const uint32_t cur =
+                    __hip_atomic_load(&A.wctr[part].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (cur < cnt) v = atomicAdd(&A.wctr[part].v, 1u);
+            }
+            v = uniform(__shfl(v, 0));
+            if (v < cnt) {
+                it = p0 + v;
+                break;
+            }
+            part = (part + 1) % kParts;
+            ++tries;
+        }
+        if (it == 0xFFFFFFFFu) break;
         const uint32_t b = uniform(A.item_bucket[it]);
         const BucketInfo bi = A.binfo[b];
         const uint32_t local = it - bi.item0;
@@ -850,12 +993,25 @@ __global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
         evals_total += S.evals;
         if (A.item_count && lane == 0) A.item_count[it] = S.found;
     }
+    // per-workgroup counters (folded into the header by k_stats_fold)
+    __shared__ BlockStats ws[kWavesPerBlock];
+    const uint32_t wid = threadIdx.x / kWave;
     if (lane == 0) {
-        if (tests) atomicAdd((unsigned long long*)&A.hdr->tests, (unsigned long long)tests);
-        if (evals_total)
-            atomicAdd((unsigned long long*)&A.hdr->evals, (unsigned long long)evals_total);
-        if (ftests) atomicAdd((unsigned long long*)&A.hdr->ftests, (unsigned long long)ftests);
-        if (btests) atomicAdd((unsigned long long*)&A.hdr->btests, (unsigned long long)btests);
+        ws[wid].tests = tests;
+        ws[wid].evals = evals_total;
+        ws[wid].ftests = ftests;
+        ws[wid].btests = btests;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        BlockStats b = ws[0];
+        for (int k = 1; k < kWavesPerBlock; ++k) {
+            b.tests += ws[k].tests;
+            b.evals += ws[k].evals;
+            b.ftests += ws[k].ftests;
+            b.btests += ws[k].btests;
+        }
+        A.bstats[blockIdx.x] = b;
     }
 }
 
@@ -879,7 +1035,7 @@ Workspace::~Workspace() {
                     (void*)qtraj_stage, (void*)req, (void*)req_ctr, (void*)b_count, (void*)b_lo,
                     (void*)b_hi, (void*)b_start, (void*)b_item, (void*)b_nch, (void*)b_clen,
                     (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res, (void*)hdr,
-                    (void*)desc})
+                    (void*)wctr, (void*)bstats, (void*)desc})
         dfree(p);
     if (hdr_host) (void)hipHostFree(hdr_host);
     if (desc_host) (void)hipHostFree(desc_host);
@@ -897,6 +1053,8 @@ int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_clen, kMaxBuckets));
     TDS_TRY(dmalloc(&w->binfo, kMaxBuckets));
     TDS_TRY(dmalloc(&w->hdr, 1));
+    TDS_TRY(dmalloc(&w->wctr, kParts));
+    TDS_TRY(dmalloc(&w->bstats, kMaxDistBlocks));
     TDS_TRY(dmalloc(&w->desc, 1));
     TDS_HIP(hipHostMalloc((void**)&w->hdr_host, sizeof(SearchHeader), hipHostMallocDefault));
     TDS_HIP(hipHostMalloc((void**)&w->desc_host, sizeof(BatchDesc), hipHostMallocDefault));
@@ -959,10 +1117,14 @@ constexpr uint64_t kMaxItemTable = 1ull << 26;  // entries (256 MiB) kept withou
 
 uint32_t resolve_chunk(int prec, uint32_t chunk) {
     if (chunk) return std::max(chunk, 64u);
-    return prec == TDS_PREC_FP64 ? 512u : 2048u;
+    return prec == TDS_PREC_FP64 ? 512u : 4096u;
 }
 
-uint32_t resolve_grid(uint32_t grid_waves) { return grid_waves ? grid_waves : 256u * 8u; }
+// Default: 4 waves per SIMD on all 256 CUs (the occupancy the distance
+// kernel's register use allows).
+uint32_t resolve_grid(uint32_t grid_waves) {
+    return std::min(grid_waves ? grid_waves : 256u * 4u * 4u, kMaxDistBlocks * kWavesPerBlock);
+}
 
 int resolve_prec(int p) {
     if (p == TDS_PREC_DEFAULT) return TDS_PREC_FP32_RECHECK;
@@ -1007,6 +1169,8 @@ DistArgs dist_args(const tds_index* idx, const Workspace* w, tds_result* out, ui
     A.item_bucket = w->item_bucket;
     A.desc = w->desc;
     A.hdr = w->hdr;
+    A.wctr = w->wctr;
+    A.bstats = w->bstats;
     A.req = w->req;
     A.rc = w->req_ctr;
     A.out = out;
@@ -1017,12 +1181,19 @@ DistArgs dist_args(const tds_index* idx, const Workspace* w, tds_result* out, ui
     return A;
 }
 
-int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_t s) {
-    const uint32_t blocks = std::max(1u, ceil_div(grid_waves, kWavesPerBlock));
+// The distance kernel between the two events (either may be null), then the
+// fold of its per-workgroup counters into the header.
+int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_t s,
+                    hipEvent_t ev_begin, hipEvent_t ev_end) {
+    const uint32_t blocks =
+        std::min(kMaxDistBlocks, std::max(1u, ceil_div(grid_waves, kWavesPerBlock)));
+    if (ev_begin) TDS_HIP(hipEventRecord(ev_begin, s));
     if (prec == TDS_PREC_FP64)
         hipLaunchKernelGGL(k_distance<TDS_PREC_FP64>, dim3(blocks), dim3(kBlock), 0, s, A);
     else
         hipLaunchKernelGGL(k_distance<TDS_PREC_FP32_RECHECK>, dim3(blocks), dim3(kBlock), 0, s, A);
+    if (ev_end) TDS_HIP(hipEventRecord(ev_end, s));
+    hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, s, A.bstats, blocks, A.hdr);
     TDS_HIP(hipGetLastError());
     return TDS_OK;
 }
@@ -1051,14 +1222,11 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
                        w->b_start, w->qp, w->qsorted, w->qf);
     hipLaunchKernelGGL(k_item_fill, dim3(nb), dim3(kBlock), 0, s, w->binfo, w->desc,
                        w->item_bucket, w->hdr);
-    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, 1u), 256)), dim3(256), 0, s,
-                       w->hdr, w->req_ctr, r_cap);
+    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, kParts), 256)), dim3(256), 0, s,
+                       w->wctr, w->req_ctr, r_cap);
     TDS_HIP(hipGetLastError());
-    if (ev_begin) TDS_HIP(hipEventRecord(ev_begin, s));
-    TDS_TRY(launch_distance(prec, dist_args(idx, w, out, 0, 0, 0xFFFFFFFFu, item_count), grid_waves,
-                            s));
-    if (ev_end) TDS_HIP(hipEventRecord(ev_end, s));
-    return TDS_OK;
+    return launch_distance(prec, dist_args(idx, w, out, 0, 0, 0xFFFFFFFFu, item_count), grid_waves,
+                           s, ev_begin, ev_end);
 }
 
 // Re-runs the distance kernel over work items [i0, i1) keeping result
@@ -1066,13 +1234,11 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
 int enqueue_range(const tds_index* idx, Workspace* w, int prec, uint32_t r_cap, tds_result* out,
                   uint64_t win_lo, uint32_t i0, uint32_t i1, uint32_t grid_waves, hipStream_t s,
                   hipEvent_t ev_begin, hipEvent_t ev_end) {
-    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, 1u), 256)), dim3(256), 0, s,
-                       w->hdr, w->req_ctr, r_cap);
+    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, kParts), 256)), dim3(256), 0, s,
+                       w->wctr, w->req_ctr, r_cap);
     TDS_HIP(hipGetLastError());
-    if (ev_begin) TDS_HIP(hipEventRecord(ev_begin, s));
-    TDS_TRY(launch_distance(prec, dist_args(idx, w, out, win_lo, i0, i1, nullptr), grid_waves, s));
-    if (ev_end) TDS_HIP(hipEventRecord(ev_end, s));
-    return TDS_OK;
+    return launch_distance(prec, dist_args(idx, w, out, win_lo, i0, i1, nullptr), grid_waves, s,
+                           ev_begin, ev_end);
 }
 
 Workspace* acquire(tds_index* idx) {

@@ -57,6 +57,34 @@ def test_batch_matches_oracle_and_alone(setup):
         assert key_sorted(a) == key_sorted(b)
 
 
+def test_device_resident_batch_of_distances(setup):
+    """The bench's step form: the same query segments once per d as requests
+    of one batch, inputs and outputs in device memory; a first call without
+    output space only counts."""
+    w, idx, _ = setup
+    Qt = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in w.Q.arrays().items()
+          if k != "traj"}
+    Qt["traj"] = torch.from_numpy(w.Q.traj.astype(np.int32)).cuda()
+    ds = (6.0, 30.0, 150.0)
+    nq = len(w.Q)
+    Qb = {k: torch.cat([v] * len(ds)) for k, v in Qt.items()}
+    st, counts, _ = idx.search_batch_raw(
+        Qb, [(i * nq, nq, d, 0.0, 80.0, 0, 0) for i, d in enumerate(ds)], out_ptr=0,
+        out_capacity=0, out_on_device=True)
+    assert st == tds.TDS_E_OVERFLOW and counts[2] > counts[0]
+    cap = max(counts) + 3
+    out = torch.empty(len(ds) * cap * 32, dtype=torch.uint8, device="cuda")
+    reqs = [(i * nq, nq, d, 0.0, 80.0, i * cap, cap) for i, d in enumerate(ds)]
+    st, got, stats = idx.search_batch_raw(Qb, reqs, out_ptr=out.data_ptr(),
+                                          out_capacity=len(ds) * cap, out_on_device=True)
+    assert st == tds.TDS_OK and got == counts and stats["passes"] == 1
+    recs = np.frombuffer(out.cpu().numpy().tobytes(), dtype=tds.RESULT_DTYPE)
+    for i, d in enumerate(ds):
+        part = recs[i * cap: i * cap + counts[i]].copy()
+        check_oracle(part, w.Q, w.D, d, 0.0, 80.0)
+        assert key_sorted(part) == key_sorted(idx.search(w.Q, d, 0.0, 80.0))
+
+
 def test_batch_overflow_is_per_request(setup):
     w, idx, reqs = setup
     b = tds.Batcher(idx, max_segments=20000, max_requests=64, result_capacity=64 * 2)
