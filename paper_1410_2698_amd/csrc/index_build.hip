@@ -6,7 +6,7 @@
 //                 (order-preserving bits of t_start) and per-block partial
 //                 min t_start / max t_end / sum of durations / extent of the
 //                 sphere centres;
-//   k_spatial_key (spatial layout) replace the key by (bin, Morton code of
+//   k_spatial_key (spatial layout) replace the key by (bin, Hilbert index of
 //                 the sphere centre on a 1024^3 grid over the centres' extent);
 //   radix sort    stable, by the key (radix_sort.hip);
 //   k_gather      write the ordered AoS records, ids and trajectory ids;
@@ -20,6 +20,7 @@
 #include <cmath>
 #include <utility>
 
+#include "hilbert.hpp"
 #include "tds_internal.hpp"
 
 namespace tds {
@@ -112,16 +113,6 @@ __device__ inline uint32_t bin_of(double ts, double tmin, double bw, uint32_t m)
     return (uint32_t)u;
 }
 
-// Spreads the low 10 bits of v to every third bit (Morton interleave).
-__device__ inline uint32_t spread3(uint32_t v) {
-    v &= 0x3FFu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
-
 __device__ inline uint32_t cell10(float c, float lo, float scale) {
     const float u = (c - lo) * scale;
     if (!(u > 0.f)) return 0u;
@@ -129,9 +120,10 @@ __device__ inline uint32_t cell10(float c, float lo, float scale) {
     return (uint32_t)u;
 }
 
-// Spatial layout key: bin in the high bits, then the Morton code of the
-// sphere centre.  Only the order inside a bin depends on the cell, so the
-// bins, and every table derived from them, are those of the temporal layout.
+// Spatial layout key: bin in the high bits, then the Hilbert index of the
+// sphere centre's cell.  Only the order inside a bin depends on the cell, so
+// the bins, and every table derived from them, are those of the temporal
+// layout.
 __global__ __launch_bounds__(kBT) void k_spatial_key(uint64_t n, const EntryF64* __restrict__ tmp64,
                                                      const EntryF32* __restrict__ tmp32,
                                                      double tmin, double bw, uint32_t m,
@@ -141,9 +133,9 @@ __global__ __launch_bounds__(kBT) void k_spatial_key(uint64_t n, const EntryF64*
     const uint64_t i = (uint64_t)blockIdx.x * kBT + threadIdx.x;
     if (i >= n) return;
     const EntryF32 f = tmp32[i];
-    const uint32_t morton = spread3(cell10(f.cx, lx, sx)) | (spread3(cell10(f.cy, ly, sy)) << 1) |
-                            (spread3(cell10(f.cz, lz, sz)) << 2);
-    keys[i] = ((uint64_t)bin_of(tmp64[i].ts, tmin, bw, m) << 30) | morton;
+    const uint32_t h =
+        hilbert3<10>(cell10(f.cx, lx, sx), cell10(f.cy, ly, sy), cell10(f.cz, lz, sz));
+    keys[i] = ((uint64_t)bin_of(tmp64[i].ts, tmin, bw, m) << 30) | h;
 }
 
 __global__ __launch_bounds__(kBT) void k_gather(uint64_t n, const uint32_t* __restrict__ perm,

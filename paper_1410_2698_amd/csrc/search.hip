@@ -35,13 +35,10 @@ constexpr uint32_t kInactive = 0xFFFFFFFFu;
 constexpr int kCpl = 4;
 constexpr uint32_t kTile = kCpl * kWave;
 
-// Records read through the constant address space with a wave-uniform index
-// are fetched with scalar loads into SGPRs: one load serves the 64 lanes of
-// the wave (FP64 entry records in the plain form, FP32 query records in the
-// filter form).
+// FP64 entry records are read through the constant address space with a
+// wave-uniform index, so the compiler fetches them with scalar loads into
+// SGPRs: one load serves the 64 lanes (query segments) of the wave.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x8 __attribute__((ext_vector_type(8)));
-typedef const __attribute__((address_space(4))) f32x8* ConstE32;
 typedef const __attribute__((address_space(4))) f64x4* ConstE64;
 
 struct IndexView {
@@ -288,9 +285,28 @@ __global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_
     }
 }
 
+// Canonical FP64 data of query segment k of request r, from the query
+// arrays (the same operations wherever it is needed, so bit-identical).
+__device__ inline void query_canon(const QueryView& Q, const Request& R, uint64_t k, QCanon& q) {
+    const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k], ts = Q.a[3][k];
+    const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k], te = Q.a[7][k];
+    const double dt = te - ts;
+    q.x = xs;
+    q.y = ys;
+    q.z = zs;
+    q.vx = (xe - xs) / dt;
+    q.vy = (ye - ys) / dt;
+    q.vz = (ze - zs) / dt;
+    q.ts = ts;
+    q.aq = dmax(ts, R.t_start);
+    q.bq = dmin(te, R.t_end);
+    q.d = R.d;
+}
+
 __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* __restrict__ desc,
                                                   const Request* __restrict__ req, IndexView I,
-                                                  QPrep* __restrict__ qp,
+                                                  QF32* __restrict__ qfu,
+                                                  uint32_t* __restrict__ qreq,
                                                   uint32_t* __restrict__ qkey,
                                                   uint32_t* __restrict__ qslot, uint32_t* b_count,
                                                   uint32_t* b_hi, uint32_t shift,
@@ -306,23 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
         if (!ok) {
             atomicOr(&hdr->err, 1u);
         } else {
-            const double d = req[r].d;
-            const double dt = te - ts;
-            QPrep p;
-            p.x = xs;
-            p.y = ys;
-            p.z = zs;
-            p.vx = (xe - xs) / dt;
-            p.vy = (ye - ys) / dt;
-            p.vz = (ze - zs) / dt;
-            p.ts = ts;
-            p.aq = dmax(ts, req[r].t_start);
-            p.bq = dmin(te, req[r].t_end);
-            p.d = d;
-            p.qid = (uint32_t)(k - req[r].q_begin);
-            p.traj = Q.traj ? Q.traj[k] : 0u;
-            p.req = r;
-            p.pad = 0;
+            QCanon p;
+            query_canon(Q, req[r], k, p);
             if (p.aq < p.bq) {
                 uint32_t lo, hi, j0, j1;
                 cand_range(I, p.aq, p.bq, &lo, &hi, &j0, &j1);
@@ -331,11 +332,12 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                                  paz = p.z + p.vz * (p.aq - ts);
                     const double pbx = p.x + p.vx * (p.bq - ts), pby = p.y + p.vy * (p.bq - ts),
                                  pbz = p.z + p.vz * (p.bq - ts);
-                    sphere32(pax, pay, paz, pbx, pby, pbz, d, p.cx, p.cy, p.cz, p.R);
-                    p.a32 = __double2float_rd(p.aq);
-                    p.b32 = __double2float_ru(p.bq);
-                    p.lo = lo;
-                    p.hi = hi;
+                    QF32 f;
+                    sphere32(pax, pay, paz, pbx, pby, pbz, p.d, f.cx, f.cy, f.cz, f.R);
+                    f.a32 = __double2float_rd(p.aq);
+                    f.b32 = __double2float_ru(p.bq);
+                    f.lo = lo;
+                    f.hi = hi;
                     const uint32_t span = min(j1 - j0, kSpanClasses - 1);
                     const uint32_t key = (j0 * kSpanClasses + span) >> shift;
                     qkey[k] = key;
@@ -343,7 +345,8 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                     // the bucket's range follows from its key unless it merges
                     // several first bins or spans an open number of bins
                     if (shift || span == kSpanClasses - 1) atomicMax(&b_hi[key], hi);
-                    qp[k] = p;
+                    qfu[k] = f;
+                    qreq[k] = r;
                 }
             }
         }
@@ -478,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const BatchDesc* __restrict_
                                                     const uint32_t* __restrict__ qkey,
                                                     const uint32_t* __restrict__ qslot,
                                                     const uint32_t* __restrict__ b_start,
-                                                    const QPrep* __restrict__ qp,
+                                                    const QF32* __restrict__ qfu,
                                                     uint32_t* __restrict__ qsorted,
                                                     QF32* __restrict__ qf) {
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -487,17 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const BatchDesc* __restrict_
     if (s == kInactive) return;
     const uint32_t pos = b_start[qkey[k]] + s;
     qsorted[pos] = (uint32_t)k;
-    const QPrep& p = qp[k];
-    QF32 f;
-    f.cx = p.cx;
-    f.cy = p.cy;
-    f.cz = p.cz;
-    f.R = p.R;
-    f.a32 = p.a32;
-    f.b32 = p.b32;
-    f.lo = p.lo;
-    f.hi = p.hi;
-    qf[pos] = f;
+    qf[pos] = qfu[k];
 }
 
 // item_bucket[i] = bucket of work item i; one block per bucket.
@@ -551,7 +544,8 @@ __global__ __launch_bounds__(256) void k_stats_fold(const BlockStats* __restrict
 
 struct DistArgs {
     IndexView I;
-    const QPrep* qp;
+    QueryView Q;             // query arrays (FP64 data of rechecked pairs)
+    const uint32_t* qreq;    // request of each query segment
     const QF32* qf;
     const uint32_t* qsorted;
     const BucketInfo* binfo;
@@ -571,7 +565,8 @@ struct DistArgs {
 
 struct WaveLDS {
     uint32_t queue[2 * kWave];  // < 64 left over + one pair per lane
-    uint8_t sel[32];            // queries of the group being queued (push_set)
+    QF32 qrec[kWave];           // filter records of the item's query group
+    uint8_t sel[kWave];         // queries of the group being queued (push_set)
 };
 
 // Evaluates `cnt` <= 64 queued pairs from position `head` (one per lane) with
@@ -588,21 +583,13 @@ __device__ __forceinline__ uint32_t drain(WaveLDS& L, uint32_t head, uint32_t cn
     bool hit = false;
     uint32_t myreq = 0, qid = 0, qtraj = 0;
     if (act) {
-        const QPrep& p = A.qp[A.qsorted[qbase + ql]];
+        const uint32_t k = A.qsorted[qbase + ql];
+        myreq = A.qreq[k];
+        const Request& R = A.req[myreq];
         QCanon q;
-        q.x = p.x;
-        q.y = p.y;
-        q.z = p.z;
-        q.vx = p.vx;
-        q.vy = p.vy;
-        q.vz = p.vz;
-        q.ts = p.ts;
-        q.aq = p.aq;
-        q.bq = p.bq;
-        q.d = p.d;
-        myreq = p.req;
-        qid = p.qid;
-        qtraj = p.traj;
+        query_canon(A.Q, R, k, q);
+        qid = (uint32_t)(k - R.q_begin);
+        qtraj = A.Q.traj ? A.Q.traj[k] : 0u;
         const EntryF64 e = A.I.e64[i];
         hit = canon_eval<true>(q, e.x, e.y, e.z, e.vx, e.vy, e.vz, e.ts, e.te, &t_lo, &t_hi);
     }
@@ -682,21 +669,22 @@ __device__ __forceinline__ float lane_val(float v, uint32_t j) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)j));
 }
 
-// FP32 filter of one query (its QF32 record q, from a scalar load) against
-// the candidate held in this lane.  A pair can only be a result if the two
+// FP32 filter of one query (its QF32 record q, read from LDS at a wave-uniform
+// address, i.e. broadcast to every lane) against the candidate held in this
+// lane.  A pair can only be a result if the two
 // bounding spheres come within d (the error margins are folded into R and r)
 // and the outward-rounded time extents overlap strictly.  With kTime false
 // the caller has established that every pair of the slot overlaps in time;
 // with kUniform true, that every query's candidate range covers it.
 template <bool kUniform, bool kTime>
-__device__ __forceinline__ bool pass32(const f32x8& q, uint32_t cand, float ecx, float ecy,
+__device__ __forceinline__ bool pass32(const QF32& q, uint32_t cand, float ecx, float ecy,
                                        float ecz, float er, float ets, float ete) {
-    const float dx = ecx - q[0], dy = ecy - q[1], dz = ecz - q[2];
+    const float dx = ecx - q.cx, dy = ecy - q.cy, dz = ecz - q.cz;
     const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const float R = q[3] + er;
+    const float R = q.R + er;
     bool p = s <= R * R;
-    if (kTime) p = p & (q[4] < ete) & (ets < q[5]);
-    if (!kUniform) p = p & (cand >= __float_as_uint(q[6])) & (cand < __float_as_uint(q[7]));
+    if (kTime) p = p & (q.a32 < ete) & (ets < q.b32);
+    if (!kUniform) p = p & (cand >= q.lo) & (cand < q.hi);
     return p;
 }
 
@@ -717,30 +705,29 @@ __device__ __forceinline__ bool box_pass(const float (&b)[7], float cx, float cy
     return s <= Rr * Rr;
 }
 
-// Tests the queries whose bits are set in gm (query 32 h + bit of the group)
+// Tests the queries whose bits are set in mk (query j = bit j of the group)
 // against the candidate held in the lane.  Queries are taken from the highest
 // down and each outcome is shifted in at the bottom (bits = 2 bits + pass), so
-// bit p of the result belongs to the p-th lowest query of gm.  gm is wave
-// uniform: the walk over its bits and the loads of the group's query records
-// qg are scalar (the records stay in the scalar cache for the whole item).
+// bit p of the result belongs to the p-th lowest query of mk.  mk is wave
+// uniform: the walk over its bits is scalar; the query records come from LDS.
 template <bool kUniform, bool kTime>
-__device__ __forceinline__ uint32_t test_set(ConstE32 qg, uint32_t h, uint32_t gm,
-                                             uint32_t cand, float ecx, float ecy, float ecz,
-                                             float er, float ets, float ete) {
-    uint32_t bits = 0;
-    while (gm) {
-        const uint32_t ja = 31u - (uint32_t)__builtin_clz(gm);
-        gm ^= 1u << ja;
-        const f32x8 qa = qg[32u * h + ja];
-        const uint32_t pa = pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
-        if (gm) {
-            const uint32_t jb = 31u - (uint32_t)__builtin_clz(gm);
-            gm ^= 1u << jb;
-            const f32x8 qb = qg[32u * h + jb];
-            const uint32_t pb = pass32<kUniform, kTime>(qb, cand, ecx, ecy, ecz, er, ets, ete);
+__device__ __forceinline__ uint64_t test_set(const WaveLDS& L, uint64_t mk, uint32_t cand,
+                                             float ecx, float ecy, float ecz, float er, float ets,
+                                             float ete) {
+    uint64_t bits = 0;
+    while (mk) {
+        const uint32_t ja = 63u - (uint32_t)__builtin_clzll(mk);
+        mk ^= 1ull << ja;
+        const QF32 qa = L.qrec[ja];
+        if (mk) {
+            const uint32_t jb = 63u - (uint32_t)__builtin_clzll(mk);
+            mk ^= 1ull << jb;
+            const QF32 qb = L.qrec[jb];
+            const uint64_t pa = pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
+            const uint64_t pb = pass32<kUniform, kTime>(qb, cand, ecx, ecy, ecz, er, ets, ete);
             bits = 4u * bits + 2u * pa + pb;
         } else {
-            bits = 2u * bits + pa;
+            bits = 2u * bits + (uint64_t)pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
         }
     }
     return bits;
@@ -749,21 +736,20 @@ __device__ __forceinline__ uint32_t test_set(ConstE32 qg, uint32_t h, uint32_t g
 // Queues the pairs recorded in bits (see test_set) for the candidate of the
 // lane, one pair per lane per round.
 __device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                         uint32_t cand, uint32_t bits, uint32_t gm, uint32_t h) {
+                                         uint32_t cand, uint64_t bits, uint64_t mk) {
     const uint32_t lane = __lane_id();
-    // ascending list of the queries of gm
+    // ascending list of the queries of mk
     wave_sync();
-    if (lane < 32 && ((gm >> lane) & 1u))
-        L.sel[__popc(gm & ((1u << lane) - 1u))] = (uint8_t)(32u * h + lane);
+    if ((mk >> lane) & 1ull) L.sel[__popcll(mk & lanemask_lt())] = (uint8_t)lane;
     wave_sync();
     const uint32_t code = (cand - S.c0) << 6;
-    uint32_t b = bits;
+    uint64_t b = bits;
     for (;;) {
         const bool act = b != 0;
         const uint64_t m = ballot(act);
         if (!m) break;
         if (act) {
-            const uint32_t j = L.sel[__builtin_ctz(b)];
+            const uint32_t j = L.sel[__builtin_ctzll(b)];
             L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
             b &= b - 1u;
         }
@@ -772,19 +758,13 @@ __device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemStat
     }
 }
 
-// One 64-candidate slot against the queries of mask mk, 32 at a time.
+// One 64-candidate slot against the queries of mask mk.
 template <bool kUniform, bool kTime>
 __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                          ConstE32 qg, uint64_t mk, uint32_t cand, float ecx,
-                                          float ecy, float ecz, float er, float ets, float ete) {
-#pragma unroll
-    for (uint32_t h = 0; h < 2; ++h) {
-        const uint32_t gm = (uint32_t)(mk >> (32u * h));
-        if (!gm) continue;
-        const uint32_t bits =
-            test_set<kUniform, kTime>(qg, h, gm, cand, ecx, ecy, ecz, er, ets, ete);
-        if (ballot(bits != 0u)) push_set(L, A, S, cand, bits, gm, h);
-    }
+                                          uint64_t mk, uint32_t cand, float ecx, float ecy,
+                                          float ecz, float er, float ets, float ete) {
+    const uint64_t bits = test_set<kUniform, kTime>(L, mk, cand, ecx, ecy, ecz, er, ets, ete);
+    if (ballot(bits != 0u)) push_set(L, A, S, cand, bits, mk);
 }
 
 // FP32 form: the wave takes the chunk kCpl * 64 candidates at a time (kCpl
@@ -793,8 +773,8 @@ __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemSta
 // one of the next 64 blocks (broadcast from its registers by readlane, so the
 // loop over blocks makes no memory access).  Each block's box is first tested
 // against every query (one lane per query), and only the queries that pass
-// are tested against the block's entries, their records coming from scalar
-// loads.  When every
+// are tested against the block's entries, their records read from the wave's
+// LDS copy of the group.  When every
 // candidate of the bucket overlaps every query of the group in time, the
 // per-pair time test is skipped: exact, since the outward-rounded FP32 times
 // then overlap as well.
@@ -802,7 +782,6 @@ template <bool kUniform>
 __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
                                                 const BucketInfo& bi) {
     const uint32_t lane = __lane_id();
-    const ConstE32 qg = (ConstE32)(A.qf + S.qbase);
     const bool has = lane < S.nq;
     QReg q = {0.f, 0.f, 0.f, 0.f, -INFINITY, INFINITY, 0u, 0u};
     if (has) {
@@ -815,7 +794,9 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
         q.b = f.b32;
         q.lo = f.lo;
         q.hi = f.hi;
+        L.qrec[lane] = f;
     }
+    wave_sync();
     const bool all_overlap =
         ballot(((double)q.a < bi.tmin_te) && (bi.tmax_ts < (double)q.b)) == ~0ull;
     const uint64_t has_mask = ballot(has);
@@ -873,10 +854,10 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
             S.ftests += (uint64_t)__popcll(mk) * (uint64_t)__popcll(vm);
             // the time test can be dropped only on full slots
             if (all_overlap && vm == ~0ull)
-                slot_fp32<kUniform, false>(L, A, S, qg, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                slot_fp32<kUniform, false>(L, A, S, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
                                            ets[k], ete[k]);
             else
-                slot_fp32<kUniform, true>(L, A, S, qg, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                slot_fp32<kUniform, true>(L, A, S, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
                                           ets[k], ete[k]);
         }
     }
@@ -885,21 +866,19 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
 // Plain FP64 form: one query segment per lane, every candidate of the chunk
 // streamed through scalar loads and tested with the canonical predicate.
 template <bool kUniform>
-__device__ __forceinline__ void scan_chunk_fp64(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                                bool has, const QPrep& p) {
-    const uint32_t qlo = p.lo, qhi = p.hi;
+__device__ __forceinline__ void scan_chunk_fp64(WaveLDS& L, const DistArgs& A, ItemState& S) {
+    const uint32_t lane = __lane_id();
+    const bool has = lane < S.nq;
     ConstE64 ce = (ConstE64)(A.I.e64);
-    QCanon q;
-    q.x = p.x;
-    q.y = p.y;
-    q.z = p.z;
-    q.vx = p.vx;
-    q.vy = p.vy;
-    q.vz = p.vz;
-    q.ts = p.ts;
-    q.aq = has ? p.aq : 1.0;
-    q.bq = has ? p.bq : 0.0;  // empty window: never a member
-    q.d = p.d;
+    QCanon q = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0};  // empty window: never a member
+    uint32_t qlo = 0, qhi = 0;
+    if (has) {
+        const uint32_t k = A.qsorted[S.qbase + lane];
+        query_canon(A.Q, A.req[A.qreq[k]], k, q);
+        const QF32 f = A.qf[S.qbase + lane];
+        qlo = f.lo;
+        qhi = f.hi;
+    }
     for (uint32_t i = S.c0; i < S.c1; ++i) {
         const f64x4 e0 = ce[2 * i], e1 = ce[2 * i + 1];  // x, y, z, vx | vy, vz, ts, te
         bool pass = canon_eval<false>(q, e0[0], e0[1], e0[2], e0[3], e1[0], e1[1], e1[2], e1[3],
@@ -913,7 +892,7 @@ __device__ __forceinline__ void scan_chunk_fp64(WaveLDS& L, const DistArgs& A, I
 }
 
 template <int kPrec>
-__global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_distance(DistArgs A) {
     __shared__ WaveLDS wl[kWavesPerBlock];
     WaveLDS& L = wl[threadIdx.x / kWave];
     const uint32_t lane = __lane_id();
@@ -975,11 +954,8 @@ __global__ __launch_bounds__(kBlock) void k_distance(DistArgs A) {
             if (all_cover) scan_chunk_fp32<true>(L, A, S, bi);
             else scan_chunk_fp32<false>(L, A, S, bi);
         } else {
-            const bool has = lane < S.nq;
-            QPrep p = {};
-            if (has) p = A.qp[A.qsorted[S.qbase + lane]];
-            if (all_cover) scan_chunk_fp64<true>(L, A, S, has, p);
-            else scan_chunk_fp64<false>(L, A, S, has, p);
+            if (all_cover) scan_chunk_fp64<true>(L, A, S);
+            else scan_chunk_fp64<false>(L, A, S);
         }
         if (S.qn) {
             wave_sync();
@@ -1031,7 +1007,7 @@ int grow(T** p, size_t* cap, size_t need) {
 }  // namespace
 
 Workspace::~Workspace() {
-    for (void* p : {(void*)qp, (void*)qkey, (void*)qslot, (void*)qsorted, (void*)qf, (void*)qstage,
+    for (void* p : {(void*)qfu, (void*)qreq, (void*)qkey, (void*)qslot, (void*)qsorted, (void*)qf, (void*)qstage,
                     (void*)qtraj_stage, (void*)req, (void*)req_ctr, (void*)b_count, (void*)b_lo,
                     (void*)b_hi, (void*)b_start, (void*)b_item, (void*)b_nch, (void*)b_clen,
                     (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res, (void*)hdr,
@@ -1064,15 +1040,17 @@ int ws_init(Workspace* w) {
 }
 
 int ws_reserve(Workspace* w, size_t nq, size_t nreq) {
-    if (w->q_cap < nq || !w->qp) {
-        for (void* p : {(void*)w->qp, (void*)w->qkey, (void*)w->qslot, (void*)w->qsorted,
-                        (void*)w->qf})
+    if (w->q_cap < nq || !w->qfu) {
+        for (void* p : {(void*)w->qfu, (void*)w->qreq, (void*)w->qkey, (void*)w->qslot,
+                        (void*)w->qsorted, (void*)w->qf})
             dfree(p);
-        w->qp = nullptr;
+        w->qfu = nullptr;
+        w->qreq = nullptr;
         w->qf = nullptr;
         w->qkey = w->qslot = w->qsorted = nullptr;
         w->q_cap = 0;
-        TDS_TRY(dmalloc(&w->qp, nq));
+        TDS_TRY(dmalloc(&w->qfu, nq));
+        TDS_TRY(dmalloc(&w->qreq, nq));
         TDS_TRY(dmalloc(&w->qkey, nq));
         TDS_TRY(dmalloc(&w->qslot, nq));
         TDS_TRY(dmalloc(&w->qsorted, nq));
@@ -1158,11 +1136,12 @@ int stage_queries(const tds_segments* Q, QueryView* V, hipStream_t s, double** s
     return TDS_OK;
 }
 
-DistArgs dist_args(const tds_index* idx, const Workspace* w, tds_result* out, uint64_t win_lo,
-                   uint32_t item_begin, uint32_t item_end, uint32_t* item_count) {
+DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q, tds_result* out,
+                   uint64_t win_lo, uint32_t item_begin, uint32_t item_end, uint32_t* item_count) {
     DistArgs A;
     A.I = view_of(idx);
-    A.qp = w->qp;
+    A.Q = Q;
+    A.qreq = w->qreq;
     A.qsorted = w->qsorted;
     A.qf = w->qf;
     A.binfo = w->binfo;
@@ -1213,31 +1192,33 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
     hipLaunchKernelGGL(k_zero, dim3(ceil_div(zn, kBlock)), dim3(kBlock), 0, s, w->hdr, w->b_count,
                        w->b_lo, w->b_hi, nb, w->req_ctr, r_cap);
     const uint32_t qblocks = std::max(1u, ceil_div(q_grid, kBlock));
-    hipLaunchKernelGGL(k_qprep, dim3(qblocks), dim3(kBlock), 0, s, Q, w->desc, w->req, I, w->qp,
+    hipLaunchKernelGGL(k_qprep, dim3(qblocks), dim3(kBlock), 0, s, Q, w->desc, w->req, I, w->qfu,
+                       w->qreq,
                        w->qkey, w->qslot, w->b_count, w->b_hi, shift, w->hdr);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_lo, w->b_hi,
                        idx->bin_first, idx->min_te, idx->max_ts, idx->m, shift, nb, chunk, w->b_start,
                        w->b_item, w->b_nch, w->b_clen, w->binfo, w->hdr);
     hipLaunchKernelGGL(k_scatter, dim3(qblocks), dim3(kBlock), 0, s, w->desc, w->qkey, w->qslot,
-                       w->b_start, w->qp, w->qsorted, w->qf);
+                       w->b_start, w->qfu, w->qsorted, w->qf);
     hipLaunchKernelGGL(k_item_fill, dim3(nb), dim3(kBlock), 0, s, w->binfo, w->desc,
                        w->item_bucket, w->hdr);
     hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, kParts), 256)), dim3(256), 0, s,
                        w->wctr, w->req_ctr, r_cap);
     TDS_HIP(hipGetLastError());
-    return launch_distance(prec, dist_args(idx, w, out, 0, 0, 0xFFFFFFFFu, item_count), grid_waves,
-                           s, ev_begin, ev_end);
+    return launch_distance(prec, dist_args(idx, w, Q, out, 0, 0, 0xFFFFFFFFu, item_count),
+                           grid_waves, s, ev_begin, ev_end);
 }
 
 // Re-runs the distance kernel over work items [i0, i1) keeping result
 // positions [win_lo, win_lo + capacity) (incremental processing).
-int enqueue_range(const tds_index* idx, Workspace* w, int prec, uint32_t r_cap, tds_result* out,
+int enqueue_range(const tds_index* idx, Workspace* w, const QueryView& Q, int prec, uint32_t r_cap,
+                  tds_result* out,
                   uint64_t win_lo, uint32_t i0, uint32_t i1, uint32_t grid_waves, hipStream_t s,
                   hipEvent_t ev_begin, hipEvent_t ev_end) {
     hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, kParts), 256)), dim3(256), 0, s,
                        w->wctr, w->req_ctr, r_cap);
     TDS_HIP(hipGetLastError());
-    return launch_distance(prec, dist_args(idx, w, out, win_lo, i0, i1, nullptr), grid_waves, s,
+    return launch_distance(prec, dist_args(idx, w, Q, out, win_lo, i0, i1, nullptr), grid_waves, s,
                            ev_begin, ev_end);
 }
 
@@ -1489,7 +1470,7 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
             }
             for (auto& win : windows) {
                 if (win.second == 0) continue;
-                TDS_TRY(enqueue_range(idx, w, prec, 1, res, win.first, i0, i1,
+                TDS_TRY(enqueue_range(idx, w, V, prec, 1, res, win.first, i0, i1,
                                       std::min(grid_waves, i1 - i0), s, w->ev0, w->ev1));
                 TDS_HIP(hipMemcpyAsync(out + written, res, win.second * sizeof(tds_result),
                                        hipMemcpyDeviceToHost, s));

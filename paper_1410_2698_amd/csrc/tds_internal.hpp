@@ -57,26 +57,11 @@ struct alignas(32) BlockBox {
 static_assert(sizeof(BlockBox) == 32, "BlockBox layout");
 constexpr uint32_t kBoxShift = 6;  // log2 of the entries per box (one wave)
 
-// Prepared query segment (one per query segment of a search).
-struct alignas(16) QPrep {
-    // canonical FP64 data
-    double x, y, z, vx, vy, vz;
-    double ts;          // original t_start (positions are relative to it)
-    double aq, bq;      // segment clipped to the window: max(ts, t_start), min(te, t_end)
-    double d;
-    // FP32 filter data
-    float cx, cy, cz, R; // sphere of the clipped segment; R >= r + d + margins
-    float a32, b32;      // aq rounded down, bq rounded up
-    uint32_t lo, hi;     // candidate range [lo, hi) in sorted entry positions
-    uint32_t qid;        // query segment id reported in records (request-local)
-    uint32_t traj;
-    uint32_t req;        // request of the segment
-    uint32_t pad;
-};
-static_assert(sizeof(QPrep) % 16 == 0, "QPrep layout");
-
-// FP32 filter record of a query segment in bucket order (32 bytes: one
-// wave-uniform scalar load).
+// FP32 filter record of a query segment (32 bytes: one wave-uniform scalar
+// load), written by the preparation kernel in query order and copied into
+// bucket order.  The FP64 data of a query segment is not stored: where it is
+// needed (recheck, plain form) it is derived again from the query arrays by
+// the same operations.
 struct alignas(32) QF32 {
     float cx, cy, cz, R;  // sphere of the clipped segment, R >= r + d + margins
     float a32, b32;       // clipped window rounded outwards
@@ -164,7 +149,8 @@ struct Workspace {
     int device = 0;
     // query-side buffers, sized for `q_cap` query segments and `r_cap` requests
     size_t q_cap = 0, r_cap = 0, item_cap = 0, res_cap = 0;
-    QPrep* qp = nullptr;
+    QF32* qfu = nullptr;            // filter records in query order
+    uint32_t* qreq = nullptr;       // request of each query segment
     uint32_t* qkey = nullptr;
     uint32_t* qslot = nullptr;
     uint32_t* qsorted = nullptr;
