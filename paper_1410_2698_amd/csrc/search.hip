@@ -705,30 +705,22 @@ __device__ __forceinline__ bool box_pass(const float (&b)[7], float cx, float cy
     return s <= Rr * Rr;
 }
 
-// Tests the queries whose bits are set in mk (query j = bit j of the group)
-// against the candidate held in the lane.  Queries are taken from the highest
-// down and each outcome is shifted in at the bottom (bits = 2 bits + pass), so
-// bit p of the result belongs to the p-th lowest query of mk.  mk is wave
-// uniform: the walk over its bits is scalar; the query records come from LDS.
+// Tests the queries whose bits are set in mk (query j = bit j of the group,
+// at most 32 of them) against the candidate held in the lane.  Queries are
+// taken from the highest down and each outcome is shifted in at the bottom
+// (bits = 2 bits + pass), so bit p of the result belongs to the p-th lowest
+// query of mk.  mk is wave uniform: the walk over its bits is scalar; the
+// query records are read from LDS at a wave-uniform address.
 template <bool kUniform, bool kTime>
-__device__ __forceinline__ uint64_t test_set(const WaveLDS& L, uint64_t mk, uint32_t cand,
+__device__ __forceinline__ uint32_t test_set(const WaveLDS& L, uint64_t mk, uint32_t cand,
                                              float ecx, float ecy, float ecz, float er, float ets,
                                              float ete) {
-    uint64_t bits = 0;
+    uint32_t bits = 0;
     while (mk) {
-        const uint32_t ja = 63u - (uint32_t)__builtin_clzll(mk);
-        mk ^= 1ull << ja;
-        const QF32 qa = L.qrec[ja];
-        if (mk) {
-            const uint32_t jb = 63u - (uint32_t)__builtin_clzll(mk);
-            mk ^= 1ull << jb;
-            const QF32 qb = L.qrec[jb];
-            const uint64_t pa = pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
-            const uint64_t pb = pass32<kUniform, kTime>(qb, cand, ecx, ecy, ecz, er, ets, ete);
-            bits = 4u * bits + 2u * pa + pb;
-        } else {
-            bits = 2u * bits + (uint64_t)pass32<kUniform, kTime>(qa, cand, ecx, ecy, ecz, er, ets, ete);
-        }
+        const uint32_t j = 63u - (uint32_t)__builtin_clzll(mk);
+        mk ^= 1ull << j;
+        const QF32 q = L.qrec[j];
+        bits = 2u * bits + (uint32_t)pass32<kUniform, kTime>(q, cand, ecx, ecy, ecz, er, ets, ete);
     }
     return bits;
 }
@@ -736,20 +728,20 @@ __device__ __forceinline__ uint64_t test_set(const WaveLDS& L, uint64_t mk, uint
 // Queues the pairs recorded in bits (see test_set) for the candidate of the
 // lane, one pair per lane per round.
 __device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                         uint32_t cand, uint64_t bits, uint64_t mk) {
+                                         uint32_t cand, uint32_t bits, uint64_t mk) {
     const uint32_t lane = __lane_id();
     // ascending list of the queries of mk
     wave_sync();
     if ((mk >> lane) & 1ull) L.sel[__popcll(mk & lanemask_lt())] = (uint8_t)lane;
     wave_sync();
     const uint32_t code = (cand - S.c0) << 6;
-    uint64_t b = bits;
+    uint32_t b = bits;
     for (;;) {
         const bool act = b != 0;
         const uint64_t m = ballot(act);
         if (!m) break;
         if (act) {
-            const uint32_t j = L.sel[__builtin_ctzll(b)];
+            const uint32_t j = L.sel[__builtin_ctz(b)];
             L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
             b &= b - 1u;
         }
@@ -758,13 +750,20 @@ __device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemStat
     }
 }
 
-// One 64-candidate slot against the queries of mask mk.
+// One 64-candidate slot against the queries of mask mk, at most 32 at a time
+// (more than 32 survivors of one block box is rare: then the queries of lanes
+// 0-31 and 32-63 go in turn).
 template <bool kUniform, bool kTime>
 __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
                                           uint64_t mk, uint32_t cand, float ecx, float ecy,
                                           float ecz, float er, float ets, float ete) {
-    const uint64_t bits = test_set<kUniform, kTime>(L, mk, cand, ecx, ecy, ecz, er, ets, ete);
-    if (ballot(bits != 0u)) push_set(L, A, S, cand, bits, mk);
+    while (mk) {
+        // all of mk, or its queries 0..31 first when it has more than 32
+        const uint64_t part = (__popcll(mk) > 32) ? (mk & 0xFFFFFFFFull) : mk;
+        mk ^= part;
+        const uint32_t bits = test_set<kUniform, kTime>(L, part, cand, ecx, ecy, ecz, er, ets, ete);
+        if (ballot(bits != 0u)) push_set(L, A, S, cand, bits, part);
+    }
 }
 
 // FP32 form: the wave takes the chunk kCpl * 64 candidates at a time (kCpl
@@ -1014,6 +1013,8 @@ Workspace::~Workspace() {
                     (void*)wctr, (void*)bstats, (void*)desc})
         dfree(p);
     if (hdr_host) (void)hipHostFree(hdr_host);
+    if (req_host) (void)hipHostFree(req_host);
+    if (rc_host) (void)hipHostFree(rc_host);
     if (desc_host) (void)hipHostFree(desc_host);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -1060,11 +1061,17 @@ int ws_reserve(Workspace* w, size_t nq, size_t nreq) {
     if (w->r_cap < nreq || !w->req) {
         dfree(w->req);
         dfree(w->req_ctr);
+        if (w->req_host) (void)hipHostFree(w->req_host);
+        if (w->rc_host) (void)hipHostFree(w->rc_host);
         w->req = nullptr;
         w->req_ctr = nullptr;
+        w->req_host = nullptr;
+        w->rc_host = nullptr;
         w->r_cap = 0;
         TDS_TRY(dmalloc(&w->req, nreq));
         TDS_TRY(dmalloc(&w->req_ctr, nreq));
+        TDS_HIP(hipHostMalloc((void**)&w->req_host, nreq * sizeof(Request), hipHostMallocDefault));
+        TDS_HIP(hipHostMalloc((void**)&w->rc_host, nreq * sizeof(ReqCounter), hipHostMallocDefault));
         w->r_cap = nreq;
     }
     return TDS_OK;
@@ -1285,6 +1292,8 @@ int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t n
         TDS_TRY(enqueue_pipeline(idx, w, V, V.n, nreq, prec, chunk, grid_waves, out, w->item_count, s,
                                  w->ev0, w->ev1));
         TDS_HIP(hipMemcpyAsync(w->hdr_host, w->hdr, sizeof(SearchHeader), hipMemcpyDeviceToHost, s));
+        TDS_HIP(hipMemcpyAsync(w->rc_host, w->req_ctr, nreq * sizeof(ReqCounter),
+                               hipMemcpyDeviceToHost, s));
         TDS_HIP(hipStreamSynchronize(s));
         *h_out = *w->hdr_host;
         float ms = 0.f;
@@ -1414,15 +1423,15 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     R.t_end = t_end;
     R.out_offset = 0;
     R.out_capacity = dev_cap;
-    TDS_HIP(hipMemcpyAsync(w->req, &R, sizeof(Request), hipMemcpyHostToDevice, s));
+    *w->req_host = R;
+    TDS_HIP(hipMemcpyAsync(w->req, w->req_host, sizeof(Request), hipMemcpyHostToDevice, s));
 
     tds_stats st{};
     st.query_segments = Q->n;
     SearchHeader h{};
     // pass 1: every item, result window [0, dev_cap)
     TDS_TRY(run_batch(idx, w, V, 1, prec, chunk, grid_waves, res, s, &st, &h));
-    ReqCounter rc{};
-    TDS_HIP(hipMemcpy(&rc, w->req_ctr, sizeof(ReqCounter), hipMemcpyDeviceToHost));
+    const ReqCounter rc = w->rc_host[0];
     const uint32_t n_items = h.n_items;
     st.active_segments = h.active;
     st.work_items = n_items;
@@ -1537,7 +1546,7 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
         TDS_TRY(grow(&w->res, &w->res_cap, (size_t)std::max<uint64_t>(out_capacity, 1)));
         res = w->res;
     }
-    std::vector<Request> R(nreq);
+    Request* R = w->req_host;
     for (uint32_t r = 0; r < nreq; ++r) {
         R[r].q_begin = reqs[r].q_begin;
         R[r].q_count = reqs[r].q_count;
@@ -1548,13 +1557,12 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
         R[r].out_capacity = reqs[r].out_capacity;
         R[r].pad = 0;
     }
-    TDS_HIP(hipMemcpyAsync(w->req, R.data(), nreq * sizeof(Request), hipMemcpyHostToDevice, s));
+    TDS_HIP(hipMemcpyAsync(w->req, R, nreq * sizeof(Request), hipMemcpyHostToDevice, s));
     tds_stats st{};
     st.query_segments = Q->n;
     SearchHeader h{};
     TDS_TRY(run_batch(idx, w, V, nreq, prec, chunk, grid_waves, res, s, &st, &h));
-    std::vector<ReqCounter> rc(nreq);
-    TDS_HIP(hipMemcpy(rc.data(), w->req_ctr, nreq * sizeof(ReqCounter), hipMemcpyDeviceToHost));
+    const ReqCounter* rc = w->rc_host;
     int status = TDS_OK;
     uint64_t total = 0;
     for (uint32_t r = 0; r < nreq; ++r) {
@@ -1568,7 +1576,7 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
                                        k * sizeof(tds_result), hipMemcpyDeviceToHost, s));
         }
     }
-    TDS_HIP(hipStreamSynchronize(s));
+    if (!dev_out) TDS_HIP(hipStreamSynchronize(s));
     st.active_segments = h.active;
     st.work_items = h.n_items;
     st.candidate_tests = h.tests;

@@ -160,6 +160,8 @@ struct Workspace {
     size_t stage_cap = 0, traj_cap = 0;
     Request* req = nullptr;
     ReqCounter* req_ctr = nullptr;
+    Request* req_host = nullptr;       // pinned staging of the requests (r_cap)
+    ReqCounter* rc_host = nullptr;     // pinned mirror of the request counters (r_cap)
     // bucket tables (kMaxBuckets each)
     uint32_t* b_count = nullptr;
     uint32_t* b_lo = nullptr;
