@@ -221,6 +221,40 @@ __device__ inline uint32_t first_true(Pred pred, uint32_t m, uint32_t g) {
     return l;
 }
 
+// Two independent first_true searches whose first windows are loaded together.
+template <class P1, class P2>
+__device__ inline void first_true2(P1 p1, uint32_t g1, P2 p2, uint32_t g2, uint32_t m,
+                                   uint32_t* r1, uint32_t* r2) {
+    g1 = min(g1, m);
+    g2 = min(g2, m);
+    const uint32_t a1 = (g1 > 0) ? g1 - 1 : 0, a2 = (g2 > 0) ? g2 - 1 : 0;
+    bool w1[4], w2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        w1[k] = (a1 + k >= m) ? true : p1(a1 + k);
+        w2[k] = (a2 + k >= m) ? true : p2(a2 + k);
+    }
+    // answer inside a window: the first true after a false (or a true at 0)
+    auto inside = [](const bool (&w)[4], uint32_t a, uint32_t* r) {
+        if (w[0]) {
+            if (a == 0) {
+                *r = 0;
+                return true;
+            }
+            return false;
+        }
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if (w[k] && !w[k - 1]) {
+                *r = a + k;
+                return true;
+            }
+        return false;
+    };
+    if (!inside(w1, a1, r1)) *r1 = first_true(p1, m, g1);
+    if (!inside(w2, a2, r2)) *r2 = first_true(p2, m, g2);
+}
+
 // Bin of time t for a search starting point (any value is correct).
 __device__ inline uint32_t guess_bin(const IndexView& I, double t) {
     const double u = floor((t - I.t_min) / I.bw);
@@ -235,15 +269,14 @@ __device__ inline uint32_t guess_bin(const IndexView& I, double t) {
 // bq (bin j1), as one contiguous span [lo, hi) of index positions.
 __device__ inline void cand_range(const IndexView& I, double aq, double bq, uint32_t* lo,
                                   uint32_t* hi, uint32_t* j0o, uint32_t* j1o) {
-    // j0 = first j with cmax_te[j] > aq (m if none)
-    const uint32_t j0 =
-        first_true([&](uint32_t j) { return I.cmax_te[j] > aq; }, I.m, guess_bin(I, aq));
-    // L = number of bins j for which some entry of a bin >= j has
-    // t_start < bq (lo_ts, the minimum t_start over bins >= j, is
-    // non-decreasing), i.e. the first j with lo_ts[j] >= bq; entries before
-    // bin_first[L] are those of bins < L
-    const uint32_t L =
-        first_true([&](uint32_t j) { return I.lo_ts[j] >= bq; }, I.m, guess_bin(I, bq) + 1u);
+    // j0 = first j with cmax_te[j] > aq (m if none); L = number of bins j for
+    // which some entry of a bin >= j has t_start < bq (lo_ts, the minimum
+    // t_start over bins >= j, is non-decreasing), i.e. the first j with
+    // lo_ts[j] >= bq; entries before bin_first[L] are those of bins < L.
+    // Both searches read their first windows before either decides.
+    uint32_t j0, L;
+    first_true2([&](uint32_t j) { return I.cmax_te[j] > aq; }, guess_bin(I, aq),
+                [&](uint32_t j) { return I.lo_ts[j] >= bq; }, guess_bin(I, bq) + 1u, I.m, &j0, &L);
     *lo = (j0 < I.m) ? I.bin_first[j0] : I.n;
     *hi = I.bin_first[L];
     *j0o = j0;
@@ -311,9 +344,26 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                                                   uint32_t* __restrict__ qslot, uint32_t* b_count,
                                                   uint32_t* b_hi, uint32_t shift,
                                                   SearchHeader* hdr) {
+    // the first requests' starts in LDS: the request of a query segment is
+    // then found without a chain of dependent global loads
+    __shared__ uint64_t s_begin[kBlock];
+    const uint32_t nreq = desc->nreq;
+    if (threadIdx.x < nreq) s_begin[threadIdx.x] = req[threadIdx.x].q_begin;
+    __syncthreads();
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k < desc->nq) {
-        const uint32_t r = request_of(req, desc->nreq, k);
+        uint32_t r;
+        if (nreq <= kBlock) {
+            uint32_t l = 0, h = nreq;
+            while (h - l > 1) {
+                const uint32_t mid = (l + h) >> 1;
+                if (s_begin[mid] <= k) l = mid;
+                else h = mid;
+            }
+            r = l;
+        } else {
+            r = request_of(req, nreq, k);
+        }
         const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k], ts = Q.a[3][k];
         const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k], te = Q.a[7][k];
         const bool ok = finite(xs) && finite(ys) && finite(zs) && finite(ts) && finite(xe) &&
