@@ -97,10 +97,10 @@ enum {
     TDS_LAYOUT_TEMPORAL = 1,
     /* Spatial subdivision of every temporal bin (the idea of the
        spatiotemporal index, Sec. 4.3): inside a bin, entries are ordered by
-       the Morton code of their bounding-sphere centre on a 1024^3 grid over
-       the data's extent, and every aligned block of 64 entries carries a
-       bounding box, against which the FP32 form tests each query before it
-       tests the block's entries.  Bins, candidate ranges and results are
+       the Hilbert index of their bounding-sphere centre's cell on a 1024^3
+       grid over the data's extent, and every aligned block of 64 entries
+       carries a bounding box, against which the FP32 form tests each query
+       before it tests the block's entries.  Bins, candidate ranges and results are
        the same as with TDS_LAYOUT_TEMPORAL. */
     TDS_LAYOUT_SPATIAL = 2
 };
