@@ -4,11 +4,12 @@
 // sorts D by ascending start time and renumbers it); stability keeps equal
 // start times in input order, which makes the renumbering deterministic.
 //
-// One pass per digit, three kernels per pass:
+// One pass per digit, five kernels per pass:
 //   rs_hist    each block counts the digits of its 2048-key tile in LDS;
-//   rs_scan    one block turns the digit-major count table into exclusive
-//              offsets (digit d of block b starts after every smaller digit
-//              and after digit d of the blocks before b);
+//   rs_scan_*  turn the digit-major count table into exclusive offsets
+//              (digit d of block b starts after every smaller digit and after
+//              digit d of the blocks before b): tile sums, a scan of the tile
+//              sums, then each tile scanned from its offset;
 //   rs_scatter each block re-reads its tile and writes every key to its
 //              offset; the rank of a key among equal digits of its tile comes
 //              from wave ballots (wave-local) plus per-wave digit counts in
@@ -41,30 +42,80 @@ __global__ __launch_bounds__(kRsThreads) void rs_hist(const uint64_t* __restrict
     hist[(uint64_t)tid * nblocks + blockIdx.x] = h[tid];
 }
 
-// Exclusive scan of `len` u32 values in place with one block of 1024 threads:
-// every thread owns a contiguous run.
-__global__ __launch_bounds__(1024) void rs_scan(uint32_t* __restrict__ v, uint32_t len) {
-    __shared__ uint32_t part[1024];
+// Exclusive scan of `len` u32 values in place, in three coalesced steps:
+//   rs_scan_part  each block sums its tile of kScanTile values;
+//   rs_scan_top   one block scans the tile sums (looping over them);
+//   rs_scan_down  each block scans its tile again, offset by its tile's sum.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+// Inclusive scan of one value per thread over a block of kScanThreads
+// (Hillis-Steele in LDS); returns the inclusive prefix, *total the block sum.
+__device__ inline uint32_t block_scan(uint32_t x, uint32_t* lds, uint32_t* total) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t per = (len + 1023) / 1024;
-    const uint32_t b = tid * per;
-    const uint32_t e = min(len, b + per);
-    uint32_t s = 0;
-    for (uint32_t i = b; i < e; ++i) s += v[i];
-    part[tid] = s;
+    lds[tid] = x;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        uint32_t t = (tid >= off) ? part[tid - off] : 0u;
+    for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
+        const uint32_t t = (tid >= off) ? lds[tid - off] : 0u;
         __syncthreads();
-        part[tid] += t;
+        lds[tid] += t;
         __syncthreads();
     }
-    uint32_t run = part[tid] - s;
-    for (uint32_t i = b; i < e; ++i) {
-        uint32_t x = v[i];
-        v[i] = run;
-        run += x;
+    const uint32_t r = lds[tid];
+    *total = lds[kScanThreads - 1];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kScanThreads) void rs_scan_part(const uint32_t* __restrict__ v,
+                                                             uint32_t len,
+                                                             uint32_t* __restrict__ part) {
+    __shared__ uint32_t lds[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        const uint64_t i = base + (uint64_t)k * kScanThreads + threadIdx.x;
+        if (i < len) s += v[i];
+    }
+    uint32_t total;
+    block_scan(s, lds, &total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void rs_scan_top(uint32_t* __restrict__ part,
+                                                            uint32_t nparts) {
+    __shared__ uint32_t lds[kScanThreads];
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < nparts; b += kScanThreads) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t x = (i < nparts) ? part[i] : 0u;
+        uint32_t total;
+        const uint32_t inc = block_scan(x, lds, &total);
+        if (i < nparts) part[i] = carry + inc - x;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void rs_scan_down(uint32_t* __restrict__ v, uint32_t len,
+                                                             const uint32_t* __restrict__ part) {
+    __shared__ uint32_t lds[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    // thread t scans kScanPer consecutive values: t's values are
+    // base + t * kScanPer + [0, kScanPer)
+    uint32_t x[kScanPer];
+    uint32_t s = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        const uint64_t i = base + (uint64_t)threadIdx.x * kScanPer + k;
+        x[k] = (i < len) ? v[i] : 0u;
+        s += x[k];
+    }
+    uint32_t total;
+    uint32_t run = block_scan(s, lds, &total) - s + part[blockIdx.x];
+    for (int k = 0; k < kScanPer; ++k) {
+        const uint64_t i = base + (uint64_t)threadIdx.x * kScanPer + k;
+        if (i < len) v[i] = run;
+        run += x[k];
     }
 }
 
@@ -138,6 +189,12 @@ int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t*
     if (hlen >= (1ull << 32)) return TDS_E_INVALID;
     uint32_t* hist = nullptr;
     TDS_TRY(dmalloc(&hist, hlen));
+    const uint32_t nparts = ceil_div(hlen, kScanTile);
+    uint32_t* part = nullptr;
+    if (dmalloc(&part, nparts) != TDS_OK) {
+        dfree(hist);
+        return TDS_E_NOMEM;
+    }
     int passes = (key_bits + 7) / 8;
     uint64_t* ka = keys;
     uint32_t* va = vals;
@@ -148,7 +205,11 @@ int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t*
         const int shift = 8 * p;
         hipLaunchKernelGGL(rs_hist, dim3(nblocks), dim3(kRsThreads), 0, stream, ka, n, shift, hist,
                            nblocks);
-        hipLaunchKernelGGL(rs_scan, dim3(1), dim3(1024), 0, stream, hist, (uint32_t)hlen);
+        hipLaunchKernelGGL(rs_scan_part, dim3(nparts), dim3(kScanThreads), 0, stream, hist,
+                           (uint32_t)hlen, part);
+        hipLaunchKernelGGL(rs_scan_top, dim3(1), dim3(kScanThreads), 0, stream, part, nparts);
+        hipLaunchKernelGGL(rs_scan_down, dim3(nparts), dim3(kScanThreads), 0, stream, hist,
+                           (uint32_t)hlen, part);
         hipLaunchKernelGGL(rs_scatter, dim3(nblocks), dim3(kRsThreads), 0, stream, ka, va, kb, vb,
                            n, shift, hist, nblocks);
         if (hipGetLastError() != hipSuccess) {
@@ -167,6 +228,7 @@ int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t*
     }
     if (hipStreamSynchronize(stream) != hipSuccess) status = TDS_E_DEVICE;
     dfree(hist);
+    dfree(part);
     return status;
 }
 

@@ -82,6 +82,16 @@ def test_index_tables_match_oracle(m, layout):
     idx.close()
 
 
+@pytest.mark.parametrize("layout", ["temporal", "spatial"])
+def test_index_tables_large(layout):
+    """98,000 entries: the radix sort's count table spans several scan tiles."""
+    w = trajgen.tiny()
+    idx = build(w.D, 0, layout)
+    ob = oracle.bins(w.D.ts, w.D.te, idx.info()["num_bins"])
+    check_tables(idx.export(), ob, len(w.D), layout)
+    idx.close()
+
+
 def test_default_layout_is_spatial():
     w = trajgen.tiny(scale=0.01)
     idx = build(w.D)
