@@ -23,6 +23,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 
 RESULT_DTYPE = np.dtype([("q_seg", "<u4"), ("e_seg", "<u4"), ("q_traj", "<u4"),
                          ("e_traj", "<u4"), ("t_lo", "<f8"), ("t_hi", "<f8")])
+TRAJ_DTYPE = np.dtype([("q_traj", "<u4"), ("e_traj", "<u4"), ("t_lo", "<f8"), ("t_hi", "<f8")])
 
 _lib = None
 
@@ -158,3 +159,40 @@ def schedule(ts, te, m: int, qts, qte, t_start=-np.inf, t_end=np.inf, tables: Op
     lib.orc_schedule(m, _ptr(tb["first"]), _ptr(tb["last"]), _ptr(tb["min_ts"]), _ptr(tb["cmax_te"]),
                      nq, _ptr(qts), _ptr(qte), float(t_start), float(t_end), _ptr(lo), _ptr(hi))
     return lo, hi
+
+
+def self_join(D, d: float, t_start: float = -np.inf, t_end: float = np.inf,
+              threads: int = 0) -> np.ndarray:
+    """Every pair of segments of D from different trajectories within d during
+    the window (the all-against-all search that motivates the paper, Sec. 1),
+    each unordered pair once, lower segment id first: the brute-force search
+    of D against itself, keeping the records with q_seg < e_seg of different
+    trajectories (the pair's interval does not depend on which side is the
+    query: the evaluation is symmetric under exchanging the two segments)."""
+    res = search(D, D, d, t_start, t_end, threads=threads)
+    keep = (res["q_traj"] != res["e_traj"]) & (res["q_seg"] < res["e_seg"])
+    return sort_results(res[keep])
+
+
+def merge_trajectories(recs: np.ndarray) -> np.ndarray:
+    """Trajectory-level intervals: per (q_traj, e_traj), the union of the
+    records' [t_lo, t_hi] as maximal intervals, taking the records in t_lo
+    order and extending the current interval while the next one starts no
+    later than its end (touching intervals merge).  Sorted by
+    (q_traj, e_traj, t_lo).  A plain loop over the records."""
+    recs = np.asarray(recs)
+    order = np.lexsort((recs["t_lo"], recs["e_traj"], recs["q_traj"]))
+    out = []
+    cur = None
+    for i in order:
+        key = (int(recs["q_traj"][i]), int(recs["e_traj"][i]))
+        lo, hi = float(recs["t_lo"][i]), float(recs["t_hi"][i])
+        if cur is not None and cur[0] == key and lo <= cur[2]:
+            cur[2] = max(cur[2], hi)
+            continue
+        if cur is not None:
+            out.append((cur[0][0], cur[0][1], cur[1], cur[2]))
+        cur = [key, lo, hi]
+    if cur is not None:
+        out.append((cur[0][0], cur[0][1], cur[1], cur[2]))
+    return np.array(out, dtype=TRAJ_DTYPE)

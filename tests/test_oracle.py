@@ -388,3 +388,61 @@ def test_schedule_is_exact_on_aligned_unit_steps():
     lo, hi = oracle.schedule(D.ts, D.te, m, np.array([3.0]), np.array([4.0]), 0.0, 3.5, tables=tb)
     run = np.flatnonzero(sorted_ts == 3)
     assert (lo[0], hi[0]) == (run[0], run[-1] + 1)
+
+
+# ---------------------------------------------------------------- trajectory level
+
+def _recs(rows):
+    """Records from (q_traj, e_traj, t_lo, t_hi) rows (segment ids = row index)."""
+    a = np.zeros(len(rows), oracle.RESULT_DTYPE)
+    for i, (qt, et, lo, hi) in enumerate(rows):
+        a[i] = (i, 1000 + i, qt, et, lo, hi)
+    return a
+
+
+def test_merge_hand_example():
+    """Touching and overlapping intervals of one trajectory pair merge, a gap
+    separates, pairs stay apart, and the output is in (pair, t_lo) order."""
+    rows = [(1, 2, 2.9, 4.0), (1, 2, 1.0, 2.0), (2, 1, 0.0, 1.0), (1, 2, 0.0, 1.0),
+            (1, 2, 5.0, 5.0), (1, 2, 2.5, 3.0), (1, 3, 7.0, 8.0), (1, 2, 3.5, 3.75)]
+    got = oracle.merge_trajectories(_recs(rows))
+    want = [(1, 2, 0.0, 2.0), (1, 2, 2.5, 4.0), (1, 2, 5.0, 5.0), (1, 3, 7.0, 8.0),
+            (2, 1, 0.0, 1.0)]
+    assert [tuple(r) for r in got.tolist()] == want
+
+
+def test_merge_preserves_the_union():
+    """Random interval sets: the merged intervals are disjoint, separated by
+    gaps, have endpoints taken from the input, and cover exactly the points
+    the input intervals cover (checked at every endpoint and midpoint)."""
+    rng = np.random.default_rng(5)
+    rows = []
+    for _ in range(400):
+        qt, et = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+        lo = float(rng.integers(0, 60)) / 4.0
+        rows.append((qt, et, lo, lo + float(rng.integers(0, 8)) / 4.0))
+    recs = _recs(rows)
+    got = oracle.merge_trajectories(recs)
+    for (qt, et) in {(r[0], r[1]) for r in rows}:
+        ins = [(lo, hi) for a, b, lo, hi in rows if (a, b) == (qt, et)]
+        outs = [(r["t_lo"], r["t_hi"]) for r in got if (r["q_traj"], r["e_traj"]) == (qt, et)]
+        assert all(outs[i][1] < outs[i + 1][0] for i in range(len(outs) - 1))
+        ends = {x for iv in ins for x in iv}
+        assert all(lo in ends and hi in ends for lo, hi in outs)
+        probes = sorted(ends | {(a + b) / 2 for a, b in ins} | {x + 0.125 for x in ends})
+        for t in probes:
+            assert any(lo <= t <= hi for lo, hi in ins) == any(lo <= t <= hi for lo, hi in outs)
+
+
+def test_self_join_is_the_symmetric_half_of_the_full_search():
+    """Searching D against itself finds every cross-trajectory pair twice with
+    bitwise identical intervals; the self-join keeps one of each."""
+    w = trajgen.tiny(scale=0.05)
+    full = oracle.search(w.D, w.D, 6.0, 3.0, 30.0)
+    cross = full[full["q_traj"] != full["e_traj"]]
+    fwd = {(int(r["q_seg"]), int(r["e_seg"])): (r["t_lo"], r["t_hi"]) for r in cross}
+    for (a, b), iv in fwd.items():
+        assert fwd[(b, a)] == iv
+    sj = oracle.self_join(w.D, 6.0, 3.0, 30.0)
+    assert sj.size * 2 == cross.size > 50
+    assert np.all(sj["q_seg"] < sj["e_seg"]) and np.all(sj["q_traj"] != sj["e_traj"])
