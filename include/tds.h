@@ -246,6 +246,50 @@ int tds_search(const tds_index* index, const tds_segments* Q, double d,
                tds_stats* stats);
 
 /*
+ * Self-join of the indexed database (the "every trajectory against every
+ * other" search that motivates the paper, Sec. 1): every pair of entry
+ * segments of different trajectories that is within d during the window,
+ * each unordered pair once, as a record whose q_seg is the lower of the two
+ * segment ids (q_traj its trajectory).  Records, intervals, output and
+ * overflow behaviour as for tds_search with Q = the indexed segments; the
+ * query data is read from the index itself.  Each pair is tested once, from
+ * the entry stored first in the index.  Waits for `stream`.
+ * Errors: TDS_E_INVALID (bad pointers, d < 0 or NaN, t_start >= t_end),
+ * TDS_E_NOMEM, TDS_E_DEVICE.
+ */
+int tds_self_join(const tds_index* index, double d, double t_start, double t_end,
+                  tds_result* out, uint64_t capacity, uint64_t* n_out,
+                  const tds_search_params* params, void* stream, tds_stats* stats);
+
+/* One trajectory-level result: trajectories q_traj and e_traj are within d
+   throughout [t_lo, t_hi] (24 bytes). */
+typedef struct tds_traj_interval {
+    uint32_t q_traj;
+    uint32_t e_traj;
+    double t_lo;
+    double t_hi;
+} tds_traj_interval;
+
+/*
+ * Trajectory-level output: merges segment-level records into maximal time
+ * intervals per (q_traj, e_traj).  Two intervals of the same trajectory pair
+ * are merged when they overlap or touch (the next one starts no later than
+ * the current one ends), so consecutive segment pairs whose intervals meet at
+ * the shared timestep become one interval; endpoints are taken unchanged from
+ * the records.  Output sorted by (q_traj, e_traj, t_lo).  recs (n records,
+ * device memory if recs_on_device, else host) is only read; out holds
+ * `capacity` intervals (device memory if out_on_device).  *n_out is always set
+ * to the total; when it exceeds capacity, out holds the first `capacity`
+ * intervals in that order and the call returns TDS_E_OVERFLOW.  Runs on the
+ * current HIP device and waits for `stream`.
+ * Errors: TDS_E_INVALID (NULL pointers, n >= 2^32 - 1), TDS_E_NOMEM,
+ * TDS_E_DEVICE.
+ */
+int tds_merge_trajectories(const tds_result* recs, uint64_t n, int recs_on_device,
+                           tds_traj_interval* out, uint64_t capacity, int out_on_device,
+                           uint64_t* n_out, void* stream);
+
+/*
  * One request of a batch: a slice of the batch's query segments searched with
  * its own distance and window, writing into its own slice of the output.
  * Requests of a batch must tile the query segments in order: the first

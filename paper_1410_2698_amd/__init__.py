@@ -24,6 +24,8 @@ from ._lib import (TDS_E_OVERFLOW, TDS_OK, TDS_PREC_FP32_RECHECK, TDS_PREC_FP64,
 RESULT_DTYPE = np.dtype([("q_seg", "<u4"), ("e_seg", "<u4"), ("q_traj", "<u4"),
                          ("e_traj", "<u4"), ("t_lo", "<f8"), ("t_hi", "<f8")])
 
+TRAJ_DTYPE = np.dtype([("q_traj", "<u4"), ("e_traj", "<u4"), ("t_lo", "<f8"), ("t_hi", "<f8")])
+
 PRECISIONS = {"fp64": TDS_PREC_FP64, "fp32": TDS_PREC_FP32_RECHECK,
               "fp32_recheck": TDS_PREC_FP32_RECHECK}
 
@@ -196,6 +198,41 @@ class Index:
                 continue
             raise TdsError(status, "tds_search")
 
+
+    def self_join_raw(self, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
+                      out_ptr: int, capacity: int, out_on_device: bool, precision: str = "fp32",
+                      chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0):
+        """One call of tds_self_join into caller memory; returns (status, n_total, stats)."""
+        p = _search_params(precision, chunk, grid_waves)
+        p.out_on_device = 1 if out_on_device else 0
+        p.device_capacity = int(device_capacity)
+        n = ctypes.c_uint64()
+        st = _lib.tds_stats()
+        status = self._lib.tds_self_join(self._h, float(d), float(t_start), float(t_end),
+                                         ctypes.c_void_p(out_ptr), ctypes.c_uint64(capacity),
+                                         ctypes.byref(n), ctypes.byref(p), _current_stream(),
+                                         ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        return status, int(n.value), self.last_stats
+
+    def self_join(self, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
+                  capacity: Optional[int] = None, precision: str = "fp32",
+                  device_capacity: int = 0) -> np.ndarray:
+        """Self-join of the indexed segments (pairs of different trajectories,
+        each once, lower segment id first) into host memory; grows the buffer
+        on overflow."""
+        cap = 1 << 16 if capacity is None else int(capacity)
+        while True:
+            buf = np.empty(max(cap, 1), RESULT_DTYPE)
+            status, n, _ = self.self_join_raw(d, t_start, t_end, out_ptr=buf.ctypes.data,
+                                              capacity=cap, out_on_device=False,
+                                              precision=precision, device_capacity=device_capacity)
+            if status == TDS_OK:
+                return buf[:n].copy()
+            if status == TDS_E_OVERFLOW and capacity is None:
+                cap = n
+                continue
+            raise TdsError(status, "tds_self_join")
 
     def search_batch_raw(self, Q, requests, *, out_ptr: int, out_capacity: int,
                          out_on_device: bool, precision: str = "fp32", chunk: int = 0,
@@ -410,3 +447,32 @@ def sort_records(r: np.ndarray) -> np.ndarray:
     """Records in (q_seg, e_seg) order."""
     key = (r["q_seg"].astype(np.uint64) << np.uint64(32)) | r["e_seg"].astype(np.uint64)
     return r[np.argsort(key, kind="stable")]
+
+
+def merge_trajectories_raw(recs_ptr: int, n: int, recs_on_device: bool, out_ptr: int,
+                           capacity: int, out_on_device: bool):
+    """One call of tds_merge_trajectories; returns (status, n_total)."""
+    lib = load()
+    n_out = ctypes.c_uint64()
+    status = lib.tds_merge_trajectories(ctypes.c_void_p(recs_ptr), int(n), 1 if recs_on_device else 0,
+                                        ctypes.c_void_p(out_ptr), int(capacity),
+                                        1 if out_on_device else 0, ctypes.byref(n_out),
+                                        _current_stream())
+    return status, int(n_out.value)
+
+
+def merge_trajectories(records: np.ndarray, capacity: Optional[int] = None) -> np.ndarray:
+    """Trajectory-level intervals of host segment records (TRAJ_DTYPE array in
+    (q_traj, e_traj, t_lo) order), merged on the GPU."""
+    recs = np.ascontiguousarray(records, dtype=RESULT_DTYPE)
+    cap = max(recs.size, 1) if capacity is None else int(capacity)
+    while True:
+        out = np.empty(max(cap, 1), TRAJ_DTYPE)
+        status, n = merge_trajectories_raw(recs.ctypes.data, recs.size, False, out.ctypes.data,
+                                           cap, False)
+        if status == TDS_OK:
+            return out[:n].copy()
+        if status == TDS_E_OVERFLOW and capacity is None:
+            cap = n
+            continue
+        raise TdsError(status, "tds_merge_trajectories")

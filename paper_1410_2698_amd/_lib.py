@@ -79,6 +79,11 @@ class tds_server_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class tds_traj_interval(ctypes.Structure):
+    _fields_ = [("q_traj", ctypes.c_uint32), ("e_traj", ctypes.c_uint32),
+                ("t_lo", ctypes.c_double), ("t_hi", ctypes.c_double)]
+
+
 # exported name -> (restype, argtypes)
 SIGNATURES = {
     "tds_abi_version": (ctypes.c_uint32, []),
@@ -96,6 +101,13 @@ SIGNATURES = {
                                   c_u64_p, ctypes.POINTER(tds_search_params), ctypes.c_void_p,
                                   ctypes.POINTER(tds_stats)]),
     "tds_search_params_default": (None, [ctypes.POINTER(tds_search_params)]),
+    "tds_self_join": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_void_p, ctypes.c_uint64, c_u64_p,
+                                     ctypes.POINTER(tds_search_params), ctypes.c_void_p,
+                                     ctypes.POINTER(tds_stats)]),
+    "tds_merge_trajectories": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                              ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, c_u64_p,
+                                              ctypes.c_void_p]),
     "tds_last_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_stats)]),
     "tds_search_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments),
                                         ctypes.POINTER(tds_request), ctypes.c_uint32, ctypes.c_void_p,

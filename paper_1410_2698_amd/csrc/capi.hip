@@ -102,6 +102,26 @@ int tds_search(const tds_index* index, const tds_segments* Q, double d, double t
                             n_out, params, (hipStream_t)stream, stats);
 }
 
+int tds_self_join(const tds_index* index, double d, double t_start, double t_end,
+                  tds_result* out, uint64_t capacity, uint64_t* n_out,
+                  const tds_search_params* params, void* stream, tds_stats* stats) {
+    if (!index || !n_out) return TDS_E_INVALID;
+    *n_out = 0;
+    DeviceGuard g(index->device);
+    if (!g.ok) return TDS_E_DEVICE;
+    return tds::self_join_impl(const_cast<tds_index*>(index), d, t_start, t_end, out, capacity,
+                               n_out, params, (hipStream_t)stream, stats);
+}
+
+int tds_merge_trajectories(const tds_result* recs, uint64_t n, int recs_on_device,
+                           tds_traj_interval* out, uint64_t capacity, int out_on_device,
+                           uint64_t* n_out, void* stream) {
+    if (!n_out) return TDS_E_INVALID;
+    *n_out = 0;
+    return tds::merge_impl(recs, n, recs_on_device != 0, out, capacity, out_on_device != 0, n_out,
+                           (hipStream_t)stream);
+}
+
 int tds_last_stats(const tds_index* index, tds_stats* stats) {
     if (!index || !stats) return TDS_E_INVALID;
     tds_index* ix = const_cast<tds_index*>(index);

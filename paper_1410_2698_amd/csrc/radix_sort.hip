@@ -95,6 +95,7 @@ __global__ __launch_bounds__(kScanThreads) void rs_scan_top(uint32_t* __restrict
         if (i < nparts) part[i] = carry + inc - x;
         carry += total;
     }
+    if (threadIdx.x == 0) part[nparts] = carry;  // the grand total
 }
 
 __global__ __launch_bounds__(kScanThreads) void rs_scan_down(uint32_t* __restrict__ v, uint32_t len,
@@ -191,7 +192,7 @@ int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t*
     TDS_TRY(dmalloc(&hist, hlen));
     const uint32_t nparts = ceil_div(hlen, kScanTile);
     uint32_t* part = nullptr;
-    if (dmalloc(&part, nparts) != TDS_OK) {
+    if (dmalloc(&part, (size_t)nparts + 1) != TDS_OK) {
         dfree(hist);
         return TDS_E_NOMEM;
     }
@@ -230,6 +231,29 @@ int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t*
     dfree(hist);
     dfree(part);
     return status;
+}
+
+int exclusive_scan_u32(uint32_t* v, uint32_t len, uint32_t* total, hipStream_t stream) {
+    if (len == 0) {
+        if (total) *total = 0;
+        return TDS_OK;
+    }
+    const uint32_t nparts = ceil_div(len, kScanTile);
+    uint32_t* part = nullptr;
+    TDS_TRY(dmalloc(&part, (size_t)nparts + 1));
+    hipLaunchKernelGGL(rs_scan_part, dim3(nparts), dim3(kScanThreads), 0, stream, v, len, part);
+    hipLaunchKernelGGL(rs_scan_top, dim3(1), dim3(kScanThreads), 0, stream, part, nparts);
+    hipLaunchKernelGGL(rs_scan_down, dim3(nparts), dim3(kScanThreads), 0, stream, v, len, part);
+    int st = (hipGetLastError() == hipSuccess) ? TDS_OK : TDS_E_DEVICE;
+    if (st == TDS_OK && total) {
+        if (hipMemcpyAsync(total, part + nparts, sizeof(uint32_t), hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            st = TDS_E_DEVICE;
+    }
+    if (!total && hipStreamSynchronize(stream) != hipSuccess) st = TDS_E_DEVICE;
+    dfree(part);
+    return st;
 }
 
 }  // namespace tds

@@ -58,6 +58,12 @@ struct QueryView {
     const double* a[8];  // xs, ys, zs, ts, xe, ye, ze, te
     const uint32_t* traj;
     uint64_t n;
+    // self-join: query segment k is index entry k (its FP64 record, input id
+    // and trajectory); each unordered pair of entries of different
+    // trajectories is then tested once, from its entry of lower position
+    const EntryF64* ent;
+    const uint32_t* ent_id;
+    const uint32_t* ent_traj;
 };
 
 IndexView view_of(const tds_index* idx) {
@@ -321,15 +327,31 @@ __global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_
 // Canonical FP64 data of query segment k of request r, from the query
 // arrays (the same operations wherever it is needed, so bit-identical).
 __device__ inline void query_canon(const QueryView& Q, const Request& R, uint64_t k, QCanon& q) {
-    const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k], ts = Q.a[3][k];
-    const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k], te = Q.a[7][k];
-    const double dt = te - ts;
-    q.x = xs;
-    q.y = ys;
-    q.z = zs;
-    q.vx = (xe - xs) / dt;
-    q.vy = (ye - ys) / dt;
-    q.vz = (ze - zs) / dt;
+    double ts, te;
+    if (Q.ent) {
+        // the entry record holds the same velocity, computed the same way
+        const EntryF64 e = Q.ent[k];
+        q.x = e.x;
+        q.y = e.y;
+        q.z = e.z;
+        q.vx = e.vx;
+        q.vy = e.vy;
+        q.vz = e.vz;
+        ts = e.ts;
+        te = e.te;
+    } else {
+        const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k];
+        const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k];
+        ts = Q.a[3][k];
+        te = Q.a[7][k];
+        const double dt = te - ts;
+        q.x = xs;
+        q.y = ys;
+        q.z = zs;
+        q.vx = (xe - xs) / dt;
+        q.vy = (ye - ys) / dt;
+        q.vz = (ze - zs) / dt;
+    }
     q.ts = ts;
     q.aq = dmax(ts, R.t_start);
     q.bq = dmin(te, R.t_end);
@@ -364,10 +386,17 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
         } else {
             r = request_of(req, nreq, k);
         }
-        const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k], ts = Q.a[3][k];
-        const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k], te = Q.a[7][k];
-        const bool ok = finite(xs) && finite(ys) && finite(zs) && finite(ts) && finite(xe) &&
-                        finite(ye) && finite(ze) && finite(te) && te > ts;
+        bool ok = true;  // index entries were validated when the index was built
+        double ts;
+        if (Q.ent) {
+            ts = Q.ent[k].ts;
+        } else {
+            const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k];
+            const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k], te = Q.a[7][k];
+            ts = Q.a[3][k];
+            ok = finite(xs) && finite(ys) && finite(zs) && finite(ts) && finite(xe) &&
+                 finite(ye) && finite(ze) && finite(te) && te > ts;
+        }
         qslot[k] = kInactive;
         if (!ok) {
             atomicOr(&hdr->err, 1u);
@@ -377,6 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
             if (p.aq < p.bq) {
                 uint32_t lo, hi, j0, j1;
                 cand_range(I, p.aq, p.bq, &lo, &hi, &j0, &j1);
+                if (Q.ent) lo = max(lo, (uint32_t)k + 1u);  // self-join: entries after k
                 if (lo < hi) {
                     const double pax = p.x + p.vx * (p.aq - ts), pay = p.y + p.vy * (p.aq - ts),
                                  paz = p.z + p.vz * (p.aq - ts);
@@ -631,17 +661,36 @@ __device__ __forceinline__ uint32_t drain(WaveLDS& L, uint32_t head, uint32_t cn
     const uint32_t i = c0 + (pk >> 6);
     double t_lo = 0.0, t_hi = 0.0;
     bool hit = false;
-    uint32_t myreq = 0, qid = 0, qtraj = 0;
+    uint32_t myreq = 0, qid = 0, qtraj = 0, eid = 0, etraj = 0;
     if (act) {
         const uint32_t k = A.qsorted[qbase + ql];
         myreq = A.qreq[k];
         const Request& R = A.req[myreq];
         QCanon q;
         query_canon(A.Q, R, k, q);
-        qid = (uint32_t)(k - R.q_begin);
-        qtraj = A.Q.traj ? A.Q.traj[k] : 0u;
+        if (A.Q.ent) {
+            qid = A.Q.ent_id[k];
+            qtraj = A.Q.ent_traj[k];
+        } else {
+            qid = (uint32_t)(k - R.q_begin);
+            qtraj = A.Q.traj ? A.Q.traj[k] : 0u;
+        }
+        eid = A.I.seg_id[i];
+        etraj = A.I.traj[i];
         const EntryF64 e = A.I.e64[i];
         hit = canon_eval<true>(q, e.x, e.y, e.z, e.vx, e.vy, e.vz, e.ts, e.te, &t_lo, &t_hi);
+        if (A.Q.ent) {
+            // self-join: pairs of one trajectory are not results, and a record
+            // names the lower segment id first (its interval is symmetric)
+            hit = hit && qtraj != etraj;
+            if (qid > eid) {
+                const uint32_t t0 = qid, t1 = qtraj;
+                qid = eid;
+                qtraj = etraj;
+                eid = t0;
+                etraj = t1;
+            }
+        }
     }
     uint64_t hm = ballot(hit);
     const uint32_t nhit = (uint32_t)__popcll(hm);
@@ -658,9 +707,9 @@ __device__ __forceinline__ uint32_t drain(WaveLDS& L, uint32_t head, uint32_t cn
             if (pos >= A.win_lo && pos - A.win_lo < R.out_capacity) {
                 tds_result rec;
                 rec.q_seg = qid;
-                rec.e_seg = A.I.seg_id[i];
+                rec.e_seg = eid;
                 rec.q_traj = qtraj;
-                rec.e_traj = A.I.traj[i];
+                rec.e_traj = etraj;
                 rec.t_lo = t_lo;
                 rec.t_hi = t_hi;
                 A.out[R.out_offset + (pos - A.win_lo)] = rec;
@@ -1428,13 +1477,35 @@ int schedule_impl(tds_index* idx, const tds_segments* Q, double t_start, double 
     return st;
 }
 
+namespace {
+int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d, double t_start,
+                double t_end, tds_result* out, uint64_t capacity, uint64_t* n_out,
+                const tds_search_params* params, hipStream_t s, tds_stats* stats);
+}  // namespace
+
 int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start, double t_end,
                 tds_result* out, uint64_t capacity, uint64_t* n_out,
                 const tds_search_params* params, hipStream_t s, tds_stats* stats) {
-    const auto t_begin = std::chrono::steady_clock::now();
     if (!idx || !n_out) return TDS_E_INVALID;
     *n_out = 0;
     TDS_TRY(validate_segments_args(Q));
+    return search_core(idx, Q, false, d, t_start, t_end, out, capacity, n_out, params, s, stats);
+}
+
+int self_join_impl(tds_index* idx, double d, double t_start, double t_end, tds_result* out,
+                   uint64_t capacity, uint64_t* n_out, const tds_search_params* params,
+                   hipStream_t s, tds_stats* stats) {
+    if (!idx || !n_out) return TDS_E_INVALID;
+    *n_out = 0;
+    return search_core(idx, nullptr, true, d, t_start, t_end, out, capacity, n_out, params, s,
+                       stats);
+}
+
+namespace {
+int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d, double t_start,
+                double t_end, tds_result* out, uint64_t capacity, uint64_t* n_out,
+                const tds_search_params* params, hipStream_t s, tds_stats* stats) {
+    const auto t_begin = std::chrono::steady_clock::now();
     if (!valid_window(d, t_start, t_end)) return TDS_E_INVALID;
     if (capacity > 0 && !out) return TDS_E_INVALID;
     tds_search_params P;
@@ -1449,9 +1520,18 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     Workspace* w = acquire(idx);
     if (!w) return TDS_E_NOMEM;
     WsGuard guard{idx, w};
-    TDS_TRY(ws_reserve(w, Q->n, 1));
+    const uint64_t nq = self_join ? idx->n : Q->n;
+    TDS_TRY(ws_reserve(w, nq, 1));
     QueryView V{};
-    TDS_TRY(stage_queries(Q, &V, s, &w->qstage, &w->stage_cap, &w->qtraj_stage, &w->traj_cap, false));
+    if (self_join) {
+        V.n = nq;
+        V.ent = idx->e64;
+        V.ent_id = idx->seg_id;
+        V.ent_traj = idx->traj;
+    } else {
+        TDS_TRY(stage_queries(Q, &V, s, &w->qstage, &w->stage_cap, &w->qtraj_stage, &w->traj_cap,
+                              false));
+    }
 
     // result buffer
     uint64_t dev_cap;
@@ -1467,7 +1547,7 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     }
     Request R{};
     R.q_begin = 0;
-    R.q_count = Q->n;
+    R.q_count = nq;
     R.d = d;
     R.t_start = t_start;
     R.t_end = t_end;
@@ -1477,7 +1557,7 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     TDS_HIP(hipMemcpyAsync(w->req, w->req_host, sizeof(Request), hipMemcpyHostToDevice, s));
 
     tds_stats st{};
-    st.query_segments = Q->n;
+    st.query_segments = nq;
     SearchHeader h{};
     // pass 1: every item, result window [0, dev_cap)
     TDS_TRY(run_batch(idx, w, V, 1, prec, chunk, grid_waves, res, s, &st, &h));
@@ -1554,6 +1634,7 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
     }
     return status;
 }
+}  // namespace
 
 // Checks that the requests tile [0, nq) in order and their output slices fit.
 int validate_requests(const tds_request* reqs, uint32_t nreq, uint64_t nq, uint64_t out_cap) {

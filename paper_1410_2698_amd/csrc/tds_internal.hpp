@@ -343,6 +343,17 @@ int enqueue_search(const tds_index* idx, Workspace* w, const double* const* qarr
 int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
                 double t_end, tds_result* out, uint64_t capacity, uint64_t* n_out,
                 const tds_search_params* params, hipStream_t stream, tds_stats* stats);
+int self_join_impl(tds_index* idx, double d, double t_start, double t_end, tds_result* out,
+                   uint64_t capacity, uint64_t* n_out, const tds_search_params* params,
+                   hipStream_t s, tds_stats* stats);
+// Trajectory-level merge of result records (traj_merge.hip).
+int merge_impl(const tds_result* recs, uint64_t n, bool recs_dev, tds_traj_interval* out,
+               uint64_t capacity, bool out_dev, uint64_t* n_out, hipStream_t s);
+
+// Exclusive scan of len u32 values in place on `stream`; *total (may be
+// NULL) receives the sum, which costs a synchronisation (radix_sort.hip).
+int exclusive_scan_u32(uint32_t* v, uint32_t len, uint32_t* total, hipStream_t stream);
+
 int schedule_impl(tds_index* idx, const tds_segments* Q, double t_start, double t_end,
                   uint32_t* lo, uint32_t* hi, hipStream_t stream);
 // Index build implementation (index_build.hip).

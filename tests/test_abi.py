@@ -69,6 +69,13 @@ def test_argument_validation_without_device_work():
     assert lib.tds_index_destroy(None) == _lib.TDS_OK
     assert lib.tds_last_stats(None, None) == _lib.TDS_E_INVALID
     assert lib.tds_index_info_get(None, None) == _lib.TDS_E_INVALID
+    n_out = ctypes.c_uint64(5)
+    assert lib.tds_merge_trajectories(None, 0, 0, None, 0, 0, ctypes.byref(n_out), None) == _lib.TDS_OK
+    assert n_out.value == 0
+    assert lib.tds_merge_trajectories(None, 3, 0, None, 0, 0, ctypes.byref(n_out), None) == \
+        _lib.TDS_E_INVALID
+    assert lib.tds_self_join(None, 1.0, 0.0, 1.0, None, 0, ctypes.byref(n_out), None, None,
+                             None) == _lib.TDS_E_INVALID
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -78,6 +85,7 @@ def test_struct_layouts_match_header(tmp_path):
         "tds_search_params": _lib.tds_search_params, "tds_stats": _lib.tds_stats,
         "tds_index_info": _lib.tds_index_info, "tds_request": _lib.tds_request,
         "tds_server_params": _lib.tds_server_params, "tds_server_stats": _lib.tds_server_stats,
+        "tds_traj_interval": _lib.tds_traj_interval,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tds.h"', "int main(void){"]
     for name, cls in structs.items():
@@ -99,3 +107,4 @@ def test_struct_layouts_match_header(tmp_path):
             assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
     import paper_1410_2698_amd as tds
     assert int(got["tds_result"]) == tds.RESULT_DTYPE.itemsize == 32
+    assert int(got["tds_traj_interval"]) == tds.TRAJ_DTYPE.itemsize == 24
