@@ -15,14 +15,16 @@ value = strictly time-overlapping (query, entry) segment pairs resolved per
 second (index independent: every such pair is decided exactly).
 
 Also reported: candidate tests per kernel-second, queries/s (one query = one
-query trajectory at one d), the roofline of the distance kernel, the served
-form (open-loop replay of the request stream: Poisson arrivals at 5,000/s of
+query trajectory at one d), the roofline of the distance kernel, the
+self-join of the 1M entries at d = 25 with its trajectory-level merge, the
+served form (open-loop replay of the request stream: Poisson arrivals at 5,000/s of
 query trajectories of 5-400 segments with random windows and d in [1, 25],
 through the serving loop) and the plain form (FP64 canonical test of every
 candidate, one request per call, host memory in and out) on the same stream,
 each with p50/p99 latency, and the oracle timed on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serve] [--tune]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serve]
+                       [--no-self-join] [--tune] [--unbatched]
 """
 from __future__ import annotations
 
@@ -84,6 +86,42 @@ def traffic_from_profile():
     return rec.get("bytes_per_launch") if rec.get("search_hip_sha256_16") == h else None
 
 
+def self_join_leg(tds, idx, D, d, reps=3):
+    """The all-against-all form over the resident index: the self-join of the
+    1M entries at distance d (device output), then the trajectory-level merge
+    of its records (device to device)."""
+    import torch
+    st, n, _ = idx.self_join_raw(d, out_ptr=0, capacity=0, out_on_device=True)
+    cap = n + 1
+    rec = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
+    out = torch.empty(cap * 24, dtype=torch.uint8, device="cuda")
+    ts, tm, kern = [], [], []
+    m = 0
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, n2, s = idx.self_join_raw(d, out_ptr=rec.data_ptr(), capacity=cap, out_on_device=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st2, m = tds.merge_trajectories_raw(rec.data_ptr(), n2, True, out.data_ptr(), cap, True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if st != tds.TDS_OK or st2 != tds.TDS_OK or n2 != n:
+            raise RuntimeError("self-join failed")
+        if r:
+            ts.append(t1 - t0)
+            tm.append(t2 - t1)
+            kern.append(s["kernel_ms"])
+    # trajectories are time-monotone, so within its own trajectory a segment
+    # overlaps only itself: the pairs resolved are the cross-trajectory ones
+    pairs = (overlap_pairs(D, D, -np.inf, np.inf) - len(D)) // 2
+    t_sj = float(np.median(ts))
+    return {"d": d, "pairs_resolved": pairs, "pairs_per_s": round(pairs / t_sj, 1),
+            "ms": round(1e3 * t_sj, 4), "kernel_ms": round(float(np.median(kern)), 4),
+            "records": n, "merge_ms": round(1e3 * float(np.median(tm)), 4),
+            "trajectory_intervals": m}
+
+
 def serve_leg(tds, idx, n_req, rate, warm):
     import trajgen
     reqs = trajgen.request_stream(n_req + warm, rate=rate)
@@ -141,6 +179,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-self-join", action="store_true")
     ap.add_argument("--tune", action="store_true", help="autotune before timing")
     ap.add_argument("--unbatched", action="store_true",
                     help="also time the step as three separate searches (context)")
@@ -271,6 +310,8 @@ def main():
 
     if not args.no_serve:
         extra.update(serve_leg(tds, idx, args.serve_requests, 5000.0, 200))
+    if not args.no_self_join:
+        extra["self_join"] = self_join_leg(tds, idx, w.D, 25.0)
 
     cpu = None
     if not args.no_cpu:

@@ -373,6 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
     if (threadIdx.x < nreq) s_begin[threadIdx.x] = req[threadIdx.x].q_begin;
     __syncthreads();
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool act = false;  // the segment gets a bucket slot
+    uint32_t key = 0;
     if (k < desc->nq) {
         uint32_t r;
         if (nreq <= kBlock) {
@@ -419,9 +421,9 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                     f.lo = lo;
                     f.hi = hi;
                     const uint32_t span = min(j1 - j0, kSpanClasses - 1);
-                    const uint32_t key = (j0 * kSpanClasses + span) >> shift;
+                    key = (j0 * kSpanClasses + span) >> shift;
+                    act = true;
                     qkey[k] = key;
-                    qslot[k] = atomicAdd(&b_count[key], 1u);
                     // the bucket's range follows from its key unless it merges
                     // several first bins or spans an open number of bins
                     if (shift || span == kSpanClasses - 1) atomicMax(&b_hi[key], hi);
@@ -431,6 +433,21 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
             }
         }
     }
+    // bucket slots: one atomic per run of equal keys in consecutive lanes
+    // (neighbouring query segments often share a bucket, e.g. in the
+    // self-join, where a wave's segments are neighbours in one bin)
+    const uint32_t lane = __lane_id();
+    const uint32_t ke = act ? key : 0xFFFFFFFFu;
+    const uint32_t prev = __shfl_up(ke, 1);
+    const uint64_t bnd = __ballot(lane == 0 || prev != ke || !act);
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const uint32_t start = 63u - (uint32_t)__clzll(bnd & upto);
+    const uint64_t above = bnd & ~upto;
+    const uint32_t next = above ? (uint32_t)__ffsll((unsigned long long)above) - 1u : 64u;
+    uint32_t base = 0;
+    if (act && lane == start) base = atomicAdd(&b_count[key], next - start);
+    base = __shfl(base, start);
+    if (act) qslot[k] = base + (lane - start);
 }
 
 // Schedule only (tds_schedule): candidate range per query segment.
