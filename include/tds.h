@@ -290,6 +290,42 @@ int tds_merge_trajectories(const tds_result* recs, uint64_t n, int recs_on_devic
                            uint64_t* n_out, void* stream);
 
 /*
+ * Fixed spatial grid (FSG) index over the entries of an existing index: the
+ * spatial method of Sec. 4.1 (Alg. 1, GPUSpatial).  The entries' spatial
+ * extent is divided into gx x gy x gz equal cells (0 selects 50, the size the
+ * paper found best); every entry is listed in each cell its bounding box
+ * (grown by a relative 1e-9 so that rounding cannot drop a result) overlaps,
+ * so ids repeat across cells.  A search visits the cells overlapped by each
+ * query segment's box grown by d, compares the listed entries with the
+ * canonical FP64 evaluation, and reports a pair found in several cells once:
+ * from the lowest cell that both boxes overlap.  The grid keeps a reference
+ * to `index` (not owned; destroy the grid first).  Requirements:
+ * gx, gy, gz <= 1024, gx * gy * gz <= 2^24.  Waits for `stream`.
+ * Errors: TDS_E_INVALID (bad pointers or sizes), TDS_E_NOMEM (more than
+ * 2^32 - 1 listings), TDS_E_DEVICE.
+ */
+typedef struct tds_fsg tds_fsg;
+int tds_fsg_build(const tds_index* index, uint32_t gx, uint32_t gy, uint32_t gz, void* stream,
+                  tds_fsg** out);
+
+/* Free the grid.  NULL is accepted. */
+int tds_fsg_destroy(tds_fsg* grid);
+
+/*
+ * Distance threshold search through the grid: the records, the meaning of
+ * out / capacity / *n_out, host or device output (params->out_on_device) and
+ * TDS_E_OVERFLOW are those of tds_search, without incremental passes (when
+ * the results exceed `capacity`, out holds an unspecified subset).  The
+ * comparison is always the canonical FP64 one (params->precision is ignored).
+ * stats: query_segments, candidate_tests (listings compared, repeats
+ * included), results, kernel_ms, total_ms.  Waits for `stream`.
+ * Errors: as tds_search.
+ */
+int tds_fsg_search(const tds_fsg* grid, const tds_segments* Q, double d, double t_start,
+                   double t_end, tds_result* out, uint64_t capacity, uint64_t* n_out,
+                   const tds_search_params* params, void* stream, tds_stats* stats);
+
+/*
  * One request of a batch: a slice of the batch's query segments searched with
  * its own distance and window, writing into its own slice of the output.
  * Requests of a batch must tile the query segments in order: the first

@@ -280,6 +280,62 @@ class Index:
             raise TdsError(status, "tds_search_batch")
 
 
+class FSG:
+    """Fixed spatial grid over the entries of an Index (the spatial method of
+    Sec. 4.1, Alg. 1); the Index must outlive the grid."""
+
+    def __init__(self, index: "Index", gx: int = 0, gy: int = 0, gz: int = 0):
+        lib = load()
+        out = ctypes.c_void_p()
+        check(lib.tds_fsg_build(index.handle, int(gx), int(gy), int(gz), _current_stream(),
+                                ctypes.byref(out)), "tds_fsg_build")
+        self._h = out
+        self._lib = lib
+        self._index = index  # keeps the entries alive
+        self.last_stats: Optional[dict] = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tds_fsg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def search_raw(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
+                   out_ptr: int, capacity: int, out_on_device: bool):
+        """One call of tds_fsg_search into caller memory; returns (status, n_total, stats)."""
+        h = _segments(Q)
+        p = _search_params("fp64")
+        p.out_on_device = 1 if out_on_device else 0
+        n = ctypes.c_uint64()
+        st = _lib.tds_stats()
+        status = self._lib.tds_fsg_search(self._h, ctypes.byref(h.struct), float(d), float(t_start),
+                                          float(t_end), ctypes.c_void_p(out_ptr),
+                                          ctypes.c_uint64(capacity), ctypes.byref(n), ctypes.byref(p),
+                                          _current_stream(), ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        return status, int(n.value), self.last_stats
+
+    def search(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
+               capacity: Optional[int] = None) -> np.ndarray:
+        """Search into host memory; grows the buffer and retries on overflow."""
+        cap = 1 << 16 if capacity is None else int(capacity)
+        while True:
+            buf = np.empty(max(cap, 1), RESULT_DTYPE)
+            status, n, _ = self.search_raw(Q, d, t_start, t_end, out_ptr=buf.ctypes.data,
+                                           capacity=cap, out_on_device=False)
+            if status == TDS_OK:
+                return buf[:n].copy()
+            if status == TDS_E_OVERFLOW and capacity is None:
+                cap = n
+                continue
+            raise TdsError(status, "tds_fsg_search")
+
+
 def _search_params(precision="fp32", chunk=0, grid_waves=0):
     lib = load()
     p = _lib.tds_search_params()

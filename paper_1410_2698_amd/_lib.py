@@ -105,6 +105,13 @@ SIGNATURES = {
                                      ctypes.c_double, ctypes.c_void_p, ctypes.c_uint64, c_u64_p,
                                      ctypes.POINTER(tds_search_params), ctypes.c_void_p,
                                      ctypes.POINTER(tds_stats)]),
+    "tds_fsg_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_uint32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "tds_fsg_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "tds_fsg_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments), ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                      ctypes.c_uint64, c_u64_p, ctypes.POINTER(tds_search_params),
+                                      ctypes.c_void_p, ctypes.POINTER(tds_stats)]),
     "tds_merge_trajectories": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                               ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, c_u64_p,
                                               ctypes.c_void_p]),

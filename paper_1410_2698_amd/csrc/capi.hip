@@ -113,6 +113,36 @@ int tds_self_join(const tds_index* index, double d, double t_start, double t_end
                                n_out, params, (hipStream_t)stream, stats);
 }
 
+int tds_fsg_build(const tds_index* index, uint32_t gx, uint32_t gy, uint32_t gz, void* stream,
+                  tds_fsg** out) {
+    if (!index || !out) return TDS_E_INVALID;
+    *out = nullptr;
+    DeviceGuard g(index->device);
+    if (!g.ok) return TDS_E_DEVICE;
+    return tds::fsg_build(index, gx, gy, gz, (hipStream_t)stream, out);
+}
+
+int tds_fsg_destroy(tds_fsg* grid) {
+    tds::fsg_destroy(grid);
+    return TDS_OK;
+}
+
+int tds_fsg_search(const tds_fsg* grid, const tds_segments* Q, double d, double t_start,
+                   double t_end, tds_result* out, uint64_t capacity, uint64_t* n_out,
+                   const tds_search_params* params, void* stream, tds_stats* stats) {
+    if (!grid || !n_out || !Q) return TDS_E_INVALID;
+    *n_out = 0;
+    if (Q->n == 0) {
+        if (!(d >= 0.0) || std::isinf(d) || !(t_start < t_end)) return TDS_E_INVALID;
+        if (stats) *stats = tds_stats{};
+        return TDS_OK;
+    }
+    DeviceGuard g(grid->device);
+    if (!g.ok) return TDS_E_DEVICE;
+    return tds::fsg_search(grid, Q, d, t_start, t_end, out, capacity, n_out, params,
+                           (hipStream_t)stream, stats);
+}
+
 int tds_merge_trajectories(const tds_result* recs, uint64_t n, int recs_on_device,
                            tds_traj_interval* out, uint64_t capacity, int out_on_device,
                            uint64_t* n_out, void* stream) {

@@ -211,6 +211,18 @@ struct tds_index {
     tds_stats last{};
 };
 
+// Fixed spatial grid over the entries of an index (fsg.hip).
+struct tds_fsg {
+    const tds_index* idx = nullptr;
+    int device = 0;
+    uint32_t g[3] = {1, 1, 1};
+    double lo[3] = {0, 0, 0};        // grid origin
+    double cw[3] = {1, 1, 1};        // cell widths (0 on a flat axis)
+    uint32_t* cell_first = nullptr;  // ncells + 1
+    uint32_t* list = nullptr;        // entry positions grouped by cell
+    uint64_t nlist = 0;
+};
+
 namespace tds {
 
 // Makes a device current for the duration of a call (restores the caller's).
@@ -346,6 +358,14 @@ int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
 int self_join_impl(tds_index* idx, double d, double t_start, double t_end, tds_result* out,
                    uint64_t capacity, uint64_t* n_out, const tds_search_params* params,
                    hipStream_t s, tds_stats* stats);
+// Fixed spatial grid index (fsg.hip).
+int fsg_build(const tds_index* idx, uint32_t gx, uint32_t gy, uint32_t gz, hipStream_t s,
+              tds_fsg** out);
+void fsg_destroy(tds_fsg* f);
+int fsg_search(const tds_fsg* f, const tds_segments* Q, double d, double t_start, double t_end,
+               tds_result* out, uint64_t capacity, uint64_t* n_out,
+               const tds_search_params* params, hipStream_t s, tds_stats* stats);
+
 // Trajectory-level merge of result records (traj_merge.hip).
 int merge_impl(const tds_result* recs, uint64_t n, bool recs_dev, tds_traj_interval* out,
                uint64_t capacity, bool out_dev, uint64_t* n_out, hipStream_t s);
