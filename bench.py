@@ -70,20 +70,64 @@ def pct(x, q):
     return round(float(np.percentile(np.asarray(x), q)), 4)
 
 
+KERNEL_SOURCES = ("search.hip", "canon.hpp", "tds_internal.hpp")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_distance_fp32_uniform1m_traffic.json")
+
+
+def kernel_source_hash():
+    """Hash of the sources the distance kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1410_2698_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profile():
     """HBM bytes per launch of the distance kernel from the committed counter
-    summary, if it was taken on the current kernel source (else None)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "k_distance_fp32_uniform1m_traffic.json")
-    src = os.path.join(ROOT, "paper_1410_2698_amd", "csrc", "search.hip")
+    summary, if it was taken on the current kernel sources (else None)."""
     try:
-        with open(path) as f:
+        with open(TRAFFIC_JSON) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        h = kernel_source_hash()
     except (OSError, ValueError):
         return None
-    return rec.get("bytes_per_launch") if rec.get("search_hip_sha256_16") == h else None
+    return rec.get("bytes_per_launch") if rec.get("kernel_sources_sha256_16") == h else None
+
+
+def summarize_traffic(fetch_csv, write_csv, command):
+    """Counter CSVs of two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE,
+    each with --calib-copy-mb 256) -> the traffic summary: the distance
+    kernel's average per launch, scaled by what the same counter reads for the
+    256 MiB calibration copy."""
+    import csv
+
+    def per_kernel(path, counter):
+        with open(path) as f:
+            rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+        dist = [float(r["Counter_Value"]) for r in rows if "k_distance<2>" in r["Kernel_Name"]]
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not dist or not copies:
+            raise SystemExit(f"{path}: no {counter} rows for the distance kernel or the copy")
+        return dist, max(copies)
+
+    fd, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
+    wd, wcopy = per_kernel(write_csv, "WRITE_SIZE")
+    ref_kib = 256 * 1024
+    ffac, wfac = ref_kib / fcopy, ref_kib / wcopy
+    fetch_b = sum(fd) / len(fd) * 1024 * ffac
+    write_b = sum(wd) / len(wd) * 1024 * wfac
+    rec = {"kernel": "k_distance<FP32_RECHECK>", "workload": "uniform1m, d in {1,5,25}",
+           "launches": len(fd), "fetch_kib_raw_avg": sum(fd) / len(fd),
+           "write_kib_raw_avg": sum(wd) / len(wd),
+           "copy_calibration": {"bytes": 256 << 20, "fetch_kib": fcopy, "write_kib": wcopy,
+                                "fetch_factor": ffac, "write_factor": wfac},
+           "bytes_per_launch": round(fetch_b + write_b),
+           "kernel_sources_sha256_16": kernel_source_hash(), "command": command}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
 
 
 def self_join_leg(tds, idx, D, d, reps=3):
@@ -120,6 +164,42 @@ def self_join_leg(tds, idx, D, d, reps=3):
             "ms": round(1e3 * t_sj, 4), "kernel_ms": round(float(np.median(kern)), 4),
             "records": n, "merge_ms": round(1e3 * float(np.median(tm)), 4),
             "trajectory_intervals": m}
+
+
+def fsg_leg(tds, idx, Qt, counts, ds, t0, t1, grids=(20, 50, 100), reps=3):
+    """The fixed spatial grid (Alg. 1) over the same resident entries and
+    queries: build time, and per d the search time and the listings compared,
+    next to the index search's counts (the records must agree in number)."""
+    import torch
+    rows = []
+    cap = max(counts.values()) + 1
+    out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
+    for g in grids:
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        grid = tds.FSG(idx, g, g, g)
+        torch.cuda.synchronize()
+        build_ms = 1e3 * (time.perf_counter() - tb)
+        for d in ds:
+            ts, kern, tested = [], [], 0
+            for r in range(reps + 1):
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                st, n, s = grid.search_raw(Qt, d, t0, t1, out_ptr=out.data_ptr(), capacity=cap,
+                                           out_on_device=True)
+                torch.cuda.synchronize()
+                if st != tds.TDS_OK or n != counts[d]:
+                    raise RuntimeError(f"grid search failed: status {st}, {n} vs {counts[d]}")
+                if r:
+                    ts.append(time.perf_counter() - ta)
+                    kern.append(s["kernel_ms"])
+                    tested = s["candidate_tests"]
+            rows.append({"cells_per_axis": g, "d": d, "build_ms": round(build_ms, 3),
+                         "ms": round(1e3 * float(np.median(ts)), 4),
+                         "kernel_ms": round(float(np.median(kern)), 4),
+                         "listings_compared": int(tested), "records": int(n)})
+        grid.close()
+    return {"fsg": rows}
 
 
 def serve_leg(tds, idx, n_req, rate, warm):
@@ -180,6 +260,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-self-join", action="store_true")
+    ap.add_argument("--no-fsg", action="store_true", help="skip the fixed spatial grid leg")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic summary from two counter CSVs and exit (no GPU)")
     ap.add_argument("--tune", action="store_true", help="autotune before timing")
     ap.add_argument("--unbatched", action="store_true",
                     help="also time the step as three separate searches (context)")
@@ -191,6 +274,12 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic,
+                          "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv "
+                          "-d gpurun_out/pmc -o p -- python3 bench.py --steps 3 --warmup 1 "
+                          "--no-cpu --no-serve --no-self-join --no-fsg --calib-copy-mb 256")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -312,6 +401,8 @@ def main():
         extra.update(serve_leg(tds, idx, args.serve_requests, 5000.0, 200))
     if not args.no_self_join:
         extra["self_join"] = self_join_leg(tds, idx, w.D, 25.0)
+    if not args.no_fsg:
+        extra.update(fsg_leg(tds, idx, Qt, counts, ds, t0, t1))
 
     cpu = None
     if not args.no_cpu:
