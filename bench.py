@@ -45,6 +45,7 @@ METRIC = "segment-pair tests/s + queries/s at exact results; p50/p99 latency vs 
 # MI355X published FP32 vector peak: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU
 # = 157.3 TFLOP/s.
 PEAK_FP32_TFLOPS = 256 * 256 * 2.4e9 / 1e12
+PEAK_HBM_BPS = 8.0e12  # MI355X HBM3E, bytes/s
 # FP operations of one FP32 filter test: 3 sub, 1 mul, 2 FMA (2 flops each),
 # 1 add, 1 mul, 3 compares (1 each) = 13.
 FLOPS_PER_TEST_FP32 = 13
@@ -64,6 +65,17 @@ def overlap_pairs(D, Q, t0, t1):
     ok = aq < bq
     n = np.searchsorted(ts, bq[ok], side="left") - np.searchsorted(te, aq[ok], side="right")
     return int(n.sum())
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def pct(x, q):
@@ -202,14 +214,14 @@ def fsg_leg(tds, idx, Qt, counts, ds, t0, t1, grids=(20, 50, 100), reps=3):
     return {"fsg": rows}
 
 
-def serve_leg(tds, idx, n_req, rate, warm):
-    import trajgen
-    reqs = trajgen.request_stream(n_req + warm, rate=rate)
+def open_loop(tds, idx, reqs):
+    """Submits reqs at their arrival times from a thread while the main thread
+    collects them; returns (latencies in ms, records, elapsed s, server stats)."""
     srv = tds.Server(idx, max_batch_segments=1 << 17, max_batch_requests=2048, slots=2,
                      result_capacity=1 << 21, default_reserve=512)
-    for r in reqs[:warm]:
+    for r in reqs[:200]:  # warm-up, not timed
         srv.wait(srv.submit(r.Q, r.d, r.t_start, r.t_end))
-    reqs = reqs[warm:]
+    reqs = reqs[200:]
     base = reqs[0].arrival
     tickets = [None] * len(reqs)
     t_start = time.perf_counter()
@@ -234,19 +246,39 @@ def serve_leg(tds, idx, n_req, rate, warm):
     elapsed = time.perf_counter() - t_start
     st = srv.stats()
     srv.close()
-    # plain form on the same requests: FP64, one request per call
+    return lat, n_rec, elapsed, st
+
+
+def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0)):
+    """The request stream through tds_server: an open-loop run at `rate` for
+    `seconds`, the plain FP64 form (one request per call) on its first 5,000
+    requests, and shorter open-loop runs at higher offered rates."""
+    import trajgen
+    n_req = int(seconds * rate)
+    reqs = trajgen.request_stream(n_req + 200, rate=rate)
+    lat, n_rec, elapsed, st = open_loop(tds, idx, reqs)
+    served = {"offered_rate": rate, "requests": len(lat),
+              "requests_per_s": round(len(lat) / elapsed, 1),
+              "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "records": n_rec,
+              "batches": st["batches"], "requeued": st["requeued"],
+              "max_batch_requests": st["max_batch_requests_seen"]}
     plain = []
-    for r in reqs:
+    for r in reqs[200:5200]:
         t0 = time.perf_counter()
         idx.search(r.Q, r.d, r.t_start, r.t_end, precision="fp64", capacity=4096)
         plain.append(1e3 * (time.perf_counter() - t0))
+    rows = []
+    for rt in sweep:
+        sreqs = trajgen.request_stream(5200, rate=rt)
+        slat, _, sel, sst = open_loop(tds, idx, sreqs)
+        rows.append({"offered_rate": rt, "requests_per_s": round(len(slat) / sel, 1),
+                     "p50_ms": pct(slat, 50), "p99_ms": pct(slat, 99),
+                     "batches": sst["batches"]})
     return {
-        "served_fp32": {"offered_rate": rate, "requests": len(reqs),
-                        "requests_per_s": round(len(reqs) / elapsed, 1),
-                        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "records": n_rec,
-                        "batches": st["batches"], "requeued": st["requeued"],
-                        "max_batch_requests": st["max_batch_requests_seen"]},
-        "plain_fp64": {"requests_per_s": round(len(plain) / (sum(plain) * 1e-3), 1),
+        "served_fp32": served,
+        "served_rate_sweep": rows,
+        "plain_fp64": {"requests": len(plain),
+                       "requests_per_s": round(len(plain) / (sum(plain) * 1e-3), 1),
                        "p50_ms": pct(plain, 50), "p99_ms": pct(plain, 99),
                        "note": "one request per call, back to back (service time, no queueing)"},
     }
@@ -266,7 +298,8 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune before timing")
     ap.add_argument("--unbatched", action="store_true",
                     help="also time the step as three separate searches (context)")
-    ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the open-loop serving run at 5,000 requests/s")
     ap.add_argument("--cpu-traj", type=int, default=500, help="query trajectories in the oracle sample")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--grid-waves", type=int, default=0)
@@ -383,6 +416,16 @@ def main():
                 "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": int(flops),
                 "flops_per_filter_test": FLOPS_PER_TEST_FP32,
                 "flops_per_block_test": FLOPS_PER_BLOCK_TEST}
+    # the other two views of the same launch: the candidate stream the method
+    # reads per pair (32-B FP32 records, as if each pair fetched its own), and
+    # the HBM bytes the counters saw
+    traffic = roofline["traffic"]
+    roofline["views"] = {
+        "candidate_stream_tb_s": round(tests_per_launch * 32 / (avg_ms * 1e-3) / 1e12, 2),
+        "candidate_stream_frac_of_hbm": round(tests_per_launch * 32 / (avg_ms * 1e-3) / PEAK_HBM_BPS, 3),
+        "dram_tb_s": round(traffic / (avg_ms * 1e-3) / 1e12, 3) if traffic else None,
+        "dram_frac_of_hbm": round(traffic / (avg_ms * 1e-3) / PEAK_HBM_BPS, 4) if traffic else None,
+        "alu_frac": roofline["frac"]}
 
     extra = {"queries_per_s": round(n_queries * args.steps / elapsed, 1),
              "candidate_tests_per_kernel_s": round(tests / (kern_ms * 1e-3), 1) if kern_ms else None,
@@ -398,7 +441,7 @@ def main():
              "ms_per_step_as_three_searches": ms_unbatched}
 
     if not args.no_serve:
-        extra.update(serve_leg(tds, idx, args.serve_requests, 5000.0, 200))
+        extra.update(serve_leg(tds, idx, args.serve_seconds, 5000.0))
     if not args.no_self_join:
         extra["self_join"] = self_join_leg(tds, idx, w.D, 25.0)
     if not args.no_fsg:
@@ -418,6 +461,16 @@ def main():
                "cores": cores, "kind": "oracle",
                "sample": f"{k} of 500 query trajectories ({len(sub)} query segments) x 1,000,000 "
                          f"entries at d=5, brute force over all pairs; {dt:.2f} s"}
+        # the same on one core, over a twentieth of the query trajectories
+        k1 = max(1, k // 20)
+        sub1 = w.Q.take(np.arange(sl[0][0], sl[k1 - 1][1]))
+        tc = time.perf_counter()
+        oracle.search(sub1, w.D, 5.0, t0, t1, threads=1)
+        dt1 = time.perf_counter() - tc
+        cpu["single_core"] = {"value": round(overlap_pairs(w.D, sub1, t0, t1) / dt1, 1),
+                              "sample": f"{k1} query trajectories ({len(sub1)} query segments); "
+                                        f"{dt1:.2f} s"}
+        cpu["cpu_model"] = cpu_model()
 
     rec = {"metric": METRIC, "value": round(value, 1), "unit": "pair tests/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),

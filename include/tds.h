@@ -281,7 +281,10 @@ typedef struct tds_traj_interval {
  * `capacity` intervals (device memory if out_on_device).  *n_out is always set
  * to the total; when it exceeds capacity, out holds the first `capacity`
  * intervals in that order and the call returns TDS_E_OVERFLOW.  Runs on the
- * current HIP device and waits for `stream`.
+ * current HIP device and waits for `stream`.  The library keeps the merge's
+ * device scratch per device (grown to the largest n merged, about 60 bytes
+ * per record, held until the process ends); calls on one device run one at a
+ * time.
  * Errors: TDS_E_INVALID (NULL pointers, n >= 2^32 - 1), TDS_E_NOMEM,
  * TDS_E_DEVICE.
  */

@@ -19,6 +19,8 @@
 #include <chrono>
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "canon.hpp"
 #include "tds_internal.hpp"
 
@@ -426,9 +428,7 @@ int fsg_search(const tds_fsg* f, const tds_segments* Q, double d, double t_start
     TDS_HIP(hipEventCreate(&e0));
     TDS_HIP(hipEventCreate(&e1));
     const uint32_t blocks = std::max(1u, std::min(ceil_div(nq, kFT / kWave), 4096u));
-    TDS_HIP(hipEventRecord(e0, s));
-    hipLaunchKernelGGL(k_fsg_search, dim3(blocks), dim3(kFT), 0, s, A);
-    TDS_HIP(hipEventRecord(e1, s));
+    hipExtLaunchKernelGGL(k_fsg_search, dim3(blocks), dim3(kFT), 0, s, e0, e1, 0u, A);
     unsigned long long h[4] = {0, 0, 0, 0};
     int st = (hipGetLastError() == hipSuccess) ? TDS_OK : TDS_E_DEVICE;
     if (st == TDS_OK &&

@@ -14,6 +14,8 @@
 //              offset; the rank of a key among equal digits of its tile comes
 //              from wave ballots (wave-local) plus per-wave digit counts in
 //              LDS, processed in tile order, so the pass is stable.
+#include <algorithm>
+
 #include "tds_internal.hpp"
 
 namespace tds {
@@ -182,27 +184,38 @@ __global__ __launch_bounds__(kRsThreads) void rs_scatter(const uint64_t* __restr
 
 }  // namespace
 
-int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                   uint32_t n, int key_bits, hipStream_t stream) {
+size_t radix_hist_len(uint32_t n) { return (size_t)kRadix * ceil_div(n, kRsTile); }
+
+size_t scan_part_len(size_t len) { return (size_t)ceil_div(len, kScanTile) + 1; }
+
+int radix_sort_u64_digits(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                          uint32_t n, uint32_t digit_mask, hipStream_t stream, uint32_t* hist,
+                          uint32_t* part) {
     if (n <= 1) return TDS_OK;
     const uint32_t nblocks = ceil_div(n, kRsTile);
     const uint64_t hlen = (uint64_t)kRadix * nblocks;
     if (hlen >= (1ull << 32)) return TDS_E_INVALID;
-    uint32_t* hist = nullptr;
-    TDS_TRY(dmalloc(&hist, hlen));
     const uint32_t nparts = ceil_div(hlen, kScanTile);
-    uint32_t* part = nullptr;
-    if (dmalloc(&part, (size_t)nparts + 1) != TDS_OK) {
-        dfree(hist);
-        return TDS_E_NOMEM;
+    uint32_t* own_hist = nullptr;
+    uint32_t* own_part = nullptr;
+    if (!hist) {
+        TDS_TRY(dmalloc(&own_hist, hlen));
+        hist = own_hist;
     }
-    int passes = (key_bits + 7) / 8;
+    if (!part) {
+        if (dmalloc(&own_part, (size_t)nparts + 1) != TDS_OK) {
+            dfree(own_hist);
+            return TDS_E_NOMEM;
+        }
+        part = own_part;
+    }
     uint64_t* ka = keys;
     uint32_t* va = vals;
     uint64_t* kb = keys_alt;
     uint32_t* vb = vals_alt;
     int status = TDS_OK;
-    for (int p = 0; p < passes; ++p) {
+    for (int p = 0; p < 8; ++p) {
+        if (!((digit_mask >> p) & 1u)) continue;
         const int shift = 8 * p;
         hipLaunchKernelGGL(rs_hist, dim3(nblocks), dim3(kRsThreads), 0, stream, ka, n, shift, hist,
                            nblocks);
@@ -227,20 +240,37 @@ int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t*
                 hipSuccess)
             status = TDS_E_DEVICE;
     }
-    if (hipStreamSynchronize(stream) != hipSuccess) status = TDS_E_DEVICE;
-    dfree(hist);
-    dfree(part);
+    if (own_hist || own_part) {
+        // buffers of this call: wait before freeing them
+        if (hipStreamSynchronize(stream) != hipSuccess) status = TDS_E_DEVICE;
+        dfree(own_hist);
+        dfree(own_part);
+    }
     return status;
 }
 
+int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                   uint32_t n, int key_bits, hipStream_t stream) {
+    const int passes = std::min(8, (key_bits + 7) / 8);
+    const uint32_t mask = (passes >= 8) ? 0xFFu : ((1u << passes) - 1u);
+    int st = radix_sort_u64_digits(keys, vals, keys_alt, vals_alt, n, mask, stream, nullptr, nullptr);
+    if (st == TDS_OK && hipStreamSynchronize(stream) != hipSuccess) st = TDS_E_DEVICE;
+    return st;
+}
+
 int exclusive_scan_u32(uint32_t* v, uint32_t len, uint32_t* total, hipStream_t stream) {
+    return exclusive_scan_u32_with(v, len, total, stream, nullptr);
+}
+
+int exclusive_scan_u32_with(uint32_t* v, uint32_t len, uint32_t* total, hipStream_t stream,
+                            uint32_t* scratch) {
     if (len == 0) {
         if (total) *total = 0;
         return TDS_OK;
     }
     const uint32_t nparts = ceil_div(len, kScanTile);
-    uint32_t* part = nullptr;
-    TDS_TRY(dmalloc(&part, (size_t)nparts + 1));
+    uint32_t* part = scratch;
+    if (!part) TDS_TRY(dmalloc(&part, (size_t)nparts + 1));
     hipLaunchKernelGGL(rs_scan_part, dim3(nparts), dim3(kScanThreads), 0, stream, v, len, part);
     hipLaunchKernelGGL(rs_scan_top, dim3(1), dim3(kScanThreads), 0, stream, part, nparts);
     hipLaunchKernelGGL(rs_scan_down, dim3(nparts), dim3(kScanThreads), 0, stream, v, len, part);
@@ -252,7 +282,7 @@ int exclusive_scan_u32(uint32_t* v, uint32_t len, uint32_t* total, hipStream_t s
             st = TDS_E_DEVICE;
     }
     if (!total && hipStreamSynchronize(stream) != hipSuccess) st = TDS_E_DEVICE;
-    dfree(part);
+    if (!scratch) dfree(part);
     return st;
 }
 

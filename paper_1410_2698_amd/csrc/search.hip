@@ -21,6 +21,8 @@
 #include <chrono>
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "canon.hpp"
 #include "tds_internal.hpp"
 
@@ -1219,18 +1221,21 @@ DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q,
     return A;
 }
 
-// The distance kernel between the two events (either may be null), then the
+// The distance kernel, timed by the two events when both are given, then the
 // fold of its per-workgroup counters into the header.
 int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_t s,
                     hipEvent_t ev_begin, hipEvent_t ev_end) {
     const uint32_t blocks =
         std::min(kMaxDistBlocks, std::max(1u, ceil_div(grid_waves, kWavesPerBlock)));
-    if (ev_begin) TDS_HIP(hipEventRecord(ev_begin, s));
-    if (prec == TDS_PREC_FP64)
-        hipLaunchKernelGGL(k_distance<TDS_PREC_FP64>, dim3(blocks), dim3(kBlock), 0, s, A);
-    else
-        hipLaunchKernelGGL(k_distance<TDS_PREC_FP32_RECHECK>, dim3(blocks), dim3(kBlock), 0, s, A);
-    if (ev_end) TDS_HIP(hipEventRecord(ev_end, s));
+    auto* kern = (prec == TDS_PREC_FP64) ? k_distance<TDS_PREC_FP64>
+                                         : k_distance<TDS_PREC_FP32_RECHECK>;
+    if (ev_begin && ev_end) {
+        // the events take the dispatch's own start and end times (no marker
+        // packets around the kernel, so no bubbles before and after it)
+        hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, ev_begin, ev_end, 0u, A);
+    } else {
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, A);
+    }
     hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, s, A.bstats, blocks, A.hdr);
     TDS_HIP(hipGetLastError());
     return TDS_OK;

@@ -316,6 +316,18 @@ __device__ inline void sphere32(double ax, double ay, double az, double bx, doub
 int radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                    uint32_t n, int key_bits, hipStream_t stream);
 
+// The same sort over the 8-bit digits set in digit_mask (bit p: key bits
+// 8p..8p+7), e.g. only the digits that differ between keys.  hist
+// (radix_hist_len(n) entries) and part (scan_part_len(radix_hist_len(n)))
+// are device scratch; when null they are allocated and freed by the call
+// (which then waits for the stream).  With caller scratch the call does not
+// wait: the sorted data is ready in stream order.
+int radix_sort_u64_digits(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                          uint32_t n, uint32_t digit_mask, hipStream_t stream, uint32_t* hist,
+                          uint32_t* part);
+size_t radix_hist_len(uint32_t n);
+size_t scan_part_len(size_t len);
+
 // Device segment staging: copies host arrays to the device when needed.
 struct SegView {
     const double* a[8];     // xs, ys, zs, ts, xe, ye, ze, te (device)
@@ -373,6 +385,9 @@ int merge_impl(const tds_result* recs, uint64_t n, bool recs_dev, tds_traj_inter
 // Exclusive scan of len u32 values in place on `stream`; *total (may be
 // NULL) receives the sum, which costs a synchronisation (radix_sort.hip).
 int exclusive_scan_u32(uint32_t* v, uint32_t len, uint32_t* total, hipStream_t stream);
+// The same with caller scratch of scan_part_len(len) entries (null: allocated).
+int exclusive_scan_u32_with(uint32_t* v, uint32_t len, uint32_t* total, hipStream_t stream,
+                            uint32_t* scratch);
 
 int schedule_impl(tds_index* idx, const tds_segments* Q, double t_start, double t_end,
                   uint32_t* lo, uint32_t* hi, hipStream_t stream);

@@ -4,7 +4,9 @@
 //
 //   1. stable radix sort of the record indices by t_lo, then by the
 //      trajectory pair: the records in (q_traj, e_traj, t_lo) order, equal
-//      keys in input order;
+//      keys in input order.  One reduction first finds which 8-bit digits of
+//      the t_lo keys differ and how many bits the trajectory ids need, so the
+//      sorts make only the passes that can change the order;
 //   2. k_run_heads / scan: one run per trajectory pair;
 //   3. k_merge_runs<false>: one thread per run walks its records and counts
 //      the merged intervals (an interval is extended while the next record
@@ -12,6 +14,7 @@
 //   4. k_merge_runs<true>: the same walk writes the intervals at their offsets
 //      (only those below the capacity).
 #include <algorithm>
+#include <mutex>
 
 #include "tds_internal.hpp"
 
@@ -27,25 +30,61 @@ __device__ inline uint64_t order_key_f64(double t) {
     return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
 
-__device__ inline uint64_t pair_key(const tds_result& r) {
-    return ((uint64_t)r.q_traj << 32) | r.e_traj;
+// red[0] = OR of the t_lo keys, red[1] = AND, red[2] = max q_traj, red[3] =
+// max e_traj (k_red_init sets the identities).
+__global__ void k_red_init(unsigned long long* red) {
+    red[0] = 0ull;
+    red[1] = ~0ull;
+    red[2] = 0ull;
+    red[3] = 0ull;
 }
 
 __global__ __launch_bounds__(kMT) void k_keys_tlo(const tds_result* __restrict__ recs, uint32_t n,
                                                   uint64_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals) {
+                                                  uint32_t* __restrict__ vals,
+                                                  unsigned long long* red) {
+    __shared__ unsigned long long s_or[kMT], s_and[kMT], s_q[kMT], s_e[kMT];
     const uint32_t i = blockIdx.x * kMT + threadIdx.x;
-    if (i >= n) return;
-    keys[i] = order_key_f64(recs[i].t_lo);
-    vals[i] = i;
+    unsigned long long ko = 0ull, ka = ~0ull, mq = 0ull, me = 0ull;
+    if (i < n) {
+        const tds_result r = recs[i];
+        const uint64_t k = order_key_f64(r.t_lo);
+        keys[i] = k;
+        vals[i] = i;
+        ko = ka = k;
+        mq = r.q_traj;
+        me = r.e_traj;
+    }
+    s_or[threadIdx.x] = ko;
+    s_and[threadIdx.x] = ka;
+    s_q[threadIdx.x] = mq;
+    s_e[threadIdx.x] = me;
+    __syncthreads();
+    for (uint32_t off = kMT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            s_or[threadIdx.x] |= s_or[threadIdx.x + off];
+            s_and[threadIdx.x] &= s_and[threadIdx.x + off];
+            s_q[threadIdx.x] = max(s_q[threadIdx.x], s_q[threadIdx.x + off]);
+            s_e[threadIdx.x] = max(s_e[threadIdx.x], s_e[threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicOr(&red[0], s_or[0]);
+        atomicAnd(&red[1], s_and[0]);
+        atomicMax(&red[2], s_q[0]);
+        atomicMax(&red[3], s_e[0]);
+    }
 }
 
+// Pair key q_traj << e_bits | e_traj (e_bits: bits of the largest e_traj).
 __global__ __launch_bounds__(kMT) void k_keys_pair(const tds_result* __restrict__ recs, uint32_t n,
-                                                   const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ vals, uint32_t e_bits,
                                                    uint64_t* __restrict__ keys) {
     const uint32_t i = blockIdx.x * kMT + threadIdx.x;
     if (i >= n) return;
-    keys[i] = pair_key(recs[vals[i]]);
+    const tds_result r = recs[vals[i]];
+    keys[i] = ((uint64_t)r.q_traj << e_bits) | r.e_traj;
 }
 
 // head[i] = 1 where a new trajectory pair starts in sorted order.
@@ -113,12 +152,94 @@ __global__ __launch_bounds__(kMT) void k_merge_runs(const tds_result* __restrict
     if (!kWrite) cnt[r] = c;
 }
 
-struct Bufs {
-    void* p[8] = {};
-    ~Bufs() {
-        for (void* q : p) dfree(q);
+// Device scratch of the merge, per device, grown on demand and kept until the
+// process ends (the merge is called repeatedly on result sets of similar
+// size; allocating and freeing per call cost more than the kernels).
+struct MergeScratch {
+    std::mutex mu;
+    size_t cap = 0;  // records the buffers hold
+    tds_result* recs = nullptr;
+    uint64_t *k1 = nullptr, *k2 = nullptr;
+    uint32_t *v1 = nullptr, *v2 = nullptr, *runs = nullptr, *run_start = nullptr, *cnt = nullptr;
+    uint32_t *hist = nullptr, *part = nullptr;
+    tds_traj_interval* stage = nullptr;
+    unsigned long long* red = nullptr;
+    unsigned long long* red_host = nullptr;  // pinned
+
+    void release() {
+        dfree(recs);
+        dfree(k1);
+        dfree(k2);
+        dfree(v1);
+        dfree(v2);
+        dfree(runs);
+        dfree(run_start);
+        dfree(cnt);
+        dfree(hist);
+        dfree(part);
+        dfree(stage);
+        recs = nullptr;
+        k1 = k2 = nullptr;
+        v1 = v2 = runs = run_start = cnt = hist = part = nullptr;
+        stage = nullptr;
+        cap = 0;
+    }
+
+    int reserve(size_t n) {
+        if (!red) {
+            TDS_TRY(dmalloc(&red, 4));
+            if (hipHostMalloc(reinterpret_cast<void**>(&red_host), 4 * sizeof(unsigned long long),
+                              hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                red_host = nullptr;
+                return TDS_E_NOMEM;
+            }
+        }
+        if (n <= cap) return TDS_OK;
+        release();
+        const size_t c = std::max<size_t>(n, 1024);
+        const size_t parts = std::max(scan_part_len(radix_hist_len((uint32_t)c)), scan_part_len(c));
+        int st = TDS_OK;
+        if (st == TDS_OK) st = dmalloc(&recs, c);
+        if (st == TDS_OK) st = dmalloc(&k1, c);
+        if (st == TDS_OK) st = dmalloc(&k2, c);
+        if (st == TDS_OK) st = dmalloc(&v1, c);
+        if (st == TDS_OK) st = dmalloc(&v2, c);
+        if (st == TDS_OK) st = dmalloc(&runs, c);
+        if (st == TDS_OK) st = dmalloc(&run_start, c + 1);
+        if (st == TDS_OK) st = dmalloc(&cnt, c);
+        if (st == TDS_OK) st = dmalloc(&hist, radix_hist_len((uint32_t)c));
+        if (st == TDS_OK) st = dmalloc(&part, parts);
+        if (st == TDS_OK) st = dmalloc(&stage, c);
+        if (st != TDS_OK) {
+            release();
+            return st;
+        }
+        cap = c;
+        return TDS_OK;
     }
 };
+
+constexpr int kMaxDevices = 64;
+MergeScratch g_scratch[kMaxDevices];
+
+// 8-bit digits in which some of the keys differ.
+uint32_t varying_digits(uint64_t ored, uint64_t anded) {
+    const uint64_t v = ored ^ anded;
+    uint32_t m = 0;
+    for (int p = 0; p < 8; ++p)
+        if ((v >> (8 * p)) & 0xFFull) m |= 1u << p;
+    return m;
+}
+
+uint32_t bit_width(uint64_t v) {
+    uint32_t b = 0;
+    while (v) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
 
 }  // namespace
 
@@ -128,72 +249,62 @@ int merge_impl(const tds_result* recs, uint64_t n, bool recs_dev, tds_traj_inter
     *n_out = 0;
     if (n == 0) return TDS_OK;
     if (!recs || (capacity && !out) || n >= 0xFFFFFFFFull) return TDS_E_INVALID;
+    int dev = 0;
+    TDS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return TDS_E_DEVICE;
+    MergeScratch& M = g_scratch[dev];
+    // one merge at a time per device: every call waits for its own work
+    // before it returns, so the next call finds the scratch free
+    std::lock_guard<std::mutex> lock(M.mu);
+    TDS_TRY(M.reserve(n));
     const uint32_t nn = (uint32_t)n;
     const uint32_t nb = ceil_div(nn, kMT);
-    Bufs B;
     const tds_result* R = recs;
     if (!recs_dev) {
-        tds_result* d = nullptr;
-        TDS_TRY(dmalloc(&d, n));
-        B.p[0] = d;
-        TDS_HIP(hipMemcpyAsync(d, recs, n * sizeof(tds_result), hipMemcpyHostToDevice, s));
-        R = d;
+        TDS_HIP(hipMemcpyAsync(M.recs, recs, n * sizeof(tds_result), hipMemcpyHostToDevice, s));
+        R = M.recs;
     }
-    uint64_t *k1 = nullptr, *k2 = nullptr;
-    uint32_t *v1 = nullptr, *v2 = nullptr, *runs = nullptr;
-    TDS_TRY(dmalloc(&k1, n));
-    B.p[1] = k1;
-    TDS_TRY(dmalloc(&k2, n));
-    B.p[2] = k2;
-    TDS_TRY(dmalloc(&v1, n));
-    B.p[3] = v1;
-    TDS_TRY(dmalloc(&v2, n));
-    B.p[4] = v2;
-    TDS_TRY(dmalloc(&runs, n));
-    B.p[5] = runs;
+    // keys, and which digits and id bits the sorts need
+    hipLaunchKernelGGL(k_red_init, dim3(1), dim3(1), 0, s, M.red);
+    hipLaunchKernelGGL(k_keys_tlo, dim3(nb), dim3(kMT), 0, s, R, nn, M.k1, M.v1, M.red);
+    TDS_HIP(hipGetLastError());
+    TDS_HIP(hipMemcpyAsync(M.red_host, M.red, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           s));
+    TDS_HIP(hipStreamSynchronize(s));
+    const uint32_t t_digits = varying_digits(M.red_host[0], M.red_host[1]);
+    const uint32_t e_bits = std::max(1u, bit_width(M.red_host[3]));
+    const uint32_t pair_bits = bit_width(M.red_host[2]) + e_bits;
+    const uint32_t pair_digits = (pair_bits >= 64) ? 0xFFu : ((1u << ((pair_bits + 7) / 8)) - 1u);
     // (q_traj, e_traj, t_lo) order: by t_lo, then stably by the pair
-    hipLaunchKernelGGL(k_keys_tlo, dim3(nb), dim3(kMT), 0, s, R, nn, k1, v1);
+    TDS_TRY(radix_sort_u64_digits(M.k1, M.v1, M.k2, M.v2, nn, t_digits, s, M.hist, M.part));
+    hipLaunchKernelGGL(k_keys_pair, dim3(nb), dim3(kMT), 0, s, R, nn, M.v1, e_bits, M.k1);
     TDS_HIP(hipGetLastError());
-    TDS_TRY(radix_sort_u64(k1, v1, k2, v2, nn, 64, s));
-    hipLaunchKernelGGL(k_keys_pair, dim3(nb), dim3(kMT), 0, s, R, nn, v1, k1);
-    TDS_HIP(hipGetLastError());
-    TDS_TRY(radix_sort_u64(k1, v1, k2, v2, nn, 64, s));
+    TDS_TRY(radix_sort_u64_digits(M.k1, M.v1, M.k2, M.v2, nn, pair_digits, s, M.hist, M.part));
     // runs of equal pairs
-    hipLaunchKernelGGL(k_run_heads, dim3(nb), dim3(kMT), 0, s, k1, nn, runs);
+    hipLaunchKernelGGL(k_run_heads, dim3(nb), dim3(kMT), 0, s, M.k1, nn, M.runs);
     TDS_HIP(hipGetLastError());
     uint32_t n_runs = 0;
-    TDS_TRY(exclusive_scan_u32(runs, nn, &n_runs, s));
-    uint32_t *run_start = nullptr, *cnt = nullptr;
-    TDS_TRY(dmalloc(&run_start, (size_t)n_runs + 1));
-    B.p[6] = run_start;
-    TDS_TRY(dmalloc(&cnt, n_runs));
-    B.p[7] = cnt;
-    hipLaunchKernelGGL(k_run_starts, dim3(nb), dim3(kMT), 0, s, k1, nn, runs, run_start, n_runs);
+    TDS_TRY(exclusive_scan_u32_with(M.runs, nn, &n_runs, s, M.part));
+    hipLaunchKernelGGL(k_run_starts, dim3(nb), dim3(kMT), 0, s, M.k1, nn, M.runs, M.run_start,
+                       n_runs);
     const uint32_t rb = ceil_div(n_runs, kMT);
-    hipLaunchKernelGGL(k_merge_runs<false>, dim3(rb), dim3(kMT), 0, s, R, v1, run_start, n_runs,
-                       cnt, nullptr, 0ull);
+    hipLaunchKernelGGL(k_merge_runs<false>, dim3(rb), dim3(kMT), 0, s, R, M.v1, M.run_start, n_runs,
+                       M.cnt, nullptr, 0ull);
     TDS_HIP(hipGetLastError());
     uint32_t total = 0;
-    TDS_TRY(exclusive_scan_u32(cnt, n_runs, &total, s));
+    TDS_TRY(exclusive_scan_u32_with(M.cnt, n_runs, &total, s, M.part));
     *n_out = total;
     const uint64_t keep = std::min<uint64_t>(total, capacity);
     if (keep) {
-        tds_traj_interval* dst = out;
-        tds_traj_interval* stage = nullptr;
-        if (!out_dev) {
-            TDS_TRY(dmalloc(&stage, keep));
-            dst = stage;
-        }
-        hipLaunchKernelGGL(k_merge_runs<true>, dim3(rb), dim3(kMT), 0, s, R, v1, run_start, n_runs,
-                           cnt, dst, keep);
-        int st = (hipGetLastError() == hipSuccess) ? TDS_OK : TDS_E_DEVICE;
-        if (st == TDS_OK && !out_dev &&
-            hipMemcpyAsync(out, stage, keep * sizeof(tds_traj_interval), hipMemcpyDeviceToHost,
-                           s) != hipSuccess)
-            st = TDS_E_DEVICE;
-        if (st == TDS_OK && hipStreamSynchronize(s) != hipSuccess) st = TDS_E_DEVICE;
-        dfree(stage);
-        TDS_TRY(st);
+        // at most one interval per record, so the staging buffer fits
+        tds_traj_interval* dst = out_dev ? out : M.stage;
+        hipLaunchKernelGGL(k_merge_runs<true>, dim3(rb), dim3(kMT), 0, s, R, M.v1, M.run_start,
+                           n_runs, M.cnt, dst, keep);
+        TDS_HIP(hipGetLastError());
+        if (!out_dev)
+            TDS_HIP(hipMemcpyAsync(out, M.stage, keep * sizeof(tds_traj_interval),
+                                   hipMemcpyDeviceToHost, s));
+        TDS_HIP(hipStreamSynchronize(s));
     }
     return total > capacity ? TDS_E_OVERFLOW : TDS_OK;
 }
