@@ -118,16 +118,20 @@ __global__ __launch_bounds__(kFT) void k_fsg_list(const EntryF64* __restrict__ e
             }
 }
 
+// first[c] = number of listings with a cell below c (c = 0..ncells): one
+// thread per cell, a binary search of the sorted cell keys.
 __global__ __launch_bounds__(kFT) void k_fsg_cell_first(const uint64_t* __restrict__ keys,
                                                         uint32_t nl, uint32_t ncells,
                                                         uint32_t* __restrict__ first) {
-    const uint32_t i = blockIdx.x * kFT + threadIdx.x;
-    if (i >= nl) return;
-    const uint32_t c = (uint32_t)keys[i];
-    const int64_t cp = (i == 0) ? -1 : (int64_t)keys[i - 1];
-    for (int64_t k = cp + 1; k <= (int64_t)c; ++k) first[k] = i;
-    if (i == nl - 1)
-        for (uint32_t k = c + 1; k <= ncells; ++k) first[k] = nl;
+    const uint32_t c = blockIdx.x * kFT + threadIdx.x;
+    if (c > ncells) return;
+    uint32_t l = 0, h = nl;
+    while (l < h) {
+        const uint32_t mid = l + (h - l) / 2;
+        if (keys[mid] < c) l = mid + 1;
+        else h = mid;
+    }
+    first[c] = l;
 }
 
 struct FsgArgs {
@@ -324,8 +328,8 @@ int fsg_build(const tds_index* idx, uint32_t gx, uint32_t gy, uint32_t gz, hipSt
     uint32_t* first = nullptr;
     if (st == TDS_OK) st = dmalloc(&first, ncells + 1);
     if (st == TDS_OK) {
-        hipLaunchKernelGGL(k_fsg_cell_first, dim3(std::max(1u, ceil_div(nl, kFT))), dim3(kFT), 0, s,
-                           keys, nl, (uint32_t)ncells, first);
+        hipLaunchKernelGGL(k_fsg_cell_first, dim3(ceil_div(ncells + 1, kFT)), dim3(kFT), 0, s, keys,
+                           nl, (uint32_t)ncells, first);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             st = TDS_E_DEVICE;
     }

@@ -264,9 +264,32 @@ __global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_
 
 // Canonical FP64 data of query segment k of request r, from the query
 // arrays (the same operations wherever it is needed, so bit-identical).
+// Canonical query data from the segment's end points (the velocity of the
+// segment as every search form computes it).
+__device__ inline void query_canon_pts(double xs, double ys, double zs, double ts, double xe,
+                                       double ye, double ze, double te, const Request& R,
+                                       QCanon& q) {
+    const double dt = te - ts;
+    q.x = xs;
+    q.y = ys;
+    q.z = zs;
+    q.vx = (xe - xs) / dt;
+    q.vy = (ye - ys) / dt;
+    q.vz = (ze - zs) / dt;
+    q.ts = ts;
+    q.aq = dmax(ts, R.t_start);
+    q.bq = dmin(te, R.t_end);
+    q.d = R.d;
+}
+
 __device__ inline void query_canon(const QueryView& Q, const Request& R, uint64_t k, QCanon& q) {
+    if (!Q.ent) {
+        query_canon_pts(Q.a[0][k], Q.a[1][k], Q.a[2][k], Q.a[3][k], Q.a[4][k], Q.a[5][k],
+                        Q.a[6][k], Q.a[7][k], R, q);
+        return;
+    }
     double ts, te;
-    if (Q.ent) {
+    {
         // the entry record holds the same velocity, computed the same way
         const EntryF64 e = Q.ent[k];
         q.x = e.x;
@@ -277,18 +300,6 @@ __device__ inline void query_canon(const QueryView& Q, const Request& R, uint64_
         q.vz = e.vz;
         ts = e.ts;
         te = e.te;
-    } else {
-        const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k];
-        const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k];
-        ts = Q.a[3][k];
-        te = Q.a[7][k];
-        const double dt = te - ts;
-        q.x = xs;
-        q.y = ys;
-        q.z = zs;
-        q.vx = (xe - xs) / dt;
-        q.vy = (ye - ys) / dt;
-        q.vz = (ze - zs) / dt;
     }
     q.ts = ts;
     q.aq = dmax(ts, R.t_start);
@@ -327,22 +338,22 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
             r = request_of(req, nreq, k);
         }
         bool ok = true;  // index entries were validated when the index was built
-        double ts;
+        QCanon p;
         if (Q.ent) {
-            ts = Q.ent[k].ts;
+            query_canon(Q, req[r], k, p);
         } else {
-            const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k];
+            // the end points are read once, for the validation and the
+            // canonical data
+            const double xs = Q.a[0][k], ys = Q.a[1][k], zs = Q.a[2][k], ts = Q.a[3][k];
             const double xe = Q.a[4][k], ye = Q.a[5][k], ze = Q.a[6][k], te = Q.a[7][k];
-            ts = Q.a[3][k];
             ok = finite(xs) && finite(ys) && finite(zs) && finite(ts) && finite(xe) &&
                  finite(ye) && finite(ze) && finite(te) && te > ts;
+            if (ok) query_canon_pts(xs, ys, zs, ts, xe, ye, ze, te, req[r], p);
         }
-        qslot[k] = kInactive;
         if (!ok) {
             atomicOr(&hdr->err, 1u);
         } else {
-            QCanon p;
-            query_canon(Q, req[r], k, p);
+            const double ts = p.ts;
             if (p.aq < p.bq) {
                 uint32_t lo, hi, j0, j1;
                 cand_range(I, p.aq, p.bq, &lo, &hi, &j0, &j1);
@@ -385,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
     uint32_t base = 0;
     if (act && lane == start) base = atomicAdd(&b_count[key], next - start);
     base = __shfl(base, start);
-    if (act) qslot[k] = base + (lane - start);
+    if (k < desc->nq) qslot[k] = act ? base + (lane - start) : kInactive;
 }
 
 // Schedule only (tds_schedule): candidate range per query segment.

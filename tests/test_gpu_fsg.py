@@ -83,6 +83,18 @@ def test_fsg_windows_overflow_and_device_output():
     idx.close()
 
 
+def test_fsg_largest_grid():
+    # 256^3 = 2^24 cells, the largest grid accepted: mostly empty cells
+    w = trajgen.tiny(scale=0.05)
+    idx = tds.Index(w.D)
+    g = tds.FSG(idx, 256, 256, 256)
+    compare(g.search(w.Q, 3.0, 0.0, 49.0), oracle.search(w.Q, w.D, 3.0, 0.0, 49.0), "256^3")
+    g.close()
+    with pytest.raises(tds.TdsError):
+        tds.FSG(idx, 256, 256, 257)
+    idx.close()
+
+
 def test_fsg_invalid_arguments():
     w = trajgen.tiny(scale=0.01)
     idx = tds.Index(w.D)
