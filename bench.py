@@ -84,6 +84,10 @@ def pct(x, q):
 
 KERNEL_SOURCES = ("search.hip", "canon.hpp", "tds_internal.hpp")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_distance_fp32_uniform1m_traffic.json")
+VALU_JSON = os.path.join(ROOT, "profiles", "k_distance_fp32_uniform1m_valu.json")
+# wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs,
+# one wave64 FP32 instruction per SIMD every 4 cycles (16 lanes), 2.4 GHz
+PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 
 
 def kernel_source_hash():
@@ -106,6 +110,40 @@ def traffic_from_profile():
     except (OSError, ValueError):
         return None
     return rec.get("bytes_per_launch") if rec.get("kernel_sources_sha256_16") == h else None
+
+
+def valu_from_profile():
+    """VALU and SALU instructions per launch of the distance kernel from the
+    committed counter summary, if taken on the current kernel sources."""
+    try:
+        with open(VALU_JSON) as f:
+            rec = json.load(f)
+        h = kernel_source_hash()
+    except (OSError, ValueError):
+        return None
+    return rec if rec.get("kernel_sources_sha256_16") == h else None
+
+
+def summarize_valu(csv_path, command):
+    """Counter CSV of one rocprofv3 --pmc run (SQ_INSTS_VALU SQ_INSTS_SALU
+    SQ_WAVES) -> the distance kernel's instruction counts per launch."""
+    import csv
+    with open(csv_path) as f:
+        rows = [r for r in csv.DictReader(f) if "k_distance<2>" in r["Kernel_Name"]]
+    per = {}
+    for r in rows:
+        per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if not per:
+        raise SystemExit(f"{csv_path}: no distance-kernel rows")
+    rec = {"kernel": "k_distance<FP32_RECHECK>", "workload": "uniform1m, d in {1,5,25}",
+           "launches": len(next(iter(per.values())))}
+    for name, vals in per.items():
+        rec[name.lower() + "_per_launch"] = sum(vals) / len(vals)
+    rec["kernel_sources_sha256_16"] = kernel_source_hash()
+    rec["command"] = command
+    with open(VALU_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
 
 
 def summarize_traffic(fetch_csv, write_csv, command):
@@ -295,6 +333,8 @@ def main():
     ap.add_argument("--no-fsg", action="store_true", help="skip the fixed spatial grid leg")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two counter CSVs and exit (no GPU)")
+    ap.add_argument("--summarize-valu", metavar="CSV",
+                    help="write the VALU instruction summary from a counter CSV and exit (no GPU)")
     ap.add_argument("--tune", action="store_true", help="autotune before timing")
     ap.add_argument("--unbatched", action="store_true",
                     help="also time the step as three separate searches (context)")
@@ -307,6 +347,12 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
+    if args.summarize_valu:
+        summarize_valu(args.summarize_valu,
+                       "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_WAVES --output-format csv "
+                       "-d gpurun_out/pmc -o p -- python3 bench.py --steps 3 --warmup 1 "
+                       "--no-cpu --no-serve --no-self-join --no-fsg")
+        return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic,
                           "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv "
@@ -426,6 +472,15 @@ def main():
         "dram_tb_s": round(traffic / (avg_ms * 1e-3) / 1e12, 3) if traffic else None,
         "dram_frac_of_hbm": round(traffic / (avg_ms * 1e-3) / PEAK_HBM_BPS, 4) if traffic else None,
         "alu_frac": roofline["frac"]}
+    valu = valu_from_profile()
+    if valu and valu.get("sq_insts_valu_per_launch"):
+        # VALU issue utilisation: wave64 VALU instructions per launch (counter
+        # run of the same command) over the launch time, against the issue peak
+        vi = valu["sq_insts_valu_per_launch"]
+        roofline["views"]["valu_wave_insts_per_launch"] = int(vi)
+        roofline["views"]["valu_issue_frac"] = round(vi / (avg_ms * 1e-3) / PEAK_VALU_WAVE_INSTS, 3)
+        if valu.get("sq_insts_salu_per_launch"):
+            roofline["views"]["salu_wave_insts_per_launch"] = int(valu["sq_insts_salu_per_launch"])
 
     extra = {"queries_per_s": round(n_queries * args.steps / elapsed, 1),
              "candidate_tests_per_kernel_s": round(tests / (kern_ms * 1e-3), 1) if kern_ms else None,
