@@ -1,0 +1,126 @@
+"""The fixed-spatial-grid, merge and radix-sort kernels run on the CPU: their
+HIP sources are compiled with g++ and AddressSanitizer against a small
+emulation of the HIP runtime (tests/emu/hip: the threads of a block as host
+threads, wave intrinsics through a per-wave barrier, device memory from
+malloc).  Every memory access the kernels make is then bounds-checked, and
+their results are compared with the oracle's.  This checks the kernels'
+indexing and the host code around them on a machine without a GPU; the GPU
+parity tests check the same entry points on the device."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import trajgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1410_2698_amd", "csrc")
+RESULT_DTYPE = np.dtype([("q_seg", "<u4"), ("e_seg", "<u4"), ("q_traj", "<u4"), ("e_traj", "<u4"),
+                         ("t_lo", "<f8"), ("t_hi", "<f8")])
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("emu") / "harness")
+    cmd = [gxx, "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
+           "-I", os.path.join(ROOT, "tests", "emu"), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           "-x", "c++", os.path.join(CSRC, "fsg.hip"), os.path.join(CSRC, "radix_sort.hip"),
+           os.path.join(CSRC, "traj_merge.hip"), "-x", "none",
+           os.path.join(ROOT, "tests", "emu", "harness.cpp"), "-o", out, "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("emulation build failed:\n" + r.stderr[-4000:])
+    return out
+
+
+def run(harness, *args):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    r = subprocess.run([harness, *map(str, args)], capture_output=True, text=True, env=env,
+                       timeout=600)
+    assert r.returncode == 0, f"emulated kernels failed:\n{r.stdout[-2000:]}\n{r.stderr[-6000:]}"
+    st, n = r.stdout.split()
+    return int(st), int(n)
+
+
+def columns(S):
+    return np.stack([np.asarray(getattr(S, k), np.float64)
+                     for k in ("xs", "ys", "zs", "ts", "xe", "ye", "ze", "te")]
+                    + [np.asarray(S.traj, np.float64)])
+
+
+def same_records(got, want):
+    key = lambda r: np.lexsort((r["e_seg"], r["q_seg"]))
+    got, want = got[key(got)], want[key(want)]
+    assert got.size == want.size
+    for f in ("q_seg", "e_seg", "q_traj", "e_traj"):
+        assert np.array_equal(got[f], want[f]), f
+    for f in ("t_lo", "t_hi"):
+        assert np.all(np.abs(got[f] - want[f]) <= 1e-9 * np.maximum(1.0, np.abs(want[f]))), f
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (7, 3, 5), (50, 50, 50)])
+def test_grid_search_emulated(harness, tmp_path, grid):
+    w = trajgen.tiny(scale=0.05)  # 100 trajectories (4,900 entries), 5 query trajectories
+    columns(w.D).tofile(tmp_path / "D.bin")
+    columns(w.Q).tofile(tmp_path / "Q.bin")
+    st, n = run(harness, "fsg", tmp_path / "D.bin", tmp_path / "Q.bin", *grid, 8.0, 0.0, 49.0,
+                tmp_path / "out.bin")
+    assert st == 0
+    got = np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE)
+    want = oracle.search(w.Q, w.D, 8.0, 0.0, 49.0)
+    assert want.size > 0 and n == want.size
+    same_records(got, want)
+
+
+def merge_emulated(harness, tmp_path, recs, cap=None):
+    recs.astype(RESULT_DTYPE).tofile(tmp_path / "recs.bin")
+    cap = recs.size if cap is None else cap
+    st, m = run(harness, "merge", tmp_path / "recs.bin", cap, tmp_path / "ivl.bin")
+    return st, m, np.fromfile(tmp_path / "ivl.bin", dtype=oracle.TRAJ_DTYPE)
+
+
+def same_intervals(got, want):
+    assert got.size == want.size
+    for f in ("q_traj", "e_traj", "t_lo", "t_hi"):
+        assert np.array_equal(got[f], want[f]), f
+
+
+def test_merge_emulated_random(harness, tmp_path):
+    rng = np.random.default_rng(4)
+    n = 3000  # two radix-sort tiles
+    recs = np.zeros(n, RESULT_DTYPE)
+    recs["q_seg"] = np.arange(n)
+    recs["q_traj"] = rng.integers(0, 40, n)
+    recs["e_traj"] = rng.integers(0, 40, n) * 70001  # ids of 22 bits: 4 pair digits
+    lo = rng.integers(-800, 800, n) / 8.0
+    recs["t_lo"] = lo
+    recs["t_hi"] = lo + rng.integers(0, 24, n) / 8.0
+    st, m, got = merge_emulated(harness, tmp_path, recs)
+    assert st == 0
+    same_intervals(got, oracle.merge_trajectories(recs))
+
+
+def test_merge_emulated_degenerate_keys(harness, tmp_path):
+    # one t_lo for every record (no t_lo digit differs: no pass of that
+    # sort) and the largest ids (all eight pair digits)
+    n = 600
+    recs = np.zeros(n, RESULT_DTYPE)
+    recs["q_traj"] = np.where(np.arange(n) % 3 == 0, 0xFFFFFFFF, 7)
+    recs["e_traj"] = np.where(np.arange(n) % 2 == 0, 0xFFFFFFFF, 0)
+    recs["t_lo"] = 2.5
+    recs["t_hi"] = 2.5 + (np.arange(n) % 5)
+    st, m, got = merge_emulated(harness, tmp_path, recs)
+    assert st == 0
+    want = oracle.merge_trajectories(recs)
+    assert want.size == 4
+    same_intervals(got, want)
+    # capacity below the total: the first intervals in order, the total reported
+    st, m, got = merge_emulated(harness, tmp_path, recs, cap=3)
+    assert st == 2 and m == 4  # TDS_E_OVERFLOW
+    same_intervals(got, want[:3])
