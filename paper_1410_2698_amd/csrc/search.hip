@@ -1238,8 +1238,8 @@ int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_
                     hipEvent_t ev_begin, hipEvent_t ev_end) {
     const uint32_t blocks =
         std::min(kMaxDistBlocks, std::max(1u, ceil_div(grid_waves, kWavesPerBlock)));
-    auto* kern = (prec == TDS_PREC_FP64) ? k_distance<TDS_PREC_FP64>
-                                         : k_distance<TDS_PREC_FP32_RECHECK>;
+    void (*kern)(DistArgs) = k_distance<TDS_PREC_FP32_RECHECK>;
+    if (prec == TDS_PREC_FP64) kern = k_distance<TDS_PREC_FP64>;
     if (ev_begin && ev_end) {
         // the events take the dispatch's own start and end times (no marker
         // packets around the kernel, so no bubbles before and after it)

@@ -1,12 +1,13 @@
-// Host harness for the CPU emulation of the grid and merge kernels (built by
-// tests/test_emulated_kernels.py with g++ and AddressSanitizer against the
-// shim in tests/emu/hip).  It builds a tds_index by hand (entries in start
-// time order; the grid does not depend on the order) and calls the library's
-// grid build / search and trajectory merge, whose kernels then run on the
-// host.
+// Host harness for the CPU emulation of the library's kernels (built by
+// tests/test_emulated_kernels.py with clang++ and AddressSanitizer against the
+// shim in tests/emu/hip).  It calls the library's internal entry points (the
+// C ABI wrappers in capi.hip are not linked), whose kernels then run on the
+// host:
 //
-//   harness fsg D.bin Q.bin gx gy gz d t0 t1 out.bin   -> "status n"
-//   harness merge recs.bin capacity out.bin            -> "status n"
+//   harness fsg D.bin Q.bin gx gy gz d t0 t1 out.bin              -> "status n"
+//   harness search D.bin Q.bin layout prec d t0 t1 cap out.bin    -> "status n ftests"
+//   harness selfjoin D.bin layout prec d t0 t1 cap out.bin        -> "status n ftests"
+//   harness merge recs.bin capacity out.bin                       -> "status n"
 //
 // D.bin / Q.bin: 9 float64 columns (xs ys zs ts xe ye ze te traj), column
 // after column.  recs.bin: tds_result records.  out.bin: the records or
@@ -23,6 +24,15 @@
 long emu_launches = 0;
 
 namespace tds {
+int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t stream,
+               tds_index** out);
+void destroy_index(tds_index* idx);
+int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start, double t_end,
+                tds_result* out, uint64_t capacity, uint64_t* n_out, const tds_search_params* params,
+                hipStream_t stream, tds_stats* stats);
+int self_join_impl(tds_index* idx, double d, double t_start, double t_end, tds_result* out,
+                   uint64_t capacity, uint64_t* n_out, const tds_search_params* params,
+                   hipStream_t stream, tds_stats* stats);
 int fsg_build(const tds_index* idx, uint32_t gx, uint32_t gy, uint32_t gz, hipStream_t s,
               tds_fsg** out);
 void fsg_destroy(tds_fsg* f);
@@ -31,16 +41,13 @@ int fsg_search(const tds_fsg* f, const tds_segments* Q, double d, double t_start
                hipStream_t s, tds_stats* stats);
 int merge_impl(const tds_result* recs, uint64_t n, bool recs_dev, tds_traj_interval* out,
                uint64_t capacity, bool out_dev, uint64_t* n_out, hipStream_t s);
-
-// The harness passes valid segment sets only.
-int validate_segments_args(const tds_segments* S) {
-    return (S && S->xs && S->ys && S->zs && S->ts && S->xe && S->ye && S->ze && S->te)
-               ? TDS_OK
-               : TDS_E_INVALID;
-}
 }  // namespace tds
 
-extern "C" void tds_search_params_default(tds_search_params* p) { std::memset(p, 0, sizeof(*p)); }
+// As in the C ABI (capi.hip, not linked here).
+extern "C" void tds_search_params_default(tds_search_params* p) {
+    std::memset(p, 0, sizeof(*p));
+    p->precision = TDS_PREC_FP32_RECHECK;
+}
 
 namespace {
 
@@ -69,61 +76,98 @@ Columns read_columns(const char* path) {
     return c;
 }
 
+// Segment view of the columns (host memory) with trajectory ids.
+struct SegSet {
+    std::vector<uint32_t> traj;
+    tds_segments s{};
+    explicit SegSet(const Columns& c) : traj(c.n) {
+        for (size_t i = 0; i < c.n; ++i) traj[i] = (uint32_t)c.col(8)[i];
+        s.xs = c.col(0);
+        s.ys = c.col(1);
+        s.zs = c.col(2);
+        s.ts = c.col(3);
+        s.xe = c.col(4);
+        s.ye = c.col(5);
+        s.ze = c.col(6);
+        s.te = c.col(7);
+        s.traj_id = traj.data();
+        s.n = c.n;
+        s.on_device = 0;
+    }
+};
+
+void write_records(const char* path, const std::vector<tds_result>& out, uint64_t n) {
+    FILE* fo = fopen(path, "wb");
+    fwrite(out.data(), sizeof(tds_result), std::min<uint64_t>(n, out.size()), fo);
+    fclose(fo);
+}
+
+tds_index* build(const Columns& D, uint32_t layout) {
+    SegSet S(D);
+    tds_build_params bp{};
+    bp.layout = layout;
+    tds_index* idx = nullptr;
+    const int st = tds::build_impl(&S.s, &bp, nullptr, &idx);
+    if (st != TDS_OK) {
+        printf("%d 0 0\n", st);
+        exit(0);
+    }
+    return idx;
+}
+
 int run_fsg(char** argv) {
     const Columns D = read_columns(argv[2]);
     const Columns Qc = read_columns(argv[3]);
     const uint32_t g[3] = {(uint32_t)atoi(argv[4]), (uint32_t)atoi(argv[5]),
                            (uint32_t)atoi(argv[6])};
     const double d = atof(argv[7]), t0 = atof(argv[8]), t1 = atof(argv[9]);
-    const size_t nd = D.n, nq = Qc.n;
-    std::vector<uint32_t> ord(nd);
-    std::iota(ord.begin(), ord.end(), 0u);
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](uint32_t a, uint32_t b) { return D.col(3)[a] < D.col(3)[b]; });
-    tds_index idx;
-    idx.n = nd;
-    std::vector<tds::EntryF64> e64(nd);
-    std::vector<uint32_t> seg_id(nd), traj(nd);
-    for (size_t p = 0; p < nd; ++p) {
-        const uint32_t i = ord[p];
-        const double xs = D.col(0)[i], ys = D.col(1)[i], zs = D.col(2)[i], ts = D.col(3)[i];
-        const double xe = D.col(4)[i], ye = D.col(5)[i], ze = D.col(6)[i], te = D.col(7)[i];
-        const double dt = te - ts;
-        e64[p] = tds::EntryF64{xs, ys, zs, (xe - xs) / dt, (ye - ys) / dt, (ze - zs) / dt, ts, te};
-        seg_id[p] = i;
-        traj[p] = (uint32_t)D.col(8)[i];
-    }
-    idx.e64 = e64.data();
-    idx.seg_id = seg_id.data();
-    idx.traj = traj.data();
+    tds_index* idx = build(D, TDS_LAYOUT_DEFAULT);
     tds_fsg* f = nullptr;
-    int st = tds::fsg_build(&idx, g[0], g[1], g[2], nullptr, &f);
+    int st = tds::fsg_build(idx, g[0], g[1], g[2], nullptr, &f);
     if (st != TDS_OK) {
         printf("%d 0\n", st);
         return 0;
     }
-    std::vector<uint32_t> qtraj(nq);
-    for (size_t i = 0; i < nq; ++i) qtraj[i] = (uint32_t)Qc.col(8)[i];
-    tds_segments Q{};
-    Q.xs = Qc.col(0);
-    Q.ys = Qc.col(1);
-    Q.zs = Qc.col(2);
-    Q.ts = Qc.col(3);
-    Q.xe = Qc.col(4);
-    Q.ye = Qc.col(5);
-    Q.ze = Qc.col(6);
-    Q.te = Qc.col(7);
-    Q.traj_id = qtraj.data();
-    Q.n = nq;
-    Q.on_device = 0;
+    SegSet Q(Qc);
     std::vector<tds_result> out(1u << 20);
     uint64_t n = 0;
-    st = tds::fsg_search(f, &Q, d, t0, t1, out.data(), out.size(), &n, nullptr, nullptr, nullptr);
-    FILE* fo = fopen(argv[10], "wb");
-    fwrite(out.data(), sizeof(tds_result), std::min<uint64_t>(n, out.size()), fo);
-    fclose(fo);
+    st = tds::fsg_search(f, &Q.s, d, t0, t1, out.data(), out.size(), &n, nullptr, nullptr, nullptr);
+    write_records(argv[10], out, n);
     tds::fsg_destroy(f);
+    tds::destroy_index(idx);
     printf("%d %llu\n", st, (unsigned long long)n);
+    return 0;
+}
+
+// search / self-join: layout and precision by their C ABI values
+int run_search(char** argv, bool self_join) {
+    int a = 2;
+    const Columns D = read_columns(argv[a++]);
+    Columns Qc;
+    if (!self_join) Qc = read_columns(argv[a++]);
+    const uint32_t layout = (uint32_t)atoi(argv[a++]);
+    const int prec = atoi(argv[a++]);
+    const double d = atof(argv[a++]), t0 = atof(argv[a++]), t1 = atof(argv[a++]);
+    const uint64_t cap = strtoull(argv[a++], nullptr, 10);
+    const char* path = argv[a++];
+    tds_index* idx = build(D, layout);
+    tds_search_params p;
+    tds_search_params_default(&p);
+    p.precision = prec;
+    p.grid_waves = 64;  // 16 persistent workgroups: fewer idle host threads
+    std::vector<tds_result> out(std::max<uint64_t>(cap, 1));
+    uint64_t n = 0;
+    tds_stats st{};
+    int status;
+    if (self_join) {
+        status = tds::self_join_impl(idx, d, t0, t1, out.data(), cap, &n, &p, nullptr, &st);
+    } else {
+        SegSet Q(Qc);
+        status = tds::search_impl(idx, &Q.s, d, t0, t1, out.data(), cap, &n, &p, nullptr, &st);
+    }
+    write_records(path, out, n);
+    tds::destroy_index(idx);
+    printf("%d %llu %llu\n", status, (unsigned long long)n, (unsigned long long)st.filter_tests);
     return 0;
 }
 
@@ -147,6 +191,8 @@ int run_merge(char** argv) {
 
 int main(int argc, char** argv) {
     if (argc >= 11 && std::string(argv[1]) == "fsg") return run_fsg(argv);
+    if (argc >= 11 && std::string(argv[1]) == "search") return run_search(argv, false);
+    if (argc >= 10 && std::string(argv[1]) == "selfjoin") return run_search(argv, true);
     if (argc >= 5 && std::string(argv[1]) == "merge") return run_merge(argv);
     fprintf(stderr, "usage: harness fsg ... | harness merge ...\n");
     return 2;

@@ -24,6 +24,7 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 #define HIP_SYMBOL(x) (&x)
+#define amdgpu_waves_per_eu(...)
 
 struct dim3 {
     unsigned x = 1, y = 1, z = 1;
@@ -95,6 +96,28 @@ inline T emu_xchg(T v, unsigned src) {
 template <class T> inline T __shfl(T v, int src, int = 64) { return emu_xchg(v, (unsigned)src); }
 template <class T> inline T __shfl_xor(T v, int m, int = 64) { return emu_xchg(v, __lane_id() ^ (unsigned)m); }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
+inline int __clzll(long long x) { return x ? __builtin_clzll((unsigned long long)x) : 64; }
+inline int __ffsll(long long x) { return __builtin_ffsll(x); }
+inline int __ffsll(unsigned long long x) { return __builtin_ffsll((long long)x); }
+template <class T> inline T __shfl_up(T v, unsigned d, int = 64) {
+    const unsigned lane = __lane_id();
+    return emu_xchg(v, lane >= d ? lane - d : lane);
+}
+// AMDGCN builtins the sources call directly
+inline unsigned long long __builtin_amdgcn_ballot_w64(bool p) { return __ballot(p); }
+inline int __builtin_amdgcn_readlane(int v, int l) { return emu_xchg(v, (unsigned)l); }
+// the sources apply it to wave-uniform values only, which every lane holds
+inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
+inline unsigned __builtin_amdgcn_readfirstlane(unsigned v) { return v; }
+inline void __builtin_amdgcn_wave_barrier() { emu_wave().bar->arrive_and_wait(); }
+#define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
+#define __HIP_MEMORY_SCOPE_AGENT 3
+#define __HIP_MEMORY_SCOPE_WORKGROUP 2
+#define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
+#define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
+inline int __float_as_int(float f) { int i; memcpy(&i, &f, 4); return i; }
+inline unsigned __float_as_uint(float f) { unsigned i; memcpy(&i, &f, 4); return i; }
+inline double __longlong_as_double(long long i) { double d; memcpy(&d, &i, 8); return d; }
 inline int __popc(unsigned x) { return __builtin_popcount(x); }
 
 template <class T> inline T atomicAdd(T* p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }

@@ -1,5 +1,7 @@
-"""The fixed-spatial-grid, merge and radix-sort kernels run on the CPU: their
-HIP sources are compiled with g++ and AddressSanitizer against a small
+"""The library's kernels run on the CPU: the HIP sources of the index build,
+the search (query preparation, bucket scan, distance kernel, FP64 recheck,
+result append), the fixed spatial grid, the merge and the radix sort are
+compiled as host code with clang++ and AddressSanitizer against a small
 emulation of the HIP runtime (tests/emu/hip: the threads of a block as host
 threads, wave intrinsics through a per-wave barrier, device memory from
 malloc).  Every memory access the kernels make is then bounds-checked, and
@@ -24,14 +26,21 @@ RESULT_DTYPE = np.dtype([("q_seg", "<u4"), ("e_seg", "<u4"), ("q_traj", "<u4"), 
 
 @pytest.fixture(scope="module")
 def harness(tmp_path_factory):
-    gxx = shutil.which("g++")
-    if gxx is None:
-        pytest.skip("g++ not available")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cxx = os.path.join(rocm, "llvm", "bin", "clang++")
+    if not os.path.exists(cxx):
+        cxx = shutil.which("clang++")
+    if cxx is None:
+        pytest.skip("clang++ not available")
     out = str(tmp_path_factory.mktemp("emu") / "harness")
-    cmd = [gxx, "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
+    # host-only build (no GPU code); the canonical evaluation is compiled
+    # without contraction, as for the GPU
+    cmd = [cxx, "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
+           "-ffp-contract=off", "-Wno-unknown-attributes", "-Wno-ignored-attributes",
            "-I", os.path.join(ROOT, "tests", "emu"), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-x", "c++", os.path.join(CSRC, "fsg.hip"), os.path.join(CSRC, "radix_sort.hip"),
-           os.path.join(CSRC, "traj_merge.hip"), "-x", "none",
+           os.path.join(CSRC, "traj_merge.hip"), os.path.join(CSRC, "index_build.hip"),
+           os.path.join(CSRC, "search.hip"), "-x", "none",
            os.path.join(ROOT, "tests", "emu", "harness.cpp"), "-o", out, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -44,8 +53,7 @@ def run(harness, *args):
     r = subprocess.run([harness, *map(str, args)], capture_output=True, text=True, env=env,
                        timeout=600)
     assert r.returncode == 0, f"emulated kernels failed:\n{r.stdout[-2000:]}\n{r.stderr[-6000:]}"
-    st, n = r.stdout.split()
-    return int(st), int(n)
+    return tuple(int(v) for v in r.stdout.split())
 
 
 def columns(S):
@@ -76,6 +84,48 @@ def test_grid_search_emulated(harness, tmp_path, grid):
     want = oracle.search(w.Q, w.D, 8.0, 0.0, 49.0)
     assert want.size > 0 and n == want.size
     same_records(got, want)
+
+
+TEMPORAL, SPATIAL = 1, 2  # index layouts (C ABI values)
+FP64, FP32 = 1, 2         # search precisions (C ABI values)
+
+
+@pytest.mark.parametrize("layout,prec,d", [(SPATIAL, FP32, 8.0), (SPATIAL, FP64, 30.0),
+                                           (TEMPORAL, FP32, 30.0)])
+def test_search_emulated(harness, tmp_path, layout, prec, d):
+    # the whole search path on the CPU: index build, query preparation,
+    # buckets, work items, distance kernel, FP64 recheck and append
+    w = trajgen.tiny(scale=0.05)
+    columns(w.D).tofile(tmp_path / "D.bin")
+    columns(w.Q).tofile(tmp_path / "Q.bin")
+    st, n, ftests = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", layout, prec, d,
+                        0.0, 49.0, 100000, tmp_path / "out.bin")
+    assert st == 0
+    want = oracle.search(w.Q, w.D, d, 0.0, 49.0)
+    assert want.size > 0 and n == want.size and ftests > 0
+    same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
+
+
+def test_search_emulated_overflow(harness, tmp_path):
+    # a result buffer smaller than the result set: the total is reported
+    w = trajgen.tiny(scale=0.05)
+    columns(w.D).tofile(tmp_path / "D.bin")
+    columns(w.Q).tofile(tmp_path / "Q.bin")
+    want = oracle.search(w.Q, w.D, 30.0, 0.0, 49.0)
+    st, n, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", SPATIAL, FP32, 30.0,
+                   0.0, 49.0, 100, tmp_path / "out.bin")
+    assert st == 2 and n == want.size  # TDS_E_OVERFLOW
+
+
+def test_self_join_emulated(harness, tmp_path):
+    w = trajgen.tiny(scale=0.04)
+    columns(w.D).tofile(tmp_path / "D.bin")
+    st, n, _ = run(harness, "selfjoin", tmp_path / "D.bin", SPATIAL, FP32, 4.0, 0.0, 49.0, 200000,
+                   tmp_path / "out.bin")
+    assert st == 0
+    want = oracle.self_join(w.D, 4.0, 0.0, 49.0)
+    assert want.size > 0 and n == want.size
+    same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
 
 
 def merge_emulated(harness, tmp_path, recs, cap=None):
