@@ -26,6 +26,10 @@
 #define HIP_SYMBOL(x) (&x)
 #define amdgpu_waves_per_eu(...)
 
+struct alignas(16) uint4 {
+    unsigned x, y, z, w;
+};
+
 struct dim3 {
     unsigned x = 1, y = 1, z = 1;
     dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
@@ -108,7 +112,6 @@ inline unsigned long long __builtin_amdgcn_ballot_w64(bool p) { return __ballot(
 inline int __builtin_amdgcn_readlane(int v, int l) { return emu_xchg(v, (unsigned)l); }
 // the sources apply it to wave-uniform values only, which every lane holds
 inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
-inline unsigned __builtin_amdgcn_readfirstlane(unsigned v) { return v; }
 inline void __builtin_amdgcn_wave_barrier() { emu_wave().bar->arrive_and_wait(); }
 #define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __HIP_MEMORY_SCOPE_AGENT 3
