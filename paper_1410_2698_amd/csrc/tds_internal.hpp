@@ -118,18 +118,6 @@ struct alignas(64) SearchHeader {
 };
 static_assert(sizeof(SearchHeader) == 64, "SearchHeader layout");
 
-// Work counters of the persistent distance kernel: the items of a launch are
-// split into kParts contiguous parts, each with its own counter on its own
-// 256-byte line, so that the atomic fetches are spread over kParts addresses
-// instead of serialising on one (workgroup b starts on part b % kParts, which
-// keeps a part's candidates in the L2 of one XCD when workgroups are dealt to
-// the XCDs round-robin).
-constexpr uint32_t kParts = 8;
-struct alignas(256) WorkCtr {
-    uint32_t v;
-    uint32_t pad[63];
-};
-
 // Per-workgroup counters of the distance kernel, folded into the header by a
 // one-block kernel after the launch (no contended atomics).
 struct alignas(32) BlockStats {
@@ -177,7 +165,6 @@ struct Workspace {
     tds_result* res = nullptr;      // device result buffer (host-output mode)
     SearchHeader* hdr = nullptr;
     SearchHeader* hdr_host = nullptr;  // pinned mirror
-    WorkCtr* wctr = nullptr;           // kParts work counters
     BlockStats* bstats = nullptr;      // kMaxDistBlocks per-workgroup counters
     BatchDesc* desc = nullptr;
     BatchDesc* desc_host = nullptr;    // pinned staging of the descriptor
