@@ -966,15 +966,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t item_end = (A.item_end == 0xFFFFFFFFu)
                                   ? uniform(min(A.hdr->n_items, A.desc->item_cap))
                                   : A.item_end;
-    // items [item_begin, item_end) dealt round-robin: wave w of the grid takes
-    // items w, w + G, w + 2G, ...  No work counter: a device-scope atomic per
-    // item (a fetch the item's loads then depend on) cost more than the
-    // imbalance it removed (35 % of the kernel on the uniform workload, none
-    // measurable on the skewed ones)
+    // items [item_begin, item_end) dealt statically, XCD by XCD: workgroups
+    // are dispatched to the XCDs round-robin, so workgroup b runs on XCD
+    // b mod 8; the items are split into 8 contiguous parts (consecutive items
+    // share buckets, hence candidate ranges) and part x is dealt round-robin
+    // to the waves of the workgroups b = x mod 8, so each bucket's candidates
+    // are fetched into one XCD's L2.  No work counter: a device-scope atomic
+    // per item (a fetch the item's loads then depend on) cost more than the
+    // imbalance it removed.
     const uint64_t n_it = item_end > A.item_begin ? item_end - A.item_begin : 0u;
-    const uint32_t gw = uniform(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
-    const uint32_t G = gridDim.x * kWavesPerBlock;
-    for (uint64_t k = gw; k < n_it; k += G) {
+    const uint32_t ng = min(gridDim.x, kXcds);
+    const uint32_t grp = blockIdx.x % ng;
+    const uint32_t gblocks = (gridDim.x - grp + ng - 1) / ng;  // workgroups of the group
+    const uint32_t gw = uniform((blockIdx.x / ng) * kWavesPerBlock + threadIdx.x / kWave);
+    const uint32_t G = gblocks * kWavesPerBlock;
+    const uint64_t p0 = n_it * grp / ng, p1 = n_it * (grp + 1) / ng;
+    for (uint64_t k = p0 + gw; k < p1; k += G) {
         const uint32_t it = A.item_begin + (uint32_t)k;
         const uint32_t b = uniform(A.item_bucket[it]);
         const BucketInfo bi = A.binfo[b];

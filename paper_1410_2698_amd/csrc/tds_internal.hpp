@@ -18,6 +18,7 @@ namespace tds {
 constexpr int kWave = 64;               // CDNA wavefront width
 constexpr int kBlock = 256;             // threads per block of the search kernels
 constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr uint32_t kXcds = 8;            // accelerator complex dies (own L2 each)
 constexpr uint32_t kMaxBins = 65535;
 constexpr uint32_t kMaxBuckets = 65536; // query buckets of one search
 constexpr uint32_t kSpanClasses = 4;    // bin-span classes per first bin
