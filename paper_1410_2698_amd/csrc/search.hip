@@ -1,14 +1,15 @@
 // Distance threshold search on the GPU (Sec. 3.1 problem, Sec. 4.2.2 search).
 //
 // Per search, on one stream:
-//   k_zero       clear the header, bucket tables and request counters;
+//   k_zero       clear the header, bucket counters and request counters;
 //   k_qprep      one thread per query segment: validate, velocity, clip to the
 //                window, candidate range [lo, hi) by bisection of the bin
 //                tables (the schedule S of Sec. 4.2.2, computed on the GPU),
 //                FP32 filter sphere, bucket key = (first bin, bin span);
 //   k_bucket_scan  one block: bucket offsets, 64-segment groups per bucket,
 //                candidate chunks per bucket and the work-item table;
-//   k_scatter    order the query segments by bucket;
+//   k_scatter    order the query segments by bucket, and fill the work-item
+//                table (item -> bucket);
 //   k_distance   persistent waves take work items round-robin (64 query
 //                segments of one bucket x one chunk of their common candidate
 //                range).  FP32 form: the lanes hold the chunk's candidates
@@ -34,6 +35,37 @@ namespace tds {
 namespace {
 
 constexpr uint32_t kInactive = 0xFFFFFFFFu;
+
+// The bucket slot counters are split into parts: about 1,500 returning
+// atomics on one address serialize for ≈ 25 µs, 32 parts bring that down to
+// the cost of the stores.  Part p counts for the query-preparation workgroups
+// [p * bpp, (p + 1) * bpp) (bpp = workgroups per part): the parts are laid
+// out one after the other in each bucket, so its segments stay close to
+// their input order, and the segments of one request (one d) stay together
+// in the 64-segment groups.  The counters are stored part by part (bucket b
+// of part p at p * buckets + b): the 64 lanes of a wave, whose keys are
+// often consecutive, then hit a few cache lines, which the atomics of one
+// instruction share (stored bucket by bucket, the same atomics took as long
+// as without parts).  1 or kCountParts parts: kCountParts when parts *
+// buckets fits the kMaxBuckets-entry tables.
+constexpr uint32_t kCountParts = 32;
+
+uint32_t count_parts(uint32_t nb) {
+    return (uint64_t)nb * kCountParts <= kMaxBuckets ? kCountParts : 1u;
+}
+
+constexpr uint32_t kPartedBuckets = kMaxBuckets / kCountParts;  // most buckets with parts
+
+// Maximum over the kCountParts parts of bucket b (nb buckets).
+__device__ __forceinline__ uint32_t parts_max(const uint32_t* c, uint32_t b, uint32_t nb) {
+    uint32_t v[kCountParts];
+#pragma unroll
+    for (uint32_t p = 0; p < kCountParts; ++p) v[p] = c[p * nb + b];
+    uint32_t m = 0;
+#pragma unroll
+    for (uint32_t p = 0; p < kCountParts; ++p) m = max(m, v[p]);
+    return m;
+}
 
 // Candidates held per lane by the FP32 form: a wave works on tiles of
 // kCpl * 64 candidates, so each query record fetched by a scalar load feeds
@@ -246,17 +278,17 @@ __device__ inline uint32_t request_of(const Request* req, uint32_t nreq, uint64_
 // ------------------------------------------------------------ kernels
 
 __global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_count,
-                                                 uint32_t* b_lo, uint32_t* b_hi, uint32_t nb,
-                                                 ReqCounter* rc, uint32_t nreq) {
-    // nreq: capacity of the request counters (all of them are cleared)
+                                                 uint32_t* b_hi, uint32_t nb,
+                                                 uint32_t nparts, ReqCounter* rc, uint32_t nreq) {
+    // nreq: capacity of the request counters (all of them are cleared);
+    // b_count and b_hi hold nparts parts for each of the nb buckets
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i == 0) {
         SearchHeader h = {};
         *hdr = h;
     }
-    if (i < nb) {
+    if (i < nb * nparts) {
         b_count[i] = 0;
-        b_lo[i] = 0xFFFFFFFFu;
         b_hi[i] = 0;
     }
     if (i < nreq) {
@@ -316,8 +348,8 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                                                   uint32_t* __restrict__ qreq,
                                                   uint32_t* __restrict__ qkey,
                                                   uint32_t* __restrict__ qslot, uint32_t* b_count,
-                                                  uint32_t* b_hi, uint32_t shift,
-                                                  SearchHeader* hdr) {
+                                                  uint32_t* b_hi, uint32_t shift, uint32_t nb,
+                                                  uint32_t bpp, SearchHeader* hdr) {
     // the first requests' starts in LDS: the request of a query segment is
     // then found without a chain of dependent global loads
     __shared__ uint64_t s_begin[kBlock];
@@ -325,6 +357,9 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
     if (threadIdx.x < nreq) s_begin[threadIdx.x] = req[threadIdx.x].q_begin;
     __syncthreads();
     const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    // this workgroup's part of the bucket counters (k_scatter finds it the
+    // same way)
+    const uint32_t part = blockIdx.x / bpp;
     bool act = false;  // the segment gets a bucket slot
     uint32_t key = 0;
     if (k < desc->nq) {
@@ -378,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                     qkey[k] = key;
                     // the bucket's range follows from its key unless it merges
                     // several first bins or spans an open number of bins
-                    if (shift || span == kSpanClasses - 1) atomicMax(&b_hi[key], hi);
+                    if (shift || span == kSpanClasses - 1) atomicMax(&b_hi[part * nb + key], hi);
                     qfu[k] = f;
                     qreq[k] = r;
                 }
@@ -397,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
     const uint64_t above = bnd & ~upto;
     const uint32_t next = above ? (uint32_t)__ffsll((unsigned long long)above) - 1u : 64u;
     uint32_t base = 0;
-    if (act && lane == start) base = atomicAdd(&b_count[key], next - start);
+    if (act && lane == start) base = atomicAdd(&b_count[part * nb + key], next - start);
     base = __shfl(base, start);
     if (k < desc->nq) qslot[k] = act ? base + (lane - start) : kInactive;
 }
@@ -428,15 +463,17 @@ __global__ __launch_bounds__(kBlock) void k_schedule(QueryView Q, double t_start
     hi_out[k] = hi;
 }
 
-// Bucket offsets, groups and the work-item table, one block.
-__global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict__ b_count,
+// Bucket offsets, groups and the work-item table, one block.  The parts of
+// each bucket's slot counter become the parts' offsets within the bucket.
+__global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ b_count,
                                                       uint32_t* __restrict__ b_lo,
-                                                      uint32_t* __restrict__ b_hi,
+                                                      const uint32_t* __restrict__ b_hi,
+                                                      uint32_t* __restrict__ b_range_hi,
                                                       const uint32_t* __restrict__ bin_first,
                                                       const double* __restrict__ min_te,
                                                       const double* __restrict__ max_ts,
                                                       uint32_t m, uint32_t shift,
-                                                      uint32_t nb, uint32_t chunk,
+                                                      uint32_t nb, uint32_t nparts, uint32_t chunk,
                                                       uint32_t* __restrict__ b_start,
                                                       uint32_t* __restrict__ b_item,
                                                       uint32_t* __restrict__ b_nch,
@@ -444,23 +481,46 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
                                                       BucketInfo* __restrict__ binfo,
                                                       SearchHeader* hdr) {
     __shared__ uint32_t pc[1024], pi[1024];
+    __shared__ uint32_t s_cnt[kPartedBuckets], s_hi[kPartedBuckets];
     const uint32_t tid = threadIdx.x;
+    if (nparts == kCountParts) {
+        // bucket totals and range maxima of the parts (nb <= kPartedBuckets),
+        // each part's count replaced by its first slot in the bucket;
+        // consecutive threads take consecutive buckets (coalesced)
+        for (uint32_t b = tid; b < nb; b += 1024) {
+            uint32_t v[kCountParts];
+#pragma unroll
+            for (uint32_t p = 0; p < kCountParts; ++p) v[p] = b_count[p * nb + b];
+            uint32_t cnt = 0;
+#pragma unroll
+            for (uint32_t p = 0; p < kCountParts; ++p) {
+                b_count[p * nb + b] = cnt;
+                cnt += v[p];
+            }
+            s_cnt[b] = cnt;
+            const uint32_t code = b << shift;
+            s_hi[b] = (cnt && (shift || code % kSpanClasses == kSpanClasses - 1))
+                          ? parts_max(b_hi, b, nb)
+                          : 0u;
+        }
+        __syncthreads();
+    }
     const uint32_t per = (nb + 1023) / 1024;
     const uint32_t b0 = tid * per, b1 = min(nb, b0 + per);
     uint32_t sc = 0, si = 0;
     for (uint32_t b = b0; b < b1; ++b) {
-        const uint32_t cnt = b_count[b];
-        uint32_t nch = 0, clen = 0;
+        const uint32_t cnt = nparts == kCountParts ? s_cnt[b] : b_count[b];
+        uint32_t nch = 0, clen = 0, lo = 0xFFFFFFFFu, hi = 0;
         if (cnt) {
             // range of the bucket: first entry of its smallest first bin to
             // the end of its last bin (from the key, or the members' maximum)
             const uint32_t code = b << shift;  // smallest (j0 * classes + span) of the bucket
             const uint32_t j0 = code / kSpanClasses, span = code % kSpanClasses;
-            const uint32_t lo = bin_first[j0];
-            uint32_t hi = b_hi[b];
-            if (shift == 0 && span < kSpanClasses - 1) hi = bin_first[min(j0 + span + 1, m)];
-            b_lo[b] = lo;
-            b_hi[b] = hi;
+            lo = bin_first[j0];
+            if (shift == 0 && span < kSpanClasses - 1)
+                hi = bin_first[min(j0 + span + 1, m)];
+            else
+                hi = nparts == kCountParts ? s_hi[b] : b_hi[b];
             // balanced chunks of at most `chunk` candidates counted from the
             // 64-entry block of lo (chunk c covers [base + c clen, base +
             // (c + 1) clen) clipped to [lo, hi)), whole 64-candidate tiles
@@ -472,6 +532,8 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
             if (clen > 2 * kTile) clen = (clen + kTile - 1) / kTile * kTile;
             nch = (len + clen - 1) / clen;
         }
+        b_lo[b] = lo;
+        b_range_hi[b] = hi;
         b_nch[b] = nch;
         b_clen[b] = clen;
         sc += cnt;
@@ -490,7 +552,13 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
     }
     uint32_t rc = pc[tid] - sc, ri = pi[tid] - si;
     for (uint32_t b = b0; b < b1; ++b) {
-        const uint32_t cnt = b_count[b];
+        uint32_t cnt;
+        if (nparts == kCountParts) {
+            cnt = s_cnt[b];
+        } else {
+            cnt = b_count[b];
+            b_count[b] = 0;  // the one part's first slot
+        }
         b_start[b] = rc;
         b_item[b] = ri;
         BucketInfo bi;
@@ -507,7 +575,7 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
             bi.tmax_ts = mx;
         }
         bi.lo = b_lo[b];
-        bi.hi = b_hi[b];
+        bi.hi = b_range_hi[b];
         bi.nch = b_nch[b];
         bi.clen = b_clen[b];
         bi.count = cnt;
@@ -526,28 +594,34 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
     }
 }
 
+// Workgroups [0, qblocks): one thread per query segment, which goes to its
+// bucket position (bucket start + its counter part's offset + its slot in
+// the part).  Workgroups [qblocks, qblocks + nb): item_bucket[i] = bucket of
+// work item i, one workgroup per bucket.
 __global__ __launch_bounds__(kBlock) void k_scatter(const BatchDesc* __restrict__ desc,
                                                     const uint32_t* __restrict__ qkey,
                                                     const uint32_t* __restrict__ qslot,
                                                     const uint32_t* __restrict__ b_start,
+                                                    const uint32_t* __restrict__ b_part,
+                                                    uint32_t nb, uint32_t bpp, uint32_t qblocks,
                                                     const QF32* __restrict__ qfu,
                                                     uint32_t* __restrict__ qsorted,
-                                                    QF32* __restrict__ qf) {
-    const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= desc->nq) return;
-    const uint32_t s = qslot[k];
-    if (s == kInactive) return;
-    const uint32_t pos = b_start[qkey[k]] + s;
-    qsorted[pos] = (uint32_t)k;
-    qf[pos] = qfu[k];
-}
-
-// item_bucket[i] = bucket of work item i; one block per bucket.
-__global__ __launch_bounds__(kBlock) void k_item_fill(const BucketInfo* __restrict__ binfo,
-                                                      const BatchDesc* __restrict__ desc,
-                                                      uint32_t* __restrict__ item_bucket,
-                                                      SearchHeader* hdr) {
-    const uint32_t b = blockIdx.x;
+                                                    QF32* __restrict__ qf,
+                                                    const BucketInfo* __restrict__ binfo,
+                                                    uint32_t* __restrict__ item_bucket,
+                                                    SearchHeader* hdr) {
+    if (blockIdx.x < qblocks) {
+        const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+        if (k >= desc->nq) return;
+        const uint32_t s = qslot[k];
+        if (s == kInactive) return;
+        const uint32_t key = qkey[k];
+        const uint32_t pos = b_start[key] + b_part[(blockIdx.x / bpp) * nb + key] + s;
+        qsorted[pos] = (uint32_t)k;
+        qf[pos] = qfu[k];
+        return;
+    }
+    const uint32_t b = blockIdx.x - qblocks;
     const BucketInfo bi = binfo[b];
     const uint32_t n = ((bi.count + kWave - 1) / kWave) * bi.nch;
     const uint32_t cap = desc->item_cap;
@@ -1065,7 +1139,7 @@ int grow(T** p, size_t* cap, size_t need) {
 Workspace::~Workspace() {
     for (void* p : {(void*)qfu, (void*)qreq, (void*)qkey, (void*)qslot, (void*)qsorted, (void*)qf, (void*)qstage,
                     (void*)qtraj_stage, (void*)req, (void*)req_ctr, (void*)b_count, (void*)b_lo,
-                    (void*)b_hi, (void*)b_start, (void*)b_item, (void*)b_nch, (void*)b_clen,
+                    (void*)b_hi, (void*)b_rhi, (void*)b_start, (void*)b_item, (void*)b_nch, (void*)b_clen,
                     (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res, (void*)hdr,
                     (void*)bstats, (void*)desc})
         dfree(p);
@@ -1080,6 +1154,7 @@ Workspace::~Workspace() {
 int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_count, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_lo, kMaxBuckets));
+    TDS_TRY(dmalloc(&w->b_rhi, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_hi, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_start, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_item, kMaxBuckets + 1));
@@ -1253,22 +1328,22 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
     const IndexView I = view_of(idx);
     const uint32_t shift = bucket_shift(idx->m);
     const uint32_t nb = bucket_count(idx->m);
-    const uint32_t zn = std::max(nb, r_cap);
+    const uint32_t nparts = count_parts(nb);
+    const uint32_t zn = std::max(nb * nparts, r_cap);
+    // k_zero also clears the request counters the distance kernel appends with
     hipLaunchKernelGGL(k_zero, dim3(ceil_div(zn, kBlock)), dim3(kBlock), 0, s, w->hdr, w->b_count,
-                       w->b_lo, w->b_hi, nb, w->req_ctr, r_cap);
+                       w->b_hi, nb, nparts, w->req_ctr, r_cap);
     const uint32_t qblocks = std::max(1u, ceil_div(q_grid, kBlock));
+    const uint32_t bpp = ceil_div(qblocks, nparts);  // workgroup b counts in part b / bpp < nparts
     hipLaunchKernelGGL(k_qprep, dim3(qblocks), dim3(kBlock), 0, s, Q, w->desc, w->req, I, w->qfu,
-                       w->qreq,
-                       w->qkey, w->qslot, w->b_count, w->b_hi, shift, w->hdr);
+                       w->qreq, w->qkey, w->qslot, w->b_count, w->b_hi, shift, nb, bpp, w->hdr);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_lo, w->b_hi,
-                       idx->bin_first, idx->min_te, idx->max_ts, idx->m, shift, nb, chunk, w->b_start,
-                       w->b_item, w->b_nch, w->b_clen, w->binfo, w->hdr);
-    hipLaunchKernelGGL(k_scatter, dim3(qblocks), dim3(kBlock), 0, s, w->desc, w->qkey, w->qslot,
-                       w->b_start, w->qfu, w->qsorted, w->qf);
-    hipLaunchKernelGGL(k_item_fill, dim3(nb), dim3(kBlock), 0, s, w->binfo, w->desc,
-                       w->item_bucket, w->hdr);
-    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, 1u), 256)), dim3(256), 0, s,
-                       w->req_ctr, r_cap);
+                       w->b_rhi,
+                       idx->bin_first, idx->min_te, idx->max_ts, idx->m, shift, nb, nparts, chunk,
+                       w->b_start, w->b_item, w->b_nch, w->b_clen, w->binfo, w->hdr);
+    hipLaunchKernelGGL(k_scatter, dim3(qblocks + nb), dim3(kBlock), 0, s, w->desc, w->qkey,
+                       w->qslot, w->b_start, w->b_count, nb, bpp, qblocks, w->qfu, w->qsorted,
+                       w->qf, w->binfo, w->item_bucket, w->hdr);
     TDS_HIP(hipGetLastError());
     return launch_distance(prec, dist_args(idx, w, Q, out, 0, 0, 0xFFFFFFFFu, item_count),
                            grid_waves, s, ev_begin, ev_end);

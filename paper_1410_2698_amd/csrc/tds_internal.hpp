@@ -152,9 +152,10 @@ struct Workspace {
     Request* req_host = nullptr;       // pinned staging of the requests (r_cap)
     ReqCounter* rc_host = nullptr;     // pinned mirror of the request counters (r_cap)
     // bucket tables (kMaxBuckets each)
-    uint32_t* b_count = nullptr;
+    uint32_t* b_count = nullptr;    // slot counters, in parts (k_qprep)
     uint32_t* b_lo = nullptr;
-    uint32_t* b_hi = nullptr;
+    uint32_t* b_hi = nullptr;       // candidate range ends of the members, in parts
+    uint32_t* b_rhi = nullptr;      // candidate range end of each bucket
     uint32_t* b_start = nullptr;
     uint32_t* b_item = nullptr;     // kMaxBuckets + 1: first item of each bucket
     uint32_t* b_nch = nullptr;
