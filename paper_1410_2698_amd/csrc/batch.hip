@@ -29,8 +29,6 @@ Batcher::~Batcher() {
     dfree(dres_);
     if (hq_) (void)hipHostFree(hq_);
     if (htraj_) (void)hipHostFree(htraj_);
-    if (hreq_) (void)hipHostFree(hreq_);
-    if (hrc_) (void)hipHostFree(hrc_);
     if (hres_) (void)hipHostFree(hres_);
     if (done_) (void)hipEventDestroy(done_);
     if (own_stream_ && stream_) (void)hipStreamDestroy(stream_);
@@ -67,8 +65,8 @@ int Batcher::init(tds_index* idx, uint64_t max_q, uint32_t max_r, uint64_t res_c
     TDS_TRY(dmalloc(&dres_, res_cap));
     TDS_HIP(hipHostMalloc((void**)&hq_, 8 * max_q * sizeof(double), hipHostMallocDefault));
     TDS_HIP(hipHostMalloc((void**)&htraj_, max_q * sizeof(uint32_t), hipHostMallocDefault));
-    TDS_HIP(hipHostMalloc((void**)&hreq_, max_r * sizeof(Request), hipHostMallocDefault));
-    TDS_HIP(hipHostMalloc((void**)&hrc_, max_r * sizeof(ReqCounter), hipHostMallocDefault));
+    hreq_ = w_->req_host;  // the workspace's pinned control block (max_r requests)
+    hrc_ = w_->rc_host;
     TDS_HIP(hipHostMalloc((void**)&hres_, res_cap * sizeof(tds_result), hipHostMallocDefault));
     return TDS_OK;
 }
@@ -126,8 +124,7 @@ int Batcher::launch(uint64_t nq, const tds_request* reqs, uint32_t nreq) {
     D->nq = nq;
     D->nreq = nreq;
     D->item_cap = (uint32_t)std::min<uint64_t>(item_cap_, 0xFFFFFFFFull);
-    TDS_HIP(hipMemcpyAsync(w_->desc, D, sizeof(BatchDesc), hipMemcpyHostToDevice, stream_));
-    TDS_HIP(hipMemcpyAsync(w_->req, hreq_, nreq * sizeof(Request), hipMemcpyHostToDevice, stream_));
+    TDS_TRY(ws_upload(w_, nreq, stream_));
     if (!exec_) {
         const double* qa[8];
         for (int k = 0; k < 8; ++k) qa[k] = dq_ + k * max_q_;
@@ -145,10 +142,7 @@ int Batcher::launch(uint64_t nq, const tds_request* reqs, uint32_t nreq) {
     }
     TDS_HIP(hipGraphLaunch(exec_, stream_));
     ++replays_;
-    TDS_HIP(hipMemcpyAsync(hrc_, w_->req_ctr, nreq * sizeof(ReqCounter), hipMemcpyDeviceToHost,
-                           stream_));
-    TDS_HIP(hipMemcpyAsync(w_->hdr_host, w_->hdr, sizeof(SearchHeader), hipMemcpyDeviceToHost,
-                           stream_));
+    TDS_TRY(ws_download(w_, nreq, stream_));
     if (copy_all_) {
         if (used_)
             TDS_HIP(hipMemcpyAsync(hres_, dres_, used_ * sizeof(tds_result), hipMemcpyDeviceToHost,

@@ -55,8 +55,8 @@ private:
     tds_result* dres_ = nullptr;
     double* hq_ = nullptr;
     uint32_t* htraj_ = nullptr;
-    Request* hreq_ = nullptr;
-    ReqCounter* hrc_ = nullptr;
+    Request* hreq_ = nullptr;     // in the workspace's pinned control block
+    ReqCounter* hrc_ = nullptr;   // (owned by the workspace)
     tds_result* hres_ = nullptr;
     bool staged_on_device_ = false;
     bool copy_all_ = false;

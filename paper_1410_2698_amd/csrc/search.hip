@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 
 #include <hip/hip_ext.h>
 
@@ -1138,15 +1139,12 @@ int grow(T** p, size_t* cap, size_t need) {
 
 Workspace::~Workspace() {
     for (void* p : {(void*)qfu, (void*)qreq, (void*)qkey, (void*)qslot, (void*)qsorted, (void*)qf, (void*)qstage,
-                    (void*)qtraj_stage, (void*)req, (void*)req_ctr, (void*)b_count, (void*)b_lo,
+                    (void*)qtraj_stage, (void*)ctl, (void*)b_count, (void*)b_lo,
                     (void*)b_hi, (void*)b_rhi, (void*)b_start, (void*)b_item, (void*)b_nch, (void*)b_clen,
-                    (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res, (void*)hdr,
-                    (void*)bstats, (void*)desc})
+                    (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res,
+                    (void*)bstats})
         dfree(p);
-    if (hdr_host) (void)hipHostFree(hdr_host);
-    if (req_host) (void)hipHostFree(req_host);
-    if (rc_host) (void)hipHostFree(rc_host);
-    if (desc_host) (void)hipHostFree(desc_host);
+    if (ctl_host) (void)hipHostFree(ctl_host);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
 }
@@ -1161,13 +1159,44 @@ int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_nch, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_clen, kMaxBuckets));
     TDS_TRY(dmalloc(&w->binfo, kMaxBuckets));
-    TDS_TRY(dmalloc(&w->hdr, 1));
     TDS_TRY(dmalloc(&w->bstats, kMaxDistBlocks));
-    TDS_TRY(dmalloc(&w->desc, 1));
-    TDS_HIP(hipHostMalloc((void**)&w->hdr_host, sizeof(SearchHeader), hipHostMallocDefault));
-    TDS_HIP(hipHostMalloc((void**)&w->desc_host, sizeof(BatchDesc), hipHostMallocDefault));
     TDS_HIP(hipEventCreate(&w->ev0));
     TDS_HIP(hipEventCreate(&w->ev1));
+    return ws_reserve(w, 0, 1);
+}
+
+namespace {
+
+// Byte offsets in the control block for r_cap requests (every part starts
+// on a 64-B boundary: the four structures are multiples of 16 B, and
+// BatchDesc and SearchHeader are 64-B aligned).
+struct CtlLayout {
+    size_t req, hdr, ctr, bytes;
+};
+
+CtlLayout ctl_layout(size_t r_cap) {
+    auto up = [](size_t v) { return (v + 63) / 64 * 64; };
+    CtlLayout L;
+    L.req = up(sizeof(BatchDesc));
+    L.hdr = up(L.req + r_cap * sizeof(Request));
+    L.ctr = up(L.hdr + sizeof(SearchHeader));
+    L.bytes = up(L.ctr + r_cap * sizeof(ReqCounter));
+    return L;
+}
+
+}  // namespace
+
+int ws_upload(Workspace* w, uint32_t nreq, hipStream_t s) {
+    const CtlLayout L = ctl_layout(w->r_cap);
+    TDS_HIP(hipMemcpyAsync(w->ctl, w->ctl_host, L.req + nreq * sizeof(Request),
+                           hipMemcpyHostToDevice, s));
+    return TDS_OK;
+}
+
+int ws_download(Workspace* w, uint32_t nreq, hipStream_t s) {
+    const CtlLayout L = ctl_layout(w->r_cap);
+    TDS_HIP(hipMemcpyAsync(w->ctl_host + L.hdr, w->ctl + L.hdr,
+                           L.ctr - L.hdr + nreq * sizeof(ReqCounter), hipMemcpyDeviceToHost, s));
     return TDS_OK;
 }
 
@@ -1189,21 +1218,32 @@ int ws_reserve(Workspace* w, size_t nq, size_t nreq) {
         TDS_TRY(dmalloc(&w->qf, nq + kQfPad));
         w->q_cap = nq;
     }
-    if (w->r_cap < nreq || !w->req) {
-        dfree(w->req);
-        dfree(w->req_ctr);
-        if (w->req_host) (void)hipHostFree(w->req_host);
-        if (w->rc_host) (void)hipHostFree(w->rc_host);
-        w->req = nullptr;
-        w->req_ctr = nullptr;
-        w->req_host = nullptr;
-        w->rc_host = nullptr;
+    if (w->r_cap < nreq || !w->ctl) {
+        dfree(w->ctl);
+        if (w->ctl_host) (void)hipHostFree(w->ctl_host);
+        w->ctl = w->ctl_host = nullptr;
+        w->desc = w->desc_host = nullptr;
+        w->req = w->req_host = nullptr;
+        w->hdr = w->hdr_host = nullptr;
+        w->req_ctr = w->rc_host = nullptr;
         w->r_cap = 0;
-        TDS_TRY(dmalloc(&w->req, nreq));
-        TDS_TRY(dmalloc(&w->req_ctr, nreq));
-        TDS_HIP(hipHostMalloc((void**)&w->req_host, nreq * sizeof(Request), hipHostMallocDefault));
-        TDS_HIP(hipHostMalloc((void**)&w->rc_host, nreq * sizeof(ReqCounter), hipHostMallocDefault));
-        w->r_cap = nreq;
+        const size_t r_cap = std::max<size_t>(nreq, 16);
+        const CtlLayout L = ctl_layout(r_cap);
+        TDS_TRY(dmalloc(&w->ctl, L.bytes));
+        TDS_HIP(hipHostMalloc((void**)&w->ctl_host, L.bytes, hipHostMallocDefault));
+        std::memset(w->ctl_host, 0, L.bytes);
+        for (int side = 0; side < 2; ++side) {
+            char* base = side ? w->ctl_host : w->ctl;
+            BatchDesc* desc = reinterpret_cast<BatchDesc*>(base);
+            Request* req = reinterpret_cast<Request*>(base + L.req);
+            SearchHeader* hdr = reinterpret_cast<SearchHeader*>(base + L.hdr);
+            ReqCounter* ctr = reinterpret_cast<ReqCounter*>(base + L.ctr);
+            (side ? w->desc_host : w->desc) = desc;
+            (side ? w->req_host : w->req) = req;
+            (side ? w->hdr_host : w->hdr) = hdr;
+            (side ? w->rc_host : w->req_ctr) = ctr;
+        }
+        w->r_cap = r_cap;
     }
     return TDS_OK;
 }
@@ -1410,8 +1450,9 @@ int reserve_items(const tds_index* idx, Workspace* w, uint64_t nq, uint32_t chun
     return TDS_OK;
 }
 
-// Runs the pipeline once for the batch already described in w (desc, req),
-// growing the item table and re-running if the bound was too small.
+// Runs the pipeline once for the batch whose requests the caller staged in
+// w->req_host (sent to the device here, with the descriptor), growing the
+// item table and re-running if the bound was too small.
 int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t nreq, int prec,
               uint32_t chunk, uint32_t grid_waves, tds_result* out, hipStream_t s,
               tds_stats* st, SearchHeader* h_out) {
@@ -1421,12 +1462,10 @@ int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t n
         w->desc_host->nq = V.n;
         w->desc_host->nreq = nreq;
         w->desc_host->item_cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
-        TDS_HIP(hipMemcpyAsync(w->desc, w->desc_host, sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+        TDS_TRY(ws_upload(w, nreq, s));  // the descriptor and the requests staged by the caller
         TDS_TRY(enqueue_pipeline(idx, w, V, V.n, nreq, prec, chunk, grid_waves, out, w->item_count, s,
                                  w->ev0, w->ev1));
-        TDS_HIP(hipMemcpyAsync(w->hdr_host, w->hdr, sizeof(SearchHeader), hipMemcpyDeviceToHost, s));
-        TDS_HIP(hipMemcpyAsync(w->rc_host, w->req_ctr, nreq * sizeof(ReqCounter),
-                               hipMemcpyDeviceToHost, s));
+        TDS_TRY(ws_download(w, nreq, s));
         TDS_HIP(hipStreamSynchronize(s));
         *h_out = *w->hdr_host;
         float ms = 0.f;
@@ -1587,8 +1626,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
     R.t_end = t_end;
     R.out_offset = 0;
     R.out_capacity = dev_cap;
-    *w->req_host = R;
-    TDS_HIP(hipMemcpyAsync(w->req, w->req_host, sizeof(Request), hipMemcpyHostToDevice, s));
+    *w->req_host = R;  // uploaded with the descriptor
 
     tds_stats st{};
     st.query_segments = nq;
@@ -1722,7 +1760,6 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
         R[r].out_capacity = reqs[r].out_capacity;
         R[r].pad = 0;
     }
-    TDS_HIP(hipMemcpyAsync(w->req, R, nreq * sizeof(Request), hipMemcpyHostToDevice, s));
     tds_stats st{};
     st.query_segments = Q->n;
     SearchHeader h{};

@@ -147,6 +147,12 @@ struct Workspace {
     double* qstage = nullptr;       // staging of host query arrays (8 * stage_cap doubles)
     uint32_t* qtraj_stage = nullptr;
     size_t stage_cap = 0, traj_cap = 0;
+    // control block, one device allocation and its pinned host mirror, laid
+    // out as [desc | req x r_cap | hdr | req_ctr x r_cap]: the batch goes to
+    // the device with one copy (desc and requests) and its counters come back
+    // with one (header and request counters)
+    char* ctl = nullptr;
+    char* ctl_host = nullptr;
     Request* req = nullptr;
     ReqCounter* req_ctr = nullptr;
     Request* req_host = nullptr;       // pinned staging of the requests (r_cap)
@@ -329,6 +335,10 @@ int validate_segments_args(const tds_segments* S);
 // Workspace set-up and growth (search.hip).
 int ws_init(Workspace* w);
 int ws_reserve(Workspace* w, size_t nq, size_t nreq);
+// Copies the batch descriptor and the first nreq requests to the device, and
+// the header and the first nreq request counters back (one copy each).
+int ws_upload(Workspace* w, uint32_t nreq, hipStream_t s);
+int ws_download(Workspace* w, uint32_t nreq, hipStream_t s);
 
 // Batched search and the graph-replaying batcher (search.hip, batch.hip).
 int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, uint32_t nreq,
