@@ -467,9 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_schedule(QueryView Q, double t_start
 // Bucket offsets, groups and the work-item table, one block.  The parts of
 // each bucket's slot counter become the parts' offsets within the bucket.
 __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ b_count,
-                                                      uint32_t* __restrict__ b_lo,
                                                       const uint32_t* __restrict__ b_hi,
-                                                      uint32_t* __restrict__ b_range_hi,
                                                       const uint32_t* __restrict__ bin_first,
                                                       const double* __restrict__ min_te,
                                                       const double* __restrict__ max_ts,
@@ -478,7 +476,6 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ b_c
                                                       uint32_t* __restrict__ b_start,
                                                       uint32_t* __restrict__ b_item,
                                                       uint32_t* __restrict__ b_nch,
-                                                      uint32_t* __restrict__ b_clen,
                                                       BucketInfo* __restrict__ binfo,
                                                       SearchHeader* hdr) {
     __shared__ uint32_t pc[1024], pi[1024];
@@ -506,39 +503,68 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ b_c
         }
         __syncthreads();
     }
+    // each thread's consecutive buckets: the record of each (all but its
+    // offsets), then the offsets after the scan.  Items per bucket are kept
+    // in s_hi (parts) or b_nch for the second pass.
     const uint32_t per = (nb + 1023) / 1024;
     const uint32_t b0 = tid * per, b1 = min(nb, b0 + per);
     uint32_t sc = 0, si = 0;
     for (uint32_t b = b0; b < b1; ++b) {
         const uint32_t cnt = nparts == kCountParts ? s_cnt[b] : b_count[b];
-        uint32_t nch = 0, clen = 0, lo = 0xFFFFFFFFu, hi = 0;
+        BucketInfo bi;
+        bi.lo = 0xFFFFFFFFu;
+        bi.hi = 0;
+        bi.nch = 0;
+        bi.clen = 0;
+        bi.count = cnt;
+        bi.start = 0;
+        bi.item0 = 0;
+        bi.pad = 0;
+        bi.tmin_te = -INFINITY;  // unknown: the kernel keeps the per-pair time test
+        bi.tmax_ts = INFINITY;
+        bi.pad2[0] = bi.pad2[1] = 0.0;
         if (cnt) {
             // range of the bucket: first entry of its smallest first bin to
             // the end of its last bin (from the key, or the members' maximum)
             const uint32_t code = b << shift;  // smallest (j0 * classes + span) of the bucket
             const uint32_t j0 = code / kSpanClasses, span = code % kSpanClasses;
-            lo = bin_first[j0];
+            const uint32_t lo = bin_first[j0];
+            uint32_t hi;
             if (shift == 0 && span < kSpanClasses - 1)
                 hi = bin_first[min(j0 + span + 1, m)];
             else
                 hi = nparts == kCountParts ? s_hi[b] : b_hi[b];
+            if (shift == 0 && span < kSpanClasses - 1) {
+                // time bounds of the bins the bucket's range covers
+                const uint32_t j1 = min(j0 + span, m - 1);
+                double mn = INFINITY, mx = -INFINITY;
+                for (uint32_t j = j0; j <= j1; ++j) {
+                    mn = fmin(mn, min_te[j]);
+                    mx = fmax(mx, max_ts[j]);
+                }
+                bi.tmin_te = mn;
+                bi.tmax_ts = mx;
+            }
             // balanced chunks of at most `chunk` candidates counted from the
             // 64-entry block of lo (chunk c covers [base + c clen, base +
             // (c + 1) clen) clipped to [lo, hi)), whole 64-candidate tiles
             // where possible, none empty
             const uint32_t len = hi - (lo & ~(uint32_t)(kWave - 1));
             const uint32_t n0 = (len + chunk - 1) / chunk;
-            clen = (len + n0 - 1) / n0;
+            uint32_t clen = (len + n0 - 1) / n0;
             clen = (clen + kWave - 1) / kWave * kWave;
             if (clen > 2 * kTile) clen = (clen + kTile - 1) / kTile * kTile;
-            nch = (len + clen - 1) / clen;
+            bi.lo = lo;
+            bi.hi = hi;
+            bi.clen = clen;
+            bi.nch = (len + clen - 1) / clen;
         }
-        b_lo[b] = lo;
-        b_range_hi[b] = hi;
-        b_nch[b] = nch;
-        b_clen[b] = clen;
+        binfo[b] = bi;
+        const uint32_t items = ((cnt + kWave - 1) / kWave) * bi.nch;
+        if (nparts == kCountParts) s_hi[b] = items;
+        else b_nch[b] = items;
         sc += cnt;
-        si += ((cnt + kWave - 1) / kWave) * nch;
+        si += items;
     }
     pc[tid] = sc;
     pi[tid] = si;
@@ -553,39 +579,21 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ b_c
     }
     uint32_t rc = pc[tid] - sc, ri = pi[tid] - si;
     for (uint32_t b = b0; b < b1; ++b) {
-        uint32_t cnt;
+        uint32_t cnt, items;
         if (nparts == kCountParts) {
             cnt = s_cnt[b];
+            items = s_hi[b];
         } else {
             cnt = b_count[b];
+            items = b_nch[b];
             b_count[b] = 0;  // the one part's first slot
         }
         b_start[b] = rc;
         b_item[b] = ri;
-        BucketInfo bi;
-        bi.tmin_te = -INFINITY;  // unknown: the kernel keeps the per-pair time test
-        bi.tmax_ts = INFINITY;
-        if (cnt && shift == 0 && (b % kSpanClasses) < kSpanClasses - 1) {
-            const uint32_t j0 = b / kSpanClasses, j1 = min(j0 + b % kSpanClasses, m - 1);
-            double mn = INFINITY, mx = -INFINITY;
-            for (uint32_t j = j0; j <= j1; ++j) {
-                mn = fmin(mn, min_te[j]);
-                mx = fmax(mx, max_ts[j]);
-            }
-            bi.tmin_te = mn;
-            bi.tmax_ts = mx;
-        }
-        bi.lo = b_lo[b];
-        bi.hi = b_range_hi[b];
-        bi.nch = b_nch[b];
-        bi.clen = b_clen[b];
-        bi.count = cnt;
-        bi.start = rc;
-        bi.item0 = ri;
-        bi.pad = 0;
-        binfo[b] = bi;
+        binfo[b].start = rc;
+        binfo[b].item0 = ri;
         rc += cnt;
-        ri += ((cnt + kWave - 1) / kWave) * b_nch[b];
+        ri += items;
     }
     if (tid == 1023) {
         b_item[nb] = pi[1023];
@@ -1139,8 +1147,8 @@ int grow(T** p, size_t* cap, size_t need) {
 
 Workspace::~Workspace() {
     for (void* p : {(void*)qfu, (void*)qreq, (void*)qkey, (void*)qslot, (void*)qsorted, (void*)qf, (void*)qstage,
-                    (void*)qtraj_stage, (void*)ctl, (void*)b_count, (void*)b_lo,
-                    (void*)b_hi, (void*)b_rhi, (void*)b_start, (void*)b_item, (void*)b_nch, (void*)b_clen,
+                    (void*)qtraj_stage, (void*)ctl, (void*)b_count,
+                    (void*)b_hi, (void*)b_start, (void*)b_item, (void*)b_nch,
                     (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res,
                     (void*)bstats})
         dfree(p);
@@ -1151,13 +1159,10 @@ Workspace::~Workspace() {
 
 int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_count, kMaxBuckets));
-    TDS_TRY(dmalloc(&w->b_lo, kMaxBuckets));
-    TDS_TRY(dmalloc(&w->b_rhi, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_hi, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_start, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_item, kMaxBuckets + 1));
     TDS_TRY(dmalloc(&w->b_nch, kMaxBuckets));
-    TDS_TRY(dmalloc(&w->b_clen, kMaxBuckets));
     TDS_TRY(dmalloc(&w->binfo, kMaxBuckets));
     TDS_TRY(dmalloc(&w->bstats, kMaxDistBlocks));
     TDS_HIP(hipEventCreate(&w->ev0));
@@ -1377,10 +1382,9 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
     const uint32_t bpp = ceil_div(qblocks, nparts);  // workgroup b counts in part b / bpp < nparts
     hipLaunchKernelGGL(k_qprep, dim3(qblocks), dim3(kBlock), 0, s, Q, w->desc, w->req, I, w->qfu,
                        w->qreq, w->qkey, w->qslot, w->b_count, w->b_hi, shift, nb, bpp, w->hdr);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_lo, w->b_hi,
-                       w->b_rhi,
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_hi,
                        idx->bin_first, idx->min_te, idx->max_ts, idx->m, shift, nb, nparts, chunk,
-                       w->b_start, w->b_item, w->b_nch, w->b_clen, w->binfo, w->hdr);
+                       w->b_start, w->b_item, w->b_nch, w->binfo, w->hdr);
     hipLaunchKernelGGL(k_scatter, dim3(qblocks + nb), dim3(kBlock), 0, s, w->desc, w->qkey,
                        w->qslot, w->b_start, w->b_count, nb, bpp, qblocks, w->qfu, w->qsorted,
                        w->qf, w->binfo, w->item_bucket, w->hdr);

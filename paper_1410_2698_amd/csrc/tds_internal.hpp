@@ -159,13 +159,10 @@ struct Workspace {
     ReqCounter* rc_host = nullptr;     // pinned mirror of the request counters (r_cap)
     // bucket tables (kMaxBuckets each)
     uint32_t* b_count = nullptr;    // slot counters, in parts (k_qprep)
-    uint32_t* b_lo = nullptr;
     uint32_t* b_hi = nullptr;       // candidate range ends of the members, in parts
-    uint32_t* b_rhi = nullptr;      // candidate range end of each bucket
     uint32_t* b_start = nullptr;
     uint32_t* b_item = nullptr;     // kMaxBuckets + 1: first item of each bucket
-    uint32_t* b_nch = nullptr;
-    uint32_t* b_clen = nullptr;
+    uint32_t* b_nch = nullptr;      // work items of each bucket (k_bucket_scan)
     BucketInfo* binfo = nullptr;    // kMaxBuckets
     uint32_t* item_bucket = nullptr; // bucket of every work item
     size_t item_bucket_cap = 0;

@@ -145,3 +145,52 @@ def test_server_alone_vs_mix(setup):
     assert st["requeued"] > 0             # small reservations forced exact re-runs
     assert st["max_batch_requests_seen"] > 1  # requests shared batches
     assert st["batches"] < 2 * len(reqs) + st["requeued"]
+
+
+def test_repeated_batch_on_the_same_buffers(setup):
+    """tds_search_batch called again and again on the same query and output
+    buffers (the bench's step), with the requests' contents and the query
+    values changing between calls: every call's records must equal direct
+    searches of what the buffers hold at that call (nothing is carried over
+    from one call to the next)."""
+    w, idx, _ = setup
+    host = {k: np.ascontiguousarray(v) for k, v in w.Q.arrays().items() if k != "traj"}
+    Qt = {k: torch.from_numpy(v).cuda() for k, v in host.items()}
+    Qt["traj"] = torch.from_numpy(w.Q.traj.astype(np.int32)).cuda()
+    nq = len(w.Q)
+    Qb = {k: torch.cat([v] * 3) for k, v in Qt.items()}
+    _, counts, _ = idx.search_batch_raw(
+        Qb, [(i * nq, nq, 150.0, 0.0, 80.0, 0, 0) for i in range(3)], out_ptr=0, out_capacity=0,
+        out_on_device=True)
+    cap = 4 * max(counts) + 16
+    out = torch.empty(3 * cap * 32, dtype=torch.uint8, device="cuda")
+    # the direct searches first, so that the batch calls follow each other
+    sequence = [((6.0, 30.0, 150.0), 0.0)] * 3 + [((12.0, 60.0, 150.0), 0.0)] * 2 + \
+               [((6.0, 30.0, 150.0), 0.0)] + [((6.0, 30.0, 150.0), 0.5)] * 2
+    direct = {}
+    for ds, shift in sequence:
+        for d in ds:
+            if (d, shift) not in direct:
+                Q = dict(host, traj=w.Q.traj.astype(np.uint32))
+                Q["xs"] = host["xs"] + shift
+                Q["xe"] = host["xe"] + shift
+                direct[(d, shift)] = key_sorted(idx.search(Q, d, 0.0, 80.0))
+    shifted = False
+    for ds, shift in sequence:
+        if shift and not shifted:
+            # new query values in the same device buffers
+            for k in ("xs", "xe"):
+                Qb[k].add_(shift)
+            shifted = True
+        reqs = [(i * nq, nq, d, 0.0, 80.0, i * cap, cap) for i, d in enumerate(ds)]
+        # unrelated eager work and a synchronisation between the calls
+        x = torch.randn(1 << 16, device="cuda")
+        float(x.sum())
+        torch.cuda.synchronize()
+        st, got, stats = idx.search_batch_raw(Qb, reqs, out_ptr=out.data_ptr(),
+                                              out_capacity=3 * cap, out_on_device=True)
+        assert st == tds.TDS_OK and stats["kernel_ms"] > 0
+        recs = np.frombuffer(out.cpu().numpy().tobytes(), dtype=tds.RESULT_DTYPE)
+        for i, d in enumerate(ds):
+            assert got[i] <= cap
+            assert key_sorted(recs[i * cap: i * cap + got[i]].copy()) == direct[(d, shift)]
