@@ -38,8 +38,9 @@ namespace {
 constexpr uint32_t kInactive = 0xFFFFFFFFu;
 
 // The bucket slot counters are split into parts: about 1,500 returning
-// atomics on one address serialize for ≈ 25 µs, 32 parts bring that down to
-// the cost of the stores.  Part p counts for the query-preparation workgroups
+// atomics on one address serialize for ≈ 25 µs; 16 parts are the best
+// balance between that and the bucket scan's work of adding up the parts
+// (8 and 32 were slower).  Part p counts for the query-preparation workgroups
 // [p * bpp, (p + 1) * bpp) (bpp = workgroups per part): the parts are laid
 // out one after the other in each bucket, so its segments stay close to
 // their input order, and the segments of one request (one d) stay together
@@ -49,7 +50,7 @@ constexpr uint32_t kInactive = 0xFFFFFFFFu;
 // instruction share (stored bucket by bucket, the same atomics took as long
 // as without parts).  1 or kCountParts parts: kCountParts when parts *
 // buckets fits the kMaxBuckets-entry tables.
-constexpr uint32_t kCountParts = 32;
+constexpr uint32_t kCountParts = 16;
 
 uint32_t count_parts(uint32_t nb) {
     return (uint64_t)nb * kCountParts <= kMaxBuckets ? kCountParts : 1u;
