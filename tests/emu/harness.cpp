@@ -5,7 +5,7 @@
 // host:
 //
 //   harness fsg D.bin Q.bin gx gy gz d t0 t1 out.bin              -> "status n"
-//   harness search D.bin Q.bin layout prec d t0 t1 cap out.bin    -> "status n ftests"
+//   harness search D.bin Q.bin layout prec d t0 t1 cap out.bin [bins] -> "status n ftests"
 //   harness selfjoin D.bin layout prec d t0 t1 cap out.bin        -> "status n ftests"
 //   harness merge recs.bin capacity out.bin                       -> "status n"
 //
@@ -102,10 +102,11 @@ void write_records(const char* path, const std::vector<tds_result>& out, uint64_
     fclose(fo);
 }
 
-tds_index* build(const Columns& D, uint32_t layout) {
+tds_index* build(const Columns& D, uint32_t layout, uint32_t num_bins = 0) {
     SegSet S(D);
     tds_build_params bp{};
     bp.layout = layout;
+    bp.num_bins = num_bins;
     tds_index* idx = nullptr;
     const int st = tds::build_impl(&S.s, &bp, nullptr, &idx);
     if (st != TDS_OK) {
@@ -140,7 +141,7 @@ int run_fsg(char** argv) {
 }
 
 // search / self-join: layout and precision by their C ABI values
-int run_search(char** argv, bool self_join) {
+int run_search(int argc, char** argv, bool self_join) {
     int a = 2;
     const Columns D = read_columns(argv[a++]);
     Columns Qc;
@@ -150,7 +151,8 @@ int run_search(char** argv, bool self_join) {
     const double d = atof(argv[a++]), t0 = atof(argv[a++]), t1 = atof(argv[a++]);
     const uint64_t cap = strtoull(argv[a++], nullptr, 10);
     const char* path = argv[a++];
-    tds_index* idx = build(D, layout);
+    const uint32_t num_bins = (a < argc) ? (uint32_t)atoi(argv[a]) : 0u;  // 0: automatic
+    tds_index* idx = build(D, layout, num_bins);
     tds_search_params p;
     tds_search_params_default(&p);
     p.precision = prec;
@@ -191,8 +193,8 @@ int run_merge(char** argv) {
 
 int main(int argc, char** argv) {
     if (argc >= 11 && std::string(argv[1]) == "fsg") return run_fsg(argv);
-    if (argc >= 11 && std::string(argv[1]) == "search") return run_search(argv, false);
-    if (argc >= 10 && std::string(argv[1]) == "selfjoin") return run_search(argv, true);
+    if (argc >= 11 && std::string(argv[1]) == "search") return run_search(argc, argv, false);
+    if (argc >= 10 && std::string(argv[1]) == "selfjoin") return run_search(argc, argv, true);
     if (argc >= 5 && std::string(argv[1]) == "merge") return run_merge(argv);
     fprintf(stderr, "usage: harness fsg ... | harness merge ...\n");
     return 2;

@@ -106,6 +106,22 @@ def test_search_emulated(harness, tmp_path, layout, prec, d):
     same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
 
 
+def test_search_emulated_many_bins(harness, tmp_path):
+    # more query buckets than the parted slot counters take (2,000 bins: 8,000
+    # buckets, one counter part); merged keys (over 16,384 bins) take minutes
+    # here and are covered by the GPU tests
+    bins = 2000
+    w = trajgen.tiny(scale=0.05)
+    columns(w.D).tofile(tmp_path / "D.bin")
+    columns(w.Q).tofile(tmp_path / "Q.bin")
+    st, n, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", SPATIAL, FP32, 8.0,
+                   0.0, 49.0, 100000, tmp_path / "out.bin", bins)
+    assert st == 0
+    want = oracle.search(w.Q, w.D, 8.0, 0.0, 49.0)
+    assert want.size > 0 and n == want.size
+    same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
+
+
 def test_search_emulated_overflow(harness, tmp_path):
     # a result buffer smaller than the result set: the total is reported
     w = trajgen.tiny(scale=0.05)

@@ -377,6 +377,25 @@ def test_results_independent_of_bins_chunks_and_grid():
         idx.close()
 
 
+def test_bucket_counter_forms():
+    """Bin counts whose query buckets use the parted slot counters (400 bins),
+    one counter part (2,000 bins: 8,000 buckets) and keys merged by a shift
+    (20,000 and 65,535 bins: more bin-span codes than bucket-table entries),
+    in single searches and in a batch of two requests."""
+    w = trajgen.dense(0.01, n_pts=41)
+    ds = (1.5, 3.0)
+    want = {d: oracle.search(w.Q, w.D, d, *w.window) for d in ds}
+    for m in (400, 2000, 20000, 65535):
+        idx = build(w.D, m)
+        assert idx.info()["num_bins"] == m
+        for d in ds:
+            compare(idx.search(w.Q, d, *w.window), want[d], f"m={m} d={d}")
+        out = idx.search_batch([(w.Q, d, *w.window) for d in ds])
+        for d, got in zip(ds, out):
+            compare(got, want[d], f"batch m={m} d={d}")
+        idx.close()
+
+
 # ---------------------------------------------------------------- edge cases
 
 def _seg(rows, traj=None):
