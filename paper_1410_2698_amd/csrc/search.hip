@@ -475,7 +475,6 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ b_c
                                                       uint32_t m, uint32_t shift,
                                                       uint32_t nb, uint32_t nparts, uint32_t chunk,
                                                       uint32_t* __restrict__ b_start,
-                                                      uint32_t* __restrict__ b_item,
                                                       uint32_t* __restrict__ b_nch,
                                                       BucketInfo* __restrict__ binfo,
                                                       SearchHeader* hdr) {
@@ -590,14 +589,12 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ b_c
             b_count[b] = 0;  // the one part's first slot
         }
         b_start[b] = rc;
-        b_item[b] = ri;
         binfo[b].start = rc;
         binfo[b].item0 = ri;
         rc += cnt;
         ri += items;
     }
     if (tid == 1023) {
-        b_item[nb] = pi[1023];
         hdr->n_items = pi[1023];
         hdr->n_buckets = nb;
         hdr->active = pc[1023];  // every active query segment has a bucket slot
@@ -1149,7 +1146,7 @@ int grow(T** p, size_t* cap, size_t need) {
 Workspace::~Workspace() {
     for (void* p : {(void*)qfu, (void*)qreq, (void*)qkey, (void*)qslot, (void*)qsorted, (void*)qf, (void*)qstage,
                     (void*)qtraj_stage, (void*)ctl, (void*)b_count,
-                    (void*)b_hi, (void*)b_start, (void*)b_item, (void*)b_nch,
+                    (void*)b_hi, (void*)b_start, (void*)b_nch,
                     (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res,
                     (void*)bstats})
         dfree(p);
@@ -1162,7 +1159,6 @@ int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_count, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_hi, kMaxBuckets));
     TDS_TRY(dmalloc(&w->b_start, kMaxBuckets));
-    TDS_TRY(dmalloc(&w->b_item, kMaxBuckets + 1));
     TDS_TRY(dmalloc(&w->b_nch, kMaxBuckets));
     TDS_TRY(dmalloc(&w->binfo, kMaxBuckets));
     TDS_TRY(dmalloc(&w->bstats, kMaxDistBlocks));
@@ -1385,7 +1381,7 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
                        w->qreq, w->qkey, w->qslot, w->b_count, w->b_hi, shift, nb, bpp, w->hdr);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, w->b_count, w->b_hi,
                        idx->bin_first, idx->min_te, idx->max_ts, idx->m, shift, nb, nparts, chunk,
-                       w->b_start, w->b_item, w->b_nch, w->binfo, w->hdr);
+                       w->b_start, w->b_nch, w->binfo, w->hdr);
     hipLaunchKernelGGL(k_scatter, dim3(qblocks + nb), dim3(kBlock), 0, s, w->desc, w->qkey,
                        w->qslot, w->b_start, w->b_count, nb, bpp, qblocks, w->qfu, w->qsorted,
                        w->qf, w->binfo, w->item_bucket, w->hdr);

@@ -161,7 +161,6 @@ struct Workspace {
     uint32_t* b_count = nullptr;    // slot counters, in parts (k_qprep)
     uint32_t* b_hi = nullptr;       // candidate range ends of the members, in parts
     uint32_t* b_start = nullptr;
-    uint32_t* b_item = nullptr;     // kMaxBuckets + 1: first item of each bucket
     uint32_t* b_nch = nullptr;      // work items of each bucket (k_bucket_scan)
     BucketInfo* binfo = nullptr;    // kMaxBuckets
     uint32_t* item_bucket = nullptr; // bucket of every work item
