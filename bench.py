@@ -1,30 +1,33 @@
 """Benchmark of the distance threshold search on one MI355X.
 
 Headline workload (one "step" = one pass of the whole search path over one
-batch): the random-uniform 1M database (2,500 trajectories x 401 timesteps =
-1,000,000 segments, start U[0,1000]^3, per-step velocity U[-5,5]^3), the full
-query set of 500 query trajectories (200,000 query segments) over [0, 400],
-searched at d = 1, 5 and 25 (three requests over the same query segments,
-run as one batch per step), FP32 bulk filter with FP64 recheck, spatial index
-layout, index and queries resident in HBM, results written to a device
-buffer.  Launch parameters (bin count, chunk, grid) are the library defaults
-(chosen by sweeps on this workload); --tune runs the autotuner on the full
-workload before the timed region instead.
+batch of queries): the galaxy-merger-shaped database (2 x 100,000 particles in
+two Plummer spheres on an approaching orbit, 20 snapshots = 3,800,000 entry
+segments) searched with 2,000 query particles (38,000 query segments) at
+d = 0.5 kpc over the full time span, FP32 bulk filter with FP64 recheck,
+spatial index layout, index and queries resident in HBM, results
+(1.7e8 records) written to a device buffer sized by a counting call.
 
 value = strictly time-overlapping (query, entry) segment pairs resolved per
-second (index independent: every such pair is decided exactly).
+second (index independent: every such pair is decided exactly; 7.6e9 per
+search).  Also reported for the headline: queries/s (one query = one query
+trajectory), the filter tests and FP64 evaluations the kernel performed per
+second, the roofline of the distance kernel (HBM and ALU views), the FP32
+endpoint error (records of the FP32-filter form against the plain FP64 form)
+and the oracle timed on the host on a sample of the same workload.
 
-Also reported: candidate tests per kernel-second, queries/s (one query = one
-query trajectory at one d), the roofline of the distance kernel, the
-self-join of the 1M entries at d = 25 with its trajectory-level merge, the
-served form (open-loop replay of the request stream: Poisson arrivals at 5,000/s of
-query trajectories of 5-400 segments with random windows and d in [1, 25],
-through the serving loop) and the plain form (FP64 canonical test of every
-candidate, one request per call, host memory in and out) on the same stream,
-each with p50/p99 latency, and the oracle timed on the host.
+The other workloads run as legs of their own (each with its step time,
+roofline, endpoint error and oracle sample): uniform1m (1M entries, 200,000
+query segments at d = 1, 5, 25 as three requests of one batch), dense (1M
+entries in [0,50]^3, 100,000 query segments, d = 2) and tiny (98,000 entries,
+4,900 query segments, d = 5); the served form on the request stream over the
+uniform1m index (Poisson arrivals of query trajectories of 5-400 segments with
+random windows and d in [1, 25]) with an open-loop rate sweep to saturation,
+and the plain FP64 form (one request per call) on the same stream; the
+self-join of the uniform1m entries and the fixed spatial grid.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serve]
-                       [--no-self-join] [--tune] [--unbatched]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs a,b,...]
+                       [--no-cpu] [--tune]
 """
 from __future__ import annotations
 
@@ -41,18 +44,45 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "segment-pair tests/s + queries/s at exact results; p50/p99 latency vs plain GPU"
+UNIT = "time-overlapping segment pairs resolved/s"
 
-# MI355X published FP32 vector peak: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU
-# = 157.3 TFLOP/s.
-PEAK_FP32_TFLOPS = 256 * 256 * 2.4e9 / 1e12
-PEAK_HBM_BPS = 8.0e12  # MI355X HBM3E, bytes/s
-# FP operations of one FP32 filter test: 3 sub, 1 mul, 2 FMA (2 flops each),
-# 1 add, 1 mul, 3 compares (1 each) = 13.
-FLOPS_PER_TEST_FP32 = 13
-# FP operations of one (query, 64-entry block) bounding-box test: per axis 2
-# sub + 2 max, then 1 mul, 2 FMA (2 each), 1 add, 1 mul, 1 compare = 20.
-FLOPS_PER_BLOCK_TEST = 20
+# MI355X published peaks: FP32 vector 256 CUs x 2.4 GHz x 256 FLOP/clk/CU =
+# 157.3 TFLOP/s, FP64 vector 78.6 TFLOP/s, HBM3E 8 TB/s.
+PEAK_FP32 = 256 * 256 * 2.4e9
+PEAK_FP64 = 78.6e12
+PEAK_HBM_BPS = 8.0e12
+# wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs,
+# one wave64 instruction per SIMD every 4 cycles (16 lanes), 2.4 GHz
+PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+
+# Algorithmic work of the distance kernel, per unit (counted by the kernel):
+# FP32 filter test: 3 sub, 1 mul, 2 FMA (2 flops each), 1 add, 1 mul,
+#   3 compares = 13;
+# (query, 64-entry block) box test: per axis 2 sub + 2 max, then 1 mul,
+#   2 FMA, 1 add, 1 mul, 1 compare = 20;
+# canonical FP64 membership of one pair: extent 2 min/max + 1 compare + 1 sub,
+#   4 time offsets, 6 position differences of 5, 3 relative velocities, d^2,
+#   C0 and C1 (6 each), A and B (5 each), the vertex clause (3 mul, 1 sub,
+#   6 compares) = 74;
+# interval of a result: discriminant 3, sqrt 1, max 1, root numerator 2,
+#   2 divisions + 1 compare, both ends clamped (5 each), order check 1 = 21.
+FLOPS_FILTER = 13
+FLOPS_BOX = 20
+FLOPS_EVAL64 = 74
+FLOPS_RESULT64 = 21
+# Bytes the kernel must move, per unit: a result record written (32 B); per
+# entry of the searched candidate ranges, its FP32 filter record (32 B), FP64
+# record (64 B) and ids (8 B), each read once; per query segment its end
+# points (64 B).
+BYTES_RESULT = 32
+BYTES_ENTRY = 32 + 64 + 8
+BYTES_QUERY = 64
 KERNEL = "k_distance<FP32_RECHECK>"
+KERNEL_SOURCES = ("search.hip", "canon.hpp", "tds_internal.hpp")
+
+
+def prof_path(workload, kind):
+    return os.path.join(ROOT, "profiles", f"k_distance_fp32_{workload}_{kind}.json")
 
 
 def overlap_pairs(D, Q, t0, t1):
@@ -82,14 +112,6 @@ def pct(x, q):
     return round(float(np.percentile(np.asarray(x), q)), 4)
 
 
-KERNEL_SOURCES = ("search.hip", "canon.hpp", "tds_internal.hpp")
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_distance_fp32_uniform1m_traffic.json")
-VALU_JSON = os.path.join(ROOT, "profiles", "k_distance_fp32_uniform1m_valu.json")
-# wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs,
-# one wave64 FP32 instruction per SIMD every 4 cycles (16 lanes), 2.4 GHz
-PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
-
-
 def kernel_source_hash():
     """Hash of the sources the distance kernel is compiled from."""
     import hashlib
@@ -100,23 +122,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile():
-    """HBM bytes per launch of the distance kernel from the committed counter
-    summary, if it was taken on the current kernel sources (else None)."""
+def load_profile(workload, kind):
+    """A committed counter summary of the distance kernel on `workload`, if
+    it was taken on the current kernel sources (else None)."""
     try:
-        with open(TRAFFIC_JSON) as f:
-            rec = json.load(f)
-        h = kernel_source_hash()
-    except (OSError, ValueError):
-        return None
-    return rec.get("bytes_per_launch") if rec.get("kernel_sources_sha256_16") == h else None
-
-
-def valu_from_profile():
-    """VALU and SALU instructions per launch of the distance kernel from the
-    committed counter summary, if taken on the current kernel sources."""
-    try:
-        with open(VALU_JSON) as f:
+        with open(prof_path(workload, kind)) as f:
             rec = json.load(f)
         h = kernel_source_hash()
     except (OSError, ValueError):
@@ -124,9 +134,14 @@ def valu_from_profile():
     return rec if rec.get("kernel_sources_sha256_16") == h else None
 
 
-def summarize_valu(csv_path, command):
+def profile_command(workload, counters):
+    return (f"rocprofv3 --pmc {counters} --output-format csv -d gpurun_out/pmc -o p -- "
+            f"python3 bench.py --legs {workload} --steps 2 --warmup 1 --no-cpu --calib-copy-mb 256")
+
+
+def summarize_valu(workload, csv_path):
     """Counter CSV of one rocprofv3 --pmc run (SQ_INSTS_VALU SQ_INSTS_SALU
-    SQ_WAVES) -> the distance kernel's instruction counts per launch."""
+    SQ_WAVES ...) -> the distance kernel's counts per launch."""
     import csv
     with open(csv_path) as f:
         rows = [r for r in csv.DictReader(f) if "k_distance<2>" in r["Kernel_Name"]]
@@ -135,18 +150,17 @@ def summarize_valu(csv_path, command):
         per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     if not per:
         raise SystemExit(f"{csv_path}: no distance-kernel rows")
-    rec = {"kernel": "k_distance<FP32_RECHECK>", "workload": "uniform1m, d in {1,5,25}",
-           "launches": len(next(iter(per.values())))}
+    rec = {"kernel": KERNEL, "workload": workload, "launches": len(next(iter(per.values())))}
     for name, vals in per.items():
         rec[name.lower() + "_per_launch"] = sum(vals) / len(vals)
     rec["kernel_sources_sha256_16"] = kernel_source_hash()
-    rec["command"] = command
-    with open(VALU_JSON, "w") as f:
+    rec["command"] = profile_command(workload, " ".join(sorted(per)))
+    with open(prof_path(workload, "valu"), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
 
 
-def summarize_traffic(fetch_csv, write_csv, command):
+def summarize_traffic(workload, fetch_csv, write_csv):
     """Counter CSVs of two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE,
     each with --calib-copy-mb 256) -> the traffic summary: the distance
     kernel's average per launch, scaled by what the same counter reads for the
@@ -168,22 +182,256 @@ def summarize_traffic(fetch_csv, write_csv, command):
     ffac, wfac = ref_kib / fcopy, ref_kib / wcopy
     fetch_b = sum(fd) / len(fd) * 1024 * ffac
     write_b = sum(wd) / len(wd) * 1024 * wfac
-    rec = {"kernel": "k_distance<FP32_RECHECK>", "workload": "uniform1m, d in {1,5,25}",
+    rec = {"kernel": KERNEL, "workload": workload,
            "launches": len(fd), "fetch_kib_raw_avg": sum(fd) / len(fd),
            "write_kib_raw_avg": sum(wd) / len(wd),
            "copy_calibration": {"bytes": 256 << 20, "fetch_kib": fcopy, "write_kib": wcopy,
                                 "fetch_factor": ffac, "write_factor": wfac},
+           "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
            "bytes_per_launch": round(fetch_b + write_b),
-           "kernel_sources_sha256_16": kernel_source_hash(), "command": command}
-    with open(TRAFFIC_JSON, "w") as f:
+           "kernel_sources_sha256_16": kernel_source_hash(),
+           "command": profile_command(workload, "FETCH_SIZE") + " (then WRITE_SIZE)"}
+    with open(prof_path(workload, "traffic"), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
 
 
+def roofline(workload, st, launches, n_entries_ranged, nq):
+    """Roofline of the distance kernel from the counters it keeps (summed over
+    `launches` launches in `st`): the HBM view (algorithmic bytes per launch
+    over the launch's time) and the ALU view (FP32 filter and box arithmetic
+    at the FP32 peak, FP64 evaluations at the FP64 peak); `bound` is the view
+    closer to its roof."""
+    L = max(launches, 1)
+    avg_s = st["kernel_ms"] / L * 1e-3
+    res = st["results"] / L
+    byts = BYTES_RESULT * res + BYTES_ENTRY * n_entries_ranged + BYTES_QUERY * nq
+    f32 = (FLOPS_FILTER * st["filter_tests"] + FLOPS_BOX * st["block_tests"]) / L
+    f64 = (FLOPS_EVAL64 * st["fp64_evals"] + FLOPS_RESULT64 * st["results"]) / L
+    alu_time = f32 / PEAK_FP32 + f64 / PEAK_FP64  # at both peaks
+    alu_peak = (f32 + f64) / alu_time if alu_time else PEAK_FP32
+    hbm = {"achieved": byts / avg_s, "peak": PEAK_HBM_BPS}
+    alu = {"achieved": (f32 + f64) / avg_s, "peak": alu_peak}
+    hbm_frac = hbm["achieved"] / hbm["peak"]
+    alu_frac = alu["achieved"] / alu["peak"]
+    traffic = load_profile(workload, "traffic")
+    valu = load_profile(workload, "valu")
+    views = {"hbm_tb_s": round(hbm["achieved"] / 1e12, 4), "hbm_frac": round(hbm_frac, 4),
+             "alu_tflop_s": round(alu["achieved"] / 1e12, 3),
+             "alu_peak_tflop_s": round(alu_peak / 1e12, 2), "alu_frac": round(alu_frac, 4),
+             "algorithmic_bytes_per_launch": int(byts),
+             "fp32_flops_per_launch": int(f32), "fp64_flops_per_launch": int(f64),
+             "filter_tests_per_s": round(st["filter_tests"] / L / avg_s, 1),
+             "fp64_evals_per_s": round(st["fp64_evals"] / L / avg_s, 1)}
+    if traffic:
+        views["dram_tb_s"] = round(traffic["bytes_per_launch"] / avg_s / 1e12, 4)
+        views["dram_frac_of_hbm"] = round(traffic["bytes_per_launch"] / avg_s / PEAK_HBM_BPS, 4)
+    if valu and valu.get("sq_insts_valu_per_launch"):
+        vi = valu["sq_insts_valu_per_launch"]
+        views["valu_wave_insts_per_launch"] = int(vi)
+        views["valu_issue_frac"] = round(vi / avg_s / PEAK_VALU_WAVE_INSTS, 3)
+    if hbm_frac >= alu_frac:
+        r = {"bound": "hbm", "achieved": round(hbm["achieved"] / 1e9, 2), "peak": 8000.0,
+             "unit": "GB/s", "frac": round(hbm_frac, 4)}
+    else:
+        r = {"bound": "alu", "achieved": round(alu["achieved"] / 1e12, 3),
+             "peak": round(alu_peak / 1e12, 2), "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
+    r["traffic"] = traffic["bytes_per_launch"] if traffic else None
+    r["kernel"] = KERNEL
+    r["avg_launch_ms"] = round(avg_s * 1e3, 4)
+    r["views"] = views
+    return r
+
+
+def ranged_entries(idx_info, D, Q, t0, t1):
+    """Entries in the union of the query segments' temporal candidate ranges
+    (bins overlapping the clipped query extents): each is read at least once."""
+    edges = np.linspace(idx_info["t_min"], idx_info["t_max"], idx_info["num_bins"] + 1)
+    a = np.maximum(Q.ts, t0)
+    b = np.minimum(Q.te, t1)
+    ok = a < b
+    if not ok.any():
+        return 0
+    lo = max(float(a[ok].min()), float(edges[0]))
+    hi = float(b[ok].max())
+    return int(np.count_nonzero((D.te > lo) & (D.ts < hi)))
+
+
+def device_segments(S):
+    """The segment arrays of S as contiguous CUDA tensors (float64, int32 traj)."""
+    import torch
+    out = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+           for k, v in S.arrays().items() if k != "traj"}
+    out["traj"] = torch.from_numpy(np.ascontiguousarray(S.traj).astype(np.int32)).cuda()
+    return out
+
+
+def sorted_records(buf, n):
+    """The n records in a CUDA byte tensor as an (n, 4) int64 tensor ordered
+    by (q_seg, e_seg)."""
+    import torch
+    rec = buf[: n * 32].view(torch.int64).view(n, 4)
+    ids = rec[:, 0]
+    key = ((ids & 0xFFFFFFFF) << 32) | ((ids >> 32) & 0xFFFFFFFF)
+    _, perm = torch.sort(key)
+    return rec[perm]
+
+
+def endpoint_error(buf32, buf64, n):
+    """FP32-filter form against the plain FP64 form (both on the device):
+    identical (q_seg, e_seg, trajectory) sets required; max and p99 of the
+    endpoint differences."""
+    import torch
+    a = sorted_records(buf32, n)
+    b = sorted_records(buf64, n)
+    if not torch.equal(a[:, :2], b[:, :2]):
+        raise RuntimeError("FP32 and FP64 forms give different record sets")
+    da = torch.cat([(a[:, 2].view(torch.float64) - b[:, 2].view(torch.float64)).abs(),
+                    (a[:, 3].view(torch.float64) - b[:, 3].view(torch.float64)).abs()])
+    p99 = 0.0
+    if n:
+        # p99 over a uniform sample of at most 2^24 differences
+        pick = torch.randint(0, da.numel(), (min(da.numel(), 1 << 24),), device=da.device,
+                             generator=torch.Generator(device=da.device).manual_seed(1))
+        p99 = float(torch.quantile(da[pick], 0.99).item())
+    out = {"records_compared": int(n), "max_abs": float(da.max().item()) if n else 0.0,
+           "p99_abs": p99, "bit_identical": bool(torch.equal(a, b))}
+    del a, b, da
+    return out
+
+
+def oracle_sample(w, d, n_traj, cores):
+    """The oracle (plain FP64 brute force) on the first n_traj query
+    trajectories at distance d, on `cores` threads: time-overlapping pairs
+    resolved per second."""
+    import oracle
+    sl = w.query_traj_slices()
+    k = max(1, min(n_traj, len(sl)))
+    sub = w.Q.take(np.arange(sl[0][0], sl[k - 1][1]))
+    t0, t1 = w.window
+    tc = time.perf_counter()
+    oracle.search(sub, w.D, d, t0, t1, threads=cores)
+    dt = time.perf_counter() - tc
+    return {"value": round(overlap_pairs(w.D, sub, t0, t1) / dt, 1), "unit": UNIT,
+            "cores": cores, "kind": "oracle",
+            "sample": f"{k} of {len(sl)} query trajectories ({len(sub)} query segments) x "
+                      f"{len(w.D):,} entries at d={d}, brute force over all pairs; {dt:.2f} s"}
+
+
+class SearchLeg:
+    """One workload on the resident index: the search of all its query
+    segments at every d of the workload (one request per d, one batch), into
+    device memory sized by a counting call."""
+
+    def __init__(self, tds, w, tuned=None, precision="fp32"):
+        import torch
+        self.tds, self.w = tds, w
+        self.tuned = tuned or {"num_bins": 0, "chunk": 0, "grid_waves": 0}
+        self.idx = tds.Index(w.D, num_bins=self.tuned["num_bins"])
+        Qt = device_segments(w.Q)
+        nq = len(w.Q)
+        self.Qb = {k: torch.cat([v] * len(w.ds)) if len(w.ds) > 1 else v for k, v in Qt.items()}
+        t0, t1 = w.window
+        self.count_reqs = [(i * nq, nq, d, t0, t1, 0, 0) for i, d in enumerate(w.ds)]
+        self.precision = precision
+        _, want, _ = self.run(self.count_reqs, 0, 0)
+        self.counts = want
+        self.cap = max(want) + 1
+        self.out = torch.empty(len(w.ds) * self.cap * 32, dtype=torch.uint8, device="cuda")
+        self.reqs = [(i * nq, nq, d, t0, t1, i * self.cap, self.cap) for i, d in enumerate(w.ds)]
+
+    def run(self, reqs, out_ptr, cap, precision=None):
+        return self.idx.search_batch_raw(self.Qb, reqs, out_ptr=out_ptr, out_capacity=cap,
+                                         out_on_device=True,
+                                         precision=precision or self.precision,
+                                         chunk=self.tuned["chunk"],
+                                         grid_waves=self.tuned["grid_waves"])
+
+    def step(self):
+        st, got, s = self.run(self.reqs, self.out.data_ptr(), len(self.w.ds) * self.cap)
+        if st != self.tds.TDS_OK or got != self.counts:
+            raise RuntimeError(f"search failed: status {st}, {got} vs {self.counts}")
+        return s
+
+    def timed(self, steps, warmup):
+        import torch
+        for _ in range(warmup):
+            self.step()
+        acc = None
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(steps):
+            s = self.step()
+            if acc is None:
+                acc = dict(s)
+            else:
+                for k in ("kernel_ms", "candidate_tests", "fp64_evals", "results", "filter_tests",
+                          "block_tests", "passes", "stage_flushes"):
+                    acc[k] += s[k]
+        torch.cuda.synchronize()
+        return time.perf_counter() - tb, acc
+
+    def fp64_form(self):
+        """The plain FP64 form of the same batch (one launch), its time, and
+        the FP32 endpoint error against it, request by request."""
+        import torch
+        out64 = torch.empty_like(self.out)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, got, s = self.run(self.reqs, out64.data_ptr(), len(self.w.ds) * self.cap, "fp64")
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t
+        if st != self.tds.TDS_OK or got != self.counts:
+            raise RuntimeError(f"FP64 search failed: status {st}, {got} vs {self.counts}")
+        errs = {}
+        for i, d in enumerate(self.w.ds):
+            a = self.out[i * self.cap * 32:]
+            b = out64[i * self.cap * 32:]
+            errs[str(d)] = endpoint_error(a, b, self.counts[i])
+        del out64
+        return {"ms": round(1e3 * t, 3), "kernel_ms": round(s["kernel_ms"], 3)}, errs
+
+    def report(self, steps, warmup, cpu_traj, cores, with_cpu=True):
+        w = self.w
+        elapsed, acc = self.timed(steps, warmup)
+        t0, t1 = w.window
+        pairs = overlap_pairs(w.D, w.Q, t0, t1) * len(w.ds)
+        info = self.idx.info()
+        n_ranged = ranged_entries(info, w.D, w.Q, t0, t1)
+        fp64, errs = self.fp64_form()
+        out = {
+            "workload": w.name, "n_entries": len(w.D), "n_query_segments": len(w.Q),
+            "d": w.ds, "num_bins": info["num_bins"],
+            "ms_per_step": round(1e3 * elapsed / steps, 4),
+            "value": round(steps * pairs / elapsed, 1), "unit": UNIT,
+            "queries_per_s": round(len(w.query_traj_slices()) * len(w.ds) * steps / elapsed, 1),
+            "overlap_pairs_per_step": pairs,
+            "results_per_d": {str(d): c for d, c in zip(w.ds, self.counts)},
+            "kernel_ms": round(acc["kernel_ms"] / steps, 4),
+            "filter_tests_per_step": acc["filter_tests"] // steps,
+            "block_tests_per_step": acc["block_tests"] // steps,
+            "fp64_evals_per_step": acc["fp64_evals"] // steps,
+            "fp64_recheck_fraction": round(acc["fp64_evals"] / max(acc["candidate_tests"], 1), 8),
+            "stage_flushes_per_step": acc["stage_flushes"] // steps,
+            "roofline": roofline(w.name, acc, acc["passes"], n_ranged, len(w.Q) * len(w.ds)),
+            "fp64_form": fp64,
+            "fp32_endpoint_error": {"max_abs": max(e["max_abs"] for e in errs.values()),
+                                    "p99_abs": max(e["p99_abs"] for e in errs.values()),
+                                    "per_d": errs},
+            "tuned": self.tuned,
+        }
+        if with_cpu:
+            out["cpu_baseline"] = oracle_sample(w, w.ds[len(w.ds) // 2], cpu_traj, cores)
+        return out
+
+    def close(self):
+        self.idx.close()
+
+
 def self_join_leg(tds, idx, D, d, reps=3):
     """The all-against-all form over the resident index: the self-join of the
-    1M entries at distance d (device output), then the trajectory-level merge
-    of its records (device to device)."""
+    entries at distance d (device output), then the trajectory-level merge of
+    its records (device to device)."""
     import torch
     st, n, _ = idx.self_join_raw(d, out_ptr=0, capacity=0, out_on_device=True)
     cap = n + 1
@@ -249,7 +497,7 @@ def fsg_leg(tds, idx, Qt, counts, ds, t0, t1, grids=(20, 50, 100), reps=3):
                          "kernel_ms": round(float(np.median(kern)), 4),
                          "listings_compared": int(tested), "records": int(n)})
         grid.close()
-    return {"fsg": rows}
+    return rows
 
 
 def open_loop(tds, idx, reqs):
@@ -287,10 +535,12 @@ def open_loop(tds, idx, reqs):
     return lat, n_rec, elapsed, st
 
 
-def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0)):
+def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0, 80000.0, 160000.0,
+                                              320000.0)):
     """The request stream through tds_server: an open-loop run at `rate` for
     `seconds`, the plain FP64 form (one request per call) on its first 5,000
-    requests, and shorter open-loop runs at higher offered rates."""
+    requests, and shorter open-loop runs at rising offered rates until the
+    achieved rate falls below the offered one (saturation)."""
     import trajgen
     n_req = int(seconds * rate)
     reqs = trajgen.request_stream(n_req + 200, rate=rate)
@@ -307,14 +557,17 @@ def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0)):
         plain.append(1e3 * (time.perf_counter() - t0))
     rows = []
     for rt in sweep:
-        sreqs = trajgen.request_stream(5200, rate=rt)
+        sreqs = trajgen.request_stream(10200, rate=rt)
         slat, _, sel, sst = open_loop(tds, idx, sreqs)
         rows.append({"offered_rate": rt, "requests_per_s": round(len(slat) / sel, 1),
                      "p50_ms": pct(slat, 50), "p99_ms": pct(slat, 99),
                      "batches": sst["batches"]})
+        if len(slat) / sel < 0.9 * rt:
+            break
     return {
         "served_fp32": served,
         "served_rate_sweep": rows,
+        "saturation_requests_per_s": max(r["requests_per_s"] for r in rows),
         "plain_fp64": {"requests": len(plain),
                        "requests_per_s": round(len(plain) / (sum(plain) * 1e-3), 1),
                        "p50_ms": pct(plain, 50), "p99_ms": pct(plain, 99),
@@ -322,47 +575,42 @@ def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0)):
     }
 
 
+LEGS = ("galaxy", "uniform1m", "dense", "tiny", "serve", "self_join", "fsg")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated legs to run (the headline is the first of "
+                         "galaxy, uniform1m, dense, tiny that runs)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-self-join", action="store_true")
-    ap.add_argument("--no-fsg", action="store_true", help="skip the fixed spatial grid leg")
-    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two counter CSVs and exit (no GPU)")
-    ap.add_argument("--summarize-valu", metavar="CSV",
-                    help="write the VALU instruction summary from a counter CSV and exit (no GPU)")
-    ap.add_argument("--tune", action="store_true", help="autotune before timing")
-    ap.add_argument("--unbatched", action="store_true",
-                    help="also time the step as three separate searches (context)")
+    ap.add_argument("--summarize-valu", nargs=2, metavar=("WORKLOAD", "CSV"),
+                    help="write the instruction-counter summary from a counter CSV and exit")
+    ap.add_argument("--tune", action="store_true", help="autotune each search leg before timing")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the open-loop serving run at 5,000 requests/s")
-    ap.add_argument("--cpu-traj", type=int, default=500, help="query trajectories in the oracle sample")
-    ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--grid-waves", type=int, default=0)
-    ap.add_argument("--num-bins", type=int, default=0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.summarize_valu:
-        summarize_valu(args.summarize_valu,
-                       "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_WAVES --output-format csv "
-                       "-d gpurun_out/pmc -o p -- python3 bench.py --steps 3 --warmup 1 "
-                       "--no-cpu --no-serve --no-self-join --no-fsg")
+        summarize_valu(*args.summarize_valu)
         return
     if args.summarize_traffic:
-        summarize_traffic(*args.summarize_traffic,
-                          "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv "
-                          "-d gpurun_out/pmc -o p -- python3 bench.py --steps 3 --warmup 1 "
-                          "--no-cpu --no-serve --no-self-join --no-fsg --calib-copy-mb 256")
+        summarize_traffic(*args.summarize_traffic)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    legs = [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in LEGS:
+            raise SystemExit(f"unknown leg {x}; legs are {','.join(LEGS)}")
 
     import torch
 
@@ -378,168 +626,79 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = trajgen.uniform1m()
-    ds = w.ds
-    t0, t1 = w.window
-    tuned = {"num_bins": args.num_bins, "chunk": args.chunk, "grid_waves": args.grid_waves}
-    if args.tune and not (args.chunk or args.grid_waves or args.num_bins):
-        best = autotune.tune(w.D, w.Q, ds, w.window, cache=None)
-        tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves")}
-    idx = tds.Index(w.D, num_bins=tuned["num_bins"])
-    Qt = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in w.Q.arrays().items()
-          if k != "traj"}
-    Qt["traj"] = torch.from_numpy(w.Q.traj.astype(np.int32)).cuda()
-    pairs = overlap_pairs(w.D, w.Q, t0, t1)
-
-    # one batch per step: the query segments once per d, one request each;
-    # a first batch with no output space counts the results
-    nq = len(w.Q)
-    Qb = {k: torch.cat([v] * len(ds)) for k, v in Qt.items()}
-    _, want, _ = idx.search_batch_raw(Qb, [(i * nq, nq, d, t0, t1, 0, 0) for i, d in enumerate(ds)],
-                                      out_ptr=0, out_capacity=0, out_on_device=True,
-                                      chunk=tuned["chunk"], grid_waves=tuned["grid_waves"])
-    counts = dict(zip(ds, want))
-    cap = max(want) + 1
-    out = torch.empty(len(ds) * cap * 32, dtype=torch.uint8, device="cuda")
-    reqs = [(i * nq, nq, d, t0, t1, i * cap, cap) for i, d in enumerate(ds)]
-
-    kern_ms, tests, evals, launches, ftests, btests = 0.0, 0, 0, 0, 0, 0
-
-    def step(record):
-        nonlocal kern_ms, tests, evals, launches, ftests, btests
-        st, got, s = idx.search_batch_raw(Qb, reqs, out_ptr=out.data_ptr(),
-                                          out_capacity=len(ds) * cap, out_on_device=True,
-                                          chunk=tuned["chunk"], grid_waves=tuned["grid_waves"])
-        if st != tds.TDS_OK or got != want:
-            raise RuntimeError(f"search failed: status {st}, {got} vs {want}")
-        if record:
-            kern_ms += s["kernel_ms"]
-            tests += s["candidate_tests"]
-            evals += s["fp64_evals"]
-            launches += s["passes"]
-            ftests += s["filter_tests"]
-            btests += s["block_tests"]
-
-    def step_unbatched():
-        for d in ds:
-            st, n, _ = idx.search_raw(Qt, d, t0, t1, out_ptr=out.data_ptr(), capacity=cap,
-                                      out_on_device=True, chunk=tuned["chunk"],
-                                      grid_waves=tuned["grid_waves"])
-            if st != tds.TDS_OK or n != counts[d]:
-                raise RuntimeError(f"search failed: status {st}, {n} vs {counts[d]}")
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - tb
-    ms_per_step = 1e3 * elapsed / args.steps
-    ms_unbatched = None
-    if args.unbatched:
-        # context: the same step as three separate searches (not the headline)
-        step_unbatched()
-        torch.cuda.synchronize()
-        tu = time.perf_counter()
-        for _ in range(3):
-            step_unbatched()
-        torch.cuda.synchronize()
-        ms_unbatched = round(1e3 * (time.perf_counter() - tu) / 3, 4)
-    n_queries = len(w.query_traj_slices()) * len(ds)
-    value = args.steps * pairs * len(ds) / elapsed
-
-    avg_ms = kern_ms / max(launches, 1)
-    tests_per_launch = tests / max(launches, 1)
-    # algorithmic work of one launch: the FP32 filter tests and block tests it
-    # performs (pairs removed by the block boxes are not counted)
-    flops = (FLOPS_PER_TEST_FP32 * ftests + FLOPS_PER_BLOCK_TEST * btests) / max(launches, 1)
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic_from_profile(), "kernel": KERNEL,
-                "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": int(flops),
-                "flops_per_filter_test": FLOPS_PER_TEST_FP32,
-                "flops_per_block_test": FLOPS_PER_BLOCK_TEST}
-    # the other two views of the same launch: the candidate stream the method
-    # reads per pair (32-B FP32 records, as if each pair fetched its own), and
-    # the HBM bytes the counters saw
-    traffic = roofline["traffic"]
-    roofline["views"] = {
-        "candidate_stream_tb_s": round(tests_per_launch * 32 / (avg_ms * 1e-3) / 1e12, 2),
-        "candidate_stream_frac_of_hbm": round(tests_per_launch * 32 / (avg_ms * 1e-3) / PEAK_HBM_BPS, 3),
-        "dram_tb_s": round(traffic / (avg_ms * 1e-3) / 1e12, 3) if traffic else None,
-        "dram_frac_of_hbm": round(traffic / (avg_ms * 1e-3) / PEAK_HBM_BPS, 4) if traffic else None,
-        "alu_frac": roofline["frac"]}
-    valu = valu_from_profile()
-    if valu and valu.get("sq_insts_valu_per_launch"):
-        # VALU issue utilisation: wave64 VALU instructions per launch (counter
-        # run of the same command) over the launch time, against the issue peak
-        vi = valu["sq_insts_valu_per_launch"]
-        roofline["views"]["valu_wave_insts_per_launch"] = int(vi)
-        roofline["views"]["valu_issue_frac"] = round(vi / (avg_ms * 1e-3) / PEAK_VALU_WAVE_INSTS, 3)
-        if valu.get("sq_insts_salu_per_launch"):
-            roofline["views"]["salu_wave_insts_per_launch"] = int(valu["sq_insts_salu_per_launch"])
-
-    extra = {"queries_per_s": round(n_queries * args.steps / elapsed, 1),
-             "candidate_tests_per_kernel_s": round(tests / (kern_ms * 1e-3), 1) if kern_ms else None,
-             "candidate_pairs_per_launch": int(tests_per_launch),
-             "fp64_recheck_fraction": round(evals / max(tests, 1), 8),
-             "filter_tests_per_launch": int(ftests / max(launches, 1)),
-             "block_tests_per_launch": int(btests / max(launches, 1)),
-             "layout": {1: "temporal", 2: "spatial"}.get(idx.info()["layout"]),
-             "fp32_endpoint_error": 0.0,
-             "results_per_d": {str(d): counts[d] for d in ds},
-             "overlap_pairs_per_search": pairs, "tuned": tuned,
-             "batch_latency_ms": round(ms_per_step, 4),
-             "ms_per_step_as_three_searches": ms_unbatched}
-
-    if not args.no_serve:
-        extra.update(serve_leg(tds, idx, args.serve_seconds, 5000.0))
-    if not args.no_self_join:
-        extra["self_join"] = self_join_leg(tds, idx, w.D, 25.0)
-    if not args.no_fsg:
-        extra.update(fsg_leg(tds, idx, Qt, counts, ds, t0, t1))
-
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        sl = w.query_traj_slices()
-        k = max(1, min(args.cpu_traj, len(sl)))
-        sub = w.Q.take(np.arange(sl[0][0], sl[k - 1][1]))
-        cores = os.cpu_count() or 1
-        tc = time.perf_counter()
-        oracle.search(sub, w.D, 5.0, t0, t1, threads=cores)
-        dt = time.perf_counter() - tc
-        cpu = {"value": round(overlap_pairs(w.D, sub, t0, t1) / dt, 1), "unit": "pair tests/s",
-               "cores": cores, "kind": "oracle",
-               "sample": f"{k} of 500 query trajectories ({len(sub)} query segments) x 1,000,000 "
-                         f"entries at d=5, brute force over all pairs; {dt:.2f} s"}
-        # the same on one core, over a twentieth of the query trajectories
-        k1 = max(1, k // 20)
-        sub1 = w.Q.take(np.arange(sl[0][0], sl[k1 - 1][1]))
-        tc = time.perf_counter()
-        oracle.search(sub1, w.D, 5.0, t0, t1, threads=1)
-        dt1 = time.perf_counter() - tc
-        cpu["single_core"] = {"value": round(overlap_pairs(w.D, sub1, t0, t1) / dt1, 1),
-                              "sample": f"{k1} query trajectories ({len(sub1)} query segments); "
-                                        f"{dt1:.2f} s"}
-        cpu["cpu_model"] = cpu_model()
-
-    rec = {"metric": METRIC, "value": round(value, 1), "unit": "pair tests/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+    cores = os.cpu_count() or 1
+    with_cpu = not args.no_cpu
+    # oracle samples: about 10-15 s for the headline, a few s for the others
+    cpu_traj = {"galaxy": 200, "uniform1m": 100, "dense": 100, "tiny": 100}
+    results = {}
+    uni = None
+    for name in ("galaxy", "uniform1m", "dense", "tiny"):
+        if name not in legs and not (name == "uniform1m" and
+                                     any(x in legs for x in ("serve", "self_join", "fsg"))):
+            continue
+        w = getattr(trajgen, name)()
+        tuned = None
+        if args.tune:
+            best = autotune.tune(w.D, w.Q, w.ds, w.window, cache=None)
+            tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves")}
+        leg = SearchLeg(tds, w, tuned)
+        if name in legs:
+            first = not results
+            results[name] = leg.report(args.steps if first else max(3, args.steps // 2),
+                                       args.warmup if first else 1, cpu_traj[name], cores,
+                                       with_cpu)
+            print(f"# {name}: {json.dumps(results[name])}", file=sys.stderr, flush=True)
+        if name == "uniform1m":
+            uni = (w, leg)
+        else:
+            leg.close()
+            del leg
+        torch.cuda.empty_cache()
+    extra = {}
+    if uni is not None:
+        w, leg = uni
+        if "serve" in legs:
+            extra.update(serve_leg(tds, leg.idx, args.serve_seconds, 5000.0))
+        if "self_join" in legs:
+            extra["self_join"] = self_join_leg(tds, leg.idx, w.D, 25.0)
+        if "fsg" in legs:
+            extra["fsg"] = fsg_leg(tds, leg.idx, device_segments(w.Q),
+                                   dict(zip(w.ds, leg.counts)), w.ds, *w.window)
+        leg.close()
+    if not results:
+        print(json.dumps({"metric": METRIC, "legs": extra}), flush=True)
+        return
+    head_name = next(iter(results))
+    head = results[head_name]
+    descr = {
+        "galaxy": "galaxy: 2 x 100,000 Plummer particles on an approaching orbit, 20 snapshots "
+                  "(3,800,000 entry segments); 2,000 query particles (38,000 segments), "
+                  "d = 0.5 kpc over the full span; FP32 filter + FP64 recheck, spatial layout",
+        "uniform1m": "uniform1m: 2,500 trajectories x 401 timesteps (1,000,000 segments), "
+                     "500 query trajectories (200,000 segments) over [0,400], d in {1,5,25} as "
+                     "three requests of one batch; FP32 filter + FP64 recheck, spatial layout",
+        "dense": "dense: 10,000 trajectories x 101 timesteps in [0,50]^3 (1,000,000 segments), "
+                 "1,000 query trajectories (100,000 segments), d = 2; FP32 filter + FP64 recheck",
+        "tiny": "tiny: 2,000 trajectories x 50 timesteps (98,000 segments), 100 query "
+                "trajectories (4,900 segments), d = 5; FP32 filter + FP64 recheck",
+    }[head_name]
+    rec = {"metric": METRIC, "value": head["value"], "unit": UNIT, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
            "data": "synthetic",
-           "config": {"workload": "uniform1m: 2,500 trajectories x 401 timesteps (1,000,000 "
-                                  "segments), 500 query trajectories (200,000 segments) over "
-                                  "[0,400], d in {1,5,25} as three requests of one batch, "
-                                  "FP32 filter + FP64 recheck, spatial layout",
-                      "n_entries": len(w.D), "n_query_segments": len(w.Q), "d": ds,
-                      "num_bins": idx.info()["num_bins"]},
-           "roofline": roofline, "cpu_baseline": cpu, **extra}
+           "config": {"workload": descr, "n_entries": head["n_entries"],
+                      "n_query_segments": head["n_query_segments"], "d": head["d"],
+                      "num_bins": head["num_bins"]},
+           "roofline": head["roofline"], "cpu_baseline": head.get("cpu_baseline"),
+           "queries_per_s": head["queries_per_s"],
+           "results_per_step": sum(head["results_per_d"].values()),
+           "fp32_endpoint_error": head["fp32_endpoint_error"],
+           "headline": head}
+    if rec["cpu_baseline"]:
+        rec["cpu_baseline"]["cpu_model"] = cpu_model()
+    rec["configs"] = {k: v for k, v in results.items() if k != head_name}
+    rec.update(extra)
     print(json.dumps(rec), flush=True)
-    idx.close()
 
 
 if __name__ == "__main__":

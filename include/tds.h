@@ -149,7 +149,9 @@ typedef struct tds_stats {
     uint64_t fp64_evals;      /* pairs evaluated by the canonical FP64 code */
     uint64_t results;         /* result records found (may exceed the capacity) */
     uint32_t passes;          /* distance-kernel launches (> 1: incremental) */
-    uint32_t reserved;
+    uint32_t stage_flushes;   /* work items whose results were reserved and written at
+                                 the item's end (first pass; each reserves with one
+                                 device-scope atomic per request in the item) */
     double kernel_ms;         /* distance kernel(s), measured with HIP events */
     double total_ms;          /* whole call, host wall clock */
     uint64_t filter_tests;    /* pairs put through the FP32 filter (FP32 form) or the

@@ -18,7 +18,7 @@ from typing import Optional
 import numpy as np
 
 from . import _lib
-from ._lib import (TDS_E_OVERFLOW, TDS_OK, TDS_PREC_FP32_RECHECK, TDS_PREC_FP64, TdsError,
+from ._lib import (TDS_E_INVALID, TDS_E_OVERFLOW, TDS_OK, TDS_PREC_FP32_RECHECK, TDS_PREC_FP64, TdsError,
                    check, load)
 
 RESULT_DTYPE = np.dtype([("q_seg", "<u4"), ("e_seg", "<u4"), ("q_traj", "<u4"),

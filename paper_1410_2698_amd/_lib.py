@@ -42,7 +42,7 @@ class tds_stats(ctypes.Structure):
     _fields_ = [("query_segments", ctypes.c_uint64), ("active_segments", ctypes.c_uint64),
                 ("work_items", ctypes.c_uint64), ("candidate_tests", ctypes.c_uint64),
                 ("fp64_evals", ctypes.c_uint64), ("results", ctypes.c_uint64),
-                ("passes", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("passes", ctypes.c_uint32), ("stage_flushes", ctypes.c_uint32),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("filter_tests", ctypes.c_uint64), ("block_tests", ctypes.c_uint64)]
 

@@ -55,6 +55,7 @@ int Batcher::init(tds_index* idx, uint64_t max_q, uint32_t max_r, uint64_t res_c
     w_->device = idx->device;
     TDS_TRY(ws_init(w_));
     TDS_TRY(ws_reserve(w_, max_q, max_r));
+    TDS_TRY(ws_reserve_stage(w_, cfg_.grid_waves));
     item_cap_ = std::min<uint64_t>(item_table_bound(idx, max_q, cfg_.chunk), 1ull << 28);
     TDS_TRY(dmalloc(&w_->item_bucket, std::max<uint64_t>(item_cap_, 1)));
     w_->item_bucket_cap = std::max<uint64_t>(item_cap_, 1);
@@ -175,6 +176,7 @@ int Batcher::finish(uint64_t* counts, tds_stats* stats, bool* table_overflow) {
         st.filter_tests = h.ftests;
         st.block_tests = h.btests;
         st.fp64_evals = h.evals;
+        st.stage_flushes = h.flushes;
         st.results = total;
         st.passes = 1;
         st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
@@ -237,6 +239,7 @@ struct ServerTicket {
     uint64_t count = 0;
     int status = TDS_OK;
     bool finished = false;
+    bool solo = false;          // next batch: this request alone (item table overflowed)
 };
 
 struct ServerSlot {
@@ -263,7 +266,43 @@ struct tds_server {
     uint64_t next_id = 1;
     tds_server_stats stats{};
     void run();
+    int run_exact(tds::ServerTicket* t);
 };
+
+// One request through tds_search's path (work-item table sized exactly),
+// results into the ticket; called by the worker without the lock.
+int tds_server::run_exact(tds::ServerTicket* t) {
+    tds_segments Q{};
+    const uint64_t L = t->L;
+    Q.xs = t->q.data();
+    Q.ys = t->q.data() + L;
+    Q.zs = t->q.data() + 2 * L;
+    Q.ts = t->q.data() + 3 * L;
+    Q.xe = t->q.data() + 4 * L;
+    Q.ye = t->q.data() + 5 * L;
+    Q.ze = t->q.data() + 6 * L;
+    Q.te = t->q.data() + 7 * L;
+    Q.traj_id = t->traj.empty() ? nullptr : t->traj.data();
+    Q.n = L;
+    Q.on_device = 0;
+    tds_search_params sp = P.search;
+    sp.out_on_device = 0;
+    uint64_t cap = std::max<uint64_t>(t->reserve, 1);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        t->results.resize(cap);
+        uint64_t n = 0;
+        const int st = tds::search_impl(idx, &Q, t->d, t->t0, t->t1, t->results.data(), cap, &n,
+                                        &sp, nullptr, nullptr);
+        if (st == TDS_OK) {
+            t->results.resize(n);
+            t->count = n;
+            return TDS_OK;
+        }
+        if (st != TDS_E_OVERFLOW) return st;
+        cap = n;
+    }
+    return TDS_E_DEVICE;
+}
 
 namespace tds {
 
@@ -287,6 +326,7 @@ void tds_server::run() {
     using namespace tds;
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
+    std::vector<ServerTicket*> requeue, exact;
     for (;;) {
         bool progressed = false;
         // completions
@@ -302,11 +342,16 @@ void tds_server::run() {
                 ServerTicket* t = sl.batch[i];
                 const uint64_t c = sl.counts[i];
                 if (table_overflow || (st != TDS_OK && st != TDS_E_OVERFLOW)) {
-                    if (table_overflow && sl.batch.size() > 1) {
-                        pending.push_front(t);  // retried in a smaller batch
+                    if (table_overflow && t->solo) {
+                        exact.push_back(t);  // alone and still too large
+                    } else if (table_overflow) {
+                        // retried alone; alone and still too large, it runs
+                        // through the exactly sized path
+                        t->solo = true;
+                        requeue.push_back(t);
                         ++stats.requeued;
                     } else {
-                        finish_ticket(this, t, table_overflow ? TDS_E_NOMEM : st);
+                        finish_ticket(this, t, st);
                     }
                 } else if (c <= sl.reqs[i].out_capacity) {
                     const tds_result* src = hr + sl.reqs[i].out_offset;
@@ -315,10 +360,22 @@ void tds_server::run() {
                     finish_ticket(this, t, TDS_OK);
                 } else {
                     t->reserve = c;  // exact size now known
-                    pending.push_front(t);
+                    requeue.push_back(t);
                     ++stats.requeued;
                 }
             }
+            // back to the front of the queue, in their order
+            for (auto it = requeue.rbegin(); it != requeue.rend(); ++it) pending.push_front(*it);
+            requeue.clear();
+            // a request whose work items alone exceed the batcher's fixed item
+            // table runs through the exactly sized search path
+            for (ServerTicket* t : exact) {
+                lk.unlock();
+                const int est = run_exact(t);
+                lk.lock();
+                finish_ticket(this, t, est);
+            }
+            exact.clear();
             sl.batch.clear();
             sl.busy = false;
             progressed = true;
@@ -339,6 +396,7 @@ void tds_server::run() {
                     cv_done.notify_all();
                     continue;
                 }
+                if (t->solo && !sl.batch.empty()) break;  // it goes alone
                 if (sl.batch.size() == sl.b.max_r() || segs + t->L > sl.b.max_q() ||
                     res + t->reserve > sl.b.res_cap())
                     break;
@@ -355,6 +413,7 @@ void tds_server::run() {
                 sl.reqs.push_back(rq);
                 segs += t->L;
                 res += t->reserve;
+                if (t->solo) break;
             }
             if (sl.batch.empty()) continue;
             stats.max_batch_requests_seen =
@@ -500,6 +559,20 @@ int tds_server_submit(tds_server* S, const tds_segments* Q, double d, double t_s
     t->q.resize(8 * Q->n);
     const double* src[8] = {Q->xs, Q->ys, Q->zs, Q->ts, Q->xe, Q->ye, Q->ze, Q->te};
     for (int k = 0; k < 8; ++k) std::memcpy(t->q.data() + (size_t)k * Q->n, src[k], Q->n * sizeof(double));
+    // the values are checked here, where they were copied: a bad segment would
+    // otherwise fail the whole batch it joins, other clients' requests included
+    for (size_t i = 0; i < 8 * (size_t)Q->n; ++i) {
+        if (!std::isfinite(t->q[i])) {
+            delete t;
+            return TDS_E_INVALID;
+        }
+    }
+    for (uint64_t i = 0; i < Q->n; ++i) {
+        if (!(t->q[7 * Q->n + i] > t->q[3 * Q->n + i])) {  // te > ts
+            delete t;
+            return TDS_E_INVALID;
+        }
+    }
     if (Q->traj_id) t->traj.assign(Q->traj_id, Q->traj_id + Q->n);
     t->d = d;
     t->t0 = t_start;

@@ -647,20 +647,21 @@ __global__ void k_reset_pass(ReqCounter* rc, uint32_t nreq) {
 // header (one block).
 __global__ __launch_bounds__(256) void k_stats_fold(const BlockStats* __restrict__ bs, uint32_t nb,
                                                     SearchHeader* hdr) {
-    __shared__ uint64_t red[4][256];
-    uint64_t v[4] = {0, 0, 0, 0};
+    __shared__ uint64_t red[5][256];
+    uint64_t v[5] = {0, 0, 0, 0, 0};
     for (uint32_t i = threadIdx.x; i < nb; i += 256) {
         const BlockStats b = bs[i];
         v[0] += b.tests;
         v[1] += b.evals;
         v[2] += b.ftests;
         v[3] += b.btests;
+        v[4] += b.flushes;
     }
-    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = v[k];
     __syncthreads();
     for (uint32_t off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off)
-            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+            for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -668,6 +669,7 @@ __global__ __launch_bounds__(256) void k_stats_fold(const BlockStats* __restrict
         hdr->evals += red[1][0];
         hdr->ftests += red[2][0];
         hdr->btests += red[3][0];
+        hdr->flushes += (uint32_t)red[4][0];
     }
 }
 
@@ -689,43 +691,99 @@ struct DistArgs {
     uint32_t item_begin;    // work items [item_begin, item_end)
     uint32_t item_end;      // 0xFFFFFFFF: every item of the search
     uint32_t* item_count;   // results per work item, or nullptr
+    tds_result* stage;      // per-wave result stages, stage_cap records each
+    uint32_t* stage_meta;   // group lane | index among the slot's staged results << 6
+    uint32_t stage_cap;     // records per wave (a multiple of 64)
+    uint32_t by_order;      // 1: a single-request item run whose results go to
+                            // their order in the item (minus win_lo), no stage
 };
 
+// Results go through a stage of stage_cap records per wave in device memory
+// and get their output positions when the stage is flushed (when the next
+// batch of evaluations might not fit, and at the end of every work item):
+// one device-scope atomic per request present in the item's query group
+// reserves exactly the staged results of that request.  A returning atomic
+// that every wave directs at its request's counter serialises across the
+// chip; one per 64 evaluations cost a search with 10^8 results most of its
+// time.  Positions within a request are unique and dense, in no fixed order.
+//
+// With by_order set (one request, one work item, re-run to fill successive
+// windows of the host's buffer), a result's position is instead its order
+// among the item's results, which a wave computes the same way on every run.
 struct WaveLDS {
     uint32_t queue[2 * kWave];  // < 64 left over + one pair per lane
     QF32 qrec[kWave];           // filter records of the item's query group
+    QCanon qc[kWave];           // canonical FP64 data of the group's queries
+    uint32_t qr[kWave];         // group lane j -> request
+    uint32_t qid[kWave];        // group lane j -> q_seg of its records
+    uint32_t qtraj[kWave];      // group lane j -> its trajectory
+    uint32_t rcnt[kWave];       // staged results per request slot (slot = lane)
+    unsigned long long rbase[kWave];  // first reserved position per request slot
     uint8_t sel[kWave];         // queries of the group being queued (push_set)
+    uint8_t rslot[kWave];       // group lane j -> first lane with j's request
 };
 
+struct ItemState {
+    uint32_t c0, c1, qbase, nq;
+    uint32_t qn, evals;
+    uint32_t found;   // results of the item so far (their order in the item)
+    uint32_t nst;     // results in the wave's stage
+    uint64_t sbase;   // the wave's stage: records [sbase, sbase + stage_cap)
+    uint64_t ftests, btests;
+};
+
+// Wave-wide ordering of device-memory accesses: stores of one lane are
+// visible to loads of the other lanes after it (the stage is written by the
+// lane that found a result and read back by the lane that copies it).
+__device__ inline void wave_sync_mem() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+// Reserves the staged results of every request slot (one atomic each) and
+// copies them from the stage to their positions; the stage is then empty.
+__device__ __forceinline__ void stage_flush(WaveLDS& L, const DistArgs& A, ItemState& S) {
+    const uint32_t lane = __lane_id();
+    wave_sync_mem();
+    const uint32_t cnt = L.rcnt[lane];  // non-zero only in slot lanes
+    unsigned long long base = 0;
+    if (cnt) base = atomicAdd(&A.rc[L.qr[lane]].count, (unsigned long long)cnt);
+    L.rbase[lane] = base;
+    L.rcnt[lane] = 0;
+    wave_sync();
+    for (uint32_t p = lane; p < S.nst; p += kWave) {
+        const uint32_t meta = A.stage_meta[S.sbase + p];
+        const uint32_t ql = meta & (kWave - 1);
+        const uint64_t pos = L.rbase[L.rslot[ql]] + (meta >> 6);
+        const Request& R = A.req[L.qr[ql]];
+        if (pos >= A.win_lo && pos - A.win_lo < R.out_capacity)
+            A.out[R.out_offset + (pos - A.win_lo)] = A.stage[S.sbase + p];
+    }
+    S.nst = 0;
+    wave_sync_mem();
+}
+
 // Evaluates `cnt` <= 64 queued pairs from position `head` (one per lane) with
-// the canonical FP64 code and appends the results.  Returns the number of
-// results.
-__device__ __forceinline__ uint32_t drain(WaveLDS& L, uint32_t head, uint32_t cnt, uint32_t c0,
-                                          uint32_t qbase, const DistArgs& A) {
+// the canonical FP64 code and stages the results (or, by order, writes them).
+__device__ __forceinline__ void drain(WaveLDS& L, uint32_t head, uint32_t cnt, ItemState& S,
+                                      const DistArgs& A) {
     const uint32_t lane = __lane_id();
     const bool act = lane < cnt;
     const uint32_t pk = act ? L.queue[head + lane] : 0u;
     const uint32_t ql = pk & (kWave - 1);
-    const uint32_t i = c0 + (pk >> 6);
+    const uint32_t i = S.c0 + (pk >> 6);
     double t_lo = 0.0, t_hi = 0.0;
     bool hit = false;
-    uint32_t myreq = 0, qid = 0, qtraj = 0, eid = 0, etraj = 0;
+    uint32_t slot = 0, qid = 0, qtraj = 0, eid = 0, etraj = 0;
     if (act) {
-        const uint32_t k = A.qsorted[qbase + ql];
-        myreq = A.qreq[k];
-        const Request& R = A.req[myreq];
-        QCanon q;
-        query_canon(A.Q, R, k, q);
-        if (A.Q.ent) {
-            qid = A.Q.ent_id[k];
-            qtraj = A.Q.ent_traj[k];
-        } else {
-            qid = (uint32_t)(k - R.q_begin);
-            qtraj = A.Q.traj ? A.Q.traj[k] : 0u;
-        }
+        const EntryF64 e = A.I.e64[i];
         eid = A.I.seg_id[i];
         etraj = A.I.traj[i];
-        const EntryF64 e = A.I.e64[i];
+        const QCanon q = L.qc[ql];
+        qid = L.qid[ql];
+        qtraj = L.qtraj[ql];
+        slot = L.rslot[ql];
         hit = canon_eval<true>(q, e.x, e.y, e.z, e.vx, e.vy, e.vz, e.ts, e.te, &t_lo, &t_hi);
         if (A.Q.ent) {
             // self-join: pairs of one trajectory are not results, and a record
@@ -740,32 +798,47 @@ __device__ __forceinline__ uint32_t drain(WaveLDS& L, uint32_t head, uint32_t cn
             }
         }
     }
-    uint64_t hm = ballot(hit);
+    tds_result rec;
+    rec.q_seg = qid;
+    rec.e_seg = eid;
+    rec.q_traj = qtraj;
+    rec.e_traj = etraj;
+    rec.t_lo = t_lo;
+    rec.t_hi = t_hi;
+    const uint64_t hm = ballot(hit);
     const uint32_t nhit = (uint32_t)__popcll(hm);
-    while (hm) {
-        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)hm) - 1u;
-        const uint32_t r = __shfl(myreq, leader);
-        const uint64_t mm = ballot(hit && myreq == r);
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(&A.rc[r].count, (unsigned long long)__popcll(mm));
-        base = __shfl(base, leader);
-        if (hit && myreq == r) {
-            const uint64_t pos = base + (uint64_t)__popcll(mm & lanemask_lt());
-            const Request& R = A.req[r];
-            if (pos >= A.win_lo && pos - A.win_lo < R.out_capacity) {
-                tds_result rec;
-                rec.q_seg = qid;
-                rec.e_seg = eid;
-                rec.q_traj = qtraj;
-                rec.e_traj = etraj;
-                rec.t_lo = t_lo;
-                rec.t_hi = t_hi;
-                A.out[R.out_offset + (pos - A.win_lo)] = rec;
-            }
-        }
-        hm &= ~mm;
+    const uint32_t rank = (uint32_t)__popcll(hm & lanemask_lt());
+    S.evals += cnt;
+    if (A.by_order) {
+        const uint64_t pos = (uint64_t)S.found + rank;
+        const Request& R = A.req[0];
+        if (hit && pos >= A.win_lo && pos - A.win_lo < R.out_capacity)
+            A.out[R.out_offset + (pos - A.win_lo)] = rec;
+        S.found += nhit;
+        return;
     }
-    return nhit;
+    if (!nhit) return;
+    if (S.nst + nhit > A.stage_cap) stage_flush(L, A, S);
+    // index of each result among the staged results of its request slot
+    uint32_t idx = 0;
+    uint64_t rem = hm;
+    while (rem) {
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)rem) - 1u;
+        const uint32_t sl = uniform((uint32_t)__shfl((int)slot, (int)leader));
+        const uint64_t mm = ballot(hit && slot == sl);
+        const uint32_t c = L.rcnt[sl];
+        if (hit && slot == sl) idx = c + (uint32_t)__popcll(mm & lanemask_lt());
+        wave_sync();
+        if (lane == leader) L.rcnt[sl] = c + (uint32_t)__popcll(mm);
+        wave_sync();
+        rem &= ~mm;
+    }
+    if (hit) {
+        A.stage[S.sbase + S.nst + rank] = rec;
+        A.stage_meta[S.sbase + S.nst + rank] = ql | (idx << 6);
+    }
+    S.nst += nhit;
+    S.found += nhit;
 }
 
 // Appends the lanes of mask m (candidate i) to the wave's pair queue.
@@ -776,33 +849,66 @@ __device__ __forceinline__ void enqueue(WaveLDS& L, uint64_t m, bool pass, uint3
 }
 
 // Evaluates full batches of 64 queued pairs; keeps the remainder queued.
-__device__ __forceinline__ void drain_full(WaveLDS& L, uint32_t c0, uint32_t qbase, uint32_t& qn,
-                                           uint32_t& evals, uint32_t& found, const DistArgs& A) {
+__device__ __forceinline__ void drain_full(WaveLDS& L, ItemState& S, const DistArgs& A) {
     const uint32_t lane = __lane_id();
     uint32_t head = 0;
     wave_sync();
-    while (qn - head >= kWave) {
-        found += drain(L, head, kWave, c0, qbase, A);
-        evals += kWave;
+    while (S.qn - head >= kWave) {
+        drain(L, head, kWave, S, A);
         head += kWave;
     }
     if (head) {
-        const uint32_t rest = qn - head;  // < 64
+        const uint32_t rest = S.qn - head;  // < 64
         wave_sync();
         uint32_t v = 0;
         if (lane < rest) v = L.queue[head + lane];
         wave_sync();
         if (lane < rest) L.queue[lane] = v;
-        qn = rest;
+        S.qn = rest;
     }
     wave_sync();
 }
 
-struct ItemState {
-    uint32_t c0, c1, qbase, nq;
-    uint32_t qn, evals, found;
-    uint64_t ftests, btests;
-};
+// Start of a work item: the canonical data, record ids and request of each
+// query segment of the group, and its request slot (the first lane of the
+// group with the same request).
+__device__ __forceinline__ void item_begin(WaveLDS& L, const DistArgs& A, const ItemState& S) {
+    const uint32_t lane = __lane_id();
+    const bool has = lane < S.nq;
+    uint32_t r = 0;
+    QCanon q = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0};  // empty window: never a member
+    uint32_t qid = 0, qtraj = 0;
+    if (has) {
+        const uint32_t k = A.qsorted[S.qbase + lane];
+        r = A.qreq[k];
+        const Request& R = A.req[r];
+        query_canon(A.Q, R, k, q);
+        if (A.Q.ent) {
+            qid = A.Q.ent_id[k];
+            qtraj = A.Q.ent_traj[k];
+        } else {
+            qid = (uint32_t)(k - R.q_begin);
+            qtraj = A.Q.traj ? A.Q.traj[k] : 0u;
+        }
+    }
+    uint32_t slot = lane;
+    uint64_t rem = ballot(has);
+    while (rem) {
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)rem) - 1u;
+        const uint32_t rr = uniform((uint32_t)__shfl((int)r, (int)leader));
+        const uint64_t mm = ballot(has && r == rr);
+        if ((mm >> lane) & 1ull) slot = leader;
+        rem &= ~mm;
+    }
+    wave_sync();
+    L.qc[lane] = q;
+    L.qr[lane] = r;
+    L.qid[lane] = qid;
+    L.qtraj[lane] = qtraj;
+    L.rslot[lane] = (uint8_t)slot;
+    L.rcnt[lane] = 0;
+    wave_sync();
+}
 
 // FP32 filter record of the query segment held by a lane (its QF32 record).
 struct QReg {
@@ -893,7 +999,7 @@ __device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemStat
             b &= b - 1u;
         }
         S.qn += (uint32_t)__popcll(m);
-        if (S.qn >= kWave) drain_full(L, S.c0, S.qbase, S.qn, S.evals, S.found, A);
+        if (S.qn >= kWave) drain_full(L, S, A);
     }
 }
 
@@ -1016,11 +1122,9 @@ __device__ __forceinline__ void scan_chunk_fp64(WaveLDS& L, const DistArgs& A, I
     const uint32_t lane = __lane_id();
     const bool has = lane < S.nq;
     ConstE64 ce = (ConstE64)(A.I.e64);
-    QCanon q = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0};  // empty window: never a member
+    const QCanon q = L.qc[lane];  // an empty window past the group's end
     uint32_t qlo = 0, qhi = 0;
     if (has) {
-        const uint32_t k = A.qsorted[S.qbase + lane];
-        query_canon(A.Q, A.req[A.qreq[k]], k, q);
         const QF32 f = A.qf[S.qbase + lane];
         qlo = f.lo;
         qhi = f.hi;
@@ -1033,7 +1137,7 @@ __device__ __forceinline__ void scan_chunk_fp64(WaveLDS& L, const DistArgs& A, I
         const uint64_t m = ballot(pass);
         if (!m) continue;
         enqueue(L, m, pass, i, S.c0, S.qn);
-        if (S.qn >= kWave) drain_full(L, S.c0, S.qbase, S.qn, S.evals, S.found, A);
+        if (S.qn >= kWave) drain_full(L, S, A);
     }
 }
 
@@ -1043,6 +1147,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     WaveLDS& L = wl[threadIdx.x / kWave];
     const uint32_t lane = __lane_id();
     uint64_t tests = 0, evals_total = 0, ftests = 0, btests = 0;
+    uint32_t flushes = 0;  // stage flushes at the end of an item
     // all items of the search, unless a range is given (incremental passes)
     const uint32_t item_end = (A.item_end == 0xFFFFFFFFu)
                                   ? uniform(min(A.hdr->n_items, A.desc->item_cap))
@@ -1056,6 +1161,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // per item (a fetch the item's loads then depend on) cost more than the
     // imbalance it removed.
     const uint64_t n_it = item_end > A.item_begin ? item_end - A.item_begin : 0u;
+    // this wave's result stage
+    const uint64_t sbase =
+        (uint64_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * A.stage_cap;
     const uint32_t ng = min(gridDim.x, kXcds);
     const uint32_t grp = blockIdx.x % ng;
     const uint32_t gblocks = (gridDim.x - grp + ng - 1) / ng;  // workgroups of the group
@@ -1070,6 +1178,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const uint32_t g = local / bi.nch;
         const uint32_t c = local - g * bi.nch;
         ItemState S;
+        S.sbase = sbase;
         S.nq = uniform(min((uint32_t)kWave, bi.count - g * kWave));
         const uint64_t base = (uint64_t)(bi.lo & ~(uint32_t)(kWave - 1)) + (uint64_t)c * bi.clen;
         S.c0 = uniform((uint32_t)max((uint64_t)bi.lo, base));
@@ -1078,6 +1187,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         S.qn = 0;
         S.evals = 0;
         S.found = 0;
+        S.nst = 0;
         S.ftests = 0;
         S.btests = 0;
         // does every query of the group cover the whole chunk?
@@ -1087,6 +1197,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             cover = f.lo <= S.c0 && f.hi >= S.c1;
         }
         const bool all_cover = ballot(cover) == ~0ull;
+        item_begin(L, A, S);
         if (kPrec == TDS_PREC_FP32_RECHECK) {
             if (all_cover) scan_chunk_fp32<true>(L, A, S, bi);
             else scan_chunk_fp32<false>(L, A, S, bi);
@@ -1096,10 +1207,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         if (S.qn) {
             wave_sync();
-            S.found += drain(L, 0, S.qn, S.c0, S.qbase, A);
-            S.evals += S.qn;
+            drain(L, 0, S.qn, S, A);
+            S.qn = 0;
         }
         wave_sync();
+        // the item's results get their positions (the next item's group has
+        // other request slots)
+        if (S.nst) {
+            stage_flush(L, A, S);
+            ++flushes;
+        }
         tests += (uint64_t)(S.c1 - S.c0) * S.nq;
         ftests += (kPrec == TDS_PREC_FP64) ? (uint64_t)(S.c1 - S.c0) * S.nq : S.ftests;
         btests += S.btests;
@@ -1114,6 +1231,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         ws[wid].evals = evals_total;
         ws[wid].ftests = ftests;
         ws[wid].btests = btests;
+        ws[wid].flushes = flushes;
+        ws[wid].pad[0] = ws[wid].pad[1] = ws[wid].pad[2] = 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1123,6 +1242,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             b.evals += ws[k].evals;
             b.ftests += ws[k].ftests;
             b.btests += ws[k].btests;
+            b.flushes += ws[k].flushes;
         }
         A.bstats[blockIdx.x] = b;
     }
@@ -1148,7 +1268,7 @@ Workspace::~Workspace() {
                     (void*)qtraj_stage, (void*)ctl, (void*)b_count,
                     (void*)b_hi, (void*)b_start, (void*)b_nch,
                     (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res,
-                    (void*)bstats})
+                    (void*)bstats, (void*)stage, (void*)stage_meta})
         dfree(p);
     if (ctl_host) (void)hipHostFree(ctl_host);
     if (ev0) (void)hipEventDestroy(ev0);
@@ -1251,6 +1371,25 @@ int ws_reserve(Workspace* w, size_t nq, size_t nreq) {
 }
 
 namespace {
+uint32_t launch_blocks(uint32_t grid_waves);
+size_t stage_total(uint32_t grid_waves);
+}  // namespace
+
+int ws_reserve_stage(Workspace* w, uint32_t grid_waves) {
+    const size_t need = stage_total(grid_waves);
+    if (w->stage_recs >= need && w->stage) return TDS_OK;
+    dfree(w->stage);
+    dfree(w->stage_meta);
+    w->stage = nullptr;
+    w->stage_meta = nullptr;
+    w->stage_recs = 0;
+    TDS_TRY(dmalloc(&w->stage, need));
+    TDS_TRY(dmalloc(&w->stage_meta, need));
+    w->stage_recs = need;
+    return TDS_OK;
+}
+
+namespace {
 
 uint32_t bucket_shift(uint32_t m) {
     uint32_t shift = 0;
@@ -1273,8 +1412,14 @@ uint64_t item_bound(uint64_t nq, uint32_t nb, uint64_t n, uint32_t chunk) {
 
 constexpr uint64_t kMaxItemTable = 1ull << 26;  // entries (256 MiB) kept without an exact count
 
+// Largest chunk: a queued pair packs its candidate's offset in the chunk
+// (at most the chunk rounded up to whole tiles) above 6 bits of query lane,
+// in 32 bits.
+constexpr uint32_t kMaxChunk = 1u << 19;
+static_assert((uint64_t)kMaxChunk + 2 * kTile < (1ull << 26), "packed queue entries");
+
 uint32_t resolve_chunk(int prec, uint32_t chunk) {
-    if (chunk) return std::max(chunk, 64u);
+    if (chunk) return std::min(std::max(chunk, 64u), kMaxChunk);
     return prec == TDS_PREC_FP64 ? 512u : 4096u;
 }
 
@@ -1282,6 +1427,27 @@ uint32_t resolve_chunk(int prec, uint32_t chunk) {
 // kernel's register use allows).
 uint32_t resolve_grid(uint32_t grid_waves) {
     return std::min(grid_waves ? grid_waves : 256u * 4u * 4u, kMaxDistBlocks * kWavesPerBlock);
+}
+
+// Waves of a distance-kernel launch of grid_waves (whole workgroups).
+uint32_t launch_blocks(uint32_t grid_waves) {
+    return std::min(kMaxDistBlocks, std::max(1u, ceil_div(grid_waves, kWavesPerBlock)));
+}
+
+// Result stage of each wave: up to kStageMax records, within a workspace
+// total of at most kStageTotal (the stages of one launch never exceed about
+// 300 MB; at the default grid every wave gets kStageMax).
+constexpr uint32_t kStageMax = 2048;
+constexpr size_t kStageTotal = size_t(1) << 23;
+
+size_t stage_total(uint32_t grid_waves) {
+    const size_t waves = (size_t)launch_blocks(grid_waves) * kWavesPerBlock;
+    return std::min(kStageTotal, waves * kStageMax);
+}
+
+uint32_t stage_per_wave(size_t recs, uint32_t blocks) {
+    const size_t per = recs / ((size_t)blocks * kWavesPerBlock);
+    return (uint32_t)std::min<size_t>(kStageMax, per / kWave * kWave);
 }
 
 int resolve_prec(int p) {
@@ -1317,8 +1483,13 @@ int stage_queries(const tds_segments* Q, QueryView* V, hipStream_t s, double** s
 }
 
 DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q, tds_result* out,
-                   uint64_t win_lo, uint32_t item_begin, uint32_t item_end, uint32_t* item_count) {
+                   uint64_t win_lo, uint32_t item_begin, uint32_t item_end, uint32_t* item_count,
+                   uint32_t grid_waves, bool by_order) {
     DistArgs A;
+    A.stage = w->stage;
+    A.stage_meta = w->stage_meta;
+    A.stage_cap = stage_per_wave(w->stage_recs, launch_blocks(grid_waves));
+    A.by_order = by_order ? 1u : 0u;
     A.I = view_of(idx);
     A.Q = Q;
     A.qreq = w->qreq;
@@ -1343,8 +1514,9 @@ DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q,
 // fold of its per-workgroup counters into the header.
 int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_t s,
                     hipEvent_t ev_begin, hipEvent_t ev_end) {
-    const uint32_t blocks =
-        std::min(kMaxDistBlocks, std::max(1u, ceil_div(grid_waves, kWavesPerBlock)));
+    const uint32_t blocks = launch_blocks(grid_waves);
+    // every wave must be able to stage a full batch of 64 evaluations
+    if (!A.stage || A.stage_cap < (uint32_t)kWave) return TDS_E_DEVICE;
     void (*kern)(DistArgs) = k_distance<TDS_PREC_FP32_RECHECK>;
     if (prec == TDS_PREC_FP64) kern = k_distance<TDS_PREC_FP64>;
     if (ev_begin && ev_end) {
@@ -1386,21 +1558,25 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
                        w->qslot, w->b_start, w->b_count, nb, bpp, qblocks, w->qfu, w->qsorted,
                        w->qf, w->binfo, w->item_bucket, w->hdr);
     TDS_HIP(hipGetLastError());
-    return launch_distance(prec, dist_args(idx, w, Q, out, 0, 0, 0xFFFFFFFFu, item_count),
+    return launch_distance(prec,
+                           dist_args(idx, w, Q, out, 0, 0, 0xFFFFFFFFu, item_count, grid_waves,
+                                     false),
                            grid_waves, s, ev_begin, ev_end);
 }
 
 // Re-runs the distance kernel over work items [i0, i1) keeping result
 // positions [win_lo, win_lo + capacity) (incremental processing).
+// by_order: one item of a one-request search, its results placed by their
+// order in the item (a window of an item larger than the device buffer).
 int enqueue_range(const tds_index* idx, Workspace* w, const QueryView& Q, int prec, uint32_t r_cap,
-                  tds_result* out,
-                  uint64_t win_lo, uint32_t i0, uint32_t i1, uint32_t grid_waves, hipStream_t s,
-                  hipEvent_t ev_begin, hipEvent_t ev_end) {
+                  tds_result* out, uint64_t win_lo, uint32_t i0, uint32_t i1, bool by_order,
+                  uint32_t grid_waves, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end) {
     hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, 1u), 256)), dim3(256), 0, s,
                        w->req_ctr, r_cap);
     TDS_HIP(hipGetLastError());
-    return launch_distance(prec, dist_args(idx, w, Q, out, win_lo, i0, i1, nullptr), grid_waves, s,
-                           ev_begin, ev_end);
+    return launch_distance(prec,
+                           dist_args(idx, w, Q, out, win_lo, i0, i1, nullptr, grid_waves, by_order),
+                           grid_waves, s, ev_begin, ev_end);
 }
 
 Workspace* acquire(tds_index* idx) {
@@ -1459,6 +1635,7 @@ int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t n
               tds_stats* st, SearchHeader* h_out) {
     uint64_t cap = 0;
     TDS_TRY(reserve_items(idx, w, V.n, chunk, &cap));
+    TDS_TRY(ws_reserve_stage(w, grid_waves));
     for (int attempt = 0; attempt < 2; ++attempt) {
         w->desc_host->nq = V.n;
         w->desc_host->nreq = nreq;
@@ -1642,6 +1819,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
     st.filter_tests = h.ftests;
     st.block_tests = h.btests;
     st.fp64_evals = h.evals;
+    st.stage_flushes = h.flushes;
     const uint64_t total = rc.count;
     float ms = 0.f;
     int status = TDS_OK;
@@ -1673,6 +1851,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
             uint64_t sum = 0;
             while (i1 < n_items && sum + cnt[i1] <= dev_cap) sum += cnt[i1++];
             std::vector<std::pair<uint64_t, uint64_t>> windows;  // (win_lo, expected)
+            const bool by_order = i1 == i0;  // one item larger than the buffer
             if (i1 == i0) {
                 i1 = i0 + 1;
                 for (uint64_t wl = 0; wl < cnt[i0]; wl += dev_cap)
@@ -1682,7 +1861,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
             }
             for (auto& win : windows) {
                 if (win.second == 0) continue;
-                TDS_TRY(enqueue_range(idx, w, V, prec, 1, res, win.first, i0, i1,
+                TDS_TRY(enqueue_range(idx, w, V, prec, 1, res, win.first, i0, i1, by_order,
                                       std::min(grid_waves, i1 - i0), s, w->ev0, w->ev1));
                 TDS_HIP(hipMemcpyAsync(out + written, res, win.second * sizeof(tds_result),
                                        hipMemcpyDeviceToHost, s));
@@ -1786,6 +1965,7 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
     st.filter_tests = h.ftests;
     st.block_tests = h.btests;
     st.fp64_evals = h.evals;
+    st.stage_flushes = h.flushes;
     st.results = total;
     st.total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_begin).count();

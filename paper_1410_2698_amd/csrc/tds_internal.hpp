@@ -113,7 +113,7 @@ struct alignas(64) SearchHeader {
     uint64_t evals;         // canonical FP64 evaluations
     uint64_t results;       // total results (all requests)
     uint32_t n_buckets;     // buckets in use
-    uint32_t pad;
+    uint32_t flushes;       // result-stage flushes at the end of a work item
     uint64_t ftests;        // pairs through the FP32 filter / FP64 predicate
     uint64_t btests;        // (query, block) bounding-box tests
 };
@@ -121,8 +121,10 @@ static_assert(sizeof(SearchHeader) == 64, "SearchHeader layout");
 
 // Per-workgroup counters of the distance kernel, folded into the header by a
 // one-block kernel after the launch (no contended atomics).
-struct alignas(32) BlockStats {
+struct alignas(64) BlockStats {
     uint64_t tests, evals, ftests, btests;
+    uint64_t flushes;  // result-stage flushes at the end of a work item
+    uint64_t pad[3];
 };
 constexpr uint32_t kMaxDistBlocks = 16384;  // grid limit of the distance kernel
 
@@ -167,6 +169,11 @@ struct Workspace {
     size_t item_bucket_cap = 0;
     uint32_t* item_count = nullptr; // results per work item (incremental mode)
     tds_result* res = nullptr;      // device result buffer (host-output mode)
+    // result stages of the distance kernel's waves (stage_recs records and
+    // their metadata, split evenly over the waves of a launch)
+    tds_result* stage = nullptr;
+    uint32_t* stage_meta = nullptr;
+    size_t stage_recs = 0;
     SearchHeader* hdr = nullptr;
     SearchHeader* hdr_host = nullptr;  // pinned mirror
     BlockStats* bstats = nullptr;      // kMaxDistBlocks per-workgroup counters
@@ -331,6 +338,9 @@ int validate_segments_args(const tds_segments* S);
 // Workspace set-up and growth (search.hip).
 int ws_init(Workspace* w);
 int ws_reserve(Workspace* w, size_t nq, size_t nreq);
+// Sizes the result stages for distance-kernel launches of up to grid_waves
+// waves (a resolved value, see resolve_config).
+int ws_reserve_stage(Workspace* w, uint32_t grid_waves);
 // Copies the batch descriptor and the first nreq requests to the device, and
 // the header and the first nreq request counters back (one copy each).
 int ws_upload(Workspace* w, uint32_t nreq, hipStream_t s);

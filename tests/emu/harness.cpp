@@ -169,7 +169,8 @@ int run_search(int argc, char** argv, bool self_join) {
     }
     write_records(path, out, n);
     tds::destroy_index(idx);
-    printf("%d %llu %llu\n", status, (unsigned long long)n, (unsigned long long)st.filter_tests);
+    printf("%d %llu %llu %llu\n", status, (unsigned long long)n, (unsigned long long)st.filter_tests,
+           (unsigned long long)st.stage_flushes);
     return 0;
 }
 

@@ -98,11 +98,29 @@ def test_search_emulated(harness, tmp_path, layout, prec, d):
     w = trajgen.tiny(scale=0.05)
     columns(w.D).tofile(tmp_path / "D.bin")
     columns(w.Q).tofile(tmp_path / "Q.bin")
-    st, n, ftests = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", layout, prec, d,
+    st, n, ftests, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", layout, prec, d,
                         0.0, 49.0, 100000, tmp_path / "out.bin")
     assert st == 0
     want = oracle.search(w.Q, w.D, d, 0.0, 49.0)
     assert want.size > 0 and n == want.size and ftests > 0
+    same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_search_emulated_stage_flushes(harness, tmp_path, prec):
+    # the database against itself at a distance larger than the data's
+    # extent: every time-overlapping pair is a result (each query segment
+    # meets the co-temporal segment of each of the 100 trajectories), so a
+    # work item of 64 query segments has 6,400 results and fills its wave's
+    # 2,048-record stage several times before it ends
+    w = trajgen.tiny(scale=0.05)
+    columns(w.D).tofile(tmp_path / "D.bin")
+    st, n, _, flushes = run(harness, "search", tmp_path / "D.bin", tmp_path / "D.bin", SPATIAL,
+                            prec, 250.0, 0.0, 49.0, 600000, tmp_path / "out.bin")
+    assert st == 0
+    want = oracle.search(w.D, w.D, 250.0, 0.0, 49.0)
+    assert want.size == len(w.D) * 100 and n == want.size
+    assert flushes > 0
     same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
 
 
@@ -114,8 +132,8 @@ def test_search_emulated_many_bins(harness, tmp_path):
     w = trajgen.tiny(scale=0.05)
     columns(w.D).tofile(tmp_path / "D.bin")
     columns(w.Q).tofile(tmp_path / "Q.bin")
-    st, n, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", SPATIAL, FP32, 8.0,
-                   0.0, 49.0, 100000, tmp_path / "out.bin", bins)
+    st, n, _, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", SPATIAL, FP32,
+                      8.0, 0.0, 49.0, 100000, tmp_path / "out.bin", bins)
     assert st == 0
     want = oracle.search(w.Q, w.D, 8.0, 0.0, 49.0)
     assert want.size > 0 and n == want.size
@@ -128,15 +146,15 @@ def test_search_emulated_overflow(harness, tmp_path):
     columns(w.D).tofile(tmp_path / "D.bin")
     columns(w.Q).tofile(tmp_path / "Q.bin")
     want = oracle.search(w.Q, w.D, 30.0, 0.0, 49.0)
-    st, n, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", SPATIAL, FP32, 30.0,
-                   0.0, 49.0, 100, tmp_path / "out.bin")
+    st, n, _, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", SPATIAL, FP32,
+                      30.0, 0.0, 49.0, 100, tmp_path / "out.bin")
     assert st == 2 and n == want.size  # TDS_E_OVERFLOW
 
 
 def test_self_join_emulated(harness, tmp_path):
     w = trajgen.tiny(scale=0.04)
     columns(w.D).tofile(tmp_path / "D.bin")
-    st, n, _ = run(harness, "selfjoin", tmp_path / "D.bin", SPATIAL, FP32, 4.0, 0.0, 49.0, 200000,
+    st, n, _, _ = run(harness, "selfjoin", tmp_path / "D.bin", SPATIAL, FP32, 4.0, 0.0, 49.0, 200000,
                    tmp_path / "out.bin")
     assert st == 0
     want = oracle.self_join(w.D, 4.0, 0.0, 49.0)

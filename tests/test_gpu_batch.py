@@ -112,6 +112,9 @@ def test_batcher_graph_replays_match_eager(setup):
         assert b.replays == i + 1
         for e, g in zip(eager, got):
             assert key_sorted(e) == key_sorted(g)
+        # every replay against the oracle, request by request
+        for (Q, d, t0, t1), g in zip(sub, got):
+            check_oracle(g, Q, w.D, d, t0, t1)
     # fp64 batcher
     b64 = tds.Batcher(idx, max_segments=20000, max_requests=64, result_capacity=64 * 4096,
                       precision="fp64")
@@ -145,6 +148,39 @@ def test_server_alone_vs_mix(setup):
     assert st["requeued"] > 0             # small reservations forced exact re-runs
     assert st["max_batch_requests_seen"] > 1  # requests shared batches
     assert st["batches"] < 2 * len(reqs) + st["requeued"]
+
+
+def test_server_rejects_a_bad_request_alone(setup):
+    """A request with a non-finite value or an empty segment is refused at
+    submission; the valid requests around it complete with the records they
+    get alone (a bad request never fails a batch it would have joined)."""
+    w, idx, reqs = setup
+    srv = tds.Server(idx, max_batch_segments=20000, max_batch_requests=16, slots=2,
+                     result_capacity=1 << 16, default_reserve=64)
+    tickets = []
+    refused = 0
+    for i, (Q, d, t0, t1) in enumerate(reqs[:24]):
+        tickets.append(srv.submit(Q, d, t0, t1))
+        if i % 6 == 2:
+            arrs = {k: np.array(v, copy=True) for k, v in Q.arrays().items()}
+            bad = [dict(arrs), dict(arrs)]
+            bad[0]["ys"] = arrs["ys"].copy()
+            bad[0]["ys"][len(Q) // 2] = np.nan
+            bad[1]["te"] = arrs["te"].copy()
+            bad[1]["te"][0] = arrs["ts"][0]  # te == ts
+            for b in bad:
+                with pytest.raises(tds.TdsError) as e:
+                    srv.submit(b, d, t0, t1)
+                assert e.value.status == tds.TDS_E_INVALID
+                refused += 1
+    got = [srv.wait(t)[0] for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert refused == 8
+    assert st["completed"] == 24 and st["failed"] == 0 and st["submitted"] == 24
+    for (Q, d, t0, t1), g in zip(reqs[:24], got):
+        check_oracle(g, Q, w.D, d, t0, t1)
+        assert key_sorted(g) == key_sorted(idx.search(Q, d, t0, t1))
 
 
 def test_repeated_batch_on_the_same_buffers(setup):
