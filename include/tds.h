@@ -248,6 +248,32 @@ int tds_search(const tds_index* index, const tds_segments* Q, double d,
                tds_stats* stats);
 
 /*
+ * tds_search for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * search, records and status codes as tds_search with device output, but
+ * every buffer beyond the caller's inputs and outputs comes from one
+ * statically sized device array of 24 MiB per device (held by the library
+ * until the process ends; its address is looked up on the first call on a
+ * device).  The call allocates no device, host or pinned memory.
+ * Requirements beyond tds_search's: Q in device memory (Q->on_device = 1) with
+ * at most 65,536 segments; `out` is device memory (params->out_on_device is
+ * ignored); at most 1,024 distance-kernel waves (params->grid_waves is capped)
+ * and at most 524,288 work items (a larger search returns TDS_E_NOMEM: split
+ * Q or use tds_search).  No incremental passes: on TDS_E_OVERFLOW `out` holds
+ * an unspecified subset of `capacity` records.  stats->kernel_ms is 0 (no
+ * timing events).  Every call on a device shares that device's array and
+ * clears what it needs at its start: calls that overlap on one device (other
+ * streams or threads) race and must be serialised by the caller.  Waits for
+ * `stream`.
+ * Errors: TDS_E_INVALID (as tds_search, plus host-memory Q or more than 65,536
+ * query segments), TDS_E_NOMEM (work items beyond the table), TDS_E_DEVICE.
+ */
+int tds_search_noalloc(const tds_index* index, const tds_segments* Q, double d,
+                       double t_start, double t_end, tds_result* out, uint64_t capacity,
+                       uint64_t* n_out, const tds_search_params* params, void* stream,
+                       tds_stats* stats);
+
+/*
  * Self-join of the indexed database (the "every trajectory against every
  * other" search that motivates the paper, Sec. 1): every pair of entry
  * segments of different trajectories that is within d during the window,

@@ -179,6 +179,23 @@ class Index:
         self.last_stats = st.as_dict()
         return status, int(n.value), self.last_stats
 
+    def search_noalloc_raw(self, Q, d: float, t_start: float = -math.inf,
+                           t_end: float = math.inf, *, out_ptr: int, capacity: int,
+                           precision: str = "fp32", chunk: int = 0, grid_waves: int = 0):
+        """One call of tds_search_noalloc (Q and out in device memory); returns
+        (status, n_total, stats)."""
+        h = _segments(Q)
+        p = _search_params(precision, chunk, grid_waves)
+        p.out_on_device = 1
+        n = ctypes.c_uint64()
+        st = _lib.tds_stats()
+        status = self._lib.tds_search_noalloc(self._h, ctypes.byref(h.struct), float(d),
+                                              float(t_start), float(t_end),
+                                              ctypes.c_void_p(out_ptr), ctypes.c_uint64(capacity),
+                                              ctypes.byref(n), ctypes.byref(p),
+                                              _current_stream(), ctypes.byref(st))
+        return status, int(n.value), st.as_dict()
+
     def search(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                capacity: Optional[int] = None, precision: str = "fp32", chunk: int = 0,
                grid_waves: int = 0, device_capacity: int = 0) -> np.ndarray:

@@ -100,6 +100,11 @@ SIGNATURES = {
                                   ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_uint64,
                                   c_u64_p, ctypes.POINTER(tds_search_params), ctypes.c_void_p,
                                   ctypes.POINTER(tds_stats)]),
+    "tds_search_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments),
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_void_p, ctypes.c_uint64, c_u64_p,
+                                          ctypes.POINTER(tds_search_params), ctypes.c_void_p,
+                                          ctypes.POINTER(tds_stats)]),
     "tds_search_params_default": (None, [ctypes.POINTER(tds_search_params)]),
     "tds_self_join": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_void_p, ctypes.c_uint64, c_u64_p,
