@@ -136,7 +136,8 @@ def load_profile(workload, kind):
 
 def profile_command(workload, counters):
     return (f"rocprofv3 --pmc {counters} --output-format csv -d gpurun_out/pmc -o p -- "
-            f"python3 bench.py --legs {workload} --steps 2 --warmup 1 --no-cpu --calib-copy-mb 256")
+            f"python3 bench.py --legs {workload} --steps 2 --warmup 1 --no-cpu --no-fp64-form "
+            f"--calib-copy-mb 256")
 
 
 def summarize_valu(workload, csv_path):
@@ -391,14 +392,14 @@ class SearchLeg:
         del out64
         return {"ms": round(1e3 * t, 3), "kernel_ms": round(s["kernel_ms"], 3)}, errs
 
-    def report(self, steps, warmup, cpu_traj, cores, with_cpu=True):
+    def report(self, steps, warmup, cpu_traj, cores, with_cpu=True, with_fp64=True):
         w = self.w
         elapsed, acc = self.timed(steps, warmup)
         t0, t1 = w.window
         pairs = overlap_pairs(w.D, w.Q, t0, t1) * len(w.ds)
         info = self.idx.info()
         n_ranged = ranged_entries(info, w.D, w.Q, t0, t1)
-        fp64, errs = self.fp64_form()
+        fp64, errs = self.fp64_form() if with_fp64 else (None, {})
         out = {
             "workload": w.name, "n_entries": len(w.D), "n_query_segments": len(w.Q),
             "d": w.ds, "num_bins": info["num_bins"],
@@ -417,7 +418,7 @@ class SearchLeg:
             "fp64_form": fp64,
             "fp32_endpoint_error": {"max_abs": max(e["max_abs"] for e in errs.values()),
                                     "p99_abs": max(e["p99_abs"] for e in errs.values()),
-                                    "per_d": errs},
+                                    "per_d": errs} if errs else None,
             "tuned": self.tuned,
         }
         if with_cpu:
@@ -587,6 +588,8 @@ def main():
                     help="comma-separated legs to run (the headline is the first of "
                          "galaxy, uniform1m, dense, tiny that runs)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64-form", action="store_true",
+                    help="skip the plain FP64 form and the endpoint-error comparison")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two counter CSVs and exit (no GPU)")
     ap.add_argument("--summarize-valu", nargs=2, metavar=("WORKLOAD", "CSV"),
@@ -646,7 +649,7 @@ def main():
             first = not results
             results[name] = leg.report(args.steps if first else max(3, args.steps // 2),
                                        args.warmup if first else 1, cpu_traj[name], cores,
-                                       with_cpu)
+                                       with_cpu, not args.no_fp64_form)
             print(f"# {name}: {json.dumps(results[name])}", file=sys.stderr, flush=True)
         if name == "uniform1m":
             uni = (w, leg)

@@ -29,7 +29,7 @@ struct Carve {
     size_t b_count, b_hi, b_start, b_nch, binfo;
     size_t item_bucket, item_count, bstats;
     size_t stage, stage_meta;
-    size_t desc, req, hdr, ctr;
+    size_t desc, req, hdr, ctr, dyn;
     size_t total;
 };
 
@@ -61,6 +61,7 @@ constexpr Carve carve() {
     c.req = take(sizeof(Request));
     c.hdr = take(sizeof(SearchHeader));
     c.ctr = take(sizeof(ReqCounter));
+    c.dyn = take((size_t)kXcds * kCtrStride * sizeof(unsigned long long));
     c.total = o;
     return c;
 }
@@ -135,6 +136,7 @@ struct ScratchWorkspace : Workspace {
         req = reinterpret_cast<Request*>(base + kCarve.req);
         hdr = reinterpret_cast<SearchHeader*>(base + kCarve.hdr);
         req_ctr = reinterpret_cast<ReqCounter*>(base + kCarve.ctr);
+        dyn_ctr = reinterpret_cast<unsigned long long*>(base + kCarve.dyn);
     }
     ~ScratchWorkspace() {
         // views only: leave nothing for ~Workspace to free
@@ -150,6 +152,7 @@ struct ScratchWorkspace : Workspace {
         req = nullptr;
         hdr = nullptr;
         req_ctr = nullptr;
+        dyn_ctr = nullptr;
     }
 };
 

@@ -139,6 +139,13 @@ __device__ inline void wave_sync() {
 
 __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Lane 0's 64-bit value in every lane (the value need not be uniform).
+__device__ inline uint64_t lane0_64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 0);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 0);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // ------------------------------------------------------------ schedule
 
 // Smallest j in [0, m] with pred(j), for a predicate that is monotone
@@ -281,7 +288,8 @@ __device__ inline uint32_t request_of(const Request* req, uint32_t nreq, uint64_
 
 __global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_count,
                                                  uint32_t* b_hi, uint32_t nb,
-                                                 uint32_t nparts, ReqCounter* rc, uint32_t nreq) {
+                                                 uint32_t nparts, ReqCounter* rc, uint32_t nreq,
+                                                 unsigned long long* dyn_ctr) {
     // nreq: capacity of the request counters (all of them are cleared);
     // b_count and b_hi hold nparts parts for each of the nb buckets
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
@@ -297,6 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_
         rc[i].count = 0;
         rc[i].pad = 0;
     }
+    if (i < kXcds * kCtrStride) dyn_ctr[i] = 0;
 }
 
 // Canonical FP64 data of query segment k of request r, from the query
@@ -637,10 +646,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const BatchDesc* __restrict_
         if (bi.item0 + i < cap) item_bucket[bi.item0 + i] = b;
 }
 
-// Resets the per-pass request counters of the distance kernel.
-__global__ void k_reset_pass(ReqCounter* rc, uint32_t nreq) {
+// Resets the per-pass request counters and the dynamic item counters of the
+// distance kernel.
+__global__ void k_reset_pass(ReqCounter* rc, uint32_t nreq, unsigned long long* dyn_ctr) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nreq) rc[i].count = 0;
+    if (i < kXcds * kCtrStride) dyn_ctr[i] = 0;
 }
 
 // Adds the per-workgroup counters of one distance-kernel launch to the
@@ -688,6 +699,7 @@ struct DistArgs {
     ReqCounter* rc;
     tds_result* out;
     uint64_t win_lo;        // first request-local result position kept
+    unsigned long long* dyn_ctr;  // per-XCD dynamic item counters (kCtrStride apart)
     uint32_t item_begin;    // work items [item_begin, item_end)
     uint32_t item_end;      // 0xFFFFFFFF: every item of the search
     uint32_t* item_count;   // results per work item, or nullptr
@@ -1152,25 +1164,62 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t item_end = (A.item_end == 0xFFFFFFFFu)
                                   ? uniform(min(A.hdr->n_items, A.desc->item_cap))
                                   : A.item_end;
-    // items [item_begin, item_end) dealt statically, XCD by XCD: workgroups
-    // are dispatched to the XCDs round-robin, so workgroup b runs on XCD
-    // b mod 8; the items are split into 8 contiguous parts (consecutive items
-    // share buckets, hence candidate ranges) and part x is dealt round-robin
-    // to the waves of the workgroups b = x mod 8, so each bucket's candidates
-    // are fetched into one XCD's L2.  No work counter: a device-scope atomic
-    // per item (a fetch the item's loads then depend on) cost more than the
-    // imbalance it removed.
+    // Items [item_begin, item_end) are split into 8 contiguous parts, one
+    // per XCD (workgroups are dispatched to the XCDs round-robin, so
+    // workgroup b runs on XCD b mod 8; consecutive items share buckets, hence
+    // candidate ranges, which then stay under one XCD's L2).  Each wave first
+    // takes one item of its XCD's part statically (item p0 + its index among
+    // the XCD's waves: no atomic on the critical path of light searches,
+    // where this round covers every item).  Items beyond that round are
+    // taken dynamically from the part's counter, and a wave whose part is
+    // used up takes from the next parts: item costs vary by orders of
+    // magnitude where results cluster (a static deal left some XCDs idle for
+    // more than half of a galaxy search).  A part's counter is read before
+    // it is incremented, so exhausted parts cost loads, not contended atomics.
     const uint64_t n_it = item_end > A.item_begin ? item_end - A.item_begin : 0u;
     // this wave's result stage
     const uint64_t sbase =
         (uint64_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * A.stage_cap;
     const uint32_t ng = min(gridDim.x, kXcds);
     const uint32_t grp = blockIdx.x % ng;
-    const uint32_t gblocks = (gridDim.x - grp + ng - 1) / ng;  // workgroups of the group
     const uint32_t gw = uniform((blockIdx.x / ng) * kWavesPerBlock + threadIdx.x / kWave);
-    const uint32_t G = gblocks * kWavesPerBlock;
-    const uint64_t p0 = n_it * grp / ng, p1 = n_it * (grp + 1) / ng;
-    for (uint64_t k = p0 + gw; k < p1; k += G) {
+    // waves of the workgroups on XCD x
+    auto waves_of = [&](uint32_t x) {
+        return ((gridDim.x - x + ng - 1) / ng) * (uint32_t)kWavesPerBlock;
+    };
+    auto part_lo = [&](uint32_t x) { return n_it * x / ng; };
+    bool dyn = false;  // does any part hold more items than its XCD has waves?
+    for (uint32_t x = 0; x < ng; ++x) dyn = dyn || part_lo(x + 1) - part_lo(x) > waves_of(x);
+    uint64_t k = part_lo(grp) + gw;
+    bool have = k < part_lo(grp + 1);
+    uint32_t xs = grp, tried = 0;
+    for (;;) {
+        if (!have) {
+            if (!dyn) break;
+            // the next dynamic item: from part xs, past its static round
+            while (tried < ng) {
+                const uint64_t ps = part_lo(xs) + waves_of(xs), pe = part_lo(xs + 1);
+                if (ps < pe) {
+                    unsigned long long* ctr = A.dyn_ctr + (size_t)xs * kCtrStride;
+                    uint64_t v = 0;
+                    if (lane == 0) v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    v = lane0_64(v);
+                    if (ps + v < pe) {
+                        if (lane == 0) v = atomicAdd(ctr, 1ull);
+                        v = lane0_64(v);
+                        if (ps + v < pe) {
+                            k = ps + v;
+                            have = true;
+                            break;
+                        }
+                    }
+                }
+                xs = (xs + 1 == ng) ? 0 : xs + 1;
+                ++tried;
+            }
+            if (!have) break;
+        }
+        have = false;
         const uint32_t it = A.item_begin + (uint32_t)k;
         const uint32_t b = uniform(A.item_bucket[it]);
         const BucketInfo bi = A.binfo[b];
@@ -1268,7 +1317,7 @@ Workspace::~Workspace() {
                     (void*)qtraj_stage, (void*)ctl, (void*)b_count,
                     (void*)b_hi, (void*)b_start, (void*)b_nch,
                     (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res,
-                    (void*)bstats, (void*)stage, (void*)stage_meta})
+                    (void*)bstats, (void*)stage, (void*)stage_meta, (void*)dyn_ctr})
         dfree(p);
     if (ctl_host) (void)hipHostFree(ctl_host);
     if (ev0) (void)hipEventDestroy(ev0);
@@ -1282,6 +1331,7 @@ int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_nch, kMaxBuckets));
     TDS_TRY(dmalloc(&w->binfo, kMaxBuckets));
     TDS_TRY(dmalloc(&w->bstats, kMaxDistBlocks));
+    TDS_TRY(dmalloc(&w->dyn_ctr, (size_t)kXcds * kCtrStride));
     TDS_HIP(hipEventCreate(&w->ev0));
     TDS_HIP(hipEventCreate(&w->ev1));
     return ws_reserve(w, 0, 1);
@@ -1486,6 +1536,7 @@ DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q,
                    uint64_t win_lo, uint32_t item_begin, uint32_t item_end, uint32_t* item_count,
                    uint32_t grid_waves, bool by_order) {
     DistArgs A;
+    A.dyn_ctr = w->dyn_ctr;
     A.stage = w->stage;
     A.stage_meta = w->stage_meta;
     A.stage_cap = stage_per_wave(w->stage_recs, launch_blocks(grid_waves));
@@ -1543,10 +1594,10 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
     const uint32_t shift = bucket_shift(idx->m);
     const uint32_t nb = bucket_count(idx->m);
     const uint32_t nparts = count_parts(nb);
-    const uint32_t zn = std::max(nb * nparts, r_cap);
+    const uint32_t zn = std::max(std::max(nb * nparts, r_cap), kXcds * kCtrStride);
     // k_zero also clears the request counters the distance kernel appends with
     hipLaunchKernelGGL(k_zero, dim3(ceil_div(zn, kBlock)), dim3(kBlock), 0, s, w->hdr, w->b_count,
-                       w->b_hi, nb, nparts, w->req_ctr, r_cap);
+                       w->b_hi, nb, nparts, w->req_ctr, r_cap, w->dyn_ctr);
     const uint32_t qblocks = std::max(1u, ceil_div(q_grid, kBlock));
     const uint32_t bpp = ceil_div(qblocks, nparts);  // workgroup b counts in part b / bpp < nparts
     hipLaunchKernelGGL(k_qprep, dim3(qblocks), dim3(kBlock), 0, s, Q, w->desc, w->req, I, w->qfu,
@@ -1571,8 +1622,8 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
 int enqueue_range(const tds_index* idx, Workspace* w, const QueryView& Q, int prec, uint32_t r_cap,
                   tds_result* out, uint64_t win_lo, uint32_t i0, uint32_t i1, bool by_order,
                   uint32_t grid_waves, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end) {
-    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, 1u), 256)), dim3(256), 0, s,
-                       w->req_ctr, r_cap);
+    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, kXcds * kCtrStride), 256)),
+                       dim3(256), 0, s, w->req_ctr, r_cap, w->dyn_ctr);
     TDS_HIP(hipGetLastError());
     return launch_distance(prec,
                            dist_args(idx, w, Q, out, win_lo, i0, i1, nullptr, grid_waves, by_order),

@@ -19,6 +19,7 @@ constexpr int kWave = 64;               // CDNA wavefront width
 constexpr int kBlock = 256;             // threads per block of the search kernels
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr uint32_t kXcds = 8;            // accelerator complex dies (own L2 each)
+constexpr uint32_t kCtrStride = 8;       // 64-bit counters 64 bytes apart (own cache lines)
 constexpr uint32_t kMaxBins = 65535;
 constexpr uint32_t kMaxBuckets = 65536; // query buckets of one search
 constexpr uint32_t kSpanClasses = 4;    // bin-span classes per first bin
@@ -174,6 +175,7 @@ struct Workspace {
     tds_result* stage = nullptr;
     uint32_t* stage_meta = nullptr;
     size_t stage_recs = 0;
+    unsigned long long* dyn_ctr = nullptr;  // kXcds dynamic item counters, kCtrStride apart
     SearchHeader* hdr = nullptr;
     SearchHeader* hdr_host = nullptr;  // pinned mirror
     BlockStats* bstats = nullptr;      // kMaxDistBlocks per-workgroup counters

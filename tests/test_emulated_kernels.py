@@ -7,7 +7,12 @@ threads, wave intrinsics through a per-wave barrier, device memory from
 malloc).  Every memory access the kernels make is then bounds-checked, and
 their results are compared with the oracle's.  This checks the kernels'
 indexing and the host code around them on a machine without a GPU; the GPU
-parity tests check the same entry points on the device."""
+parity tests check the same entry points on the device.
+
+The emulated runs spend most of their time waiting in barriers, not
+computing, so all of them are started together (a module fixture) and each
+test checks its own run's output."""
+import concurrent.futures as cf
 import os
 import shutil
 import subprocess
@@ -22,17 +27,81 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1410_2698_amd", "csrc")
 RESULT_DTYPE = np.dtype([("q_seg", "<u4"), ("e_seg", "<u4"), ("q_traj", "<u4"), ("e_traj", "<u4"),
                          ("t_lo", "<f8"), ("t_hi", "<f8")])
+TEMPORAL, SPATIAL = 1, 2  # index layouts (C ABI values)
+FP64, FP32 = 1, 2         # search precisions (C ABI values)
 
 
-@pytest.fixture(scope="module")
-def harness(tmp_path_factory):
+def columns(S):
+    return np.stack([np.asarray(getattr(S, k), np.float64)
+                     for k in ("xs", "ys", "zs", "ts", "xe", "ye", "ze", "te")]
+                    + [np.asarray(S.traj, np.float64)])
+
+
+def _merge_random():
+    rng = np.random.default_rng(4)
+    n = 3000  # two radix-sort tiles
+    recs = np.zeros(n, RESULT_DTYPE)
+    recs["q_seg"] = np.arange(n)
+    recs["q_traj"] = rng.integers(0, 40, n)
+    recs["e_traj"] = rng.integers(0, 40, n) * 70001  # ids of 22 bits: 4 pair digits
+    lo = rng.integers(-800, 800, n) / 8.0
+    recs["t_lo"] = lo
+    recs["t_hi"] = lo + rng.integers(0, 24, n) / 8.0
+    return recs
+
+
+def _merge_degenerate():
+    # one t_lo for every record (no t_lo digit differs: no pass of that
+    # sort) and the largest ids (all eight pair digits)
+    n = 600
+    recs = np.zeros(n, RESULT_DTYPE)
+    recs["q_traj"] = np.where(np.arange(n) % 3 == 0, 0xFFFFFFFF, 7)
+    recs["e_traj"] = np.where(np.arange(n) % 2 == 0, 0xFFFFFFFF, 0)
+    recs["t_lo"] = 2.5
+    recs["t_hi"] = 2.5 + (np.arange(n) % 5)
+    return recs
+
+
+def _jobs():
+    """Every emulated run: name -> (kind, inputs, arguments after the inputs).
+    Kinds "search" and "fsg" take D and Q, "selfjoin" D, "merge" records."""
+    tiny = trajgen.tiny(scale=0.05)  # 100 trajectories (4,900 entries), 5 query trajectories
+    tiny04 = trajgen.tiny(scale=0.04)
+    J = {}
+    for g in [(1, 1, 1), (7, 3, 5), (50, 50, 50)]:
+        J["fsg_%dx%dx%d" % g] = ("fsg", (tiny.D, tiny.Q), [*g, 8.0, 0.0, 49.0])
+    for layout, prec, d in [(SPATIAL, FP32, 8.0), (SPATIAL, FP64, 30.0), (TEMPORAL, FP32, 30.0)]:
+        J[f"search_{layout}_{prec}_{d:g}"] = ("search", (tiny.D, tiny.Q),
+                                              [layout, prec, d, 0.0, 49.0, 100000])
+    # the database against itself at a distance larger than the data's
+    # extent: every time-overlapping pair is a result (each query segment
+    # meets the co-temporal segment of each of the 100 trajectories), so a
+    # work item of 64 query segments has 6,400 results and fills its wave's
+    # 2,048-record stage several times before it ends; the items outnumber
+    # the emulated waves, so the dynamic item counters are used as well
+    for prec in (FP32, FP64):
+        J[f"flush_{prec}"] = ("search", (tiny.D, tiny.D),
+                              [SPATIAL, prec, 250.0, 0.0, 49.0, 600000])
+    # more query buckets than the parted slot counters take (2,000 bins:
+    # 8,000 buckets, one counter part); merged keys (over 16,384 bins) take
+    # minutes here and are covered by the GPU tests
+    J["many_bins"] = ("search", (tiny.D, tiny.Q), [SPATIAL, FP32, 8.0, 0.0, 49.0, 100000, 2000])
+    # a result buffer smaller than the result set: the total is reported
+    J["overflow"] = ("search", (tiny.D, tiny.Q), [SPATIAL, FP32, 30.0, 0.0, 49.0, 100])
+    J["selfjoin"] = ("selfjoin", (tiny04.D,), [SPATIAL, FP32, 4.0, 0.0, 49.0, 200000])
+    J["merge_random"] = ("merge", _merge_random(), [3000])
+    J["merge_degenerate"] = ("merge", _merge_degenerate(), [600])
+    J["merge_degenerate_cap3"] = ("merge", _merge_degenerate(), [3])
+    return J, {"tiny": tiny, "tiny04": tiny04}
+
+
+def _build_harness(out):
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     cxx = os.path.join(rocm, "llvm", "bin", "clang++")
     if not os.path.exists(cxx):
         cxx = shutil.which("clang++")
     if cxx is None:
         pytest.skip("clang++ not available")
-    out = str(tmp_path_factory.mktemp("emu") / "harness")
     # host-only build (no GPU code); the canonical evaluation is compiled
     # without contraction, as for the GPU
     cmd = [cxx, "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
@@ -45,21 +114,46 @@ def harness(tmp_path_factory):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("emulation build failed:\n" + r.stderr[-4000:])
-    return out
 
 
-def run(harness, *args):
+def _run_job(harness, d, kind, inputs, args):
+    os.makedirs(d, exist_ok=True)
+    out = os.path.join(d, "out.bin")
+    if kind == "merge":
+        inputs.astype(RESULT_DTYPE).tofile(os.path.join(d, "recs.bin"))
+        argv = [harness, "merge", os.path.join(d, "recs.bin"), *args, out]
+    else:
+        files = []
+        for i, S in enumerate(inputs):
+            f = os.path.join(d, f"in{i}.bin")
+            columns(S).tofile(f)
+            files.append(f)
+        # harness <kind> <inputs> <six numbers> <out> [bins]
+        argv = [harness, kind, *files, *args[:6], out, *args[6:]]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
-    r = subprocess.run([harness, *map(str, args)], capture_output=True, text=True, env=env,
-                       timeout=600)
+    r = subprocess.run([str(a) for a in argv], capture_output=True, text=True, env=env,
+                       timeout=900)
+    return r, out
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    base = tmp_path_factory.mktemp("emu")
+    harness = str(base / "harness")
+    _build_harness(harness)
+    jobs, data = _jobs()
+    order = sorted(jobs, key=lambda n: (not n.startswith("flush"), n))  # heaviest first
+    with cf.ThreadPoolExecutor(4) as ex:
+        futs = {n: ex.submit(_run_job, harness, str(base / n), *jobs[n]) for n in order}
+        res = {n: f.result() for n, f in futs.items()}
+    return res, data
+
+
+def result(emu, name):
+    """(integers the harness printed, path of its output file) of one run."""
+    r, out = emu[0][name]
     assert r.returncode == 0, f"emulated kernels failed:\n{r.stdout[-2000:]}\n{r.stderr[-6000:]}"
-    return tuple(int(v) for v in r.stdout.split())
-
-
-def columns(S):
-    return np.stack([np.asarray(getattr(S, k), np.float64)
-                     for k in ("xs", "ys", "zs", "ts", "xe", "ye", "ze", "te")]
-                    + [np.asarray(S.traj, np.float64)])
+    return tuple(int(v) for v in r.stdout.split()), out
 
 
 def same_records(got, want):
@@ -72,101 +166,63 @@ def same_records(got, want):
         assert np.all(np.abs(got[f] - want[f]) <= 1e-9 * np.maximum(1.0, np.abs(want[f]))), f
 
 
-@pytest.mark.parametrize("grid", [(1, 1, 1), (7, 3, 5), (50, 50, 50)])
-def test_grid_search_emulated(harness, tmp_path, grid):
-    w = trajgen.tiny(scale=0.05)  # 100 trajectories (4,900 entries), 5 query trajectories
-    columns(w.D).tofile(tmp_path / "D.bin")
-    columns(w.Q).tofile(tmp_path / "Q.bin")
-    st, n = run(harness, "fsg", tmp_path / "D.bin", tmp_path / "Q.bin", *grid, 8.0, 0.0, 49.0,
-                tmp_path / "out.bin")
+@pytest.mark.parametrize("grid", ["1x1x1", "7x3x5", "50x50x50"])
+def test_grid_search_emulated(emu, grid):
+    (st, n), out = result(emu, f"fsg_{grid}")
+    w = emu[1]["tiny"]
     assert st == 0
-    got = np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE)
     want = oracle.search(w.Q, w.D, 8.0, 0.0, 49.0)
     assert want.size > 0 and n == want.size
-    same_records(got, want)
-
-
-TEMPORAL, SPATIAL = 1, 2  # index layouts (C ABI values)
-FP64, FP32 = 1, 2         # search precisions (C ABI values)
+    same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
 
 
 @pytest.mark.parametrize("layout,prec,d", [(SPATIAL, FP32, 8.0), (SPATIAL, FP64, 30.0),
                                            (TEMPORAL, FP32, 30.0)])
-def test_search_emulated(harness, tmp_path, layout, prec, d):
+def test_search_emulated(emu, layout, prec, d):
     # the whole search path on the CPU: index build, query preparation,
     # buckets, work items, distance kernel, FP64 recheck and append
-    w = trajgen.tiny(scale=0.05)
-    columns(w.D).tofile(tmp_path / "D.bin")
-    columns(w.Q).tofile(tmp_path / "Q.bin")
-    st, n, ftests, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", layout, prec, d,
-                        0.0, 49.0, 100000, tmp_path / "out.bin")
+    (st, n, ftests, _), out = result(emu, f"search_{layout}_{prec}_{d:g}")
+    w = emu[1]["tiny"]
     assert st == 0
     want = oracle.search(w.Q, w.D, d, 0.0, 49.0)
     assert want.size > 0 and n == want.size and ftests > 0
-    same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
+    same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
 
 
 @pytest.mark.parametrize("prec", [FP32, FP64])
-def test_search_emulated_stage_flushes(harness, tmp_path, prec):
-    # the database against itself at a distance larger than the data's
-    # extent: every time-overlapping pair is a result (each query segment
-    # meets the co-temporal segment of each of the 100 trajectories), so a
-    # work item of 64 query segments has 6,400 results and fills its wave's
-    # 2,048-record stage several times before it ends
-    w = trajgen.tiny(scale=0.05)
-    columns(w.D).tofile(tmp_path / "D.bin")
-    st, n, _, flushes = run(harness, "search", tmp_path / "D.bin", tmp_path / "D.bin", SPATIAL,
-                            prec, 250.0, 0.0, 49.0, 600000, tmp_path / "out.bin")
+def test_search_emulated_stage_flushes(emu, prec):
+    (st, n, _, flushes), out = result(emu, f"flush_{prec}")
+    w = emu[1]["tiny"]
     assert st == 0
     want = oracle.search(w.D, w.D, 250.0, 0.0, 49.0)
     assert want.size == len(w.D) * 100 and n == want.size
     assert flushes > 0
-    same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
+    same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
 
 
-def test_search_emulated_many_bins(harness, tmp_path):
-    # more query buckets than the parted slot counters take (2,000 bins: 8,000
-    # buckets, one counter part); merged keys (over 16,384 bins) take minutes
-    # here and are covered by the GPU tests
-    bins = 2000
-    w = trajgen.tiny(scale=0.05)
-    columns(w.D).tofile(tmp_path / "D.bin")
-    columns(w.Q).tofile(tmp_path / "Q.bin")
-    st, n, _, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", SPATIAL, FP32,
-                      8.0, 0.0, 49.0, 100000, tmp_path / "out.bin", bins)
+def test_search_emulated_many_bins(emu):
+    (st, n, _, _), out = result(emu, "many_bins")
+    w = emu[1]["tiny"]
     assert st == 0
     want = oracle.search(w.Q, w.D, 8.0, 0.0, 49.0)
     assert want.size > 0 and n == want.size
-    same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
+    same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
 
 
-def test_search_emulated_overflow(harness, tmp_path):
-    # a result buffer smaller than the result set: the total is reported
-    w = trajgen.tiny(scale=0.05)
-    columns(w.D).tofile(tmp_path / "D.bin")
-    columns(w.Q).tofile(tmp_path / "Q.bin")
+def test_search_emulated_overflow(emu):
+    (st, n, _, _), _ = result(emu, "overflow")
+    w = emu[1]["tiny"]
     want = oracle.search(w.Q, w.D, 30.0, 0.0, 49.0)
-    st, n, _, _ = run(harness, "search", tmp_path / "D.bin", tmp_path / "Q.bin", SPATIAL, FP32,
-                      30.0, 0.0, 49.0, 100, tmp_path / "out.bin")
     assert st == 2 and n == want.size  # TDS_E_OVERFLOW
 
 
-def test_self_join_emulated(harness, tmp_path):
-    w = trajgen.tiny(scale=0.04)
-    columns(w.D).tofile(tmp_path / "D.bin")
-    st, n, _, _ = run(harness, "selfjoin", tmp_path / "D.bin", SPATIAL, FP32, 4.0, 0.0, 49.0, 200000,
-                   tmp_path / "out.bin")
+def test_self_join_emulated(emu):
+    (st, n, _, _), out = result(emu, "selfjoin")
+    w = emu[1]["tiny04"]
     assert st == 0
     want = oracle.self_join(w.D, 4.0, 0.0, 49.0)
     assert want.size > 0 and n == want.size
-    same_records(np.fromfile(tmp_path / "out.bin", dtype=RESULT_DTYPE), want)
-
-
-def merge_emulated(harness, tmp_path, recs, cap=None):
-    recs.astype(RESULT_DTYPE).tofile(tmp_path / "recs.bin")
-    cap = recs.size if cap is None else cap
-    st, m = run(harness, "merge", tmp_path / "recs.bin", cap, tmp_path / "ivl.bin")
-    return st, m, np.fromfile(tmp_path / "ivl.bin", dtype=oracle.TRAJ_DTYPE)
+    same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
 
 
 def same_intervals(got, want):
@@ -175,36 +231,21 @@ def same_intervals(got, want):
         assert np.array_equal(got[f], want[f]), f
 
 
-def test_merge_emulated_random(harness, tmp_path):
-    rng = np.random.default_rng(4)
-    n = 3000  # two radix-sort tiles
-    recs = np.zeros(n, RESULT_DTYPE)
-    recs["q_seg"] = np.arange(n)
-    recs["q_traj"] = rng.integers(0, 40, n)
-    recs["e_traj"] = rng.integers(0, 40, n) * 70001  # ids of 22 bits: 4 pair digits
-    lo = rng.integers(-800, 800, n) / 8.0
-    recs["t_lo"] = lo
-    recs["t_hi"] = lo + rng.integers(0, 24, n) / 8.0
-    st, m, got = merge_emulated(harness, tmp_path, recs)
+def test_merge_emulated_random(emu):
+    (st, m), out = result(emu, "merge_random")
     assert st == 0
-    same_intervals(got, oracle.merge_trajectories(recs))
+    same_intervals(np.fromfile(out, dtype=oracle.TRAJ_DTYPE),
+                   oracle.merge_trajectories(_merge_random()))
 
 
-def test_merge_emulated_degenerate_keys(harness, tmp_path):
-    # one t_lo for every record (no t_lo digit differs: no pass of that
-    # sort) and the largest ids (all eight pair digits)
-    n = 600
-    recs = np.zeros(n, RESULT_DTYPE)
-    recs["q_traj"] = np.where(np.arange(n) % 3 == 0, 0xFFFFFFFF, 7)
-    recs["e_traj"] = np.where(np.arange(n) % 2 == 0, 0xFFFFFFFF, 0)
-    recs["t_lo"] = 2.5
-    recs["t_hi"] = 2.5 + (np.arange(n) % 5)
-    st, m, got = merge_emulated(harness, tmp_path, recs)
-    assert st == 0
+def test_merge_emulated_degenerate_keys(emu):
+    recs = _merge_degenerate()
     want = oracle.merge_trajectories(recs)
     assert want.size == 4
-    same_intervals(got, want)
+    (st, m), out = result(emu, "merge_degenerate")
+    assert st == 0
+    same_intervals(np.fromfile(out, dtype=oracle.TRAJ_DTYPE), want)
     # capacity below the total: the first intervals in order, the total reported
-    st, m, got = merge_emulated(harness, tmp_path, recs, cap=3)
+    (st, m), out = result(emu, "merge_degenerate_cap3")
     assert st == 2 and m == 4  # TDS_E_OVERFLOW
-    same_intervals(got, want[:3])
+    same_intervals(np.fromfile(out, dtype=oracle.TRAJ_DTYPE), want[:3])
