@@ -26,8 +26,11 @@ random windows and d in [1, 25]) with an open-loop rate sweep to saturation,
 and the plain FP64 form (one request per call) on the same stream; the
 self-join of the uniform1m entries and the fixed spatial grid.
 
+Each search leg first runs the autotuner on its workload (bin count, chunk,
+grid, tile, wavefront mapping; untimed) and times the configuration it picks.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs a,b,...]
-                       [--no-cpu] [--tune]
+                       [--no-cpu] [--no-tune] [--no-fp64-form]
 """
 from __future__ import annotations
 
@@ -324,17 +327,18 @@ class SearchLeg:
     segments at every d of the workload (one request per d, one batch), into
     device memory sized by a counting call."""
 
-    def __init__(self, tds, w, tuned=None, precision="fp32"):
+    def __init__(self, tds, w, tuned=None, precision=None):
         import torch
         self.tds, self.w = tds, w
-        self.tuned = tuned or {"num_bins": 0, "chunk": 0, "grid_waves": 0}
+        self.tuned = tuned or {"num_bins": 0, "chunk": 0, "grid_waves": 0, "tile": 0,
+                               "precision": "fp32"}
         self.idx = tds.Index(w.D, num_bins=self.tuned["num_bins"])
         Qt = device_segments(w.Q)
         nq = len(w.Q)
         self.Qb = {k: torch.cat([v] * len(w.ds)) if len(w.ds) > 1 else v for k, v in Qt.items()}
         t0, t1 = w.window
         self.count_reqs = [(i * nq, nq, d, t0, t1, 0, 0) for i, d in enumerate(w.ds)]
-        self.precision = precision
+        self.precision = precision or self.tuned["precision"]
         _, want, _ = self.run(self.count_reqs, 0, 0)
         self.counts = want
         self.cap = max(want) + 1
@@ -346,7 +350,8 @@ class SearchLeg:
                                          out_on_device=True,
                                          precision=precision or self.precision,
                                          chunk=self.tuned["chunk"],
-                                         grid_waves=self.tuned["grid_waves"])
+                                         grid_waves=self.tuned["grid_waves"],
+                                         tile=self.tuned["tile"])
 
     def step(self):
         st, got, s = self.run(self.reqs, self.out.data_ptr(), len(self.w.ds) * self.cap)
@@ -594,7 +599,8 @@ def main():
                     help="write the traffic summary from two counter CSVs and exit (no GPU)")
     ap.add_argument("--summarize-valu", nargs=2, metavar=("WORKLOAD", "CSV"),
                     help="write the instruction-counter summary from a counter CSV and exit")
-    ap.add_argument("--tune", action="store_true", help="autotune each search leg before timing")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="library defaults instead of the autotuner's choice for each search leg")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the open-loop serving run at 5,000 requests/s")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -641,9 +647,12 @@ def main():
             continue
         w = getattr(trajgen, name)()
         tuned = None
-        if args.tune:
+        if not args.no_tune and name in legs:
+            tb = time.perf_counter()
             best = autotune.tune(w.D, w.Q, w.ds, w.window, cache=None)
-            tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves")}
+            tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves", "tile", "precision")}
+            tuned["trials"] = best["trials"]
+            tuned["tuning_s"] = round(time.perf_counter() - tb, 2)
         leg = SearchLeg(tds, w, tuned)
         if name in legs:
             first = not results

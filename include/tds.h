@@ -137,7 +137,11 @@ typedef struct tds_search_params {
        it, the search is re-run in increments that each fit (Sec. 3.2).
        0 = min(capacity, 2^24). */
     uint64_t device_capacity;
-    uint64_t reserved[4];
+    /* FP32 form: candidates each lane holds per tile of the distance kernel
+       (the tile is 64 x this); 2 or 4, 0 = 4. */
+    uint32_t tile;
+    uint32_t reserved32;
+    uint64_t reserved[3];
 } tds_search_params;
 
 /* Counters of the last search (tests and benchmarks). */

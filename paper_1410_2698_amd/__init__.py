@@ -160,15 +160,11 @@ class Index:
 
     def search_raw(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                    out_ptr: int, capacity: int, out_on_device: bool, precision: str = "fp32",
-                   chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0):
+                   chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0, tile: int = 0):
         """One call of tds_search into caller memory; returns (status, n_total, stats)."""
         h = _segments(Q)
-        p = _lib.tds_search_params()
-        self._lib.tds_search_params_default(ctypes.byref(p))
-        p.precision = PRECISIONS[precision]
+        p = _search_params(precision, chunk, grid_waves, tile)
         p.out_on_device = 1 if out_on_device else 0
-        p.chunk = int(chunk)
-        p.grid_waves = int(grid_waves)
         p.device_capacity = int(device_capacity)
         n = ctypes.c_uint64()
         st = _lib.tds_stats()
@@ -181,11 +177,12 @@ class Index:
 
     def search_noalloc_raw(self, Q, d: float, t_start: float = -math.inf,
                            t_end: float = math.inf, *, out_ptr: int, capacity: int,
-                           precision: str = "fp32", chunk: int = 0, grid_waves: int = 0):
+                           precision: str = "fp32", chunk: int = 0, grid_waves: int = 0,
+                           tile: int = 0):
         """One call of tds_search_noalloc (Q and out in device memory); returns
         (status, n_total, stats)."""
         h = _segments(Q)
-        p = _search_params(precision, chunk, grid_waves)
+        p = _search_params(precision, chunk, grid_waves, tile)
         p.out_on_device = 1
         n = ctypes.c_uint64()
         st = _lib.tds_stats()
@@ -198,7 +195,7 @@ class Index:
 
     def search(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                capacity: Optional[int] = None, precision: str = "fp32", chunk: int = 0,
-               grid_waves: int = 0, device_capacity: int = 0) -> np.ndarray:
+               grid_waves: int = 0, device_capacity: int = 0, tile: int = 0) -> np.ndarray:
         """Search into host memory; grows the buffer and retries on overflow.
         Returns the records (unspecified order) as a NumPy structured array."""
         cap = 1 << 16 if capacity is None else int(capacity)
@@ -207,7 +204,7 @@ class Index:
             status, n, _ = self.search_raw(Q, d, t_start, t_end, out_ptr=buf.ctypes.data,
                                            capacity=cap, out_on_device=False, precision=precision,
                                            chunk=chunk, grid_waves=grid_waves,
-                                           device_capacity=device_capacity)
+                                           device_capacity=device_capacity, tile=tile)
             if status == TDS_OK:
                 return buf[:n].copy()
             if status == TDS_E_OVERFLOW and capacity is None:
@@ -218,9 +215,10 @@ class Index:
 
     def self_join_raw(self, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                       out_ptr: int, capacity: int, out_on_device: bool, precision: str = "fp32",
-                      chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0):
+                      chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0,
+                      tile: int = 0):
         """One call of tds_self_join into caller memory; returns (status, n_total, stats)."""
-        p = _search_params(precision, chunk, grid_waves)
+        p = _search_params(precision, chunk, grid_waves, tile)
         p.out_on_device = 1 if out_on_device else 0
         p.device_capacity = int(device_capacity)
         n = ctypes.c_uint64()
@@ -253,7 +251,7 @@ class Index:
 
     def search_batch_raw(self, Q, requests, *, out_ptr: int, out_capacity: int,
                          out_on_device: bool, precision: str = "fp32", chunk: int = 0,
-                         grid_waves: int = 0):
+                         grid_waves: int = 0, tile: int = 0):
         """One call of tds_search_batch into caller memory.  ``requests`` holds
         (q_begin, q_count, d, t_start, t_end, out_offset, out_capacity) tuples
         that tile Q in order.  Returns (status, counts, stats)."""
@@ -263,7 +261,7 @@ class Index:
             r.q_begin, r.q_count, r.d, r.t_start, r.t_end = int(qb), int(qc), float(d), float(t0), float(t1)
             r.out_offset, r.out_capacity = int(oo), int(oc)
         counts = (ctypes.c_uint64 * len(requests))()
-        p = _search_params(precision, chunk, grid_waves)
+        p = _search_params(precision, chunk, grid_waves, tile)
         p.out_on_device = 1 if out_on_device else 0
         st = _lib.tds_stats()
         status = self._lib.tds_search_batch(self._h, ctypes.byref(h.struct), reqs, len(requests),
@@ -353,13 +351,14 @@ class FSG:
             raise TdsError(status, "tds_fsg_search")
 
 
-def _search_params(precision="fp32", chunk=0, grid_waves=0):
+def _search_params(precision="fp32", chunk=0, grid_waves=0, tile=0):
     lib = load()
     p = _lib.tds_search_params()
     lib.tds_search_params_default(ctypes.byref(p))
     p.precision = PRECISIONS[precision]
     p.chunk = int(chunk)
     p.grid_waves = int(grid_waves)
+    p.tile = int(tile)
     return p
 
 
@@ -448,7 +447,8 @@ class Server:
 
     def __init__(self, index: Index, *, max_batch_segments: int = 0, max_batch_requests: int = 0,
                  slots: int = 0, result_capacity: int = 0, default_reserve: int = 0,
-                 max_pending: int = 0, precision: str = "fp32", chunk: int = 0, grid_waves: int = 0):
+                 max_pending: int = 0, precision: str = "fp32", chunk: int = 0, grid_waves: int = 0,
+                 tile: int = 0):
         self._lib = load()
         self.index = index
         p = _lib.tds_server_params()
@@ -458,7 +458,7 @@ class Server:
         p.result_capacity = result_capacity
         p.default_reserve = default_reserve
         p.max_pending = max_pending
-        p.search = _search_params(precision, chunk, grid_waves)
+        p.search = _search_params(precision, chunk, grid_waves, tile)
         out = ctypes.c_void_p()
         check(self._lib.tds_server_create(index.handle, ctypes.byref(p), ctypes.byref(out)),
               "tds_server_create")

@@ -1,11 +1,22 @@
 """Autotuner for the search launch parameters.
 
-Sweeps, on the caller's database and a sample of its queries, the number of
-temporal bins (the paper's bin-count sweeps, Sec. 5.3-5.5, chose it by
-measurement as well), the candidate chunk length of a work item and the size
-of the persistent distance-kernel grid, timing whole searches (device-side
-output, inputs resident) and keeping the fastest.  Results are cached in a
-JSON file keyed by device name and workload signature.
+On the caller's database and queries it times whole batched searches (every
+d of the workload as one request of one batch, device output, inputs
+resident) and picks, by coordinate descent from the library defaults:
+
+* the number of temporal bins, as a multiple of the automatic count (the bin
+  width; the paper chose it by measurement as well, Sec. 5.3-5.5);
+* the work-item chunk: candidates of a bucket's range taken by one wave for
+  its group of 64 query segments;
+* the persistent grid of the distance kernel (waves);
+* the tile: candidates each lane holds per step of the FP32 form (2 or 4);
+* the wavefront mapping: the FP32 form (lanes hold candidates, the group's
+  query segments are walked in turn, survivors rechecked in FP64) or the FP64
+  form (lanes hold query segments, candidates are streamed to all of them).
+
+Every configuration gives the same records (the tests check the chosen one
+against the oracle); only the time differs.  Results are cached in a JSON
+file keyed by device name and workload signature.
 """
 from __future__ import annotations
 
@@ -18,15 +29,23 @@ import numpy as np
 
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "tds_autotune.json")
 
+SPACE = {
+    "bins_factor": (1.0, 2.0, 0.5),
+    "chunk": (4096, 1024, 2048, 8192),
+    "grid_waves": (4096, 2048, 8192),
+    "tile": (4, 2),
+    "precision": ("fp32", "fp64"),
+}
+
 
 def _device_name() -> str:
     import torch
     return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
 
 
-def signature(n_entries: int, n_query: int, ds, window, precision: str) -> str:
-    return f"n={n_entries};q={n_query};d={','.join(f'{x:g}' for x in ds)};" \
-           f"w={window[0]:g},{window[1]:g};p={precision}"
+def signature(n_entries: int, n_query: int, ds, window) -> str:
+    return (f"n={n_entries};q={n_query};d={','.join(f'{x:g}' for x in ds)};"
+            f"w={window[0]:g},{window[1]:g}")
 
 
 def _load_cache(path: str) -> dict:
@@ -37,61 +56,93 @@ def _load_cache(path: str) -> dict:
         return {}
 
 
-def tune(D, Q, ds: Iterable[float], window, *, precision: str = "fp32",
-         bins: Iterable[float] = (1.0, 0.5, 2.0), chunks: Iterable[int] = (1024, 2048, 4096),
-         grids: Iterable[int] = (1024, 2048, 4096), reps: int = 3,
-         cache: Optional[str] = CACHE, force: bool = False) -> dict:
-    """Return {"num_bins", "chunk", "grid_waves", "ms", ...} for the fastest
-    configuration.  ``bins`` are multiples of the automatic bin count."""
+def tune(D, Q, ds: Iterable[float], window, *, space: Optional[dict] = None, reps: int = 3,
+         rounds: int = 2, cache: Optional[str] = CACHE, force: bool = False) -> dict:
+    """Return {"num_bins", "chunk", "grid_waves", "tile", "precision", "ms",
+    "trials", ...} for the fastest configuration found.  ``space`` maps each
+    knob to its candidate values, the first being the starting point."""
     import torch
 
     import paper_1410_2698_amd as tds
 
+    space = dict(SPACE, **(space or {}))
     ds = list(ds)
-    key = f"{_device_name()}|{signature(len(D), len(Q), ds, window, precision)}"
+    key = f"{_device_name()}|{signature(len(D), len(Q), ds, window)}|" + \
+          json.dumps({k: list(v) for k, v in sorted(space.items())})
     if cache and not force:
         hit = _load_cache(cache).get(key)
         if hit:
-            return hit
+            return dict(hit, cached=True)
     Qt = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in Q.arrays().items()
           if k != "traj"}
-    results = []
+    Qt["traj"] = torch.from_numpy(np.ascontiguousarray(Q.traj).astype(np.int32)).cuda()
+    nq = len(Q)
+    Qb = {k: torch.cat([v] * len(ds)) for k, v in Qt.items()} if len(ds) > 1 else Qt
+    t0, t1 = window
     probe = tds.Index(D)
     auto_m = probe.info()["num_bins"]
     probe.close()
-    for f in bins:
-        m = max(1, min(65535, int(round(auto_m * f))))
-        idx = tds.Index(D, num_bins=m)
-        counts = {}
-        for d in ds:
-            _, counts[d], _ = idx.search_raw(Qt, d, *window, out_ptr=0, capacity=0,
-                                             out_on_device=True, precision=precision)
-        cap = max(counts.values()) + 1
-        out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
-        for c in chunks:
-            for g in grids:
-                ts = []
-                for r in range(reps + 1):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    for d in ds:
-                        st, n, _ = idx.search_raw(Qt, d, *window, out_ptr=out.data_ptr(),
-                                                  capacity=cap, out_on_device=True,
-                                                  precision=precision, chunk=c, grid_waves=g)
-                        if st != tds.TDS_OK or n != counts[d]:
-                            raise RuntimeError("autotune: search failed")
-                    torch.cuda.synchronize()
-                    if r:
-                        ts.append(time.perf_counter() - t0)
-                results.append({"num_bins": m, "bins_factor": f, "chunk": c, "grid_waves": g,
-                                "ms": 1e3 * float(np.median(ts))})
+
+    indexes = {}  # bins factor -> (index, counts, output buffer, requests)
+
+    def index_for(f):
+        if f not in indexes:
+            m = max(1, min(65535, int(round(auto_m * f))))
+            idx = tds.Index(D, num_bins=m)
+            st, counts, _ = idx.search_batch_raw(
+                Qb, [(i * nq, nq, d, t0, t1, 0, 0) for i, d in enumerate(ds)], out_ptr=0,
+                out_capacity=0, out_on_device=True)
+            cap = max(counts) + 1
+            out = torch.empty(len(ds) * cap * 32, dtype=torch.uint8, device="cuda")
+            reqs = [(i * nq, nq, d, t0, t1, i * cap, cap) for i, d in enumerate(ds)]
+            indexes[f] = (idx, m, counts, out, reqs)
+        return indexes[f]
+
+    timed = {}
+
+    def measure(c):
+        k = tuple(sorted(c.items()))
+        if k in timed:
+            return timed[k]
+        idx, m, counts, out, reqs = index_for(c["bins_factor"])
+        ts = []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            st, got, _ = idx.search_batch_raw(Qb, reqs, out_ptr=out.data_ptr(),
+                                              out_capacity=out.numel() // 32, out_on_device=True,
+                                              precision=c["precision"], chunk=c["chunk"],
+                                              grid_waves=c["grid_waves"], tile=c["tile"])
+            torch.cuda.synchronize()
+            if st != tds.TDS_OK or got != counts:
+                raise RuntimeError(f"autotune: search failed ({st}, {got} vs {counts}) at {c}")
+            if r:
+                ts.append(time.perf_counter() - ta)
+        timed[k] = 1e3 * float(np.median(ts))
+        return timed[k]
+
+    best = {k: v[0] for k, v in space.items()}
+    best_ms = measure(best)
+    for _ in range(rounds):
+        changed = False
+        for knob, values in space.items():
+            for v in values:
+                if v == best[knob]:
+                    continue
+                c = dict(best, **{knob: v})
+                ms = measure(c)
+                if ms < best_ms:
+                    best, best_ms, changed = c, ms, True
+        if not changed:
+            break
+    m = index_for(best["bins_factor"])[1]
+    for idx, *_ in indexes.values():
         idx.close()
-    best = min(results, key=lambda r: r["ms"])
-    best = dict(best, candidates=len(results))
+    res = dict(best, num_bins=m, ms=best_ms, trials=len(timed))
     if cache:
         data = _load_cache(cache)
-        data[key] = best
+        data[key] = res
         os.makedirs(os.path.dirname(cache), exist_ok=True)
         with open(cache, "w") as f:
             json.dump(data, f, indent=1)
-    return best
+    return dict(res, cached=False)

@@ -71,9 +71,10 @@ __device__ __forceinline__ uint32_t parts_max(const uint32_t* c, uint32_t b, uin
 
 // Candidates held per lane by the FP32 form: a wave works on tiles of
 // kCpl * 64 candidates, so each query record fetched by a scalar load feeds
-// kCpl * 64 pair tests.
-constexpr int kCpl = 4;
-constexpr uint32_t kTile = kCpl * kWave;
+// kCpl * 64 pair tests.  kCpl is a launch choice (2 or 4, the autotuner's tile
+// size); chunks are rounded to whole tiles of the larger one.
+constexpr int kCplMax = 4;
+constexpr uint32_t kTile = kCplMax * kWave;
 
 // FP64 entry records are read through the constant address space with a
 // wave-uniform index, so the compiler fetches them with scalar loads into
@@ -708,6 +709,7 @@ struct DistArgs {
     uint32_t stage_cap;     // records per wave (a multiple of 64)
     uint32_t by_order;      // 1: a single-request item run whose results go to
                             // their order in the item (minus win_lo), no stage
+    uint32_t cpl;           // FP32 form: candidates per lane per tile (2 or 4)
 };
 
 // Results go through a stage of stage_cap records per wave in device memory
@@ -1042,9 +1044,10 @@ __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemSta
 // candidate of the bucket overlaps every query of the group in time, the
 // per-pair time test is skipped: exact, since the outward-rounded FP32 times
 // then overlap as well.
-template <bool kUniform>
+template <bool kUniform, int kCpl>
 __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
                                                 const BucketInfo& bi) {
+    constexpr uint32_t kStep = kCpl * kWave;  // candidates per tile
     const uint32_t lane = __lane_id();
     const bool has = lane < S.nq;
     QReg q = {0.f, 0.f, 0.f, 0.f, -INFINITY, INFINITY, 0u, 0u};
@@ -1068,7 +1071,7 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
     const uint32_t last_blk = (S.c1 - 1) >> kBoxShift;
     uint32_t wb = 0xFFFFFFFFu;  // first block of the box window held in the lanes
     float wbox[7];
-    for (uint32_t tile = S.c0 & ~(uint32_t)(kWave - 1); tile < S.c1; tile += kTile) {
+    for (uint32_t tile = S.c0 & ~(uint32_t)(kWave - 1); tile < S.c1; tile += kStep) {
         uint32_t cand[kCpl];
         float ecx[kCpl], ecy[kCpl], ecz[kCpl], er[kCpl], ets[kCpl], ete[kCpl];
         bool valid[kCpl];
@@ -1153,7 +1156,7 @@ __device__ __forceinline__ void scan_chunk_fp64(WaveLDS& L, const DistArgs& A, I
     }
 }
 
-template <int kPrec>
+template <int kPrec, int kCplT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_distance(DistArgs A) {
     __shared__ WaveLDS wl[kWavesPerBlock];
     WaveLDS& L = wl[threadIdx.x / kWave];
@@ -1248,8 +1251,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const bool all_cover = ballot(cover) == ~0ull;
         item_begin(L, A, S);
         if (kPrec == TDS_PREC_FP32_RECHECK) {
-            if (all_cover) scan_chunk_fp32<true>(L, A, S, bi);
-            else scan_chunk_fp32<false>(L, A, S, bi);
+            if (all_cover) scan_chunk_fp32<true, kCplT>(L, A, S, bi);
+            else scan_chunk_fp32<false, kCplT>(L, A, S, bi);
         } else {
             if (all_cover) scan_chunk_fp64<true>(L, A, S);
             else scan_chunk_fp64<false>(L, A, S);
@@ -1500,6 +1503,12 @@ uint32_t stage_per_wave(size_t recs, uint32_t blocks) {
     return (uint32_t)std::min<size_t>(kStageMax, per / kWave * kWave);
 }
 
+// FP32 form's candidates per lane per tile: 0 selects 4; 2 and 4 are built.
+uint32_t resolve_tile(uint32_t t) {
+    if (t == 0) return 4;
+    return (t == 2 || t == 4) ? t : 0;
+}
+
 int resolve_prec(int p) {
     if (p == TDS_PREC_DEFAULT) return TDS_PREC_FP32_RECHECK;
     if (p != TDS_PREC_FP64 && p != TDS_PREC_FP32_RECHECK) return -1;
@@ -1534,8 +1543,9 @@ int stage_queries(const tds_segments* Q, QueryView* V, hipStream_t s, double** s
 
 DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q, tds_result* out,
                    uint64_t win_lo, uint32_t item_begin, uint32_t item_end, uint32_t* item_count,
-                   uint32_t grid_waves, bool by_order) {
+                   uint32_t grid_waves, bool by_order, uint32_t cpl) {
     DistArgs A;
+    A.cpl = cpl;
     A.dyn_ctr = w->dyn_ctr;
     A.stage = w->stage;
     A.stage_meta = w->stage_meta;
@@ -1568,8 +1578,9 @@ int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_
     const uint32_t blocks = launch_blocks(grid_waves);
     // every wave must be able to stage a full batch of 64 evaluations
     if (!A.stage || A.stage_cap < (uint32_t)kWave) return TDS_E_DEVICE;
-    void (*kern)(DistArgs) = k_distance<TDS_PREC_FP32_RECHECK>;
-    if (prec == TDS_PREC_FP64) kern = k_distance<TDS_PREC_FP64>;
+    void (*kern)(DistArgs) = (A.cpl == 2) ? k_distance<TDS_PREC_FP32_RECHECK, 2>
+                                          : k_distance<TDS_PREC_FP32_RECHECK, 4>;
+    if (prec == TDS_PREC_FP64) kern = k_distance<TDS_PREC_FP64, 4>;
     if (ev_begin && ev_end) {
         // the events take the dispatch's own start and end times (no marker
         // packets around the kernel, so no bubbles before and after it)
@@ -1587,7 +1598,7 @@ int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_
 // queries, bucket table, ordering, item table, distance kernel over every
 // item.  q_grid and r_cap are the capacities the launches are shaped for.
 int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, size_t q_grid,
-                     uint32_t r_cap, int prec, uint32_t chunk, uint32_t grid_waves,
+                     uint32_t r_cap, int prec, uint32_t chunk, uint32_t grid_waves, uint32_t cpl,
                      tds_result* out, uint32_t* item_count, hipStream_t s, hipEvent_t ev_begin,
                      hipEvent_t ev_end) {
     const IndexView I = view_of(idx);
@@ -1611,7 +1622,7 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
     TDS_HIP(hipGetLastError());
     return launch_distance(prec,
                            dist_args(idx, w, Q, out, 0, 0, 0xFFFFFFFFu, item_count, grid_waves,
-                                     false),
+                                     false, cpl),
                            grid_waves, s, ev_begin, ev_end);
 }
 
@@ -1621,12 +1632,14 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
 // order in the item (a window of an item larger than the device buffer).
 int enqueue_range(const tds_index* idx, Workspace* w, const QueryView& Q, int prec, uint32_t r_cap,
                   tds_result* out, uint64_t win_lo, uint32_t i0, uint32_t i1, bool by_order,
-                  uint32_t grid_waves, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end) {
+                  uint32_t grid_waves, uint32_t cpl, hipStream_t s, hipEvent_t ev_begin,
+                  hipEvent_t ev_end) {
     hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, kXcds * kCtrStride), 256)),
                        dim3(256), 0, s, w->req_ctr, r_cap, w->dyn_ctr);
     TDS_HIP(hipGetLastError());
     return launch_distance(prec,
-                           dist_args(idx, w, Q, out, win_lo, i0, i1, nullptr, grid_waves, by_order),
+                           dist_args(idx, w, Q, out, win_lo, i0, i1, nullptr, grid_waves, by_order,
+                                     cpl),
                            grid_waves, s, ev_begin, ev_end);
 }
 
@@ -1682,7 +1695,7 @@ int reserve_items(const tds_index* idx, Workspace* w, uint64_t nq, uint32_t chun
 // w->req_host (sent to the device here, with the descriptor), growing the
 // item table and re-running if the bound was too small.
 int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t nreq, int prec,
-              uint32_t chunk, uint32_t grid_waves, tds_result* out, hipStream_t s,
+              uint32_t chunk, uint32_t grid_waves, uint32_t cpl, tds_result* out, hipStream_t s,
               tds_stats* st, SearchHeader* h_out) {
     uint64_t cap = 0;
     TDS_TRY(reserve_items(idx, w, V.n, chunk, &cap));
@@ -1692,8 +1705,8 @@ int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t n
         w->desc_host->nreq = nreq;
         w->desc_host->item_cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
         TDS_TRY(ws_upload(w, nreq, s));  // the descriptor and the requests staged by the caller
-        TDS_TRY(enqueue_pipeline(idx, w, V, V.n, nreq, prec, chunk, grid_waves, out, w->item_count, s,
-                                 w->ev0, w->ev1));
+        TDS_TRY(enqueue_pipeline(idx, w, V, V.n, nreq, prec, chunk, grid_waves, cpl, out,
+                                 w->item_count, s, w->ev0, w->ev1));
         TDS_TRY(ws_download(w, nreq, s));
         TDS_HIP(hipStreamSynchronize(s));
         *h_out = *w->hdr_host;
@@ -1721,6 +1734,8 @@ int resolve_config(const tds_search_params* params, PipelineConfig* cfg) {
     if (cfg->prec < 0) return TDS_E_INVALID;
     cfg->chunk = resolve_chunk(cfg->prec, P.chunk);
     cfg->grid_waves = resolve_grid(P.grid_waves);
+    cfg->cpl = resolve_tile(P.tile);
+    if (!cfg->cpl) return TDS_E_INVALID;
     return TDS_OK;
 }
 
@@ -1735,8 +1750,8 @@ int enqueue_search(const tds_index* idx, Workspace* w, const double* const* qarr
     for (int k = 0; k < 8; ++k) V.a[k] = qarrays[k];
     V.traj = qtraj;
     V.n = q_grid;
-    return enqueue_pipeline(idx, w, V, q_grid, r_cap, cfg.prec, cfg.chunk, cfg.grid_waves, out,
-                            w->item_count, s, nullptr, nullptr);
+    return enqueue_pipeline(idx, w, V, q_grid, r_cap, cfg.prec, cfg.chunk, cfg.grid_waves,
+                            cfg.cpl, out, w->item_count, s, nullptr, nullptr);
 }
 
 int schedule_impl(tds_index* idx, const tds_segments* Q, double t_start, double t_end,
@@ -1817,6 +1832,8 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
     if (prec < 0) return TDS_E_INVALID;
     const uint32_t chunk = resolve_chunk(prec, P.chunk);
     const uint32_t grid_waves = resolve_grid(P.grid_waves);
+    const uint32_t cpl = resolve_tile(P.tile);
+    if (!cpl) return TDS_E_INVALID;
     const bool dev_out = P.out_on_device != 0;
 
     Workspace* w = acquire(idx);
@@ -1861,7 +1878,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
     st.query_segments = nq;
     SearchHeader h{};
     // pass 1: every item, result window [0, dev_cap)
-    TDS_TRY(run_batch(idx, w, V, 1, prec, chunk, grid_waves, res, s, &st, &h));
+    TDS_TRY(run_batch(idx, w, V, 1, prec, chunk, grid_waves, cpl, res, s, &st, &h));
     const ReqCounter rc = w->rc_host[0];
     const uint32_t n_items = h.n_items;
     st.active_segments = h.active;
@@ -1913,7 +1930,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
             for (auto& win : windows) {
                 if (win.second == 0) continue;
                 TDS_TRY(enqueue_range(idx, w, V, prec, 1, res, win.first, i0, i1, by_order,
-                                      std::min(grid_waves, i1 - i0), s, w->ev0, w->ev1));
+                                      std::min(grid_waves, i1 - i0), cpl, s, w->ev0, w->ev1));
                 TDS_HIP(hipMemcpyAsync(out + written, res, win.second * sizeof(tds_result),
                                        hipMemcpyDeviceToHost, s));
                 TDS_HIP(hipStreamSynchronize(s));
@@ -1967,6 +1984,8 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
     if (prec < 0) return TDS_E_INVALID;
     const uint32_t chunk = resolve_chunk(prec, P.chunk);
     const uint32_t grid_waves = resolve_grid(P.grid_waves);
+    const uint32_t cpl = resolve_tile(P.tile);
+    if (!cpl) return TDS_E_INVALID;
     const bool dev_out = P.out_on_device != 0;
 
     Workspace* w = acquire(idx);
@@ -1994,7 +2013,7 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
     tds_stats st{};
     st.query_segments = Q->n;
     SearchHeader h{};
-    TDS_TRY(run_batch(idx, w, V, nreq, prec, chunk, grid_waves, res, s, &st, &h));
+    TDS_TRY(run_batch(idx, w, V, nreq, prec, chunk, grid_waves, cpl, res, s, &st, &h));
     const ReqCounter* rc = w->rc_host;
     int status = TDS_OK;
     uint64_t total = 0;

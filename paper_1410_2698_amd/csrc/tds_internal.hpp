@@ -359,6 +359,7 @@ struct PipelineConfig {
     int prec;
     uint32_t chunk;
     uint32_t grid_waves;
+    uint32_t cpl;  // FP32 form: candidates per lane per tile
 };
 int resolve_config(const tds_search_params* params, PipelineConfig* cfg);
 uint64_t item_table_bound(const tds_index* idx, uint64_t nq, uint32_t chunk);
