@@ -137,10 +137,16 @@ def load_profile(workload, kind):
     return rec if rec.get("kernel_sources_sha256_16") == h else None
 
 
+# Launch parameters the profiles are taken with (the autotuner's choice for
+# the workload on MI355X; the bench's own tuning picks them again).
+PROFILE_PARAMS = {"galaxy": "num_bins=38,chunk=1024,grid_waves=8192,tile=4,precision=fp32",
+                  "uniform1m": "num_bins=400,chunk=4096,grid_waves=4096,tile=4,precision=fp32"}
+
+
 def profile_command(workload, counters):
     return (f"rocprofv3 --pmc {counters} --output-format csv -d gpurun_out/pmc -o p -- "
             f"python3 bench.py --legs {workload} --steps 2 --warmup 1 --no-cpu --no-fp64-form "
-            f"--calib-copy-mb 256")
+            f"--calib-copy-mb 256 --fixed {PROFILE_PARAMS[workload]}")
 
 
 def summarize_valu(workload, csv_path):
@@ -331,7 +337,7 @@ class SearchLeg:
         import torch
         self.tds, self.w = tds, w
         self.tuned = tuned or {"num_bins": 0, "chunk": 0, "grid_waves": 0, "tile": 0,
-                               "precision": "fp32"}
+                               "refine": "default", "precision": "fp32"}
         self.idx = tds.Index(w.D, num_bins=self.tuned["num_bins"])
         Qt = device_segments(w.Q)
         nq = len(w.Q)
@@ -351,7 +357,7 @@ class SearchLeg:
                                          precision=precision or self.precision,
                                          chunk=self.tuned["chunk"],
                                          grid_waves=self.tuned["grid_waves"],
-                                         tile=self.tuned["tile"])
+                                         tile=self.tuned["tile"], refine=self.tuned["refine"])
 
     def step(self):
         st, got, s = self.run(self.reqs, self.out.data_ptr(), len(self.w.ds) * self.cap)
@@ -508,53 +514,83 @@ def fsg_leg(tds, idx, Qt, counts, ds, t0, t1, grids=(20, 50, 100), reps=3):
 
 def open_loop(tds, idx, reqs):
     """Submits reqs at their arrival times from a thread while the main thread
-    collects them; returns (latencies in ms, records, elapsed s, server stats)."""
+    collects them.  Returns (latency from submission in ms, latency from the
+    scheduled arrival in ms, records, elapsed s, server stats): when the
+    submitting thread falls behind the arrivals, the second shows it."""
     srv = tds.Server(idx, max_batch_segments=1 << 17, max_batch_requests=2048, slots=2,
                      result_capacity=1 << 21, default_reserve=512)
     for r in reqs[:200]:  # warm-up, not timed
         srv.wait(srv.submit(r.Q, r.d, r.t_start, r.t_end))
     reqs = reqs[200:]
+    handles = [tds.prepare_segments(r.Q) for r in reqs]  # marshalled before the run
     base = reqs[0].arrival
     tickets = [None] * len(reqs)
+    late = [0.0] * len(reqs)
     t_start = time.perf_counter()
 
     def submitter():
         for i, r in enumerate(reqs):
-            dt = (r.arrival - base) - (time.perf_counter() - t_start)
+            due = r.arrival - base
+            dt = due - (time.perf_counter() - t_start)
             if dt > 0:
                 time.sleep(dt)
-            tickets[i] = srv.submit(r.Q, r.d, r.t_start, r.t_end)
+            late[i] = max(0.0, time.perf_counter() - t_start - due)
+            tickets[i] = srv.submit(handles[i], r.d, r.t_start, r.t_end)
 
     th = threading.Thread(target=submitter)
     th.start()
-    lat, n_rec = [], 0
+    lat, lat_arr, n_rec = [], [], 0
     for i in range(len(reqs)):
         while tickets[i] is None:
             time.sleep(0.0002)
         recs, ms = srv.wait(tickets[i])
         lat.append(ms)
+        lat_arr.append(ms + 1e3 * late[i])
         n_rec += recs.size
     th.join()
     elapsed = time.perf_counter() - t_start
     st = srv.stats()
     srv.close()
-    return lat, n_rec, elapsed, st
+    return lat, lat_arr, n_rec, elapsed, st
+
+
+def flood(tds, idx, reqs):
+    """Every request submitted at once (marshalled beforehand): the server's
+    throughput when it always has work queued, and the latencies then."""
+    srv = tds.Server(idx, max_batch_segments=1 << 17, max_batch_requests=2048, slots=2,
+                     result_capacity=1 << 21, default_reserve=512, max_pending=len(reqs) + 1)
+    for r in reqs[:200]:
+        srv.wait(srv.submit(r.Q, r.d, r.t_start, r.t_end))
+    reqs = reqs[200:]
+    handles = [tds.prepare_segments(r.Q) for r in reqs]
+    t0 = time.perf_counter()
+    tickets = [srv.submit(h, r.d, r.t_start, r.t_end) for h, r in zip(handles, reqs)]
+    t_sub = time.perf_counter() - t0
+    lat = [srv.wait(t)[1] for t in tickets]
+    elapsed = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return {"requests": len(reqs), "requests_per_s": round(len(reqs) / elapsed, 1),
+            "submit_s": round(t_sub, 4), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "batches": st["batches"], "max_batch_requests": st["max_batch_requests_seen"]}
 
 
 def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0, 80000.0, 160000.0,
                                               320000.0)):
     """The request stream through tds_server: an open-loop run at `rate` for
     `seconds`, the plain FP64 form (one request per call) on its first 5,000
-    requests, and shorter open-loop runs at rising offered rates until the
-    achieved rate falls below the offered one (saturation)."""
+    requests, open-loop runs at rising offered rates until the achieved rate
+    falls below the offered one, and a flood of 20,000 requests submitted at
+    once (the server's saturation throughput)."""
     import trajgen
     n_req = int(seconds * rate)
     reqs = trajgen.request_stream(n_req + 200, rate=rate)
-    lat, n_rec, elapsed, st = open_loop(tds, idx, reqs)
+    lat, lat_arr, n_rec, elapsed, st = open_loop(tds, idx, reqs)
     served = {"offered_rate": rate, "requests": len(lat),
               "requests_per_s": round(len(lat) / elapsed, 1),
-              "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "records": n_rec,
-              "batches": st["batches"], "requeued": st["requeued"],
+              "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+              "p50_from_arrival_ms": pct(lat_arr, 50), "p99_from_arrival_ms": pct(lat_arr, 99),
+              "records": n_rec, "batches": st["batches"], "requeued": st["requeued"],
               "max_batch_requests": st["max_batch_requests_seen"]}
     plain = []
     for r in reqs[200:5200]:
@@ -564,16 +600,20 @@ def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0, 80000.0
     rows = []
     for rt in sweep:
         sreqs = trajgen.request_stream(10200, rate=rt)
-        slat, _, sel, sst = open_loop(tds, idx, sreqs)
+        slat, sarr, _, sel, sst = open_loop(tds, idx, sreqs)
         rows.append({"offered_rate": rt, "requests_per_s": round(len(slat) / sel, 1),
                      "p50_ms": pct(slat, 50), "p99_ms": pct(slat, 99),
+                     "p50_from_arrival_ms": pct(sarr, 50), "p99_from_arrival_ms": pct(sarr, 99),
                      "batches": sst["batches"]})
         if len(slat) / sel < 0.9 * rt:
             break
+    fl = flood(tds, idx, trajgen.request_stream(20200, rate=1e9, seed=91))
     return {
         "served_fp32": served,
         "served_rate_sweep": rows,
-        "saturation_requests_per_s": max(r["requests_per_s"] for r in rows),
+        "served_flood": fl,
+        "saturation_requests_per_s": max([r["requests_per_s"] for r in rows] +
+                                         [fl["requests_per_s"]]),
         "plain_fp64": {"requests": len(plain),
                        "requests_per_s": round(len(plain) / (sum(plain) * 1e-3), 1),
                        "p50_ms": pct(plain, 50), "p99_ms": pct(plain, 99),
@@ -601,6 +641,9 @@ def main():
                     help="write the instruction-counter summary from a counter CSV and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="library defaults instead of the autotuner's choice for each search leg")
+    ap.add_argument("--fixed", default="",
+                    help="launch parameters for every search leg instead of tuning, e.g. "
+                         "num_bins=38,chunk=1024,grid_waves=8192,tile=4,precision=fp32")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the open-loop serving run at 5,000 requests/s")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -647,10 +690,17 @@ def main():
             continue
         w = getattr(trajgen, name)()
         tuned = None
-        if not args.no_tune and name in legs:
+        if args.fixed:
+            tuned = {"num_bins": 0, "chunk": 0, "grid_waves": 0, "tile": 0, "refine": "default",
+                     "precision": "fp32"}
+            for kv in args.fixed.split(","):
+                k, v = kv.split("=")
+                tuned[k] = v if k in ("precision", "refine") else int(v)
+        elif not args.no_tune and name in legs:
             tb = time.perf_counter()
             best = autotune.tune(w.D, w.Q, w.ds, w.window, cache=None)
-            tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves", "tile", "precision")}
+            tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves", "tile", "refine",
+                                          "precision")}
             tuned["trials"] = best["trials"]
             tuned["tuning_s"] = round(time.perf_counter() - tb, 2)
         leg = SearchLeg(tds, w, tuned)

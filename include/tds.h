@@ -105,6 +105,20 @@ enum {
     TDS_LAYOUT_SPATIAL = 2
 };
 
+/* Place of the FP32 form's closest-approach refinement: a pair that passes
+   the bounding-sphere test is dropped when FP32 lower bounds on the smallest
+   distance of the two moving points exceed d by more than the rounding of
+   the FP32 data and arithmetic; the rest are decided in FP64. */
+enum {
+    TDS_REFINE_DEFAULT = 0, /* currently TDS_REFINE_QUEUED */
+    /* A stage of the pair queue, 64 pairs at a time (least register pressure
+       in the filter; best where few pairs pass the sphere test). */
+    TDS_REFINE_QUEUED = 1,
+    /* In the filter's walk over the queries of a block, from the candidate's
+       data in registers (best where most pairs pass the sphere test). */
+    TDS_REFINE_INLINE = 2
+};
+
 /* Index parameters; a NULL pointer or 0 fields select defaults. */
 typedef struct tds_build_params {
     /* Number m of temporal bins (Sec. 4.2.1).  0 = auto: the full temporal
@@ -140,7 +154,9 @@ typedef struct tds_search_params {
     /* FP32 form: candidates each lane holds per tile of the distance kernel
        (the tile is 64 x this); 2 or 4, 0 = 4. */
     uint32_t tile;
-    uint32_t reserved32;
+    /* FP32 form: where the closest-approach refinement of the filter runs
+       (TDS_REFINE_*).  Both places drop the same pairs. */
+    uint32_t refine;
     uint64_t reserved[3];
 } tds_search_params;
 

@@ -52,7 +52,15 @@ class _SegHandle:
         self.keep = keep
 
 
+def prepare_segments(S) -> _SegHandle:
+    """The C view of a segment set, built once (for callers that submit the
+    same queries many times or want the marshalling out of a timed loop)."""
+    return _segments(S)
+
+
 def _segments(S) -> _SegHandle:
+    if isinstance(S, _SegHandle):
+        return S
     """Marshal a segment set: an object or dict with xs..te (+ traj), either
     NumPy arrays (host memory) or torch CUDA tensors (device memory)."""
     get = (lambda k: S[k]) if isinstance(S, dict) else (lambda k: getattr(S, k))
@@ -160,10 +168,10 @@ class Index:
 
     def search_raw(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                    out_ptr: int, capacity: int, out_on_device: bool, precision: str = "fp32",
-                   chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0, tile: int = 0):
+                   chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0, tile: int = 0, refine: str = "default"):
         """One call of tds_search into caller memory; returns (status, n_total, stats)."""
         h = _segments(Q)
-        p = _search_params(precision, chunk, grid_waves, tile)
+        p = _search_params(precision, chunk, grid_waves, tile, refine)
         p.out_on_device = 1 if out_on_device else 0
         p.device_capacity = int(device_capacity)
         n = ctypes.c_uint64()
@@ -178,11 +186,11 @@ class Index:
     def search_noalloc_raw(self, Q, d: float, t_start: float = -math.inf,
                            t_end: float = math.inf, *, out_ptr: int, capacity: int,
                            precision: str = "fp32", chunk: int = 0, grid_waves: int = 0,
-                           tile: int = 0):
+                           tile: int = 0, refine: str = "default"):
         """One call of tds_search_noalloc (Q and out in device memory); returns
         (status, n_total, stats)."""
         h = _segments(Q)
-        p = _search_params(precision, chunk, grid_waves, tile)
+        p = _search_params(precision, chunk, grid_waves, tile, refine)
         p.out_on_device = 1
         n = ctypes.c_uint64()
         st = _lib.tds_stats()
@@ -195,7 +203,7 @@ class Index:
 
     def search(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                capacity: Optional[int] = None, precision: str = "fp32", chunk: int = 0,
-               grid_waves: int = 0, device_capacity: int = 0, tile: int = 0) -> np.ndarray:
+               grid_waves: int = 0, device_capacity: int = 0, tile: int = 0, refine: str = "default") -> np.ndarray:
         """Search into host memory; grows the buffer and retries on overflow.
         Returns the records (unspecified order) as a NumPy structured array."""
         cap = 1 << 16 if capacity is None else int(capacity)
@@ -204,7 +212,8 @@ class Index:
             status, n, _ = self.search_raw(Q, d, t_start, t_end, out_ptr=buf.ctypes.data,
                                            capacity=cap, out_on_device=False, precision=precision,
                                            chunk=chunk, grid_waves=grid_waves,
-                                           device_capacity=device_capacity, tile=tile)
+                                           device_capacity=device_capacity, tile=tile,
+                                           refine=refine)
             if status == TDS_OK:
                 return buf[:n].copy()
             if status == TDS_E_OVERFLOW and capacity is None:
@@ -216,9 +225,9 @@ class Index:
     def self_join_raw(self, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                       out_ptr: int, capacity: int, out_on_device: bool, precision: str = "fp32",
                       chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0,
-                      tile: int = 0):
+                      tile: int = 0, refine: str = "default"):
         """One call of tds_self_join into caller memory; returns (status, n_total, stats)."""
-        p = _search_params(precision, chunk, grid_waves, tile)
+        p = _search_params(precision, chunk, grid_waves, tile, refine)
         p.out_on_device = 1 if out_on_device else 0
         p.device_capacity = int(device_capacity)
         n = ctypes.c_uint64()
@@ -251,7 +260,7 @@ class Index:
 
     def search_batch_raw(self, Q, requests, *, out_ptr: int, out_capacity: int,
                          out_on_device: bool, precision: str = "fp32", chunk: int = 0,
-                         grid_waves: int = 0, tile: int = 0):
+                         grid_waves: int = 0, tile: int = 0, refine: str = "default"):
         """One call of tds_search_batch into caller memory.  ``requests`` holds
         (q_begin, q_count, d, t_start, t_end, out_offset, out_capacity) tuples
         that tile Q in order.  Returns (status, counts, stats)."""
@@ -261,7 +270,7 @@ class Index:
             r.q_begin, r.q_count, r.d, r.t_start, r.t_end = int(qb), int(qc), float(d), float(t0), float(t1)
             r.out_offset, r.out_capacity = int(oo), int(oc)
         counts = (ctypes.c_uint64 * len(requests))()
-        p = _search_params(precision, chunk, grid_waves, tile)
+        p = _search_params(precision, chunk, grid_waves, tile, refine)
         p.out_on_device = 1 if out_on_device else 0
         st = _lib.tds_stats()
         status = self._lib.tds_search_batch(self._h, ctypes.byref(h.struct), reqs, len(requests),
@@ -351,7 +360,10 @@ class FSG:
             raise TdsError(status, "tds_fsg_search")
 
 
-def _search_params(precision="fp32", chunk=0, grid_waves=0, tile=0):
+REFINES = {"default": 0, "queued": 1, "inline": 2}
+
+
+def _search_params(precision="fp32", chunk=0, grid_waves=0, tile=0, refine="default"):
     lib = load()
     p = _lib.tds_search_params()
     lib.tds_search_params_default(ctypes.byref(p))
@@ -359,6 +371,7 @@ def _search_params(precision="fp32", chunk=0, grid_waves=0, tile=0):
     p.chunk = int(chunk)
     p.grid_waves = int(grid_waves)
     p.tile = int(tile)
+    p.refine = REFINES[refine]
     return p
 
 
@@ -448,7 +461,7 @@ class Server:
     def __init__(self, index: Index, *, max_batch_segments: int = 0, max_batch_requests: int = 0,
                  slots: int = 0, result_capacity: int = 0, default_reserve: int = 0,
                  max_pending: int = 0, precision: str = "fp32", chunk: int = 0, grid_waves: int = 0,
-                 tile: int = 0):
+                 tile: int = 0, refine: str = "default"):
         self._lib = load()
         self.index = index
         p = _lib.tds_server_params()
@@ -458,7 +471,7 @@ class Server:
         p.result_capacity = result_capacity
         p.default_reserve = default_reserve
         p.max_pending = max_pending
-        p.search = _search_params(precision, chunk, grid_waves, tile)
+        p.search = _search_params(precision, chunk, grid_waves, tile, refine)
         out = ctypes.c_void_p()
         check(self._lib.tds_server_create(index.handle, ctypes.byref(p), ctypes.byref(out)),
               "tds_server_create")

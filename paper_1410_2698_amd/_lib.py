@@ -36,7 +36,7 @@ class tds_search_params(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("out_on_device", ctypes.c_int32),
                 ("chunk", ctypes.c_uint32), ("grid_waves", ctypes.c_uint32),
                 ("device_capacity", ctypes.c_uint64), ("tile", ctypes.c_uint32),
-                ("reserved32", ctypes.c_uint32), ("reserved", ctypes.c_uint64 * 3)]
+                ("refine", ctypes.c_uint32), ("reserved", ctypes.c_uint64 * 3)]
 
 
 class tds_stats(ctypes.Structure):

@@ -10,6 +10,8 @@ resident) and picks, by coordinate descent from the library defaults:
   its group of 64 query segments;
 * the persistent grid of the distance kernel (waves);
 * the tile: candidates each lane holds per step of the FP32 form (2 or 4);
+* where the FP32 form refines the pairs its sphere test passes: in a stage of
+  the pair queue or inline in the filter walk (the same pairs are dropped);
 * the wavefront mapping: the FP32 form (lanes hold candidates, the group's
   query segments are walked in turn, survivors rechecked in FP64) or the FP64
   form (lanes hold query segments, candidates are streamed to all of them).
@@ -34,6 +36,7 @@ SPACE = {
     "chunk": (4096, 1024, 2048, 8192),
     "grid_waves": (4096, 2048, 8192),
     "tile": (4, 2),
+    "refine": ("queued", "inline"),
     "precision": ("fp32", "fp64"),
 }
 
@@ -57,10 +60,14 @@ def _load_cache(path: str) -> dict:
 
 
 def tune(D, Q, ds: Iterable[float], window, *, space: Optional[dict] = None, reps: int = 3,
-         rounds: int = 2, cache: Optional[str] = CACHE, force: bool = False) -> dict:
-    """Return {"num_bins", "chunk", "grid_waves", "tile", "precision", "ms",
+         min_ms: float = 30.0, rounds: int = 2, cache: Optional[str] = CACHE,
+         force: bool = False) -> dict:
+    """Return {"num_bins", "chunk", "grid_waves", "tile", "refine", "precision", "ms",
     "trials", ...} for the fastest configuration found.  ``space`` maps each
-    knob to its candidate values, the first being the starting point."""
+    knob to its candidate values, the first being the starting point.  Each
+    configuration is timed over at least ``reps`` searches and ``min_ms`` of
+    searching, and scored by its fastest search (host-side noise only ever
+    adds time)."""
     import torch
 
     import paper_1410_2698_amd as tds
@@ -106,23 +113,33 @@ def tune(D, Q, ds: Iterable[float], window, *, space: Optional[dict] = None, rep
             return timed[k]
         idx, m, counts, out, reqs = index_for(c["bins_factor"])
         ts = []
-        for r in range(reps + 1):
+        r = 0
+        while r <= reps or 1e3 * sum(ts) < min_ms:
+            r += 1
             torch.cuda.synchronize()
             ta = time.perf_counter()
             st, got, _ = idx.search_batch_raw(Qb, reqs, out_ptr=out.data_ptr(),
                                               out_capacity=out.numel() // 32, out_on_device=True,
                                               precision=c["precision"], chunk=c["chunk"],
-                                              grid_waves=c["grid_waves"], tile=c["tile"])
+                                              grid_waves=c["grid_waves"], tile=c["tile"],
+                                              refine=c["refine"])
             torch.cuda.synchronize()
             if st != tds.TDS_OK or got != counts:
                 raise RuntimeError(f"autotune: search failed ({st}, {got} vs {counts}) at {c}")
-            if r:
+            if r > 1:  # the first search of a configuration is a warm-up
                 ts.append(time.perf_counter() - ta)
-        timed[k] = 1e3 * float(np.median(ts))
+        timed[k] = 1e3 * float(np.min(ts))
         return timed[k]
 
     best = {k: v[0] for k, v in space.items()}
+    start = dict(best)
+    # warm-up (clocks, code objects of the kernel variants): the starting
+    # point runs for a while before anything is timed
+    index_for(best["bins_factor"])
+    measure(best)
+    timed.clear()
     best_ms = measure(best)
+    trials = 1
     for _ in range(rounds):
         changed = False
         for knob, values in space.items():
@@ -131,14 +148,20 @@ def tune(D, Q, ds: Iterable[float], window, *, space: Optional[dict] = None, rep
                     continue
                 c = dict(best, **{knob: v})
                 ms = measure(c)
+                trials += 1
                 if ms < best_ms:
                     best, best_ms, changed = c, ms, True
         if not changed:
             break
+    if best != start:
+        # the starting point and the winner timed again, side by side
+        timed.clear()
+        a_ms, b_ms = measure(start), measure(best)
+        best, best_ms = (best, b_ms) if b_ms < a_ms else (start, a_ms)
     m = index_for(best["bins_factor"])[1]
     for idx, *_ in indexes.values():
         idx.close()
-    res = dict(best, num_bins=m, ms=best_ms, trials=len(timed))
+    res = dict(best, num_bins=m, ms=best_ms, trials=trials)
     if cache:
         data = _load_cache(cache)
         data[key] = res

@@ -144,13 +144,21 @@ __global__ __launch_bounds__(kBT) void k_gather(uint64_t n, const uint32_t* __re
                                                 const uint32_t* __restrict__ traj_in,
                                                 EntryF64* __restrict__ e64,
                                                 EntryF32* __restrict__ e32,
+                                                EntryV32* __restrict__ ev32,
                                                 uint32_t* __restrict__ seg_id,
                                                 uint32_t* __restrict__ traj) {
     const uint64_t i = (uint64_t)blockIdx.x * kBT + threadIdx.x;
     if (i >= n) return;
     const uint32_t src = perm[i];
-    e64[i] = tmp64[src];
+    const EntryF64 e = tmp64[src];
+    e64[i] = e;
     e32[i] = tmp32[src];
+    EntryV32 v;
+    v.vx = __double2float_rn(e.vx);
+    v.vy = __double2float_rn(e.vy);
+    v.vz = __double2float_rn(e.vz);
+    v.tm = __double2float_rn(0.5 * (e.ts + e.te));
+    ev32[i] = v;
     seg_id[i] = src;
     traj[i] = traj_in ? traj_in[src] : 0u;
 }
@@ -294,6 +302,7 @@ void destroy_index(tds_index* idx) {
     idx->pool.clear();
     dfree(idx->e64);
     dfree(idx->e32);
+    dfree(idx->ev32);
     dfree(idx->seg_id);
     dfree(idx->traj);
     dfree(idx->bin_first);
@@ -438,6 +447,7 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
     do {
         if ((st = dmalloc(&idx->e64, n))) break;
         if ((st = dmalloc(&idx->e32, n))) break;
+        if ((st = dmalloc(&idx->ev32, n))) break;
         if ((st = dmalloc(&idx->seg_id, n))) break;
         if ((st = dmalloc(&idx->traj, n))) break;
         if ((st = dmalloc(&idx->bin_first, (size_t)m + 1))) break;
@@ -453,10 +463,11 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
         destroy_index(idx);
         return st;
     }
-    idx->device_bytes = n * (sizeof(EntryF64) + sizeof(EntryF32) + 8) + (size_t)m * 52 + 4 +
+    idx->device_bytes = n * (sizeof(EntryF64) + sizeof(EntryF32) + sizeof(EntryV32) + 8) +
+                        (size_t)m * 52 + 4 +
                         (idx->bbox ? (size_t)nblk * sizeof(BlockBox) : 0);
     hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kBT), 0, stream, n, vals, tmp64, tmp32, S.traj,
-                       idx->e64, idx->e32, idx->seg_id, idx->traj);
+                       idx->e64, idx->e32, idx->ev32, idx->seg_id, idx->traj);
     hipLaunchKernelGGL(k_bin_first, dim3(nb), dim3(kBT), 0, stream, n, idx->e64, tmin, bw, m,
                        idx->bin_first);
     hipLaunchKernelGGL(k_bin_stats, dim3(m), dim3(kBT), 0, stream, idx->e64, idx->bin_first,

@@ -90,6 +90,7 @@ struct IndexView {
     const uint32_t* bin_first;
     const double* cmax_te;
     const double* lo_ts;
+    const EntryV32* ev32;  // FP32 motion of the entries (filter refinement)
     const BlockBox* bbox;  // block boxes (spatial layout) or nullptr
     double t_min, bw;      // bin origin and width (search starting points)
     uint32_t n, m;
@@ -116,6 +117,7 @@ IndexView view_of(const tds_index* idx) {
     v.bin_first = idx->bin_first;
     v.cmax_te = idx->cmax_te;
     v.lo_ts = idx->lo_ts;
+    v.ev32 = idx->ev32;
     v.bbox = idx->bbox;
     v.t_min = idx->t_min;
     v.bw = idx->bw;
@@ -710,6 +712,7 @@ struct DistArgs {
     uint32_t by_order;      // 1: a single-request item run whose results go to
                             // their order in the item (minus win_lo), no stage
     uint32_t cpl;           // FP32 form: candidates per lane per tile (2 or 4)
+    uint32_t inline_refine; // FP32 form: refinement in the filter walk, not the queue
 };
 
 // Results go through a stage of stage_cap records per wave in device memory
@@ -726,6 +729,7 @@ struct DistArgs {
 // among the item's results, which a wave computes the same way on every run.
 struct WaveLDS {
     uint32_t queue[2 * kWave];  // < 64 left over + one pair per lane
+    uint32_t rq[2 * kWave];     // FP32 form: refined pairs awaiting the FP64 evaluation
     QF32 qrec[kWave];           // filter records of the item's query group
     QCanon qc[kWave];           // canonical FP64 data of the group's queries
     uint32_t qr[kWave];         // group lane j -> request
@@ -740,6 +744,8 @@ struct WaveLDS {
 struct ItemState {
     uint32_t c0, c1, qbase, nq;
     uint32_t qn, evals;
+    uint32_t rqn;     // pairs in the refined queue (FP32 form)
+    bool refine;      // FP32 form: queued pairs go through the refinement first
     uint32_t found;   // results of the item so far (their order in the item)
     uint32_t nst;     // results in the wave's stage
     uint64_t sbase;   // the wave's stage: records [sbase, sbase + stage_cap)
@@ -780,11 +786,11 @@ __device__ __forceinline__ void stage_flush(WaveLDS& L, const DistArgs& A, ItemS
 
 // Evaluates `cnt` <= 64 queued pairs from position `head` (one per lane) with
 // the canonical FP64 code and stages the results (or, by order, writes them).
-__device__ __forceinline__ void drain(WaveLDS& L, uint32_t head, uint32_t cnt, ItemState& S,
-                                      const DistArgs& A) {
+__device__ __forceinline__ void drain(WaveLDS& L, const uint32_t* queue, uint32_t head,
+                                      uint32_t cnt, ItemState& S, const DistArgs& A) {
     const uint32_t lane = __lane_id();
     const bool act = lane < cnt;
-    const uint32_t pk = act ? L.queue[head + lane] : 0u;
+    const uint32_t pk = act ? queue[head + lane] : 0u;
     const uint32_t ql = pk & (kWave - 1);
     const uint32_t i = S.c0 + (pk >> 6);
     double t_lo = 0.0, t_hi = 0.0;
@@ -862,24 +868,157 @@ __device__ __forceinline__ void enqueue(WaveLDS& L, uint64_t m, bool pass, uint3
     qn += (uint32_t)__popcll(m);
 }
 
-// Evaluates full batches of 64 queued pairs; keeps the remainder queued.
-__device__ __forceinline__ void drain_full(WaveLDS& L, ItemState& S, const DistArgs& A) {
+// Closest-approach refinement of the FP32 filter, for a pair that passed the
+// sphere and time tests: lower bounds, in FP32, on the smallest distance of
+// the two moving points over their common extent.  The pair is dropped only
+// when one of them exceeds d by more than the FP32 data and arithmetic can
+// account for, so every pair the canonical FP64 evaluation accepts is kept.
+//
+// Query: centre cq = its position at tq (mid time of its clipped extent),
+// velocity vq, clipped extent [qa, qb] rounded outwards; entry likewise (cl,
+// vl, tl, [la, lb]).  On the common extent [a, b] (rounded outwards, so it
+// contains the exact one), with tm = (a + b) / 2 and h = (b - a) / 2, the
+// relative position is D(tau) = Dm + W tau for |tau| <= h, Dm = (cq - cl) +
+// (vq (tm - tq) - vl (tm - tl)), W = vq - vl.  Its distance from the origin is
+// at least
+//   (1) |Dm| - h |W|                    (triangle inequality),
+//   (2) |Dm x W| / |W|                  (distance to the line of motion),
+//   (3) min(|Dm - h W|, |Dm + h W|)     when the vertex -Dm.W / |W|^2 lies
+//                                       outside [-h, h] for certain.
+// Error budget (u = 2^-24): rounding of the FP32 data to nearest and the
+// operations forming Dm and W move D(tau) by at most about 10 u S, S = |cq|1 +
+// |cl|1 + (|vq|1 + |vl|1)(|a| + |b| + |tq| + |tl| + 1) (L1 norms; this also
+// covers the FP64 rounding of the canonical evaluation, about 1e-15 S); E =
+// 2^-17 S is used.  The squared forms below are evaluated with errors below
+// 10 u (|Dm|1 + h|W|1)^2 and 20 u |Dm|1^2 |W|1^2, bounded by 2^-17 and 2^-16
+// times those magnitudes.  Every test is "value > bound", so overflow to
+// infinity or NaN never drops a pair.
+__device__ __forceinline__ bool refine32(float cqx, float cqy, float cqz, float vqx, float vqy,
+                                         float vqz, float tq, float qa, float qb, float clx,
+                                         float cly, float clz, float vlx, float vly, float vlz,
+                                         float tl, float la, float lb, float d) {
+    const float a = fmaxf(qa, la), b = fminf(qb, lb);
+    const float tm = 0.5f * (a + b), h = 0.5f * (b - a);
+    const float dq = tm - tq, dl = tm - tl;
+    const float dx = (cqx - clx) + (vqx * dq - vlx * dl);
+    const float dy = (cqy - cly) + (vqy * dq - vly * dl);
+    const float dz = (cqz - clz) + (vqz * dq - vlz * dl);
+    const float wx = vqx - vlx, wy = vqy - vly, wz = vqz - vlz;
+    const float vsum = (fabsf(vqx) + fabsf(vqy) + fabsf(vqz)) + (fabsf(vlx) + fabsf(vly) + fabsf(vlz));
+    const float S = (fabsf(cqx) + fabsf(cqy) + fabsf(cqz)) + (fabsf(clx) + fabsf(cly) + fabsf(clz)) +
+                    vsum * ((fabsf(a) + fabsf(b)) + (fabsf(tq) + fabsf(tl)) + 1.0f);
+    const float R = (d + 0x1p-17f * S) * (1.0f + 0x1p-20f);
+    const float R2 = (R * R) * (1.0f + 0x1p-20f);
+    const float dm1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
+    const float w1 = fabsf(wx) + fabsf(wy) + fabsf(wz);
+    const float Dm2 = (dx * dx + dy * dy) + dz * dz;
+    const float WW = (wx * wx + wy * wy) + wz * wz;
+    const float DW = (dx * wx + dy * wy) + dz * wz;
+    const float span = dm1 + h * w1;
+    const float errA = 0x1p-17f * (span * span);
+    // (1)
+    const float hw = (h * sqrtf(WW)) * (1.0f + 0x1p-18f);
+    const float Rh = R + hw;
+    if (Dm2 - errA > (Rh * Rh) * (1.0f + 0x1p-20f)) return false;
+    // (2), multiplied through by |W|^2
+    const float cross = dm1 * w1;
+    if ((Dm2 * WW - DW * DW) - 0x1p-16f * (cross * cross) > (R2 * WW) * (1.0f + 0x1p-18f))
+        return false;
+    // (3)
+    if (fabsf(DW) > h * WW + 0x1p-17f * (cross + h * (w1 * w1))) {
+        const float ax = dx - h * wx, ay = dy - h * wy, az = dz - h * wz;
+        const float bx = dx + h * wx, by = dy + h * wy, bz = dz + h * wz;
+        const float D0 = (ax * ax + ay * ay) + az * az, D1 = (bx * bx + by * by) + bz * bz;
+        if (fminf(D0, D1) - errA > R2) return false;
+    }
+    return true;
+}
+
+// FP32 form: the closest-approach refinement (refine32) of `cnt` <= 64 queued
+// sphere survivors from position `head`, one per lane; the pairs it keeps go
+// to the refined queue.  A stage of its own, so that its registers are not
+// held across the filter's tile loop and searches with few survivors seldom
+// run it.
+__device__ __forceinline__ void refine_step(WaveLDS& L, uint32_t head, uint32_t cnt,
+                                            ItemState& S, const DistArgs& A) {
     const uint32_t lane = __lane_id();
+    const bool act = lane < cnt;
+    const uint32_t pk = act ? L.queue[head + lane] : 0u;
+    bool keep = false;
+    if (act) {
+        const uint32_t ql = pk & (kWave - 1);
+        const uint32_t i = S.c0 + (pk >> 6);
+        const EntryF32 e = A.I.e32[i];
+        const EntryV32 v = A.I.ev32[i];
+        const QF32 f = L.qrec[ql];
+        keep = true;
+        // an unbounded sphere (stored centre 0) passes unrefined
+        if (e.r < INFINITY && f.R < INFINITY) {
+            const QCanon& q = L.qc[ql];
+            keep = refine32(f.cx, f.cy, f.cz, __double2float_rn(q.vx), __double2float_rn(q.vy),
+                            __double2float_rn(q.vz), __double2float_rn(0.5 * (q.aq + q.bq)), f.a32,
+                            f.b32, e.cx, e.cy, e.cz, v.vx, v.vy, v.vz, v.tm, e.ts, e.te,
+                            __double2float_ru(q.d));
+        }
+    }
+    const uint64_t m = ballot(keep);
+    if (keep) L.rq[S.rqn + (uint32_t)__popcll(m & lanemask_lt())] = pk;
+    S.rqn += (uint32_t)__popcll(m);
+    wave_sync();
+}
+
+// Moves entries [from, n) of a queue to its front.
+__device__ __forceinline__ void queue_shift(uint32_t* queue, uint32_t from, uint32_t n) {
+    const uint32_t lane = __lane_id();
+    const uint32_t rest = n - from;  // < 64
+    wave_sync();
+    uint32_t v = 0;
+    if (lane < rest) v = queue[from + lane];
+    wave_sync();
+    if (lane < rest) queue[lane] = v;
+    wave_sync();
+}
+
+// Evaluates full batches of 64 queued pairs (FP32 form: refined first, then
+// evaluated 64 refined pairs at a time); keeps the remainders queued.
+__device__ __forceinline__ void drain_full(WaveLDS& L, ItemState& S, const DistArgs& A) {
     uint32_t head = 0;
     wave_sync();
     while (S.qn - head >= kWave) {
-        drain(L, head, kWave, S, A);
+        if (S.refine) {
+            refine_step(L, head, kWave, S, A);
+            if (S.rqn >= kWave) {
+                drain(L, L.rq, 0, kWave, S, A);
+                queue_shift(L.rq, kWave, S.rqn);
+                S.rqn -= kWave;
+            }
+        } else {
+            drain(L, L.queue, head, kWave, S, A);
+        }
         head += kWave;
     }
     if (head) {
-        const uint32_t rest = S.qn - head;  // < 64
-        wave_sync();
-        uint32_t v = 0;
-        if (lane < rest) v = L.queue[head + lane];
-        wave_sync();
-        if (lane < rest) L.queue[lane] = v;
-        S.qn = rest;
+        queue_shift(L.queue, head, S.qn);
+        S.qn -= head;
     }
+    wave_sync();
+}
+
+// Evaluates everything still queued (end of a work item).
+__device__ __forceinline__ void drain_rest(WaveLDS& L, ItemState& S, const DistArgs& A) {
+    wave_sync();
+    if (S.qn) {
+        if (S.refine) refine_step(L, 0, S.qn, S, A);
+        else drain(L, L.queue, 0, S.qn, S, A);
+        S.qn = 0;
+    }
+    uint32_t head = 0;
+    while (S.rqn - head > 0) {
+        const uint32_t c = min(S.rqn - head, (uint32_t)kWave);
+        drain(L, L.rq, head, c, S, A);
+        head += c;
+    }
+    S.rqn = 0;
     wave_sync();
 }
 
@@ -992,26 +1131,49 @@ __device__ __forceinline__ uint32_t test_set(const WaveLDS& L, uint64_t mk, uint
     return bits;
 }
 
+
 // Queues the pairs recorded in bits (see test_set) for the candidate of the
-// lane, one pair per lane per round.
+// lane, one pair per lane per round.  With kInline, each pair first goes
+// through the closest-approach refinement here, from the candidate's FP32
+// data in registers (its motion loaded once per call) and the query's in
+// LDS; otherwise the refinement is a stage of the queue (refine_step).
+template <bool kInline>
 __device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                         uint32_t cand, uint32_t bits, uint64_t mk) {
+                                         uint32_t cand, uint32_t bits, uint64_t mk, float ecx,
+                                         float ecy, float ecz, float er, float ets, float ete) {
     const uint32_t lane = __lane_id();
     // ascending list of the queries of mk
     wave_sync();
     if ((mk >> lane) & 1ull) L.sel[__popcll(mk & lanemask_lt())] = (uint8_t)lane;
     wave_sync();
+    EntryV32 ev = {0.f, 0.f, 0.f, 0.f};
+    if (kInline && bits) ev = A.I.ev32[cand];  // lanes with bits hold candidates of the chunk
     const uint32_t code = (cand - S.c0) << 6;
     uint32_t b = bits;
     for (;;) {
         const bool act = b != 0;
-        const uint64_t m = ballot(act);
-        if (!m) break;
+        if (!ballot(act)) break;
+        bool keep = false;
+        uint32_t j = 0;
         if (act) {
-            const uint32_t j = L.sel[__builtin_ctz(b)];
-            L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
+            j = L.sel[__builtin_ctz(b)];
             b &= b - 1u;
+            keep = true;
+            if (kInline) {
+                const QF32& f = L.qrec[j];
+                // an unbounded sphere (stored centre 0) passes unrefined
+                if (er < INFINITY && f.R < INFINITY) {
+                    const QCanon& q = L.qc[j];
+                    keep = refine32(f.cx, f.cy, f.cz, __double2float_rn(q.vx),
+                                    __double2float_rn(q.vy), __double2float_rn(q.vz),
+                                    __double2float_rn(0.5 * (q.aq + q.bq)), f.a32, f.b32, ecx,
+                                    ecy, ecz, ev.vx, ev.vy, ev.vz, ev.tm, ets, ete,
+                                    __double2float_ru(q.d));
+                }
+            }
         }
+        const uint64_t m = ballot(keep);
+        if (keep) L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
         S.qn += (uint32_t)__popcll(m);
         if (S.qn >= kWave) drain_full(L, S, A);
     }
@@ -1020,7 +1182,7 @@ __device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemStat
 // One 64-candidate slot against the queries of mask mk, at most 32 at a time
 // (more than 32 survivors of one block box is rare: then the queries of lanes
 // 0-31 and 32-63 go in turn).
-template <bool kUniform, bool kTime>
+template <bool kUniform, bool kTime, bool kInline>
 __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
                                           uint64_t mk, uint32_t cand, float ecx, float ecy,
                                           float ecz, float er, float ets, float ete) {
@@ -1029,7 +1191,8 @@ __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemSta
         const uint64_t part = (__popcll(mk) > 32) ? (mk & 0xFFFFFFFFull) : mk;
         mk ^= part;
         const uint32_t bits = test_set<kUniform, kTime>(L, part, cand, ecx, ecy, ecz, er, ets, ete);
-        if (ballot(bits != 0u)) push_set(L, A, S, cand, bits, part);
+        if (ballot(bits != 0u))
+            push_set<kInline>(L, A, S, cand, bits, part, ecx, ecy, ecz, er, ets, ete);
     }
 }
 
@@ -1044,7 +1207,7 @@ __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemSta
 // candidate of the bucket overlaps every query of the group in time, the
 // per-pair time test is skipped: exact, since the outward-rounded FP32 times
 // then overlap as well.
-template <bool kUniform, int kCpl>
+template <bool kUniform, int kCpl, bool kInline>
 __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
                                                 const BucketInfo& bi) {
     constexpr uint32_t kStep = kCpl * kWave;  // candidates per tile
@@ -1121,10 +1284,10 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
             S.ftests += (uint64_t)__popcll(mk) * (uint64_t)__popcll(vm);
             // the time test can be dropped only on full slots
             if (all_overlap && vm == ~0ull)
-                slot_fp32<kUniform, false>(L, A, S, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                slot_fp32<kUniform, false, kInline>(L, A, S, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
                                            ets[k], ete[k]);
             else
-                slot_fp32<kUniform, true>(L, A, S, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
+                slot_fp32<kUniform, true, kInline>(L, A, S, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
                                           ets[k], ete[k]);
         }
     }
@@ -1156,7 +1319,7 @@ __device__ __forceinline__ void scan_chunk_fp64(WaveLDS& L, const DistArgs& A, I
     }
 }
 
-template <int kPrec, int kCplT>
+template <int kPrec, int kCplT, bool kInline>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_distance(DistArgs A) {
     __shared__ WaveLDS wl[kWavesPerBlock];
     WaveLDS& L = wl[threadIdx.x / kWave];
@@ -1237,6 +1400,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         S.c1 = uniform((uint32_t)min((uint64_t)bi.hi, base + bi.clen));
         S.qbase = uniform(bi.start + g * kWave);
         S.qn = 0;
+        S.rqn = 0;
+        S.refine = kPrec == TDS_PREC_FP32_RECHECK && !kInline;
         S.evals = 0;
         S.found = 0;
         S.nst = 0;
@@ -1251,18 +1416,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const bool all_cover = ballot(cover) == ~0ull;
         item_begin(L, A, S);
         if (kPrec == TDS_PREC_FP32_RECHECK) {
-            if (all_cover) scan_chunk_fp32<true, kCplT>(L, A, S, bi);
-            else scan_chunk_fp32<false, kCplT>(L, A, S, bi);
+            if (all_cover) scan_chunk_fp32<true, kCplT, kInline>(L, A, S, bi);
+            else scan_chunk_fp32<false, kCplT, kInline>(L, A, S, bi);
         } else {
             if (all_cover) scan_chunk_fp64<true>(L, A, S);
             else scan_chunk_fp64<false>(L, A, S);
         }
-        if (S.qn) {
-            wave_sync();
-            drain(L, 0, S.qn, S, A);
-            S.qn = 0;
-        }
-        wave_sync();
+        drain_rest(L, S, A);
         // the item's results get their positions (the next item's group has
         // other request slots)
         if (S.nst) {
@@ -1503,10 +1663,16 @@ uint32_t stage_per_wave(size_t recs, uint32_t blocks) {
     return (uint32_t)std::min<size_t>(kStageMax, per / kWave * kWave);
 }
 
-// FP32 form's candidates per lane per tile: 0 selects 4; 2 and 4 are built.
-uint32_t resolve_tile(uint32_t t) {
-    if (t == 0) return 4;
-    return (t == 2 || t == 4) ? t : 0;
+// FP32 form's kernel variant: candidates per lane per tile (0 selects 4; 2
+// and 4 are built) in the low byte, the place of the closest-approach
+// refinement (TDS_REFINE_*, 0 selects the queue stage) above it; 0 if either
+// is not built.
+uint32_t resolve_tile(uint32_t t, uint32_t refine = 0) {
+    if (t == 0) t = 4;
+    if (t != 2 && t != 4) return 0;
+    if (refine == TDS_REFINE_DEFAULT) refine = TDS_REFINE_QUEUED;
+    if (refine != TDS_REFINE_QUEUED && refine != TDS_REFINE_INLINE) return 0;
+    return t | (refine << 8);
 }
 
 int resolve_prec(int p) {
@@ -1545,7 +1711,8 @@ DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q,
                    uint64_t win_lo, uint32_t item_begin, uint32_t item_end, uint32_t* item_count,
                    uint32_t grid_waves, bool by_order, uint32_t cpl) {
     DistArgs A;
-    A.cpl = cpl;
+    A.cpl = cpl & 0xFFu;
+    A.inline_refine = (cpl >> 8) == TDS_REFINE_INLINE ? 1u : 0u;
     A.dyn_ctr = w->dyn_ctr;
     A.stage = w->stage;
     A.stage_meta = w->stage_meta;
@@ -1578,9 +1745,14 @@ int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_
     const uint32_t blocks = launch_blocks(grid_waves);
     // every wave must be able to stage a full batch of 64 evaluations
     if (!A.stage || A.stage_cap < (uint32_t)kWave) return TDS_E_DEVICE;
-    void (*kern)(DistArgs) = (A.cpl == 2) ? k_distance<TDS_PREC_FP32_RECHECK, 2>
-                                          : k_distance<TDS_PREC_FP32_RECHECK, 4>;
-    if (prec == TDS_PREC_FP64) kern = k_distance<TDS_PREC_FP64, 4>;
+    void (*kern)(DistArgs);
+    if (A.inline_refine)
+        kern = (A.cpl == 2) ? k_distance<TDS_PREC_FP32_RECHECK, 2, true>
+                            : k_distance<TDS_PREC_FP32_RECHECK, 4, true>;
+    else
+        kern = (A.cpl == 2) ? k_distance<TDS_PREC_FP32_RECHECK, 2, false>
+                            : k_distance<TDS_PREC_FP32_RECHECK, 4, false>;
+    if (prec == TDS_PREC_FP64) kern = k_distance<TDS_PREC_FP64, 4, false>;
     if (ev_begin && ev_end) {
         // the events take the dispatch's own start and end times (no marker
         // packets around the kernel, so no bubbles before and after it)
@@ -1734,7 +1906,7 @@ int resolve_config(const tds_search_params* params, PipelineConfig* cfg) {
     if (cfg->prec < 0) return TDS_E_INVALID;
     cfg->chunk = resolve_chunk(cfg->prec, P.chunk);
     cfg->grid_waves = resolve_grid(P.grid_waves);
-    cfg->cpl = resolve_tile(P.tile);
+    cfg->cpl = resolve_tile(P.tile, P.refine);
     if (!cfg->cpl) return TDS_E_INVALID;
     return TDS_OK;
 }
@@ -1832,7 +2004,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
     if (prec < 0) return TDS_E_INVALID;
     const uint32_t chunk = resolve_chunk(prec, P.chunk);
     const uint32_t grid_waves = resolve_grid(P.grid_waves);
-    const uint32_t cpl = resolve_tile(P.tile);
+    const uint32_t cpl = resolve_tile(P.tile, P.refine);
     if (!cpl) return TDS_E_INVALID;
     const bool dev_out = P.out_on_device != 0;
 
@@ -1984,7 +2156,7 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
     if (prec < 0) return TDS_E_INVALID;
     const uint32_t chunk = resolve_chunk(prec, P.chunk);
     const uint32_t grid_waves = resolve_grid(P.grid_waves);
-    const uint32_t cpl = resolve_tile(P.tile);
+    const uint32_t cpl = resolve_tile(P.tile, P.refine);
     if (!cpl) return TDS_E_INVALID;
     const bool dev_out = P.out_on_device != 0;
 

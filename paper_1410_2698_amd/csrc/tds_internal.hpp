@@ -47,6 +47,16 @@ struct alignas(32) EntryF32 {
 };
 static_assert(sizeof(EntryF32) == 32, "EntryF32 layout");
 
+// FP32 motion of an index entry for the closest-approach refinement of the
+// FP32 filter: velocity and the mid time of its extent, each rounded to
+// nearest (16 bytes: one vector load per lane).  The sphere centre of its
+// EntryF32 record is the position at that time.
+struct alignas(16) EntryV32 {
+    float vx, vy, vz;
+    float tm;
+};
+static_assert(sizeof(EntryV32) == 16, "EntryV32 layout");
+
 // Bounding box of the FP32 filter spheres of one aligned block of 64 index
 // entries (spatial layout): every centre lies in [lo, hi] and every radius is
 // at most rmax.  32 bytes: one scalar load.
@@ -194,6 +204,7 @@ struct tds_index {
     double t_min = 0, t_max = 0, bw = 0;
     tds::EntryF64* e64 = nullptr;
     tds::EntryF32* e32 = nullptr;
+    tds::EntryV32* ev32 = nullptr; // FP32 velocity and mid time (refinement of the filter)
     uint32_t* seg_id = nullptr;    // index position -> input position
     uint32_t* traj = nullptr;      // index position -> trajectory id
     uint32_t* bin_first = nullptr; // m + 1

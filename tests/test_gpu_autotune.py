@@ -15,7 +15,7 @@ from paper_1410_2698_amd import autotune  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("num_bins", "chunk", "grid_waves", "tile", "precision")
+KEYS = ("num_bins", "chunk", "grid_waves", "tile", "refine", "precision")
 
 
 def test_autotune_choice_is_exact_and_cached(tmp_path):
@@ -23,7 +23,7 @@ def test_autotune_choice_is_exact_and_cached(tmp_path):
     w = trajgen.uniform1m(0.05, n_pts=81)  # 10,000 entries, 2,000 query segments
     ds = [30.0, 90.0]
     space = {"bins_factor": (1.0, 2.0), "chunk": (4096, 1024), "grid_waves": (4096, 1024),
-             "tile": (4, 2), "precision": ("fp32", "fp64")}
+             "tile": (4, 2), "refine": ("queued", "inline"), "precision": ("fp32", "fp64")}
     cache = str(tmp_path / "tune.json")
     best = autotune.tune(w.D, w.Q, ds, w.window, space=space, reps=1, cache=cache)
     assert not best["cached"]
@@ -33,7 +33,7 @@ def test_autotune_choice_is_exact_and_cached(tmp_path):
     total = 0
     for d in ds:
         got = idx.search(w.Q, d, *w.window, precision=best["precision"], chunk=best["chunk"],
-                         grid_waves=best["grid_waves"], tile=best["tile"])
+                         grid_waves=best["grid_waves"], tile=best["tile"], refine=best["refine"])
         want = oracle.sort_results(oracle.search(w.Q, w.D, d, *w.window))
         compare(tds.sort_records(got), want, f"tuned d={d}")
         total += want.size
@@ -46,16 +46,19 @@ def test_autotune_choice_is_exact_and_cached(tmp_path):
 
 def test_every_tile_and_mapping_gives_the_same_records():
     """The knobs the autotuner moves do not change the records: both tiles
-    of the FP32 form and the FP64 form, bit for bit."""
+    and both places of the refinement in the FP32 form and the FP64 form,
+    bit for bit."""
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     w = trajgen.dense(0.02, n_pts=41)
     idx = tds.Index(w.D)
     ref = tds.sort_records(idx.search(w.Q, 4.0, *w.window, precision="fp64"))
     assert ref.size > 100
     for tile in (2, 4):
-        for chunk in (256, 1024, 4096):
-            got = tds.sort_records(idx.search(w.Q, 4.0, *w.window, tile=tile, chunk=chunk))
-            assert got.tobytes() == ref.tobytes(), (tile, chunk)
+        for refine in ("queued", "inline"):
+            for chunk in (256, 1024, 4096):
+                got = tds.sort_records(idx.search(w.Q, 4.0, *w.window, tile=tile, chunk=chunk,
+                                                  refine=refine))
+                assert got.tobytes() == ref.tobytes(), (tile, refine, chunk)
     with pytest.raises(tds.TdsError):
         idx.search(w.Q, 4.0, *w.window, tile=3)
     idx.close()
