@@ -139,8 +139,11 @@ def load_profile(workload, kind):
 
 # Launch parameters the profiles are taken with (the autotuner's choice for
 # the workload on MI355X; the bench's own tuning picks them again).
-PROFILE_PARAMS = {"galaxy": "num_bins=38,chunk=1024,grid_waves=8192,tile=4,precision=fp32",
-                  "uniform1m": "num_bins=400,chunk=4096,grid_waves=4096,tile=4,precision=fp32"}
+PROFILE_PARAMS = {
+    "galaxy": "num_bins=38,chunk=1024,grid_waves=8192,tile=2,refine=inline,deal=dynamic,"
+              "precision=fp32",
+    "uniform1m": "num_bins=400,chunk=4096,grid_waves=4096,tile=4,refine=queued,deal=static,"
+                 "precision=fp32"}
 
 
 def profile_command(workload, counters):
@@ -337,7 +340,7 @@ class SearchLeg:
         import torch
         self.tds, self.w = tds, w
         self.tuned = tuned or {"num_bins": 0, "chunk": 0, "grid_waves": 0, "tile": 0,
-                               "refine": "default", "precision": "fp32"}
+                               "refine": "default", "deal": "default", "precision": "fp32"}
         self.idx = tds.Index(w.D, num_bins=self.tuned["num_bins"])
         Qt = device_segments(w.Q)
         nq = len(w.Q)
@@ -357,7 +360,8 @@ class SearchLeg:
                                          precision=precision or self.precision,
                                          chunk=self.tuned["chunk"],
                                          grid_waves=self.tuned["grid_waves"],
-                                         tile=self.tuned["tile"], refine=self.tuned["refine"])
+                                         tile=self.tuned["tile"], refine=self.tuned["refine"],
+                                         deal=self.tuned["deal"])
 
     def step(self):
         st, got, s = self.run(self.reqs, self.out.data_ptr(), len(self.w.ds) * self.cap)
@@ -512,13 +516,13 @@ def fsg_leg(tds, idx, Qt, counts, ds, t0, t1, grids=(20, 50, 100), reps=3):
     return rows
 
 
-def open_loop(tds, idx, reqs):
+def open_loop(tds, idx, reqs, route=0):
     """Submits reqs at their arrival times from a thread while the main thread
     collects them.  Returns (latency from submission in ms, latency from the
     scheduled arrival in ms, records, elapsed s, server stats): when the
     submitting thread falls behind the arrivals, the second shows it."""
     srv = tds.Server(idx, max_batch_segments=1 << 17, max_batch_requests=2048, slots=2,
-                     result_capacity=1 << 21, default_reserve=512)
+                     result_capacity=1 << 21, default_reserve=512, cpu_route_tests=route)
     for r in reqs[:200]:  # warm-up, not timed
         srv.wait(srv.submit(r.Q, r.d, r.t_start, r.t_end))
     reqs = reqs[200:]
@@ -608,8 +612,19 @@ def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0, 80000.0
         if len(slat) / sel < 0.9 * rt:
             break
     fl = flood(tds, idx, trajgen.request_stream(20200, rate=1e9, seed=91))
+    # hybrid: requests with at most HOST_ROUTE_TESTS candidate pairs searched
+    # on host threads, the same stream
+    rlat, rarr, rrec, rel, rst = open_loop(tds, idx, reqs, route=HOST_ROUTE_TESTS)
+    routed = {"offered_rate": rate, "requests": len(rlat), "cpu_route_tests": HOST_ROUTE_TESTS,
+              "cpu_routed": rst["cpu_routed"], "requests_per_s": round(len(rlat) / rel, 1),
+              "p50_ms": pct(rlat, 50), "p99_ms": pct(rlat, 99),
+              "p50_from_arrival_ms": pct(rarr, 50), "p99_from_arrival_ms": pct(rarr, 99),
+              "records": rrec, "batches": rst["batches"]}
+    if rrec != n_rec:
+        raise RuntimeError(f"routed serving found {rrec} records, GPU-only {n_rec}")
     return {
         "served_fp32": served,
+        "served_hybrid": routed,
         "served_rate_sweep": rows,
         "served_flood": fl,
         "saturation_requests_per_s": max([r["requests_per_s"] for r in rows] +
@@ -620,6 +635,11 @@ def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0, 80000.0
                        "note": "one request per call, back to back (service time, no queueing)"},
     }
 
+
+# Host route threshold of the hybrid serving run: requests whose candidate
+# ranges hold at most this many pairs (on the uniform1m index, about 20
+# clipped query segments of 2,500 candidates each) run on the host.
+HOST_ROUTE_TESTS = 50000
 
 LEGS = ("galaxy", "uniform1m", "dense", "tiny", "serve", "self_join", "fsg")
 
@@ -692,15 +712,15 @@ def main():
         tuned = None
         if args.fixed:
             tuned = {"num_bins": 0, "chunk": 0, "grid_waves": 0, "tile": 0, "refine": "default",
-                     "precision": "fp32"}
+                     "deal": "default", "precision": "fp32"}
             for kv in args.fixed.split(","):
                 k, v = kv.split("=")
-                tuned[k] = v if k in ("precision", "refine") else int(v)
+                tuned[k] = v if k in ("precision", "refine", "deal") else int(v)
         elif not args.no_tune and name in legs:
             tb = time.perf_counter()
             best = autotune.tune(w.D, w.Q, w.ds, w.window, cache=None)
             tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves", "tile", "refine",
-                                          "precision")}
+                                          "deal", "precision")}
             tuned["trials"] = best["trials"]
             tuned["tuning_s"] = round(time.perf_counter() - tb, 2)
         leg = SearchLeg(tds, w, tuned)

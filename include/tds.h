@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define TDS_ABI_VERSION 2u
+#define TDS_ABI_VERSION 3u
 
 /* Status codes. */
 enum {
@@ -119,6 +119,19 @@ enum {
     TDS_REFINE_INLINE = 2
 };
 
+/* Dealing of the distance kernel's work items to its waves.  Items are split
+   into one contiguous part per XCD (so a candidate range stays under one
+   L2) and every wave first takes one item of its part. */
+enum {
+    TDS_DEAL_DEFAULT = 0, /* currently TDS_DEAL_DYNAMIC */
+    /* The rest from per-part counters, a wave whose part is used up taking
+       from the others (balances searches whose item costs vary widely). */
+    TDS_DEAL_DYNAMIC = 1,
+    /* The rest round-robin over the part's waves, no counters (cheapest when
+       items cost about the same). */
+    TDS_DEAL_STATIC = 2
+};
+
 /* Index parameters; a NULL pointer or 0 fields select defaults. */
 typedef struct tds_build_params {
     /* Number m of temporal bins (Sec. 4.2.1).  0 = auto: the full temporal
@@ -157,7 +170,10 @@ typedef struct tds_search_params {
     /* FP32 form: where the closest-approach refinement of the filter runs
        (TDS_REFINE_*).  Both places drop the same pairs. */
     uint32_t refine;
-    uint64_t reserved[3];
+    /* How the distance kernel's work items reach its waves (TDS_DEAL_*). */
+    uint32_t deal;
+    uint32_t reserved32;
+    uint64_t reserved[2];
 } tds_search_params;
 
 /* Counters of the last search (tests and benchmarks). */
@@ -453,13 +469,19 @@ typedef struct tds_server_params {
     uint64_t result_capacity;    /* result records per batch (0 = 2^21) */
     uint64_t default_reserve;    /* records reserved per request until known (0 = 1024) */
     uint32_t max_pending;        /* queued requests before submit refuses (0 = 1 << 20) */
-    uint32_t reserved0;
+    /* Host route (hybrid CPU + GPU serving, 0 = off): a request whose
+       candidate ranges hold at most this many (query, entry) pairs is searched
+       on 4 host threads over a host copy of the index (the same records as
+       on the GPU, bit for bit), the rest in GPU batches.  The host copy takes
+       about 72 bytes per entry of host memory. */
+    uint32_t cpu_route_tests;
     tds_search_params search;    /* precision, chunk, grid (output fields ignored) */
 } tds_server_params;
 
 typedef struct tds_server_stats {
     uint64_t submitted, completed, batches, requeued, failed;
     uint64_t max_batch_requests_seen;
+    uint64_t cpu_routed; /* requests completed by the host route */
 } tds_server_stats;
 
 /* Errors: TDS_E_INVALID, TDS_E_NOMEM, TDS_E_DEVICE.  params may be NULL. */

@@ -168,10 +168,10 @@ class Index:
 
     def search_raw(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                    out_ptr: int, capacity: int, out_on_device: bool, precision: str = "fp32",
-                   chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0, tile: int = 0, refine: str = "default"):
+                   chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0, tile: int = 0, refine: str = "default", deal: str = "default"):
         """One call of tds_search into caller memory; returns (status, n_total, stats)."""
         h = _segments(Q)
-        p = _search_params(precision, chunk, grid_waves, tile, refine)
+        p = _search_params(precision, chunk, grid_waves, tile, refine, deal)
         p.out_on_device = 1 if out_on_device else 0
         p.device_capacity = int(device_capacity)
         n = ctypes.c_uint64()
@@ -186,11 +186,11 @@ class Index:
     def search_noalloc_raw(self, Q, d: float, t_start: float = -math.inf,
                            t_end: float = math.inf, *, out_ptr: int, capacity: int,
                            precision: str = "fp32", chunk: int = 0, grid_waves: int = 0,
-                           tile: int = 0, refine: str = "default"):
+                           tile: int = 0, refine: str = "default", deal: str = "default"):
         """One call of tds_search_noalloc (Q and out in device memory); returns
         (status, n_total, stats)."""
         h = _segments(Q)
-        p = _search_params(precision, chunk, grid_waves, tile, refine)
+        p = _search_params(precision, chunk, grid_waves, tile, refine, deal)
         p.out_on_device = 1
         n = ctypes.c_uint64()
         st = _lib.tds_stats()
@@ -203,7 +203,8 @@ class Index:
 
     def search(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                capacity: Optional[int] = None, precision: str = "fp32", chunk: int = 0,
-               grid_waves: int = 0, device_capacity: int = 0, tile: int = 0, refine: str = "default") -> np.ndarray:
+               grid_waves: int = 0, device_capacity: int = 0, tile: int = 0, refine: str = "default",
+               deal: str = "default") -> np.ndarray:
         """Search into host memory; grows the buffer and retries on overflow.
         Returns the records (unspecified order) as a NumPy structured array."""
         cap = 1 << 16 if capacity is None else int(capacity)
@@ -213,7 +214,7 @@ class Index:
                                            capacity=cap, out_on_device=False, precision=precision,
                                            chunk=chunk, grid_waves=grid_waves,
                                            device_capacity=device_capacity, tile=tile,
-                                           refine=refine)
+                                           refine=refine, deal=deal)
             if status == TDS_OK:
                 return buf[:n].copy()
             if status == TDS_E_OVERFLOW and capacity is None:
@@ -225,9 +226,9 @@ class Index:
     def self_join_raw(self, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                       out_ptr: int, capacity: int, out_on_device: bool, precision: str = "fp32",
                       chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0,
-                      tile: int = 0, refine: str = "default"):
+                      tile: int = 0, refine: str = "default", deal: str = "default"):
         """One call of tds_self_join into caller memory; returns (status, n_total, stats)."""
-        p = _search_params(precision, chunk, grid_waves, tile, refine)
+        p = _search_params(precision, chunk, grid_waves, tile, refine, deal)
         p.out_on_device = 1 if out_on_device else 0
         p.device_capacity = int(device_capacity)
         n = ctypes.c_uint64()
@@ -260,7 +261,7 @@ class Index:
 
     def search_batch_raw(self, Q, requests, *, out_ptr: int, out_capacity: int,
                          out_on_device: bool, precision: str = "fp32", chunk: int = 0,
-                         grid_waves: int = 0, tile: int = 0, refine: str = "default"):
+                         grid_waves: int = 0, tile: int = 0, refine: str = "default", deal: str = "default"):
         """One call of tds_search_batch into caller memory.  ``requests`` holds
         (q_begin, q_count, d, t_start, t_end, out_offset, out_capacity) tuples
         that tile Q in order.  Returns (status, counts, stats)."""
@@ -270,7 +271,7 @@ class Index:
             r.q_begin, r.q_count, r.d, r.t_start, r.t_end = int(qb), int(qc), float(d), float(t0), float(t1)
             r.out_offset, r.out_capacity = int(oo), int(oc)
         counts = (ctypes.c_uint64 * len(requests))()
-        p = _search_params(precision, chunk, grid_waves, tile, refine)
+        p = _search_params(precision, chunk, grid_waves, tile, refine, deal)
         p.out_on_device = 1 if out_on_device else 0
         st = _lib.tds_stats()
         status = self._lib.tds_search_batch(self._h, ctypes.byref(h.struct), reqs, len(requests),
@@ -361,9 +362,11 @@ class FSG:
 
 
 REFINES = {"default": 0, "queued": 1, "inline": 2}
+DEALS = {"default": 0, "dynamic": 1, "static": 2}
 
 
-def _search_params(precision="fp32", chunk=0, grid_waves=0, tile=0, refine="default"):
+def _search_params(precision="fp32", chunk=0, grid_waves=0, tile=0, refine="default",
+                   deal="default"):
     lib = load()
     p = _lib.tds_search_params()
     lib.tds_search_params_default(ctypes.byref(p))
@@ -372,6 +375,7 @@ def _search_params(precision="fp32", chunk=0, grid_waves=0, tile=0, refine="defa
     p.grid_waves = int(grid_waves)
     p.tile = int(tile)
     p.refine = REFINES[refine]
+    p.deal = DEALS[deal]
     return p
 
 
@@ -461,7 +465,8 @@ class Server:
     def __init__(self, index: Index, *, max_batch_segments: int = 0, max_batch_requests: int = 0,
                  slots: int = 0, result_capacity: int = 0, default_reserve: int = 0,
                  max_pending: int = 0, precision: str = "fp32", chunk: int = 0, grid_waves: int = 0,
-                 tile: int = 0, refine: str = "default"):
+                 tile: int = 0, refine: str = "default", deal: str = "default",
+                 cpu_route_tests: int = 0):
         self._lib = load()
         self.index = index
         p = _lib.tds_server_params()
@@ -471,7 +476,8 @@ class Server:
         p.result_capacity = result_capacity
         p.default_reserve = default_reserve
         p.max_pending = max_pending
-        p.search = _search_params(precision, chunk, grid_waves, tile, refine)
+        p.cpu_route_tests = int(cpu_route_tests)
+        p.search = _search_params(precision, chunk, grid_waves, tile, refine, deal)
         out = ctypes.c_void_p()
         check(self._lib.tds_server_create(index.handle, ctypes.byref(p), ctypes.byref(out)),
               "tds_server_create")

@@ -36,7 +36,8 @@ class tds_search_params(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("out_on_device", ctypes.c_int32),
                 ("chunk", ctypes.c_uint32), ("grid_waves", ctypes.c_uint32),
                 ("device_capacity", ctypes.c_uint64), ("tile", ctypes.c_uint32),
-                ("refine", ctypes.c_uint32), ("reserved", ctypes.c_uint64 * 3)]
+                ("refine", ctypes.c_uint32), ("deal", ctypes.c_uint32),
+                ("reserved32", ctypes.c_uint32), ("reserved", ctypes.c_uint64 * 2)]
 
 
 class tds_stats(ctypes.Structure):
@@ -68,13 +69,14 @@ class tds_server_params(ctypes.Structure):
     _fields_ = [("max_batch_segments", ctypes.c_uint64), ("max_batch_requests", ctypes.c_uint32),
                 ("slots", ctypes.c_uint32), ("result_capacity", ctypes.c_uint64),
                 ("default_reserve", ctypes.c_uint64), ("max_pending", ctypes.c_uint32),
-                ("reserved0", ctypes.c_uint32), ("search", tds_search_params)]
+                ("cpu_route_tests", ctypes.c_uint32), ("search", tds_search_params)]
 
 
 class tds_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("requeued", ctypes.c_uint64),
-                ("failed", ctypes.c_uint64), ("max_batch_requests_seen", ctypes.c_uint64)]
+                ("failed", ctypes.c_uint64), ("max_batch_requests_seen", ctypes.c_uint64),
+                ("cpu_routed", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtds.so")
-SOURCES = ["capi.hip", "index_build.hip", "radix_sort.hip", "search.hip", "batch.hip", "traj_merge.hip", "fsg.hip", "noalloc.hip"]
+SOURCES = ["capi.hip", "index_build.hip", "radix_sort.hip", "search.hip", "batch.hip", "traj_merge.hip", "fsg.hip", "noalloc.hip",
+           "host_search.hip"]
 ARCH = os.environ.get("TDS_OFFLOAD_ARCH", "gfx950")
 
 

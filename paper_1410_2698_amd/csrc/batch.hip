@@ -20,6 +20,10 @@
 
 namespace tds {
 
+// Host threads of the serving loop's host route (tds_server_params.cpu_route_tests).
+constexpr uint32_t kHostRouteThreads = 4;
+
+
 Batcher::~Batcher() {
     if (exec_) (void)hipGraphExecDestroy(exec_);
     if (graph_) (void)hipGraphDestroy(graph_);
@@ -240,6 +244,7 @@ struct ServerTicket {
     int status = TDS_OK;
     bool finished = false;
     bool solo = false;          // next batch: this request alone (item table overflowed)
+    bool cpu = false;           // routed to the host search
 };
 
 struct ServerSlot {
@@ -262,12 +267,43 @@ struct tds_server {
     std::unordered_map<uint64_t, tds::ServerTicket*> tickets;
     std::vector<std::unique_ptr<tds::ServerSlot>> slots;
     std::thread worker;
+    // host route: requests with few candidate pairs run on host threads
+    std::unique_ptr<tds::HostIndex> host;
+    std::deque<tds::ServerTicket*> cpu_pending;
+    std::condition_variable cv_cpu;
+    std::vector<std::thread> cpu_workers;
     bool stop = false;
     uint64_t next_id = 1;
     tds_server_stats stats{};
     void run();
+    void cpu_run();
     int run_exact(tds::ServerTicket* t);
 };
+
+// Host-route worker: searches queued small requests on the host copy of the
+// index, one at a time, until the server stops and its queue is empty.
+void tds_server::cpu_run() {
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        cv_cpu.wait(lk, [&] { return stop || !cpu_pending.empty(); });
+        if (cpu_pending.empty()) break;  // stopping
+        tds::ServerTicket* t = cpu_pending.front();
+        cpu_pending.pop_front();
+        lk.unlock();
+        std::vector<tds_result> r;
+        tds::host_search(*host, t->q.data(), t->traj.empty() ? nullptr : t->traj.data(), t->L,
+                         t->d, t->t0, t->t1, &r);
+        lk.lock();
+        t->count = r.size();
+        t->results = std::move(r);
+        t->status = TDS_OK;
+        t->finished = true;
+        t->done = std::chrono::steady_clock::now();
+        ++stats.completed;
+        ++stats.cpu_routed;
+        cv_done.notify_all();
+    }
+}
 
 // One request through tds_search's path (work-item table sized exactly),
 // results into the ticket; called by the worker without the lock.
@@ -542,6 +578,16 @@ int tds_server_create(const tds_index* index, const tds_server_params* params, t
         sl->b.set_copy_all(true);
         S->slots.push_back(std::move(sl));
     }
+    if (P.cpu_route_tests) {
+        S->host = std::make_unique<tds::HostIndex>();
+        const int st = tds::host_index_load(S->idx, S->host.get());
+        if (st != TDS_OK) {
+            delete S;
+            return st;
+        }
+        for (uint32_t i = 0; i < tds::kHostRouteThreads; ++i)
+            S->cpu_workers.emplace_back([S] { S->cpu_run(); });
+    }
     S->worker = std::thread([S] { S->run(); });
     *out = S;
     return TDS_OK;
@@ -578,21 +624,32 @@ int tds_server_submit(tds_server* S, const tds_segments* Q, double d, double t_s
     t->t0 = t_start;
     t->t1 = t_end;
     t->reserve = reserve ? reserve : S->P.default_reserve;
+    // host route: a request with few candidate pairs (the cost model: the
+    // pair tests of its candidate ranges) is searched on the host
+    if (S->host)
+        t->cpu = tds::host_candidates(*S->host, t->q.data(), t->L, t_start, t_end) <=
+                 S->P.cpu_route_tests;
     std::unique_lock<std::mutex> lk(S->mu);
-    if (S->pending.size() >= S->P.max_pending) {
+    auto queued = [&] { return S->pending.size() + S->cpu_pending.size(); };
+    if (queued() >= S->P.max_pending) {
         if (!blocking) {
             delete t;
             return TDS_E_BUSY;
         }
-        S->cv_done.wait(lk, [&] { return S->pending.size() < S->P.max_pending; });
+        S->cv_done.wait(lk, [&] { return queued() < S->P.max_pending; });
     }
     t->id = S->next_id++;
     t->submit = std::chrono::steady_clock::now();
     S->tickets[t->id] = t;
-    S->pending.push_back(t);
     ++S->stats.submitted;
     *ticket = t->id;
-    S->cv_work.notify_one();
+    if (t->cpu) {
+        S->cpu_pending.push_back(t);
+        S->cv_cpu.notify_one();
+    } else {
+        S->pending.push_back(t);
+        S->cv_work.notify_one();
+    }
     return TDS_OK;
 }
 
@@ -640,7 +697,10 @@ int tds_server_destroy(tds_server* S) {
         S->stop = true;
     }
     S->cv_work.notify_all();
+    S->cv_cpu.notify_all();
     if (S->worker.joinable()) S->worker.join();
+    for (auto& th : S->cpu_workers)
+        if (th.joinable()) th.join();
     tds::DeviceGuard g(S->device);
     for (auto& kv : S->tickets) delete kv.second;
     S->tickets.clear();

@@ -1,6 +1,6 @@
 // The canonical FP64 evaluation of one (query, entry) pair, shared by every
 // search kernel of the library (temporal/spatial index search, self-join,
-// fixed spatial grid).  Compiled without FP contraction (-ffp-contract=off),
+// fixed spatial grid) and by the host search that serves small requests.  Compiled without FP contraction (-ffp-contract=off),
 // so the operations below are performed exactly in the order written.
 #pragma once
 
@@ -8,8 +8,8 @@
 
 namespace tds {
 
-__device__ inline double dmax(double a, double b) { return a > b ? a : b; }
-__device__ inline double dmin(double a, double b) { return a < b ? a : b; }
+__host__ __device__ inline double dmax(double a, double b) { return a > b ? a : b; }
+__host__ __device__ inline double dmin(double a, double b) { return a < b ? a : b; }
 
 // Query side of the canonical evaluation.  aq = max(ts_q, t_start) and
 // bq = min(te_q, t_end) are exact, so max(aq, ts_l) is the common start of
@@ -26,7 +26,7 @@ struct QCanon {
 // in cancellation-free form (Higham, Accuracy and Stability of Numerical
 // Algorithms, Sec. 1.8).  Compiled without FP contraction.
 template <bool kInterval>
-__device__ __forceinline__ bool canon_eval(const QCanon& q, double lx, double ly, double lz,
+__host__ __device__ __forceinline__ bool canon_eval(const QCanon& q, double lx, double ly, double lz,
                                            double lvx, double lvy, double lvz, double lts,
                                            double lte, double* t_lo, double* t_hi) {
     const double a = dmax(q.aq, lts);

@@ -713,6 +713,7 @@ struct DistArgs {
                             // their order in the item (minus win_lo), no stage
     uint32_t cpl;           // FP32 form: candidates per lane per tile (2 or 4)
     uint32_t inline_refine; // FP32 form: refinement in the filter walk, not the queue
+    uint32_t deal;          // TDS_DEAL_STATIC or TDS_DEAL_DYNAMIC
 };
 
 // Results go through a stage of stage_cap records per wave in device memory
@@ -1354,34 +1355,46 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         return ((gridDim.x - x + ng - 1) / ng) * (uint32_t)kWavesPerBlock;
     };
     auto part_lo = [&](uint32_t x) { return n_it * x / ng; };
+    // static deal (chosen per launch): every item round-robin over the
+    // XCD's waves, no counter at all
+    const bool stat = A.deal == TDS_DEAL_STATIC;
     bool dyn = false;  // does any part hold more items than its XCD has waves?
-    for (uint32_t x = 0; x < ng; ++x) dyn = dyn || part_lo(x + 1) - part_lo(x) > waves_of(x);
+    if (!stat)
+        for (uint32_t x = 0; x < ng; ++x) dyn = dyn || part_lo(x + 1) - part_lo(x) > waves_of(x);
     uint64_t k = part_lo(grp) + gw;
     bool have = k < part_lo(grp + 1);
-    uint32_t xs = grp, tried = 0;
+    uint32_t xs = grp;  // the part dynamic items are taken from
     for (;;) {
         if (!have) {
             if (!dyn) break;
-            // the next dynamic item: from part xs, past its static round
-            while (tried < ng) {
-                const uint64_t ps = part_lo(xs) + waves_of(xs), pe = part_lo(xs + 1);
-                if (ps < pe) {
-                    unsigned long long* ctr = A.dyn_ctr + (size_t)xs * kCtrStride;
-                    uint64_t v = 0;
-                    if (lane == 0) v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    v = lane0_64(v);
-                    if (ps + v < pe) {
-                        if (lane == 0) v = atomicAdd(ctr, 1ull);
-                        v = lane0_64(v);
-                        if (ps + v < pe) {
-                            k = ps + v;
-                            have = true;
-                            break;
-                        }
+            // the next dynamic item: the parts' counters are read at once,
+            // one part per lane in rotation from part xs, and the first part
+            // with items left past its static round is taken from; losing
+            // the race for a part's last items exhausts that part, so this
+            // ends after at most ng + 1 rounds
+            for (uint32_t round = 0; round <= ng && !have; ++round) {
+                bool avail = false;
+                if (lane < ng) {
+                    const uint32_t x = (xs + lane) % ng;
+                    const uint64_t ps = part_lo(x) + waves_of(x), pe = part_lo(x + 1);
+                    if (ps < pe) {
+                        const uint64_t v = __hip_atomic_load(A.dyn_ctr + (size_t)x * kCtrStride,
+                                                             __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                        avail = ps + v < pe;
                     }
                 }
-                xs = (xs + 1 == ng) ? 0 : xs + 1;
-                ++tried;
+                const uint64_t am = ballot(avail);
+                if (!am) break;  // every part is used up
+                xs = (xs + (uint32_t)__ffsll((unsigned long long)am) - 1u) % ng;
+                uint64_t v = 0;
+                if (lane == 0) v = atomicAdd(A.dyn_ctr + (size_t)xs * kCtrStride, 1ull);
+                v = lane0_64(v);
+                const uint64_t ps = part_lo(xs) + waves_of(xs), pe = part_lo(xs + 1);
+                if (ps + v < pe) {
+                    k = ps + v;
+                    have = true;
+                }
             }
             if (!have) break;
         }
@@ -1434,6 +1447,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         btests += S.btests;
         evals_total += S.evals;
         if (A.item_count && lane == 0) A.item_count[it] = S.found;
+        if (stat) {
+            // the wave's next item of its part
+            k += waves_of(grp);
+            have = k < part_lo(grp + 1);
+        }
     }
     // per-workgroup counters (folded into the header by k_stats_fold)
     __shared__ BlockStats ws[kWavesPerBlock];
@@ -1663,16 +1681,19 @@ uint32_t stage_per_wave(size_t recs, uint32_t blocks) {
     return (uint32_t)std::min<size_t>(kStageMax, per / kWave * kWave);
 }
 
-// FP32 form's kernel variant: candidates per lane per tile (0 selects 4; 2
-// and 4 are built) in the low byte, the place of the closest-approach
-// refinement (TDS_REFINE_*, 0 selects the queue stage) above it; 0 if either
-// is not built.
-uint32_t resolve_tile(uint32_t t, uint32_t refine = 0) {
+// Kernel variant and dealing of a launch, packed: candidates per lane per
+// tile of the FP32 form (0 selects 4; 2 and 4 are built) in the low byte,
+// the place of the closest-approach refinement (TDS_REFINE_*, 0 selects the
+// queue stage) in the next, the dealing of the work items (TDS_DEAL_*, 0
+// selects the dynamic tail) above; 0 if any of them is unknown.
+uint32_t resolve_tile(uint32_t t, uint32_t refine = 0, uint32_t deal = 0) {
     if (t == 0) t = 4;
     if (t != 2 && t != 4) return 0;
     if (refine == TDS_REFINE_DEFAULT) refine = TDS_REFINE_QUEUED;
     if (refine != TDS_REFINE_QUEUED && refine != TDS_REFINE_INLINE) return 0;
-    return t | (refine << 8);
+    if (deal == TDS_DEAL_DEFAULT) deal = TDS_DEAL_DYNAMIC;
+    if (deal != TDS_DEAL_DYNAMIC && deal != TDS_DEAL_STATIC) return 0;
+    return t | (refine << 8) | (deal << 16);
 }
 
 int resolve_prec(int p) {
@@ -1712,7 +1733,8 @@ DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q,
                    uint32_t grid_waves, bool by_order, uint32_t cpl) {
     DistArgs A;
     A.cpl = cpl & 0xFFu;
-    A.inline_refine = (cpl >> 8) == TDS_REFINE_INLINE ? 1u : 0u;
+    A.inline_refine = ((cpl >> 8) & 0xFFu) == TDS_REFINE_INLINE ? 1u : 0u;
+    A.deal = cpl >> 16;
     A.dyn_ctr = w->dyn_ctr;
     A.stage = w->stage;
     A.stage_meta = w->stage_meta;
@@ -1906,7 +1928,7 @@ int resolve_config(const tds_search_params* params, PipelineConfig* cfg) {
     if (cfg->prec < 0) return TDS_E_INVALID;
     cfg->chunk = resolve_chunk(cfg->prec, P.chunk);
     cfg->grid_waves = resolve_grid(P.grid_waves);
-    cfg->cpl = resolve_tile(P.tile, P.refine);
+    cfg->cpl = resolve_tile(P.tile, P.refine, P.deal);
     if (!cfg->cpl) return TDS_E_INVALID;
     return TDS_OK;
 }
@@ -2004,7 +2026,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
     if (prec < 0) return TDS_E_INVALID;
     const uint32_t chunk = resolve_chunk(prec, P.chunk);
     const uint32_t grid_waves = resolve_grid(P.grid_waves);
-    const uint32_t cpl = resolve_tile(P.tile, P.refine);
+    const uint32_t cpl = resolve_tile(P.tile, P.refine, P.deal);
     if (!cpl) return TDS_E_INVALID;
     const bool dev_out = P.out_on_device != 0;
 
@@ -2156,7 +2178,7 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
     if (prec < 0) return TDS_E_INVALID;
     const uint32_t chunk = resolve_chunk(prec, P.chunk);
     const uint32_t grid_waves = resolve_grid(P.grid_waves);
-    const uint32_t cpl = resolve_tile(P.tile, P.refine);
+    const uint32_t cpl = resolve_tile(P.tile, P.refine, P.deal);
     if (!cpl) return TDS_E_INVALID;
     const bool dev_out = P.out_on_device != 0;
 

@@ -351,6 +351,25 @@ int validate_segments_args(const tds_segments* S);
 // Workspace set-up and growth (search.hip).
 int ws_init(Workspace* w);
 int ws_reserve(Workspace* w, size_t nq, size_t nreq);
+// Host copy of an index for the host search (host_search.hip): the entries
+// in index order and the tables that give a query's candidate range.
+struct HostIndex {
+    uint64_t n = 0;
+    uint32_t m = 0;
+    std::vector<EntryF64> e64;
+    std::vector<uint32_t> seg_id, traj, bin_first;
+    std::vector<double> cmax_te, lo_ts;
+};
+// Copies the index tables to host memory (waits for the device).
+int host_index_load(const tds_index* idx, HostIndex* h);
+// Sum over the query segments of Q (8 arrays of L values, xs .. te, host
+// memory) of their candidate range lengths in the window: the pair tests a
+// search of Q makes without spatial pruning.
+uint64_t host_candidates(const HostIndex& h, const double* q, uint64_t L, double t0, double t1);
+// The search of Q (validated values) on the host; records in query order.
+void host_search(const HostIndex& h, const double* q, const uint32_t* qtraj, uint64_t L,
+                 double d, double t0, double t1, std::vector<tds_result>* out);
+
 // Sizes the result stages for distance-kernel launches of up to grid_waves
 // waves (a resolved value, see resolve_config).
 int ws_reserve_stage(Workspace* w, uint32_t grid_waves);

@@ -8,6 +8,7 @@
 //   harness search D.bin Q.bin layout prec d t0 t1 cap out.bin [bins] -> "status n ftests"
 //   harness selfjoin D.bin layout prec d t0 t1 cap out.bin        -> "status n ftests"
 //   harness merge recs.bin capacity out.bin                       -> "status n"
+//   harness hostsearch D.bin Q.bin d t0 t1 out.bin                -> "status n candidates"
 //
 // D.bin / Q.bin: 9 float64 columns (xs ys zs ts xe ye ze te traj), column
 // after column.  recs.bin: tds_result records.  out.bin: the records or
@@ -174,6 +175,28 @@ int run_search(int argc, char** argv, bool self_join) {
     return 0;
 }
 
+// The serving loop's host route: the index built by the (emulated) kernels,
+// copied to host memory, searched on the host.
+int run_hostsearch(char** argv) {
+    const Columns D = read_columns(argv[2]);
+    const Columns Qc = read_columns(argv[3]);
+    const double d = atof(argv[4]), t0 = atof(argv[5]), t1 = atof(argv[6]);
+    tds_index* idx = build(D, TDS_LAYOUT_DEFAULT);
+    tds::HostIndex h;
+    const int st = tds::host_index_load(idx, &h);
+    SegSet Q(Qc);
+    std::vector<tds_result> out;
+    uint64_t cand = 0;
+    if (st == TDS_OK) {
+        cand = tds::host_candidates(h, Qc.col(0), Qc.n, t0, t1);
+        tds::host_search(h, Qc.col(0), Q.traj.data(), Qc.n, d, t0, t1, &out);
+    }
+    write_records(argv[7], out, out.size());
+    tds::destroy_index(idx);
+    printf("%d %llu %llu\n", st, (unsigned long long)out.size(), (unsigned long long)cand);
+    return 0;
+}
+
 int run_merge(char** argv) {
     const std::vector<char> raw = read_file(argv[2]);
     const size_t n = raw.size() / sizeof(tds_result);
@@ -197,6 +220,7 @@ int main(int argc, char** argv) {
     if (argc >= 11 && std::string(argv[1]) == "search") return run_search(argc, argv, false);
     if (argc >= 10 && std::string(argv[1]) == "selfjoin") return run_search(argc, argv, true);
     if (argc >= 5 && std::string(argv[1]) == "merge") return run_merge(argv);
+    if (argc >= 8 && std::string(argv[1]) == "hostsearch") return run_hostsearch(argv);
     fprintf(stderr, "usage: harness fsg ... | harness merge ...\n");
     return 2;
 }

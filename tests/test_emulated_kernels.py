@@ -89,6 +89,8 @@ def _jobs():
     # a result buffer smaller than the result set: the total is reported
     J["overflow"] = ("search", (tiny.D, tiny.Q), [SPATIAL, FP32, 30.0, 0.0, 49.0, 100])
     J["selfjoin"] = ("selfjoin", (tiny04.D,), [SPATIAL, FP32, 4.0, 0.0, 49.0, 200000])
+    # the serving loop's host route over a host copy of the index
+    J["hostsearch"] = ("hostsearch", (tiny.D, tiny.Q), [30.0, 3.5, 40.25])
     J["merge_random"] = ("merge", _merge_random(), [3000])
     J["merge_degenerate"] = ("merge", _merge_degenerate(), [600])
     J["merge_degenerate_cap3"] = ("merge", _merge_degenerate(), [3])
@@ -109,7 +111,7 @@ def _build_harness(out):
            "-I", os.path.join(ROOT, "tests", "emu"), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-x", "c++", os.path.join(CSRC, "fsg.hip"), os.path.join(CSRC, "radix_sort.hip"),
            os.path.join(CSRC, "traj_merge.hip"), os.path.join(CSRC, "index_build.hip"),
-           os.path.join(CSRC, "search.hip"), "-x", "none",
+           os.path.join(CSRC, "search.hip"), os.path.join(CSRC, "host_search.hip"), "-x", "none",
            os.path.join(ROOT, "tests", "emu", "harness.cpp"), "-o", out, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -128,8 +130,10 @@ def _run_job(harness, d, kind, inputs, args):
             f = os.path.join(d, f"in{i}.bin")
             columns(S).tofile(f)
             files.append(f)
-        # harness <kind> <inputs> <six numbers> <out> [bins]
-        argv = [harness, kind, *files, *args[:6], out, *args[6:]]
+        if kind == "hostsearch":  # harness hostsearch D Q d t0 t1 <out>
+            argv = [harness, kind, *files, *args, out]
+        else:  # harness <kind> <inputs> <six numbers> <out> [bins]
+            argv = [harness, kind, *files, *args[:6], out, *args[6:]]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
     r = subprocess.run([str(a) for a in argv], capture_output=True, text=True, env=env,
                        timeout=900)
@@ -223,6 +227,23 @@ def test_self_join_emulated(emu):
     want = oracle.self_join(w.D, 4.0, 0.0, 49.0)
     assert want.size > 0 and n == want.size
     same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
+
+
+def test_host_search_emulated(emu):
+    """The host search of the serving loop's host route (host copy of the
+    index, same candidate ranges and canonical FP64 evaluation) against the
+    oracle, in a window that clips segments at both ends."""
+    (st, n, cand), out = result(emu, "hostsearch")
+    w = emu[1]["tiny"]
+    assert st == 0
+    want = oracle.search(w.Q, w.D, 30.0, 3.5, 40.25)
+    assert want.size > 100 and n == want.size
+    assert cand >= 5 * 36 * 100  # at least one candidate per trajectory per clipped segment
+    got = np.fromfile(out, dtype=RESULT_DTYPE)
+    same_records(got, want)
+    # the evaluation is the kernels' canonical one: endpoints bit for bit
+    key = lambda r: np.lexsort((r["e_seg"], r["q_seg"]))
+    assert got[key(got)].tobytes() == want[key(want)].tobytes()
 
 
 def same_intervals(got, want):

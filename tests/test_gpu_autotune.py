@@ -15,7 +15,7 @@ from paper_1410_2698_amd import autotune  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("num_bins", "chunk", "grid_waves", "tile", "refine", "precision")
+KEYS = ("num_bins", "chunk", "grid_waves", "tile", "refine", "deal", "precision")
 
 
 def test_autotune_choice_is_exact_and_cached(tmp_path):
@@ -23,7 +23,8 @@ def test_autotune_choice_is_exact_and_cached(tmp_path):
     w = trajgen.uniform1m(0.05, n_pts=81)  # 10,000 entries, 2,000 query segments
     ds = [30.0, 90.0]
     space = {"bins_factor": (1.0, 2.0), "chunk": (4096, 1024), "grid_waves": (4096, 1024),
-             "tile": (4, 2), "refine": ("queued", "inline"), "precision": ("fp32", "fp64")}
+             "tile": (4, 2), "refine": ("queued", "inline"), "deal": ("dynamic", "static"),
+             "precision": ("fp32", "fp64")}
     cache = str(tmp_path / "tune.json")
     best = autotune.tune(w.D, w.Q, ds, w.window, space=space, reps=1, cache=cache)
     assert not best["cached"]
@@ -33,7 +34,8 @@ def test_autotune_choice_is_exact_and_cached(tmp_path):
     total = 0
     for d in ds:
         got = idx.search(w.Q, d, *w.window, precision=best["precision"], chunk=best["chunk"],
-                         grid_waves=best["grid_waves"], tile=best["tile"], refine=best["refine"])
+                         grid_waves=best["grid_waves"], tile=best["tile"], refine=best["refine"],
+                         deal=best["deal"])
         want = oracle.sort_results(oracle.search(w.Q, w.D, d, *w.window))
         compare(tds.sort_records(got), want, f"tuned d={d}")
         total += want.size
@@ -55,10 +57,11 @@ def test_every_tile_and_mapping_gives_the_same_records():
     assert ref.size > 100
     for tile in (2, 4):
         for refine in ("queued", "inline"):
-            for chunk in (256, 1024, 4096):
+            for chunk, deal in ((256, "dynamic"), (256, "static"), (1024, "dynamic"),
+                                (4096, "static")):
                 got = tds.sort_records(idx.search(w.Q, 4.0, *w.window, tile=tile, chunk=chunk,
-                                                  refine=refine))
-                assert got.tobytes() == ref.tobytes(), (tile, refine, chunk)
+                                                  refine=refine, deal=deal, grid_waves=256))
+                assert got.tobytes() == ref.tobytes(), (tile, refine, chunk, deal)
     with pytest.raises(tds.TdsError):
         idx.search(w.Q, 4.0, *w.window, tile=3)
     idx.close()

@@ -230,3 +230,30 @@ def test_repeated_batch_on_the_same_buffers(setup):
         for i, d in enumerate(ds):
             assert got[i] <= cap
             assert key_sorted(recs[i * cap: i * cap + got[i]].copy()) == direct[(d, shift)]
+
+
+def test_server_host_route_matches_gpu_and_oracle(setup):
+    """Hybrid serving: requests whose candidate ranges hold few pairs are
+    searched on host threads over a host copy of the index, the rest in GPU
+    batches; every request's records are the oracle's and bit-identical to
+    tds_search on its own, whichever side ran it."""
+    w, idx, reqs = setup
+    # the candidate pairs of each request decide its route: a threshold at
+    # their median sends about half of the requests to each side
+    lens = []
+    for Q, d, t0, t1 in reqs:
+        a = np.maximum(Q.ts, t0)
+        b = np.minimum(Q.te, t1)
+        lens.append(int(np.sum(b > a)))
+    srv = tds.Server(idx, max_batch_segments=20000, max_batch_requests=16, slots=2,
+                     result_capacity=1 << 16, default_reserve=64,
+                     cpu_route_tests=int(np.median(lens)) * 125)
+    tickets = [srv.submit(Q, d, t0, t1) for Q, d, t0, t1 in reqs]
+    got = [srv.wait(t)[0] for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert 0 < st["cpu_routed"] < len(reqs), st
+    for (Q, d, t0, t1), g in zip(reqs, got):
+        check_oracle(g, Q, w.D, d, t0, t1)
+        assert key_sorted(g) == key_sorted(idx.search(Q, d, t0, t1))
