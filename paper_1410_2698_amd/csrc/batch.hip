@@ -23,6 +23,30 @@ namespace tds {
 // Host threads of the serving loop's host route (tds_server_params.cpu_route_tests).
 constexpr uint32_t kHostRouteThreads = 4;
 
+namespace {
+
+// Copies the counted records of each request of a batch (at most its
+// capacity) from the device result buffer to the same positions of the pinned
+// host buffer, which the kernel writes directly: a batch's reservations are
+// sized before its counts are known, so one copy of the reserved ranges moves
+// mostly unused records.  Workgroup b takes requests b, b + grid, ...; a
+// record is two 16-byte stores.
+__global__ __launch_bounds__(256) void k_copy_counted(const Request* __restrict__ req,
+                                                      const ReqCounter* __restrict__ rc,
+                                                      uint32_t nreq,
+                                                      const tds_result* __restrict__ src,
+                                                      tds_result* __restrict__ dst) {
+    for (uint32_t r = blockIdx.x; r < nreq; r += gridDim.x) {
+        const Request R = req[r];
+        const uint64_t n = min((uint64_t)rc[r].count, R.out_capacity);
+        const uint4* s = reinterpret_cast<const uint4*>(src + R.out_offset);
+        uint4* d = reinterpret_cast<uint4*>(dst + R.out_offset);
+        for (uint64_t i = threadIdx.x; i < 2 * n; i += blockDim.x) d[i] = s[i];
+    }
+}
+
+}  // namespace
+
 
 Batcher::~Batcher() {
     if (exec_) (void)hipGraphExecDestroy(exec_);
@@ -72,7 +96,8 @@ int Batcher::init(tds_index* idx, uint64_t max_q, uint32_t max_r, uint64_t res_c
     TDS_HIP(hipHostMalloc((void**)&htraj_, max_q * sizeof(uint32_t), hipHostMallocDefault));
     hreq_ = w_->req_host;  // the workspace's pinned control block (max_r requests)
     hrc_ = w_->rc_host;
-    TDS_HIP(hipHostMalloc((void**)&hres_, res_cap * sizeof(tds_result), hipHostMallocDefault));
+    TDS_HIP(hipHostMalloc((void**)&hres_, res_cap * sizeof(tds_result), hipHostMallocMapped));
+    TDS_HIP(hipHostGetDevicePointer((void**)&hres_dev_, hres_, 0));
     return TDS_OK;
 }
 
@@ -148,10 +173,10 @@ int Batcher::launch(uint64_t nq, const tds_request* reqs, uint32_t nreq) {
     TDS_HIP(hipGraphLaunch(exec_, stream_));
     ++replays_;
     TDS_TRY(ws_download(w_, nreq, stream_));
-    if (copy_all_) {
-        if (used_)
-            TDS_HIP(hipMemcpyAsync(hres_, dres_, used_ * sizeof(tds_result), hipMemcpyDeviceToHost,
-                                   stream_));
+    if (copy_all_ && used_) {
+        hipLaunchKernelGGL(k_copy_counted, dim3(std::min<uint32_t>(nreq, 1024u)), dim3(256), 0,
+                           stream_, w_->req, w_->req_ctr, nreq, dres_, hres_dev_);
+        TDS_HIP(hipGetLastError());
     }
     TDS_HIP(hipEventRecord(done_, stream_));
     return TDS_OK;
@@ -627,7 +652,7 @@ int tds_server_submit(tds_server* S, const tds_segments* Q, double d, double t_s
     // host route: a request with few candidate pairs (the cost model: the
     // pair tests of its candidate ranges) is searched on the host
     if (S->host)
-        t->cpu = tds::host_candidates(*S->host, t->q.data(), t->L, t_start, t_end) <=
+        t->cpu = tds::host_candidates(*S->host, t->q.data(), t->L, d, t_start, t_end) <=
                  S->P.cpu_route_tests;
     std::unique_lock<std::mutex> lk(S->mu);
     auto queued = [&] { return S->pending.size() + S->cpu_pending.size(); };

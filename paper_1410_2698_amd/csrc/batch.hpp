@@ -29,7 +29,8 @@ public:
     int finish(uint64_t* counts, tds_stats* stats, bool* table_overflow);
     // Copies each request's records into out (after finish).
     int copy_out(tds_result* out, const uint64_t* counts);
-    // Records of request r in pinned memory (after finish, copy_all mode).
+    // Records of the batch in pinned memory, at their requests' offsets
+    // (after finish, copy_all mode: the counted records of each request).
     const tds_result* host_results() const { return hres_; }
     int run(const tds_segments* Q, const tds_request* reqs, uint32_t nreq, tds_result* out,
             uint64_t* counts, tds_stats* stats);
@@ -58,6 +59,7 @@ private:
     Request* hreq_ = nullptr;     // in the workspace's pinned control block
     ReqCounter* hrc_ = nullptr;   // (owned by the workspace)
     tds_result* hres_ = nullptr;
+    tds_result* hres_dev_ = nullptr;  // hres_ as the device sees it
     bool staged_on_device_ = false;
     bool copy_all_ = false;
     hipGraph_t graph_ = nullptr;

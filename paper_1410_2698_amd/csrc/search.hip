@@ -716,6 +716,19 @@ struct DistArgs {
     uint32_t deal;          // TDS_DEAL_STATIC or TDS_DEAL_DYNAMIC
 };
 
+// FP32 data of a query segment for the closest-approach refinement (one per
+// group lane): its velocity and the time of its sphere centre (the mid time
+// of its clipped extent), each rounded to nearest; d rounded up; and the
+// query's parts of the refinement's error scale.
+struct QRef {
+    float vx, vy, vz, tq;
+    float d;
+    float sc;  // |cx| + |cy| + |cz| of the sphere centre
+    float sv;  // |vx| + |vy| + |vz|
+    float st;  // |a| + |b| + |tq| + 1, [a, b] the clipped extent rounded outwards
+};
+static_assert(sizeof(QRef) == 32, "QRef layout");
+
 // Results go through a stage of stage_cap records per wave in device memory
 // and get their output positions when the stage is flushed (when the next
 // batch of evaluations might not fit, and at the end of every work item):
@@ -728,19 +741,29 @@ struct DistArgs {
 // With by_order set (one request, one work item, re-run to fill successive
 // windows of the host's buffer), a result's position is instead its order
 // among the item's results, which a wave computes the same way on every run.
-struct WaveLDS {
+// Filter record of a query segment as the wave keeps it in LDS: the sphere
+// and the clipped extent of its QF32 record (the candidate range stays in the
+// registers of the query's lane).
+struct QF24 {
+    float cx, cy, cz, R;
+    float a32, b32;
+};
+static_assert(sizeof(QF24) == 24, "QF24 layout");
+
+// The wave's LDS: 10,240 bytes, so that four workgroups of four waves fit in a
+// compute unit's 160 KB.  Per-lane values of the group (the request of query
+// j, its request slot, the staged results of a slot) live in the registers of
+// lane j (ItemState) and are read across lanes by shuffles.
+struct alignas(64) WaveLDS {
     uint32_t queue[2 * kWave];  // < 64 left over + one pair per lane
     uint32_t rq[2 * kWave];     // FP32 form: refined pairs awaiting the FP64 evaluation
-    QF32 qrec[kWave];           // filter records of the item's query group
+    QF24 qrec[kWave];           // filter records of the item's query group
+    QRef qref[kWave];           // FP32 form: refinement data of the group's queries
     QCanon qc[kWave];           // canonical FP64 data of the group's queries
-    uint32_t qr[kWave];         // group lane j -> request
     uint32_t qid[kWave];        // group lane j -> q_seg of its records
     uint32_t qtraj[kWave];      // group lane j -> its trajectory
-    uint32_t rcnt[kWave];       // staged results per request slot (slot = lane)
-    unsigned long long rbase[kWave];  // first reserved position per request slot
-    uint8_t sel[kWave];         // queries of the group being queued (push_set)
-    uint8_t rslot[kWave];       // group lane j -> first lane with j's request
 };
+static_assert(sizeof(WaveLDS) == 10240, "WaveLDS size");
 
 struct ItemState {
     uint32_t c0, c1, qbase, nq;
@@ -751,6 +774,10 @@ struct ItemState {
     uint32_t nst;     // results in the wave's stage
     uint64_t sbase;   // the wave's stage: records [sbase, sbase + stage_cap)
     uint64_t ftests, btests;
+    // per lane j of the group
+    uint32_t qr;      // request of query j
+    uint32_t rslot;   // its request slot: the first lane with the same request
+    uint32_t rcnt;    // staged results of request slot j (slot lanes only)
 };
 
 // Wave-wide ordering of device-memory accesses: stores of one lane are
@@ -767,19 +794,23 @@ __device__ inline void wave_sync_mem() {
 __device__ __forceinline__ void stage_flush(WaveLDS& L, const DistArgs& A, ItemState& S) {
     const uint32_t lane = __lane_id();
     wave_sync_mem();
-    const uint32_t cnt = L.rcnt[lane];  // non-zero only in slot lanes
-    unsigned long long base = 0;
-    if (cnt) base = atomicAdd(&A.rc[L.qr[lane]].count, (unsigned long long)cnt);
-    L.rbase[lane] = base;
-    L.rcnt[lane] = 0;
-    wave_sync();
-    for (uint32_t p = lane; p < S.nst; p += kWave) {
-        const uint32_t meta = A.stage_meta[S.sbase + p];
+    unsigned long long base = 0;  // first reserved position of slot `lane`
+    if (S.rcnt) base = atomicAdd(&A.rc[S.qr].count, (unsigned long long)S.rcnt);
+    S.rcnt = 0;
+    for (uint32_t p0 = 0; p0 < S.nst; p0 += kWave) {
+        const uint32_t p = p0 + lane;
+        const bool act = p < S.nst;
+        const uint32_t meta = act ? A.stage_meta[S.sbase + p] : 0u;
         const uint32_t ql = meta & (kWave - 1);
-        const uint64_t pos = L.rbase[L.rslot[ql]] + (meta >> 6);
-        const Request& R = A.req[L.qr[ql]];
-        if (pos >= A.win_lo && pos - A.win_lo < R.out_capacity)
-            A.out[R.out_offset + (pos - A.win_lo)] = A.stage[S.sbase + p];
+        // every lane takes part in the shuffles
+        const uint32_t slot = (uint32_t)__shfl((int)S.rslot, (int)ql);
+        const uint64_t pos = (uint64_t)__shfl(base, (int)slot) + (meta >> 6);
+        const uint32_t r = (uint32_t)__shfl((int)S.qr, (int)ql);
+        if (act) {
+            const Request& R = A.req[r];
+            if (pos >= A.win_lo && pos - A.win_lo < R.out_capacity)
+                A.out[R.out_offset + (pos - A.win_lo)] = A.stage[S.sbase + p];
+        }
     }
     S.nst = 0;
     wave_sync_mem();
@@ -794,9 +825,10 @@ __device__ __forceinline__ void drain(WaveLDS& L, const uint32_t* queue, uint32_
     const uint32_t pk = act ? queue[head + lane] : 0u;
     const uint32_t ql = pk & (kWave - 1);
     const uint32_t i = S.c0 + (pk >> 6);
+    const uint32_t slot = (uint32_t)__shfl((int)S.rslot, (int)ql);  // every lane takes part
     double t_lo = 0.0, t_hi = 0.0;
     bool hit = false;
-    uint32_t slot = 0, qid = 0, qtraj = 0, eid = 0, etraj = 0;
+    uint32_t qid = 0, qtraj = 0, eid = 0, etraj = 0;
     if (act) {
         const EntryF64 e = A.I.e64[i];
         eid = A.I.seg_id[i];
@@ -804,7 +836,6 @@ __device__ __forceinline__ void drain(WaveLDS& L, const uint32_t* queue, uint32_
         const QCanon q = L.qc[ql];
         qid = L.qid[ql];
         qtraj = L.qtraj[ql];
-        slot = L.rslot[ql];
         hit = canon_eval<true>(q, e.x, e.y, e.z, e.vx, e.vy, e.vz, e.ts, e.te, &t_lo, &t_hi);
         if (A.Q.ent) {
             // self-join: pairs of one trajectory are not results, and a record
@@ -847,11 +878,9 @@ __device__ __forceinline__ void drain(WaveLDS& L, const uint32_t* queue, uint32_
         const uint32_t leader = (uint32_t)__ffsll((unsigned long long)rem) - 1u;
         const uint32_t sl = uniform((uint32_t)__shfl((int)slot, (int)leader));
         const uint64_t mm = ballot(hit && slot == sl);
-        const uint32_t c = L.rcnt[sl];
+        const uint32_t c = uniform((uint32_t)__builtin_amdgcn_readlane((int)S.rcnt, (int)sl));
         if (hit && slot == sl) idx = c + (uint32_t)__popcll(mm & lanemask_lt());
-        wave_sync();
-        if (lane == leader) L.rcnt[sl] = c + (uint32_t)__popcll(mm);
-        wave_sync();
+        if (lane == sl) S.rcnt = c + (uint32_t)__popcll(mm);
         rem &= ~mm;
     }
     if (hit) {
@@ -887,28 +916,30 @@ __device__ __forceinline__ void enqueue(WaveLDS& L, uint64_t m, bool pass, uint3
 //   (3) min(|Dm - h W|, |Dm + h W|)     when the vertex -Dm.W / |W|^2 lies
 //                                       outside [-h, h] for certain.
 // Error budget (u = 2^-24): rounding of the FP32 data to nearest and the
-// operations forming Dm and W move D(tau) by at most about 10 u S, S = |cq|1 +
-// |cl|1 + (|vq|1 + |vl|1)(|a| + |b| + |tq| + |tl| + 1) (L1 norms; this also
-// covers the FP64 rounding of the canonical evaluation, about 1e-15 S); E =
-// 2^-17 S is used.  The squared forms below are evaluated with errors below
-// 10 u (|Dm|1 + h|W|1)^2 and 20 u |Dm|1^2 |W|1^2, bounded by 2^-17 and 2^-16
-// times those magnitudes.  Every test is "value > bound", so overflow to
-// infinity or NaN never drops a pair.
-__device__ __forceinline__ bool refine32(float cqx, float cqy, float cqz, float vqx, float vqy,
-                                         float vqz, float tq, float qa, float qb, float clx,
-                                         float cly, float clz, float vlx, float vly, float vlz,
-                                         float tl, float la, float lb, float d) {
-    const float a = fmaxf(qa, la), b = fminf(qb, lb);
+// operations forming Dm and W move D(tau) by at most about 10 u S0, S0 =
+// |cq|1 + |cl|1 + (|vq|1 + |vl|1)(|a| + |b| + |tq| + |tl| + 1) (L1 norms; this
+// also covers the FP64 rounding of the canonical evaluation, about 1e-15 S0).
+// The scale used is S = (sc_q + sc_l) + (sv_q + sv_l)(st_q + st_l) >= S0 (the
+// parts of each side are precomputed, QRef and the candidate's registers;
+// |a| + |b| <= |qa| + |qb| + |la| + |lb| since a is qa or la and b is qb or
+// lb), and E = 2^-17 S.  The squared forms below are evaluated with errors
+// below 10 u (|Dm|1 + h|W|1)^2 and 20 u |Dm|1^2 |W|1^2, bounded by 2^-17 and
+// 2^-16 times those magnitudes.  |W| comes from the hardware square root
+// (within 1 ulp; its operand is kept normal by adding 2^-100, which only
+// raises it) and is inflated by 2^-18.  Every test is "value > bound", so
+// overflow to infinity or NaN never drops a pair.
+__device__ __forceinline__ bool refine32(const QF24& f, const QRef& r, float clx, float cly,
+                                         float clz, float vlx, float vly, float vlz, float tl,
+                                         float la, float lb, float scl, float svl, float stl) {
+    const float a = fmaxf(f.a32, la), b = fminf(f.b32, lb);
     const float tm = 0.5f * (a + b), h = 0.5f * (b - a);
-    const float dq = tm - tq, dl = tm - tl;
-    const float dx = (cqx - clx) + (vqx * dq - vlx * dl);
-    const float dy = (cqy - cly) + (vqy * dq - vly * dl);
-    const float dz = (cqz - clz) + (vqz * dq - vlz * dl);
-    const float wx = vqx - vlx, wy = vqy - vly, wz = vqz - vlz;
-    const float vsum = (fabsf(vqx) + fabsf(vqy) + fabsf(vqz)) + (fabsf(vlx) + fabsf(vly) + fabsf(vlz));
-    const float S = (fabsf(cqx) + fabsf(cqy) + fabsf(cqz)) + (fabsf(clx) + fabsf(cly) + fabsf(clz)) +
-                    vsum * ((fabsf(a) + fabsf(b)) + (fabsf(tq) + fabsf(tl)) + 1.0f);
-    const float R = (d + 0x1p-17f * S) * (1.0f + 0x1p-20f);
+    const float dq = tm - r.tq, dl = tm - tl;
+    const float dx = (f.cx - clx) + (r.vx * dq - vlx * dl);
+    const float dy = (f.cy - cly) + (r.vy * dq - vly * dl);
+    const float dz = (f.cz - clz) + (r.vz * dq - vlz * dl);
+    const float wx = r.vx - vlx, wy = r.vy - vly, wz = r.vz - vlz;
+    const float S = (r.sc + scl) + (r.sv + svl) * (r.st + stl);
+    const float R = (r.d + 0x1p-17f * S) * (1.0f + 0x1p-20f);
     const float R2 = (R * R) * (1.0f + 0x1p-20f);
     const float dm1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
     const float w1 = fabsf(wx) + fabsf(wy) + fabsf(wz);
@@ -918,7 +949,7 @@ __device__ __forceinline__ bool refine32(float cqx, float cqy, float cqz, float 
     const float span = dm1 + h * w1;
     const float errA = 0x1p-17f * (span * span);
     // (1)
-    const float hw = (h * sqrtf(WW)) * (1.0f + 0x1p-18f);
+    const float hw = (h * __builtin_amdgcn_sqrtf(WW + 0x1p-100f)) * (1.0f + 0x1p-18f);
     const float Rh = R + hw;
     if (Dm2 - errA > (Rh * Rh) * (1.0f + 0x1p-20f)) return false;
     // (2), multiplied through by |W|^2
@@ -935,11 +966,37 @@ __device__ __forceinline__ bool refine32(float cqx, float cqy, float cqz, float 
     return true;
 }
 
+// The query's refinement data, from its canonical data and filter record.
+__device__ __forceinline__ QRef qref_of(const QCanon& q, const QF32& f) {
+    QRef r;
+    r.vx = __double2float_rn(q.vx);
+    r.vy = __double2float_rn(q.vy);
+    r.vz = __double2float_rn(q.vz);
+    r.tq = __double2float_rn(0.5 * (q.aq + q.bq));
+    r.d = __double2float_ru(q.d);
+    r.sc = (fabsf(f.cx) + fabsf(f.cy)) + fabsf(f.cz);
+    r.sv = (fabsf(r.vx) + fabsf(r.vy)) + fabsf(r.vz);
+    r.st = ((fabsf(f.a32) + fabsf(f.b32)) + fabsf(r.tq)) + 1.0f;
+    return r;
+}
+
+// The candidate's parts of the refinement's error scale (see refine32).
+struct ERef {
+    float sc, sv, st;
+};
+__device__ __forceinline__ ERef eref_of(float cx, float cy, float cz, const EntryV32& v, float ts,
+                                        float te) {
+    ERef e;
+    e.sc = (fabsf(cx) + fabsf(cy)) + fabsf(cz);
+    e.sv = (fabsf(v.vx) + fabsf(v.vy)) + fabsf(v.vz);
+    e.st = (fabsf(ts) + fabsf(te)) + fabsf(v.tm);
+    return e;
+}
+
 // FP32 form: the closest-approach refinement (refine32) of `cnt` <= 64 queued
 // sphere survivors from position `head`, one per lane; the pairs it keeps go
 // to the refined queue.  A stage of its own, so that its registers are not
-// held across the filter's tile loop and searches with few survivors seldom
-// run it.
+// held across the filter's walk and searches with few survivors seldom run it.
 __device__ __forceinline__ void refine_step(WaveLDS& L, uint32_t head, uint32_t cnt,
                                             ItemState& S, const DistArgs& A) {
     const uint32_t lane = __lane_id();
@@ -951,15 +1008,13 @@ __device__ __forceinline__ void refine_step(WaveLDS& L, uint32_t head, uint32_t 
         const uint32_t i = S.c0 + (pk >> 6);
         const EntryF32 e = A.I.e32[i];
         const EntryV32 v = A.I.ev32[i];
-        const QF32 f = L.qrec[ql];
+        const QF24 f = L.qrec[ql];
         keep = true;
         // an unbounded sphere (stored centre 0) passes unrefined
         if (e.r < INFINITY && f.R < INFINITY) {
-            const QCanon& q = L.qc[ql];
-            keep = refine32(f.cx, f.cy, f.cz, __double2float_rn(q.vx), __double2float_rn(q.vy),
-                            __double2float_rn(q.vz), __double2float_rn(0.5 * (q.aq + q.bq)), f.a32,
-                            f.b32, e.cx, e.cy, e.cz, v.vx, v.vy, v.vz, v.tm, e.ts, e.te,
-                            __double2float_ru(q.d));
+            const ERef x = eref_of(e.cx, e.cy, e.cz, v, e.ts, e.te);
+            keep = refine32(f, L.qref[ql], e.cx, e.cy, e.cz, v.vx, v.vy, v.vz, v.tm, e.ts, e.te,
+                            x.sc, x.sv, x.st);
         }
     }
     const uint64_t m = ballot(keep);
@@ -1026,7 +1081,7 @@ __device__ __forceinline__ void drain_rest(WaveLDS& L, ItemState& S, const DistA
 // Start of a work item: the canonical data, record ids and request of each
 // query segment of the group, and its request slot (the first lane of the
 // group with the same request).
-__device__ __forceinline__ void item_begin(WaveLDS& L, const DistArgs& A, const ItemState& S) {
+__device__ __forceinline__ void item_begin(WaveLDS& L, const DistArgs& A, ItemState& S) {
     const uint32_t lane = __lane_id();
     const bool has = lane < S.nq;
     uint32_t r = 0;
@@ -1056,11 +1111,11 @@ __device__ __forceinline__ void item_begin(WaveLDS& L, const DistArgs& A, const 
     }
     wave_sync();
     L.qc[lane] = q;
-    L.qr[lane] = r;
     L.qid[lane] = qid;
     L.qtraj[lane] = qtraj;
-    L.rslot[lane] = (uint8_t)slot;
-    L.rcnt[lane] = 0;
+    S.qr = r;
+    S.rslot = slot;
+    S.rcnt = 0;
     wave_sync();
 }
 
@@ -1076,124 +1131,69 @@ __device__ __forceinline__ float lane_val(float v, uint32_t j) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)j));
 }
 
-// FP32 filter of one query (its QF32 record q, read from LDS at a wave-uniform
+// FP32 filter of one query (its record q, read from LDS at a wave-uniform
 // address, i.e. broadcast to every lane) against the candidate held in this
-// lane.  A pair can only be a result if the two
-// bounding spheres come within d (the error margins are folded into R and r)
-// and the outward-rounded time extents overlap strictly.  With kTime false
-// the caller has established that every pair of the slot overlaps in time;
-// with kUniform true, that every query's candidate range covers it.
-template <bool kUniform, bool kTime>
-__device__ __forceinline__ bool pass32(const QF32& q, uint32_t cand, float ecx, float ecy,
-                                       float ecz, float er, float ets, float ete) {
-    const float dx = ecx - q.cx, dy = ecy - q.cy, dz = ecz - q.cz;
-    const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const float R = q.R + er;
-    bool p = s <= R * R;
+// lane.  A pair can only be a result if the two bounding spheres come within
+// d (the error margins are folded into R and r) and the outward-rounded time
+// extents overlap strictly.  With kTime false the caller has established
+// that every pair of the slot overlaps in time.
+template <bool kTime>
+__device__ __forceinline__ bool pass32(const QF24& q, float ecx, float ecy, float ecz, float er,
+                                       float ets, float ete) {
+    bool p = sphere_pass(q.cx, q.cy, q.cz, q.R, ecx, ecy, ecz, er);
     if (kTime) p = p & (q.a32 < ete) & (ets < q.b32);
-    if (!kUniform) p = p & (cand >= q.lo) & (cand < q.hi);
     return p;
 }
 
-// Bounding-box test of a query sphere (cx, cy, cz, R) against a block box
-// (lx, ly, lz, hx, hy, hz, rmax).  It is the filter's own arithmetic with the
-// centre distance replaced by the distance to the box: per axis the gap
-// fl(lo - c) or fl(c - hi) is at most the filter's |fl(c_l - c)| for every
-// centre c_l in the box (rounding to nearest is monotone and odd), squares,
-// FMAs and fl(R + r) are monotone in their operands, and r <= rmax; so
-// whenever the filter passes a pair of the block, this test passes.
-__device__ __forceinline__ bool box_pass(const float (&b)[7], float cx, float cy, float cz,
-                                         float R) {
-    const float gx = fmaxf(fmaxf(b[0] - cx, cx - b[3]), 0.f);
-    const float gy = fmaxf(fmaxf(b[1] - cy, cy - b[4]), 0.f);
-    const float gz = fmaxf(fmaxf(b[2] - cz, cz - b[5]), 0.f);
-    const float s = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
-    const float Rr = R + b[6];
-    return s <= Rr * Rr;
-}
-
-// Tests the queries whose bits are set in mk (query j = bit j of the group,
-// at most 32 of them) against the candidate held in the lane.  Queries are
-// taken from the highest down and each outcome is shifted in at the bottom
-// (bits = 2 bits + pass), so bit p of the result belongs to the p-th lowest
-// query of mk.  mk is wave uniform: the walk over its bits is scalar; the
-// query records are read from LDS at a wave-uniform address.
-template <bool kUniform, bool kTime>
-__device__ __forceinline__ uint32_t test_set(const WaveLDS& L, uint64_t mk, uint32_t cand,
-                                             float ecx, float ecy, float ecz, float er, float ets,
-                                             float ete) {
-    uint32_t bits = 0;
-    while (mk) {
-        const uint32_t j = 63u - (uint32_t)__builtin_clzll(mk);
-        mk ^= 1ull << j;
-        const QF32 q = L.qrec[j];
-        bits = 2u * bits + (uint32_t)pass32<kUniform, kTime>(q, cand, ecx, ecy, ecz, er, ets, ete);
-    }
-    return bits;
-}
-
-
-// Queues the pairs recorded in bits (see test_set) for the candidate of the
-// lane, one pair per lane per round.  With kInline, each pair first goes
-// through the closest-approach refinement here, from the candidate's FP32
-// data in registers (its motion loaded once per call) and the query's in
-// LDS; otherwise the refinement is a stage of the queue (refine_step).
-template <bool kInline>
-__device__ __forceinline__ void push_set(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                         uint32_t cand, uint32_t bits, uint64_t mk, float ecx,
-                                         float ecy, float ecz, float er, float ets, float ete) {
-    const uint32_t lane = __lane_id();
-    // ascending list of the queries of mk
-    wave_sync();
-    if ((mk >> lane) & 1ull) L.sel[__popcll(mk & lanemask_lt())] = (uint8_t)lane;
-    wave_sync();
-    EntryV32 ev = {0.f, 0.f, 0.f, 0.f};
-    if (kInline && bits) ev = A.I.ev32[cand];  // lanes with bits hold candidates of the chunk
-    const uint32_t code = (cand - S.c0) << 6;
-    uint32_t b = bits;
-    for (;;) {
-        const bool act = b != 0;
-        if (!ballot(act)) break;
-        bool keep = false;
-        uint32_t j = 0;
-        if (act) {
-            j = L.sel[__builtin_ctz(b)];
-            b &= b - 1u;
-            keep = true;
-            if (kInline) {
-                const QF32& f = L.qrec[j];
-                // an unbounded sphere (stored centre 0) passes unrefined
-                if (er < INFINITY && f.R < INFINITY) {
-                    const QCanon& q = L.qc[j];
-                    keep = refine32(f.cx, f.cy, f.cz, __double2float_rn(q.vx),
-                                    __double2float_rn(q.vy), __double2float_rn(q.vz),
-                                    __double2float_rn(0.5 * (q.aq + q.bq)), f.a32, f.b32, ecx,
-                                    ecy, ecz, ev.vx, ev.vy, ev.vz, ev.tm, ets, ete,
-                                    __double2float_ru(q.d));
-                }
-            }
-        }
-        const uint64_t m = ballot(keep);
-        if (keep) L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
-        S.qn += (uint32_t)__popcll(m);
-        if (S.qn >= kWave) drain_full(L, S, A);
-    }
-}
-
-// One 64-candidate slot against the queries of mask mk, at most 32 at a time
-// (more than 32 survivors of one block box is rare: then the queries of lanes
-// 0-31 and 32-63 go in turn).
+// One 64-candidate slot (candidate `cand` in the lane) against the queries of
+// mask mk, in ascending order.  For each query, the sphere and time test of
+// every lane's candidate, then, with kInline, the closest-approach refinement
+// of the pairs that passed (the candidate's motion is loaded at the slot's
+// first survivor); the pairs kept are queued, and full batches of 64 go on to
+// the FP64 evaluation.  Without kInline the sphere survivors are queued and
+// the refinement is a stage of the queue (refine_step).  mk is wave uniform:
+// the walk over its bits is scalar, and the query records are read from LDS
+// at wave-uniform addresses.  With kUniform false, the queries of `part`
+// have candidate ranges that cover the slot only in part: their bounds are
+// read from the registers of their lanes (qlo, qhi) and checked per pair.
 template <bool kUniform, bool kTime, bool kInline>
 __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemState& S,
-                                          uint64_t mk, uint32_t cand, float ecx, float ecy,
-                                          float ecz, float er, float ets, float ete) {
+                                          uint64_t mk, uint64_t part, uint32_t qlo, uint32_t qhi,
+                                          uint32_t cand, float ecx, float ecy, float ecz,
+                                          float er, float ets, float ete) {
+    const uint32_t code = (cand - S.c0) << 6;  // used in lanes whose candidate is in the chunk
+    bool motion = false;
+    EntryV32 ev = {0.f, 0.f, 0.f, 0.f};
     while (mk) {
-        // all of mk, or its queries 0..31 first when it has more than 32
-        const uint64_t part = (__popcll(mk) > 32) ? (mk & 0xFFFFFFFFull) : mk;
-        mk ^= part;
-        const uint32_t bits = test_set<kUniform, kTime>(L, part, cand, ecx, ecy, ecz, er, ets, ete);
-        if (ballot(bits != 0u))
-            push_set<kInline>(L, A, S, cand, bits, part, ecx, ecy, ecz, er, ets, ete);
+        const uint32_t j = (uint32_t)__builtin_ctzll(mk);
+        mk &= mk - 1u;
+        const QF24 q = L.qrec[j];
+        bool p = pass32<kTime>(q, ecx, ecy, ecz, er, ets, ete);
+        if (!kUniform && ((part >> j) & 1ull)) {
+            const uint32_t lo = uniform((uint32_t)__builtin_amdgcn_readlane((int)qlo, (int)j));
+            const uint32_t hi = uniform((uint32_t)__builtin_amdgcn_readlane((int)qhi, (int)j));
+            p = p & (cand >= lo) & (cand < hi);
+        }
+        uint64_t m = ballot(p);
+        if (!m) continue;
+        if (kInline) {
+            if (!motion) {
+                motion = true;
+                // lanes outside the chunk load its last entry (they never pass)
+                const uint32_t i = (cand >= S.c0 && cand < S.c1) ? cand : S.c1 - 1u;
+                ev = A.I.ev32[i];
+            }
+            // an unbounded sphere (stored centre 0) passes unrefined
+            if (p && er < INFINITY && q.R < INFINITY) {
+                const ERef ex = eref_of(ecx, ecy, ecz, ev, ets, ete);
+                p = refine32(q, L.qref[j], ecx, ecy, ecz, ev.vx, ev.vy, ev.vz, ev.tm, ets, ete,
+                             ex.sc, ex.sv, ex.st);
+            }
+            m = ballot(p);
+        }
+        if (p) L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
+        S.qn += (uint32_t)__popcll(m);
+        if (S.qn >= kWave) drain_full(L, S, A);
     }
 }
 
@@ -1225,7 +1225,8 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
         q.b = f.b32;
         q.lo = f.lo;
         q.hi = f.hi;
-        L.qrec[lane] = f;
+        L.qrec[lane] = QF24{f.cx, f.cy, f.cz, f.R, f.a32, f.b32};
+        if (kInline || S.refine) L.qref[lane] = qref_of(L.qc[lane], f);
     }
     wave_sync();
     const bool all_overlap =
@@ -1270,8 +1271,11 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
         for (int k = 0; k < kCpl; ++k) {
             const uint32_t b0 = tile + k * kWave;  // first entry of the block
             if (b0 >= S.c1) break;
-            uint64_t mk = has_mask;
-            if (!kUniform) mk &= ballot(q.lo < b0 + kWave && q.hi > b0);
+            uint64_t mk = has_mask, part = 0;
+            if (!kUniform) {
+                mk &= ballot(q.lo < b0 + kWave && q.hi > b0);
+                part = mk & ~ballot(q.lo <= b0 && q.hi >= b0 + kWave);
+            }
             if (cull && mk) {
                 const uint32_t bl = tb + k - wb;
                 float box[7];
@@ -1285,11 +1289,11 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
             S.ftests += (uint64_t)__popcll(mk) * (uint64_t)__popcll(vm);
             // the time test can be dropped only on full slots
             if (all_overlap && vm == ~0ull)
-                slot_fp32<kUniform, false, kInline>(L, A, S, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
-                                           ets[k], ete[k]);
+                slot_fp32<kUniform, false, kInline>(L, A, S, mk, part, q.lo, q.hi, cand[k], ecx[k],
+                                                    ecy[k], ecz[k], er[k], ets[k], ete[k]);
             else
-                slot_fp32<kUniform, true, kInline>(L, A, S, mk, cand[k], ecx[k], ecy[k], ecz[k], er[k],
-                                          ets[k], ete[k]);
+                slot_fp32<kUniform, true, kInline>(L, A, S, mk, part, q.lo, q.hi, cand[k], ecx[k],
+                                                   ecy[k], ecz[k], er[k], ets[k], ete[k]);
         }
     }
 }
@@ -1453,26 +1457,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             have = k < part_lo(grp + 1);
         }
     }
-    // per-workgroup counters (folded into the header by k_stats_fold)
-    __shared__ BlockStats ws[kWavesPerBlock];
+    // per-workgroup counters (folded into the header by k_stats_fold), each
+    // wave's in the front of its own LDS, which it no longer uses
     const uint32_t wid = threadIdx.x / kWave;
+    wave_sync();
     if (lane == 0) {
-        ws[wid].tests = tests;
-        ws[wid].evals = evals_total;
-        ws[wid].ftests = ftests;
-        ws[wid].btests = btests;
-        ws[wid].flushes = flushes;
-        ws[wid].pad[0] = ws[wid].pad[1] = ws[wid].pad[2] = 0;
+        BlockStats& w = *reinterpret_cast<BlockStats*>(wl[wid].queue);
+        w.tests = tests;
+        w.evals = evals_total;
+        w.ftests = ftests;
+        w.btests = btests;
+        w.flushes = flushes;
+        w.pad[0] = w.pad[1] = w.pad[2] = 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        BlockStats b = ws[0];
+        BlockStats b = *reinterpret_cast<const BlockStats*>(wl[0].queue);
         for (int k = 1; k < kWavesPerBlock; ++k) {
-            b.tests += ws[k].tests;
-            b.evals += ws[k].evals;
-            b.ftests += ws[k].ftests;
-            b.btests += ws[k].btests;
-            b.flushes += ws[k].flushes;
+            const BlockStats& w = *reinterpret_cast<const BlockStats*>(wl[k].queue);
+            b.tests += w.tests;
+            b.evals += w.evals;
+            b.ftests += w.ftests;
+            b.btests += w.btests;
+            b.flushes += w.flushes;
         }
         A.bstats[blockIdx.x] = b;
     }

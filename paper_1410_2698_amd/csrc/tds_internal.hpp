@@ -292,6 +292,20 @@ inline void dfree(void* p) {
 
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// FP64 -> FP32 conversions rounded to nearest, downwards and upwards (host
+// and device code alike).
+__host__ __device__ inline float f32_rn(double x) { return (float)x; }
+__host__ __device__ inline float f32_ru(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+__host__ __device__ inline float f32_rd(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = nextafterf(f, -INFINITY);
+    return f;
+}
+
 // FP32 bounding sphere of the segment from a to b (FP64 end points), used by
 // the FP32 candidate filter: centre rounded to nearest; radius
 // (r + extra)(1 + 8u) + 2u|c| + 1e-18 rounded up, u = 2^-24.  The margin
@@ -300,25 +314,55 @@ inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1)
 // of the canonical arithmetic, so a pair whose canonical evaluation is a
 // result always passes the filter.  Beyond 1e18 the radius is +inf and the
 // centre 0 (the pair always passes).
-__device__ inline void sphere32(double ax, double ay, double az, double bx, double by, double bz,
-                                double extra, float& cx32, float& cy32, float& cz32, float& r32) {
+__host__ __device__ inline void sphere32(double ax, double ay, double az, double bx, double by,
+                                         double bz, double extra, float& cx32, float& cy32,
+                                         float& cz32, float& r32) {
     const double u = 5.9604644775390625e-08;
     const double cx = 0.5 * (ax + bx), cy = 0.5 * (ay + by), cz = 0.5 * (az + bz);
     const double hx = 0.5 * (bx - ax), hy = 0.5 * (by - ay), hz = 0.5 * (bz - az);
     const double rr = sqrt(hx * hx + hy * hy + hz * hz);
     const double cn = sqrt(cx * cx + cy * cy + cz * cz);
     const double R = (rr + extra) * (1.0 + 8.0 * u) + 2.0 * u * cn + 1e-18;
-    cx32 = __double2float_rn(cx);
-    cy32 = __double2float_rn(cy);
-    cz32 = __double2float_rn(cz);
+    cx32 = f32_rn(cx);
+    cy32 = f32_rn(cy);
+    cz32 = f32_rn(cz);
     if (R < 1e18 && cn < 1e18) {
-        r32 = __double2float_ru(R);
+        r32 = f32_ru(R);
     } else {
         // infinite radius, centre at the origin: every distance test against
         // it passes without forming inf - inf
         cx32 = cy32 = cz32 = 0.f;
-        r32 = __int_as_float(0x7f800000);
+        r32 = INFINITY;
     }
+}
+
+// The FP32 filter of a pair: the bounding spheres of the query (centre c,
+// radius R = its own radius + d + margins) and of the entry come within
+// reach, and the outward-rounded time extents overlap strictly.  A pair that
+// fails cannot be a result of the canonical evaluation (sphere32).
+__host__ __device__ inline bool sphere_pass(float cx, float cy, float cz, float R, float ecx,
+                                            float ecy, float ecz, float er) {
+    const float dx = ecx - cx, dy = ecy - cy, dz = ecz - cz;
+    const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float Rr = R + er;
+    return s <= Rr * Rr;
+}
+
+// Bounding-box test of a query sphere (cx, cy, cz, R) against a block box
+// (lx, ly, lz, hx, hy, hz, rmax).  It is the filter's own arithmetic with the
+// centre distance replaced by the distance to the box: per axis the gap
+// fl(lo - c) or fl(c - hi) is at most the filter's |fl(c_l - c)| for every
+// centre c_l in the box (rounding to nearest is monotone and odd), squares,
+// FMAs and fl(R + r) are monotone in their operands, and r <= rmax; so
+// whenever the filter passes a pair of the block, this test passes.
+__host__ __device__ inline bool box_pass(const float (&b)[7], float cx, float cy, float cz,
+                                         float R) {
+    const float gx = fmaxf(fmaxf(b[0] - cx, cx - b[3]), 0.f);
+    const float gy = fmaxf(fmaxf(b[1] - cy, cy - b[4]), 0.f);
+    const float gz = fmaxf(fmaxf(b[2] - cz, cz - b[5]), 0.f);
+    const float s = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+    const float Rr = R + b[6];
+    return s <= Rr * Rr;
 }
 
 // Stable LSD radix sort of (key, value) pairs on `stream`; keys_bits is the
@@ -357,15 +401,18 @@ struct HostIndex {
     uint64_t n = 0;
     uint32_t m = 0;
     std::vector<EntryF64> e64;
+    std::vector<EntryF32> e32;
+    std::vector<BlockBox> bbox;  // spatial layout only
     std::vector<uint32_t> seg_id, traj, bin_first;
     std::vector<double> cmax_te, lo_ts;
 };
 // Copies the index tables to host memory (waits for the device).
 int host_index_load(const tds_index* idx, HostIndex* h);
-// Sum over the query segments of Q (8 arrays of L values, xs .. te, host
-// memory) of their candidate range lengths in the window: the pair tests a
-// search of Q makes without spatial pruning.
-uint64_t host_candidates(const HostIndex& h, const double* q, uint64_t L, double t0, double t1);
+// The pair tests a host search of Q (8 arrays of L values, xs .. te, host
+// memory) at distance d makes: over the query segments active in the window,
+// the candidates of their ranges left after the block-box test.
+uint64_t host_candidates(const HostIndex& h, const double* q, uint64_t L, double d, double t0,
+                         double t1);
 // The search of Q (validated values) on the host; records in query order.
 void host_search(const HostIndex& h, const double* q, const uint32_t* qtraj, uint64_t L,
                  double d, double t0, double t1, std::vector<tds_result>* out);

@@ -152,11 +152,15 @@ int run_search(int argc, char** argv, bool self_join) {
     const double d = atof(argv[a++]), t0 = atof(argv[a++]), t1 = atof(argv[a++]);
     const uint64_t cap = strtoull(argv[a++], nullptr, 10);
     const char* path = argv[a++];
-    const uint32_t num_bins = (a < argc) ? (uint32_t)atoi(argv[a]) : 0u;  // 0: automatic
+    const uint32_t num_bins = (a < argc) ? (uint32_t)atoi(argv[a++]) : 0u;  // 0: automatic
+    const uint32_t refine = (a < argc) ? (uint32_t)atoi(argv[a++]) : 0u;    // TDS_REFINE_*
+    const uint32_t tile = (a < argc) ? (uint32_t)atoi(argv[a++]) : 0u;
     tds_index* idx = build(D, layout, num_bins);
     tds_search_params p;
     tds_search_params_default(&p);
     p.precision = prec;
+    p.refine = refine;
+    p.tile = tile;
     p.grid_waves = 64;  // 16 persistent workgroups: fewer idle host threads
     std::vector<tds_result> out(std::max<uint64_t>(cap, 1));
     uint64_t n = 0;
@@ -188,7 +192,7 @@ int run_hostsearch(char** argv) {
     std::vector<tds_result> out;
     uint64_t cand = 0;
     if (st == TDS_OK) {
-        cand = tds::host_candidates(h, Qc.col(0), Qc.n, t0, t1);
+        cand = tds::host_candidates(h, Qc.col(0), Qc.n, d, t0, t1);
         tds::host_search(h, Qc.col(0), Q.traj.data(), Qc.n, d, t0, t1, &out);
     }
     write_records(argv[7], out, out.size());

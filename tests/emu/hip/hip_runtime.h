@@ -113,6 +113,12 @@ inline int __builtin_amdgcn_readlane(int v, int l) { return emu_xchg(v, (unsigne
 // the sources apply it to wave-uniform values only, which every lane holds
 inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
 inline void __builtin_amdgcn_wave_barrier() { emu_wave().bar->arrive_and_wait(); }
+// the hardware square root is accurate to 1 ulp: the emulation errs low by
+// one ulp, the side a lower bound built on it must tolerate
+inline float __builtin_amdgcn_sqrtf(float x) {
+    const float r = std::sqrt(x);
+    return (r > 0.f && r < INFINITY) ? std::nextafter(r, 0.f) : r;
+}
 #define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __HIP_MEMORY_SCOPE_AGENT 3
 #define __HIP_MEMORY_SCOPE_WORKGROUP 2

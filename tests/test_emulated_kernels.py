@@ -29,6 +29,7 @@ RESULT_DTYPE = np.dtype([("q_seg", "<u4"), ("e_seg", "<u4"), ("q_traj", "<u4"), 
                          ("t_lo", "<f8"), ("t_hi", "<f8")])
 TEMPORAL, SPATIAL = 1, 2  # index layouts (C ABI values)
 FP64, FP32 = 1, 2         # search precisions (C ABI values)
+QUEUED, INLINE = 1, 2     # places of the FP32 refinement (C ABI values)
 
 
 def columns(S):
@@ -82,6 +83,12 @@ def _jobs():
     for prec in (FP32, FP64):
         J[f"flush_{prec}"] = ("search", (tiny.D, tiny.D),
                               [SPATIAL, prec, 250.0, 0.0, 49.0, 600000])
+    # the closest-approach refinement inline in the filter walk, at both
+    # tiles, on a sparse and a dense search (at d = 250 every time-overlapping
+    # pair passes every test)
+    for d, tile in [(8.0, 2), (30.0, 4), (250.0, 2)]:
+        J[f"inline_{d:g}_{tile}"] = ("search", (tiny.D, tiny.Q),
+                                     [SPATIAL, FP32, d, 0.0, 49.0, 100000, 0, INLINE, tile])
     # more query buckets than the parted slot counters take (2,000 bins:
     # 8,000 buckets, one counter part); merged keys (over 16,384 bins) take
     # minutes here and are covered by the GPU tests
@@ -91,6 +98,7 @@ def _jobs():
     J["selfjoin"] = ("selfjoin", (tiny04.D,), [SPATIAL, FP32, 4.0, 0.0, 49.0, 200000])
     # the serving loop's host route over a host copy of the index
     J["hostsearch"] = ("hostsearch", (tiny.D, tiny.Q), [30.0, 3.5, 40.25])
+    J["hostsearch_all"] = ("hostsearch", (tiny.D, tiny.Q), [250.0, 3.5, 40.25])
     J["merge_random"] = ("merge", _merge_random(), [3000])
     J["merge_degenerate"] = ("merge", _merge_degenerate(), [600])
     J["merge_degenerate_cap3"] = ("merge", _merge_degenerate(), [3])
@@ -204,6 +212,18 @@ def test_search_emulated_stage_flushes(emu, prec):
     same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
 
 
+@pytest.mark.parametrize("d,tile", [(8.0, 2), (30.0, 4), (250.0, 2)])
+def test_search_emulated_inline_refinement(emu, d, tile):
+    (st, n, ftests, _), out = result(emu, f"inline_{d:g}_{tile}")
+    w = emu[1]["tiny"]
+    assert st == 0
+    want = oracle.search(w.Q, w.D, d, 0.0, 49.0)
+    assert want.size > 0 and n == want.size and ftests > 0
+    if d == 250.0:
+        assert want.size == len(w.Q) * 100
+    same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
+
+
 def test_search_emulated_many_bins(emu):
     (st, n, _, _), out = result(emu, "many_bins")
     w = emu[1]["tiny"]
@@ -229,16 +249,25 @@ def test_self_join_emulated(emu):
     same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
 
 
-def test_host_search_emulated(emu):
+@pytest.mark.parametrize("job,d", [("hostsearch", 30.0), ("hostsearch_all", 250.0)])
+def test_host_search_emulated(emu, job, d):
     """The host search of the serving loop's host route (host copy of the
-    index, same candidate ranges and canonical FP64 evaluation) against the
-    oracle, in a window that clips segments at both ends."""
-    (st, n, cand), out = result(emu, "hostsearch")
+    index, same candidate ranges, FP32 filter and canonical FP64 evaluation)
+    against the oracle, in a window that clips segments at both ends.  At
+    d = 30 the block boxes prune candidates; at d = 250 every time-overlapping
+    pair is a result and nothing is pruned."""
+    (st, n, cand), out = result(emu, job)
     w = emu[1]["tiny"]
     assert st == 0
-    want = oracle.search(w.Q, w.D, 30.0, 3.5, 40.25)
+    want = oracle.search(w.Q, w.D, d, 3.5, 40.25)
     assert want.size > 100 and n == want.size
-    assert cand >= 5 * 36 * 100  # at least one candidate per trajectory per clipped segment
+    # pair tests after the box test: at least the results; at d = 250 all of
+    # the clipped segments' candidate ranges (at least 5 x 36 x 100 pairs),
+    # at d = 30 fewer
+    assert cand >= n
+    all_pairs = result(emu, "hostsearch_all")[0][2]
+    assert all_pairs >= 5 * 36 * 100
+    assert cand == all_pairs if d == 250.0 else cand < all_pairs
     got = np.fromfile(out, dtype=RESULT_DTYPE)
     same_records(got, want)
     # the evaluation is the kernels' canonical one: endpoints bit for bit
