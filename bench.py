@@ -157,7 +157,7 @@ def summarize_valu(workload, csv_path):
     SQ_WAVES ...) -> the distance kernel's counts per launch."""
     import csv
     with open(csv_path) as f:
-        rows = [r for r in csv.DictReader(f) if "k_distance<2>" in r["Kernel_Name"]]
+        rows = [r for r in csv.DictReader(f) if "k_distance<2," in r["Kernel_Name"]]
     per = {}
     for r in rows:
         per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
@@ -183,7 +183,7 @@ def summarize_traffic(workload, fetch_csv, write_csv):
     def per_kernel(path, counter):
         with open(path) as f:
             rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
-        dist = [float(r["Counter_Value"]) for r in rows if "k_distance<2>" in r["Kernel_Name"]]
+        dist = [float(r["Counter_Value"]) for r in rows if "k_distance<2," in r["Kernel_Name"]]
         copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
         if not dist or not copies:
             raise SystemExit(f"{path}: no {counter} rows for the distance kernel or the copy")
@@ -558,11 +558,12 @@ def open_loop(tds, idx, reqs, route=0):
     return lat, lat_arr, n_rec, elapsed, st
 
 
-def flood(tds, idx, reqs):
+def flood(tds, idx, reqs, route=0):
     """Every request submitted at once (marshalled beforehand): the server's
     throughput when it always has work queued, and the latencies then."""
     srv = tds.Server(idx, max_batch_segments=1 << 17, max_batch_requests=2048, slots=2,
-                     result_capacity=1 << 21, default_reserve=512, max_pending=len(reqs) + 1)
+                     result_capacity=1 << 21, default_reserve=512, max_pending=len(reqs) + 1,
+                     cpu_route_tests=route)
     for r in reqs[:200]:
         srv.wait(srv.submit(r.Q, r.d, r.t_start, r.t_end))
     reqs = reqs[200:]
@@ -574,9 +575,13 @@ def flood(tds, idx, reqs):
     elapsed = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
-    return {"requests": len(reqs), "requests_per_s": round(len(reqs) / elapsed, 1),
-            "submit_s": round(t_sub, 4), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
-            "batches": st["batches"], "max_batch_requests": st["max_batch_requests_seen"]}
+    out = {"requests": len(reqs), "requests_per_s": round(len(reqs) / elapsed, 1),
+           "submit_s": round(t_sub, 4), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+           "batches": st["batches"], "max_batch_requests": st["max_batch_requests_seen"]}
+    if route:
+        out["cpu_route_tests"] = route
+        out["cpu_routed"] = st["cpu_routed"]
+    return out
 
 
 def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0, 80000.0, 160000.0,
@@ -622,11 +627,14 @@ def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0, 80000.0
               "records": rrec, "batches": rst["batches"]}
     if rrec != n_rec:
         raise RuntimeError(f"routed serving found {rrec} records, GPU-only {n_rec}")
+    rfl = flood(tds, idx, trajgen.request_stream(20200, rate=1e9, seed=91),
+                route=HOST_ROUTE_TESTS)
     return {
         "served_fp32": served,
         "served_hybrid": routed,
         "served_rate_sweep": rows,
         "served_flood": fl,
+        "served_hybrid_flood": rfl,
         "saturation_requests_per_s": max([r["requests_per_s"] for r in rows] +
                                          [fl["requests_per_s"]]),
         "plain_fp64": {"requests": len(plain),
@@ -637,8 +645,9 @@ def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0, 80000.0
 
 
 # Host route threshold of the hybrid serving run: requests whose candidate
-# ranges hold at most this many pairs (on the uniform1m index, about 20
-# clipped query segments of 2,500 candidates each) run on the host.
+# ranges hold at most this many pairs after the block-box test run on the
+# host (on the uniform1m index nearly every request of the stream: its query
+# trajectories have 5-400 segments, each meeting a few 64-entry blocks).
 HOST_ROUTE_TESTS = 50000
 
 LEGS = ("galaxy", "uniform1m", "dense", "tiny", "serve", "self_join", "fsg")

@@ -789,27 +789,61 @@ __device__ inline void wave_sync_mem() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
 
+// Staged records each lane copies per round of a flush (their loads in
+// flight together).
+constexpr int kFlushUnroll = 4;
+
 // Reserves the staged results of every request slot (one atomic each) and
 // copies them from the stage to their positions; the stage is then empty.
+// Slot lane s learns where its request's results go: staged result k of the
+// slot has request position base + k and is kept when that position falls
+// in the window [win_lo, win_lo + out_capacity), at out[dst + k].  The copy
+// then reads kFlushUnroll records per lane before it writes any, so a flush
+// waits for about one memory round trip per 256 records.
 __device__ __forceinline__ void stage_flush(WaveLDS& L, const DistArgs& A, ItemState& S) {
     const uint32_t lane = __lane_id();
     wave_sync_mem();
-    unsigned long long base = 0;  // first reserved position of slot `lane`
-    if (S.rcnt) base = atomicAdd(&A.rc[S.qr].count, (unsigned long long)S.rcnt);
+    int64_t dst = 0;
+    uint32_t klo = 0, khi = 0;  // kept staged results of slot `lane`: [klo, khi)
+    if (S.rcnt) {
+        const uint64_t base =
+            (uint64_t)atomicAdd(&A.rc[S.qr].count, (unsigned long long)S.rcnt);
+        const Request& R = A.req[S.qr];
+        const uint64_t w0 = A.win_lo, w1 = A.win_lo + R.out_capacity, n = S.rcnt;
+        klo = (uint32_t)min(max(w0, base) - base, n);
+        khi = (uint32_t)min(max(w1, base) - base, n);
+        dst = (int64_t)R.out_offset + (int64_t)base - (int64_t)A.win_lo;
+    }
     S.rcnt = 0;
-    for (uint32_t p0 = 0; p0 < S.nst; p0 += kWave) {
-        const uint32_t p = p0 + lane;
-        const bool act = p < S.nst;
-        const uint32_t meta = act ? A.stage_meta[S.sbase + p] : 0u;
-        const uint32_t ql = meta & (kWave - 1);
-        // every lane takes part in the shuffles
-        const uint32_t slot = (uint32_t)__shfl((int)S.rslot, (int)ql);
-        const uint64_t pos = (uint64_t)__shfl(base, (int)slot) + (meta >> 6);
-        const uint32_t r = (uint32_t)__shfl((int)S.qr, (int)ql);
-        if (act) {
-            const Request& R = A.req[r];
-            if (pos >= A.win_lo && pos - A.win_lo < R.out_capacity)
-                A.out[R.out_offset + (pos - A.win_lo)] = A.stage[S.sbase + p];
+    for (uint32_t p0 = 0; p0 < S.nst; p0 += kFlushUnroll * kWave) {
+        uint32_t meta[kFlushUnroll];
+        uint4 ra[kFlushUnroll], rb[kFlushUnroll];
+#pragma unroll
+        for (int u = 0; u < kFlushUnroll; ++u) {
+            const uint32_t p = p0 + u * kWave + lane;
+            meta[u] = 0xFFFFFFFFu;  // no record (a real one is below 2^17)
+            ra[u] = rb[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (p < S.nst) {
+                meta[u] = A.stage_meta[S.sbase + p];
+                const uint4* src = reinterpret_cast<const uint4*>(A.stage + S.sbase + p);
+                ra[u] = src[0];
+                rb[u] = src[1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFlushUnroll; ++u) {
+            // every lane takes part in the shuffles
+            const uint32_t ql = meta[u] & (kWave - 1);
+            const uint32_t k = (meta[u] >> 6) & 0x3FFFFFFu;
+            const uint32_t slot = (uint32_t)__shfl((int)S.rslot, (int)ql);
+            const int64_t d = __shfl((long long)dst, (int)slot);
+            const uint32_t lo = (uint32_t)__shfl((int)klo, (int)slot);
+            const uint32_t hi = (uint32_t)__shfl((int)khi, (int)slot);
+            if (meta[u] != 0xFFFFFFFFu && k >= lo && k < hi) {
+                uint4* o = reinterpret_cast<uint4*>(A.out + (d + (int64_t)k));
+                o[0] = ra[u];
+                o[1] = rb[u];
+            }
         }
     }
     S.nst = 0;

@@ -29,6 +29,7 @@
 struct alignas(16) uint4 {
     unsigned x, y, z, w;
 };
+inline uint4 make_uint4(unsigned x, unsigned y, unsigned z, unsigned w) { return {x, y, z, w}; }
 
 struct dim3 {
     unsigned x = 1, y = 1, z = 1;
