@@ -339,8 +339,9 @@ class SearchLeg:
     def __init__(self, tds, w, tuned=None, precision=None):
         import torch
         self.tds, self.w = tds, w
-        self.tuned = tuned or {"num_bins": 0, "chunk": 0, "grid_waves": 0, "tile": 0,
-                               "refine": "default", "deal": "default", "precision": "fp32"}
+        self.tuned = dict({"num_bins": 0, "chunk": 0, "grid_waves": 0, "tile": 0,
+                           "refine": "default", "deal": "default", "output": "default",
+                           "precision": "fp32"}, **(tuned or {}))
         self.idx = tds.Index(w.D, num_bins=self.tuned["num_bins"])
         Qt = device_segments(w.Q)
         nq = len(w.Q)
@@ -361,7 +362,7 @@ class SearchLeg:
                                          chunk=self.tuned["chunk"],
                                          grid_waves=self.tuned["grid_waves"],
                                          tile=self.tuned["tile"], refine=self.tuned["refine"],
-                                         deal=self.tuned["deal"])
+                                         deal=self.tuned["deal"], output=self.tuned["output"])
 
     def step(self):
         st, got, s = self.run(self.reqs, self.out.data_ptr(), len(self.w.ds) * self.cap)
@@ -721,15 +722,15 @@ def main():
         tuned = None
         if args.fixed:
             tuned = {"num_bins": 0, "chunk": 0, "grid_waves": 0, "tile": 0, "refine": "default",
-                     "deal": "default", "precision": "fp32"}
+                     "deal": "default", "output": "default", "precision": "fp32"}
             for kv in args.fixed.split(","):
                 k, v = kv.split("=")
-                tuned[k] = v if k in ("precision", "refine", "deal") else int(v)
+                tuned[k] = v if k in ("precision", "refine", "deal", "output") else int(v)
         elif not args.no_tune and name in legs:
             tb = time.perf_counter()
             best = autotune.tune(w.D, w.Q, w.ds, w.window, cache=None)
             tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves", "tile", "refine",
-                                          "deal", "precision")}
+                                          "deal", "output", "precision")}
             tuned["trials"] = best["trials"]
             tuned["tuning_s"] = round(time.perf_counter() - tb, 2)
         leg = SearchLeg(tds, w, tuned)

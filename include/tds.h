@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define TDS_ABI_VERSION 3u
+#define TDS_ABI_VERSION 4u
 
 /* Status codes. */
 enum {
@@ -132,6 +132,24 @@ enum {
     TDS_DEAL_STATIC = 2
 };
 
+/* How the results of a one-request search (tds_search, tds_self_join, a
+   one-request tds_search_batch) reach the output buffer.  Batches of several
+   requests, the batcher and the server always stage.  Both modes give the
+   same records; positions within a request are in no fixed order. */
+enum {
+    TDS_OUTPUT_DEFAULT = 0, /* currently TDS_OUTPUT_DIRECT */
+    /* Each wave reserves a chunk of output positions at a time (one
+       device-scope atomic per chunk) and writes its results straight to it;
+       a short pass after the distance kernel moves the results found past the
+       final count into the chunks' unused tails.  Positions of the buffer
+       between the count and the capacity may be written as well. */
+    TDS_OUTPUT_DIRECT = 1,
+    /* Each wave stages its results in device memory and, at the end of each
+       work item (or when the stage is full), reserves exactly their number
+       per request and copies them out. */
+    TDS_OUTPUT_STAGED = 2
+};
+
 /* Index parameters; a NULL pointer or 0 fields select defaults. */
 typedef struct tds_build_params {
     /* Number m of temporal bins (Sec. 4.2.1).  0 = auto: the full temporal
@@ -172,7 +190,8 @@ typedef struct tds_search_params {
     uint32_t refine;
     /* How the distance kernel's work items reach its waves (TDS_DEAL_*). */
     uint32_t deal;
-    uint32_t reserved32;
+    /* How a one-request search's results reach the output (TDS_OUTPUT_*). */
+    uint32_t output;
     uint64_t reserved[2];
 } tds_search_params;
 
@@ -185,9 +204,10 @@ typedef struct tds_stats {
     uint64_t fp64_evals;      /* pairs evaluated by the canonical FP64 code */
     uint64_t results;         /* result records found (may exceed the capacity) */
     uint32_t passes;          /* distance-kernel launches (> 1: incremental) */
-    uint32_t stage_flushes;   /* work items whose results were reserved and written at
-                                 the item's end (first pass; each reserves with one
-                                 device-scope atomic per request in the item) */
+    uint32_t stage_flushes;   /* first pass, staged output: work items whose results
+                                 were reserved and written at the item's end (one
+                                 device-scope atomic per request in the item); direct
+                                 output: chunk reservations */
     double kernel_ms;         /* distance kernel(s), measured with HIP events */
     double total_ms;          /* whole call, host wall clock */
     uint64_t filter_tests;    /* pairs put through the FP32 filter (FP32 form) or the

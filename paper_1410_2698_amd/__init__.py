@@ -168,10 +168,11 @@ class Index:
 
     def search_raw(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                    out_ptr: int, capacity: int, out_on_device: bool, precision: str = "fp32",
-                   chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0, tile: int = 0, refine: str = "default", deal: str = "default"):
+                   chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0, tile: int = 0, refine: str = "default", deal: str = "default",
+                   output: str = "default"):
         """One call of tds_search into caller memory; returns (status, n_total, stats)."""
         h = _segments(Q)
-        p = _search_params(precision, chunk, grid_waves, tile, refine, deal)
+        p = _search_params(precision, chunk, grid_waves, tile, refine, deal, output)
         p.out_on_device = 1 if out_on_device else 0
         p.device_capacity = int(device_capacity)
         n = ctypes.c_uint64()
@@ -186,11 +187,12 @@ class Index:
     def search_noalloc_raw(self, Q, d: float, t_start: float = -math.inf,
                            t_end: float = math.inf, *, out_ptr: int, capacity: int,
                            precision: str = "fp32", chunk: int = 0, grid_waves: int = 0,
-                           tile: int = 0, refine: str = "default", deal: str = "default"):
+                           tile: int = 0, refine: str = "default", deal: str = "default",
+                   output: str = "default"):
         """One call of tds_search_noalloc (Q and out in device memory); returns
         (status, n_total, stats)."""
         h = _segments(Q)
-        p = _search_params(precision, chunk, grid_waves, tile, refine, deal)
+        p = _search_params(precision, chunk, grid_waves, tile, refine, deal, output)
         p.out_on_device = 1
         n = ctypes.c_uint64()
         st = _lib.tds_stats()
@@ -204,7 +206,7 @@ class Index:
     def search(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                capacity: Optional[int] = None, precision: str = "fp32", chunk: int = 0,
                grid_waves: int = 0, device_capacity: int = 0, tile: int = 0, refine: str = "default",
-               deal: str = "default") -> np.ndarray:
+               deal: str = "default", output: str = "default") -> np.ndarray:
         """Search into host memory; grows the buffer and retries on overflow.
         Returns the records (unspecified order) as a NumPy structured array."""
         cap = 1 << 16 if capacity is None else int(capacity)
@@ -214,7 +216,7 @@ class Index:
                                            capacity=cap, out_on_device=False, precision=precision,
                                            chunk=chunk, grid_waves=grid_waves,
                                            device_capacity=device_capacity, tile=tile,
-                                           refine=refine, deal=deal)
+                                           refine=refine, deal=deal, output=output)
             if status == TDS_OK:
                 return buf[:n].copy()
             if status == TDS_E_OVERFLOW and capacity is None:
@@ -226,9 +228,10 @@ class Index:
     def self_join_raw(self, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
                       out_ptr: int, capacity: int, out_on_device: bool, precision: str = "fp32",
                       chunk: int = 0, grid_waves: int = 0, device_capacity: int = 0,
-                      tile: int = 0, refine: str = "default", deal: str = "default"):
+                      tile: int = 0, refine: str = "default", deal: str = "default",
+                   output: str = "default"):
         """One call of tds_self_join into caller memory; returns (status, n_total, stats)."""
-        p = _search_params(precision, chunk, grid_waves, tile, refine, deal)
+        p = _search_params(precision, chunk, grid_waves, tile, refine, deal, output)
         p.out_on_device = 1 if out_on_device else 0
         p.device_capacity = int(device_capacity)
         n = ctypes.c_uint64()
@@ -261,7 +264,8 @@ class Index:
 
     def search_batch_raw(self, Q, requests, *, out_ptr: int, out_capacity: int,
                          out_on_device: bool, precision: str = "fp32", chunk: int = 0,
-                         grid_waves: int = 0, tile: int = 0, refine: str = "default", deal: str = "default"):
+                         grid_waves: int = 0, tile: int = 0, refine: str = "default", deal: str = "default",
+                   output: str = "default"):
         """One call of tds_search_batch into caller memory.  ``requests`` holds
         (q_begin, q_count, d, t_start, t_end, out_offset, out_capacity) tuples
         that tile Q in order.  Returns (status, counts, stats)."""
@@ -271,7 +275,7 @@ class Index:
             r.q_begin, r.q_count, r.d, r.t_start, r.t_end = int(qb), int(qc), float(d), float(t0), float(t1)
             r.out_offset, r.out_capacity = int(oo), int(oc)
         counts = (ctypes.c_uint64 * len(requests))()
-        p = _search_params(precision, chunk, grid_waves, tile, refine, deal)
+        p = _search_params(precision, chunk, grid_waves, tile, refine, deal, output)
         p.out_on_device = 1 if out_on_device else 0
         st = _lib.tds_stats()
         status = self._lib.tds_search_batch(self._h, ctypes.byref(h.struct), reqs, len(requests),
@@ -363,10 +367,11 @@ class FSG:
 
 REFINES = {"default": 0, "queued": 1, "inline": 2}
 DEALS = {"default": 0, "dynamic": 1, "static": 2}
+OUTPUTS = {"default": 0, "direct": 1, "staged": 2}
 
 
 def _search_params(precision="fp32", chunk=0, grid_waves=0, tile=0, refine="default",
-                   deal="default"):
+                   deal="default", output="default"):
     lib = load()
     p = _lib.tds_search_params()
     lib.tds_search_params_default(ctypes.byref(p))
@@ -376,6 +381,7 @@ def _search_params(precision="fp32", chunk=0, grid_waves=0, tile=0, refine="defa
     p.tile = int(tile)
     p.refine = REFINES[refine]
     p.deal = DEALS[deal]
+    p.output = OUTPUTS[output]
     return p
 
 
@@ -466,6 +472,7 @@ class Server:
                  slots: int = 0, result_capacity: int = 0, default_reserve: int = 0,
                  max_pending: int = 0, precision: str = "fp32", chunk: int = 0, grid_waves: int = 0,
                  tile: int = 0, refine: str = "default", deal: str = "default",
+                   output: str = "default",
                  cpu_route_tests: int = 0):
         self._lib = load()
         self.index = index
@@ -477,7 +484,7 @@ class Server:
         p.default_reserve = default_reserve
         p.max_pending = max_pending
         p.cpu_route_tests = int(cpu_route_tests)
-        p.search = _search_params(precision, chunk, grid_waves, tile, refine, deal)
+        p.search = _search_params(precision, chunk, grid_waves, tile, refine, deal, output)
         out = ctypes.c_void_p()
         check(self._lib.tds_server_create(index.handle, ctypes.byref(p), ctypes.byref(out)),
               "tds_server_create")

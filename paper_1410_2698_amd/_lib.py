@@ -37,7 +37,7 @@ class tds_search_params(ctypes.Structure):
                 ("chunk", ctypes.c_uint32), ("grid_waves", ctypes.c_uint32),
                 ("device_capacity", ctypes.c_uint64), ("tile", ctypes.c_uint32),
                 ("refine", ctypes.c_uint32), ("deal", ctypes.c_uint32),
-                ("reserved32", ctypes.c_uint32), ("reserved", ctypes.c_uint64 * 2)]
+                ("output", ctypes.c_uint32), ("reserved", ctypes.c_uint64 * 2)]
 
 
 class tds_stats(ctypes.Structure):

@@ -14,6 +14,8 @@ resident) and picks, by coordinate descent from the library defaults:
   the pair queue or inline in the filter walk (the same pairs are dropped);
 * the dealing of work items: one static round then dynamic per-XCD counters,
   or all static (no atomics);
+* the output of a one-request search: direct (per-wave reservations of the
+  output, a fill pass afterwards) or staged (per-wave stages copied out);
 * the wavefront mapping: the FP32 form (lanes hold candidates, the group's
   query segments are walked in turn, survivors rechecked in FP64) or the FP64
   form (lanes hold query segments, candidates are streamed to all of them).
@@ -40,6 +42,7 @@ SPACE = {
     "tile": (4, 2),
     "refine": ("queued", "inline"),
     "deal": ("dynamic", "static"),
+    "output": ("direct", "staged"),
     "precision": ("fp32", "fp64"),
 }
 
@@ -65,7 +68,8 @@ def _load_cache(path: str) -> dict:
 def tune(D, Q, ds: Iterable[float], window, *, space: Optional[dict] = None, reps: int = 3,
          min_ms: float = 30.0, rounds: int = 2, cache: Optional[str] = CACHE,
          force: bool = False) -> dict:
-    """Return {"num_bins", "chunk", "grid_waves", "tile", "refine", "deal", "precision", "ms",
+    """Return {"num_bins", "chunk", "grid_waves", "tile", "refine", "deal", "output",
+    "precision", "ms",
     "trials", ...} for the fastest configuration found.  ``space`` maps each
     knob to its candidate values, the first being the starting point.  Each
     configuration is timed over at least ``reps`` searches and ``min_ms`` of
@@ -125,7 +129,8 @@ def tune(D, Q, ds: Iterable[float], window, *, space: Optional[dict] = None, rep
                                               out_capacity=out.numel() // 32, out_on_device=True,
                                               precision=c["precision"], chunk=c["chunk"],
                                               grid_waves=c["grid_waves"], tile=c["tile"],
-                                              refine=c["refine"], deal=c["deal"])
+                                              refine=c["refine"], deal=c["deal"],
+                                              output=c["output"])
             torch.cuda.synchronize()
             if st != tds.TDS_OK or got != counts:
                 raise RuntimeError(f"autotune: search failed ({st}, {got} vs {counts}) at {c}")

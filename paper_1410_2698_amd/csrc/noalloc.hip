@@ -61,7 +61,7 @@ constexpr Carve carve() {
     c.req = take(sizeof(Request));
     c.hdr = take(sizeof(SearchHeader));
     c.ctr = take(sizeof(ReqCounter));
-    c.dyn = take((size_t)kXcds * kCtrStride * sizeof(unsigned long long));
+    c.dyn = take((size_t)kCtrSlots * kCtrStride * sizeof(unsigned long long));
     c.total = o;
     return c;
 }

@@ -308,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_zero(SearchHeader* hdr, uint32_t* b_
         rc[i].count = 0;
         rc[i].pad = 0;
     }
-    if (i < kXcds * kCtrStride) dyn_ctr[i] = 0;
+    if (i < kCtrSlots * kCtrStride) dyn_ctr[i] = 0;
 }
 
 // Canonical FP64 data of query segment k of request r, from the query
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const BatchDesc* __restrict_
 __global__ void k_reset_pass(ReqCounter* rc, uint32_t nreq, unsigned long long* dyn_ctr) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nreq) rc[i].count = 0;
-    if (i < kXcds * kCtrStride) dyn_ctr[i] = 0;
+    if (i < kCtrSlots * kCtrStride) dyn_ctr[i] = 0;
 }
 
 // Adds the per-workgroup counters of one distance-kernel launch to the
@@ -687,6 +687,132 @@ __global__ __launch_bounds__(256) void k_stats_fold(const BlockStats* __restrict
     }
 }
 
+// Waves of a distance-kernel launch that may use direct output (the fill
+// plan keeps one 16-bit entry per chunk it looks at, at most one more than
+// the waves, in LDS).
+constexpr uint32_t kMaxDirectWaves = 16384;
+
+// Exclusive prefix sums of f(0..n-1) into out[0..n] (out[n] = total) by one
+// workgroup of 1024 threads, 1024 values per round.
+template <class F>
+__device__ void block_scan_1024(uint32_t n, F f, uint64_t* __restrict__ out) {
+    __shared__ uint64_t wsum[1024 / kWave];
+    __shared__ uint64_t carry_s;
+    const uint32_t t = threadIdx.x, lane = t % kWave, wv = t / kWave;
+    if (t == 0) carry_s = 0;
+    __syncthreads();
+    for (uint32_t r0 = 0; r0 < n; r0 += 1024) {
+        const uint32_t i = r0 + t;
+        const uint64_t v = i < n ? f(i) : 0;
+        uint64_t x = v;
+        for (uint32_t o = 1; o < kWave; o <<= 1) {
+            const uint64_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == kWave - 1) wsum[wv] = x;
+        __syncthreads();
+        uint64_t before = carry_s;
+        for (uint32_t k = 0; k < wv; ++k) before += wsum[k];
+        if (i < n) out[i] = before + x - v;
+        __syncthreads();
+        if (t == 1023) carry_s = before + x;
+        __syncthreads();
+    }
+    if (t == 0) out[n] = carry_s;
+}
+
+// Direct output, after the distance kernel (one workgroup): the plan of the
+// fill.  T = min(count, capacity) is the end of the dense output.  The
+// holes are the unused tails of the waves' last chunks below T (at most one
+// per wave); the sources are the results at positions at or past T, in
+// position order, of which the first (total hole size) are moved.  Those lie
+// within W (C - 1) positions of T (every hole is shorter than C), so the
+// chunks c0 = T / C .. c0 + W are enough, and positions past the capacity
+// within W C of it are in the scratch buffer.  Writes the source prefix sums
+// per chunk, the hole prefix sums and starts per wave, and (T, c0, chunks).
+__global__ __launch_bounds__(1024) void k_fill_plan(const Request* __restrict__ req,
+                                                    const ReqCounter* __restrict__ rc,
+                                                    const unsigned long long* __restrict__ dir_ctr,
+                                                    const uint64_t* __restrict__ dlast, uint32_t nw,
+                                                    uint32_t C, uint64_t* __restrict__ s_pre,
+                                                    uint64_t* __restrict__ d_pre,
+                                                    uint64_t* __restrict__ d_start,
+                                                    uint64_t* __restrict__ plan) {
+    __shared__ uint16_t used[kMaxDirectWaves + 1];  // positions used of chunk c0 + i
+    const uint32_t t = threadIdx.x;
+    const uint64_t count = rc[0].count, cap = req[0].out_capacity, R = *dir_ctr;
+    const uint64_t T = min(count, cap);
+    const uint64_t c0 = T / C, nch = R / C;
+    const uint32_t ns = nch > c0 ? (uint32_t)min(nch - c0, (uint64_t)nw + 1) : 0u;
+    for (uint32_t i = t; i < ns; i += 1024) used[i] = (uint16_t)C;  // full unless a last chunk
+    __syncthreads();
+    for (uint32_t w = t; w < nw; w += 1024) {
+        const uint64_t v = dlast[w];
+        if (v == ~0ull) continue;
+        const uint64_t k = v >> 16;
+        if (k >= c0 && k - c0 < ns) used[k - c0] = (uint16_t)(v & 0xFFFFu);
+    }
+    __syncthreads();
+    block_scan_1024(
+        ns,
+        [&](uint32_t i) -> uint64_t {
+            const uint64_t cb = (c0 + i) * C, a = max(cb, T), e = cb + used[i];
+            return e > a ? e - a : 0;
+        },
+        s_pre);
+    block_scan_1024(
+        nw,
+        [&](uint32_t w) -> uint64_t {
+            const uint64_t v = dlast[w];
+            if (v == ~0ull) return 0;
+            const uint64_t cb = (v >> 16) * C, a = cb + (v & 0xFFFFu), e = min(cb + C, T);
+            d_start[w] = a;
+            return e > a ? e - a : 0;
+        },
+        d_pre);
+    if (t == 0) {
+        plan[0] = T;
+        plan[1] = c0;
+        plan[2] = ns;
+    }
+}
+
+// Direct output: moves source t of the plan to hole position t (any pairing
+// of the two lists makes the output dense; a source is never a hole below T).
+__global__ __launch_bounds__(256) void k_fill_copy(const uint64_t* __restrict__ plan,
+                                                   const uint64_t* __restrict__ s_pre,
+                                                   const uint64_t* __restrict__ d_pre,
+                                                   const uint64_t* __restrict__ d_start,
+                                                   uint32_t nw, uint32_t C,
+                                                   const Request* __restrict__ req,
+                                                   tds_result* __restrict__ out,
+                                                   const tds_result* __restrict__ scratch) {
+    const uint64_t T = plan[0], c0 = plan[1];
+    const uint32_t ns = (uint32_t)plan[2];
+    const uint64_t total = d_pre[nw];
+    const Request R = req[0];
+    for (uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+         t += (uint64_t)gridDim.x * 256) {
+        uint32_t lo = 0, hi = nw;  // last hole with d_pre <= t
+        while (hi - lo > 1) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (d_pre[m] <= t) lo = m;
+            else hi = m;
+        }
+        const uint64_t dst = d_start[lo] + (t - d_pre[lo]);
+        uint32_t a = 0, b = ns;  // last source chunk with s_pre <= t
+        while (b - a > 1) {
+            const uint32_t m = (a + b) >> 1;
+            if (s_pre[m] <= t) a = m;
+            else b = m;
+        }
+        const uint64_t src = max((c0 + a) * C, T) + (t - s_pre[a]);
+        const tds_result v =
+            src < R.out_capacity ? out[R.out_offset + src] : scratch[src - R.out_capacity];
+        out[R.out_offset + dst] = v;
+    }
+}
+
 struct DistArgs {
     IndexView I;
     QueryView Q;             // query arrays (FP64 data of rechecked pairs)
@@ -714,6 +840,14 @@ struct DistArgs {
     uint32_t cpl;           // FP32 form: candidates per lane per tile (2 or 4)
     uint32_t inline_refine; // FP32 form: refinement in the filter walk, not the queue
     uint32_t deal;          // TDS_DEAL_STATIC or TDS_DEAL_DYNAMIC
+    // direct output (one request, not by_order): results go straight to the
+    // request's output through per-wave reservations of dir_chunk positions
+    uint32_t direct;
+    uint32_t dir_chunk;
+    unsigned long long* dir_ctr;  // next free position (reservation counter)
+    tds_result* dscratch;   // positions [cap, cap + dscratch_cap) (the stage buffer)
+    uint64_t dscratch_cap;
+    uint64_t* dlast;        // per wave: last reservation (chunk << 16 | used), ~0: none
 };
 
 // FP32 data of a query segment for the closest-approach refinement (one per
@@ -741,6 +875,16 @@ static_assert(sizeof(QRef) == 32, "QRef layout");
 // With by_order set (one request, one work item, re-run to fill successive
 // windows of the host's buffer), a result's position is instead its order
 // among the item's results, which a wave computes the same way on every run.
+//
+// Direct output (a one-request search's first pass): a wave reserves
+// dir_chunk consecutive positions of the request at a time (one atomic per
+// reservation, aligned chunks since every reservation has that size) and
+// writes its results straight to them, keeping its last reservation open from
+// one item to the next.  At the end each wave's last chunk may be partly
+// used; positions at or past the output capacity go to a scratch buffer.  A
+// fill pass (k_fill_plan, k_fill_copy) then moves the results found past the
+// final count (or the capacity) into the unused tails below it, so that the
+// output is dense again.  No result takes the round trip through a stage.
 // Filter record of a query segment as the wave keeps it in LDS: the sphere
 // and the clipped extent of its QF32 record (the candidate range stays in the
 // registers of the query's lane).
@@ -774,6 +918,10 @@ struct ItemState {
     uint32_t nst;     // results in the wave's stage
     uint64_t sbase;   // the wave's stage: records [sbase, sbase + stage_cap)
     uint64_t ftests, btests;
+    // direct output: the wave's open reservation [dpos, dend) (kept across
+    // items) and its reservations so far
+    uint64_t dpos, dend;
+    uint32_t nres;
     // per lane j of the group
     uint32_t qr;      // request of query j
     uint32_t rslot;   // its request slot: the first lane with the same request
@@ -900,6 +1048,30 @@ __device__ __forceinline__ void drain(WaveLDS& L, const uint32_t* queue, uint32_
         const Request& R = A.req[0];
         if (hit && pos >= A.win_lo && pos - A.win_lo < R.out_capacity)
             A.out[R.out_offset + (pos - A.win_lo)] = rec;
+        S.found += nhit;
+        return;
+    }
+    if (A.direct) {
+        if (!nhit) return;
+        // nhit <= 64 <= dir_chunk: at most one new reservation
+        const uint64_t room = S.dend - S.dpos;
+        uint64_t pos = S.dpos + rank;
+        if (nhit > room) {
+            unsigned long long nb = 0;
+            if (lane == 0) nb = atomicAdd(A.dir_ctr, (unsigned long long)A.dir_chunk);
+            const uint64_t b = lane0_64(nb);
+            if (rank >= room) pos = b + (rank - room);
+            S.dpos = b + (nhit - room);
+            S.dend = b + A.dir_chunk;
+            ++S.nres;
+        } else {
+            S.dpos += nhit;
+        }
+        if (hit) {
+            const Request& R = A.req[0];
+            if (pos < R.out_capacity) A.out[R.out_offset + pos] = rec;
+            else if (pos - R.out_capacity < A.dscratch_cap) A.dscratch[pos - R.out_capacity] = rec;
+        }
         S.found += nhit;
         return;
     }
@@ -1364,7 +1536,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     WaveLDS& L = wl[threadIdx.x / kWave];
     const uint32_t lane = __lane_id();
     uint64_t tests = 0, evals_total = 0, ftests = 0, btests = 0;
-    uint32_t flushes = 0;  // stage flushes at the end of an item
+    uint32_t flushes = 0;  // stage flushes at the end of an item (direct output: reservations)
+    uint64_t dpos = 0, dend = 0, found_total = 0;  // direct output (see DistArgs)
     // all items of the search, unless a range is given (incremental passes)
     const uint32_t item_end = (A.item_end == 0xFFFFFFFFu)
                                   ? uniform(min(A.hdr->n_items, A.desc->item_cap))
@@ -1458,6 +1631,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         S.nst = 0;
         S.ftests = 0;
         S.btests = 0;
+        S.dpos = dpos;
+        S.dend = dend;
+        S.nres = 0;
         // does every query of the group cover the whole chunk?
         bool cover = true;
         if (lane < S.nq) {
@@ -1480,6 +1656,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             stage_flush(L, A, S);
             ++flushes;
         }
+        dpos = S.dpos;
+        dend = S.dend;
+        flushes += S.nres;
+        found_total += S.found;
         tests += (uint64_t)(S.c1 - S.c0) * S.nq;
         ftests += (kPrec == TDS_PREC_FP64) ? (uint64_t)(S.c1 - S.c0) * S.nq : S.ftests;
         btests += S.btests;
@@ -1491,9 +1671,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             have = k < part_lo(grp + 1);
         }
     }
+    const uint32_t wid = threadIdx.x / kWave;
+    if (A.direct && lane == 0) {
+        // the wave's results and its last reservation (chunk, positions used)
+        if (found_total) atomicAdd(&A.rc[0].count, (unsigned long long)found_total);
+        A.dlast[blockIdx.x * kWavesPerBlock + wid] =
+            dend ? ((dend / A.dir_chunk - 1) << 16) | (A.dir_chunk - (dend - dpos)) : ~0ull;
+    }
     // per-workgroup counters (folded into the header by k_stats_fold), each
     // wave's in the front of its own LDS, which it no longer uses
-    const uint32_t wid = threadIdx.x / kWave;
     wave_sync();
     if (lane == 0) {
         BlockStats& w = *reinterpret_cast<BlockStats*>(wl[wid].queue);
@@ -1539,7 +1725,9 @@ Workspace::~Workspace() {
                     (void*)qtraj_stage, (void*)ctl, (void*)b_count,
                     (void*)b_hi, (void*)b_start, (void*)b_nch,
                     (void*)binfo, (void*)item_bucket, (void*)item_count, (void*)res,
-                    (void*)bstats, (void*)stage, (void*)stage_meta, (void*)dyn_ctr})
+                    (void*)bstats, (void*)stage, (void*)stage_meta, (void*)dyn_ctr,
+                    (void*)dlast, (void*)fill_s, (void*)fill_d, (void*)fill_dstart,
+                    (void*)fill_plan})
         dfree(p);
     if (ctl_host) (void)hipHostFree(ctl_host);
     if (ev0) (void)hipEventDestroy(ev0);
@@ -1553,7 +1741,7 @@ int ws_init(Workspace* w) {
     TDS_TRY(dmalloc(&w->b_nch, kMaxBuckets));
     TDS_TRY(dmalloc(&w->binfo, kMaxBuckets));
     TDS_TRY(dmalloc(&w->bstats, kMaxDistBlocks));
-    TDS_TRY(dmalloc(&w->dyn_ctr, (size_t)kXcds * kCtrStride));
+    TDS_TRY(dmalloc(&w->dyn_ctr, (size_t)kCtrSlots * kCtrStride));
     TDS_HIP(hipEventCreate(&w->ev0));
     TDS_HIP(hipEventCreate(&w->ev1));
     return ws_reserve(w, 0, 1);
@@ -1649,6 +1837,20 @@ size_t stage_total(uint32_t grid_waves);
 
 int ws_reserve_stage(Workspace* w, uint32_t grid_waves) {
     const size_t need = stage_total(grid_waves);
+    const uint32_t waves = launch_blocks(grid_waves) * kWavesPerBlock;
+    if (w->stage_waves < waves || !w->dlast) {
+        for (void* p : {(void*)w->dlast, (void*)w->fill_s, (void*)w->fill_d,
+                        (void*)w->fill_dstart, (void*)w->fill_plan})
+            dfree(p);
+        w->dlast = w->fill_s = w->fill_d = w->fill_dstart = w->fill_plan = nullptr;
+        w->stage_waves = 0;
+        TDS_TRY(dmalloc(&w->dlast, waves));
+        TDS_TRY(dmalloc(&w->fill_s, (size_t)waves + 2));
+        TDS_TRY(dmalloc(&w->fill_d, (size_t)waves + 1));
+        TDS_TRY(dmalloc(&w->fill_dstart, waves));
+        TDS_TRY(dmalloc(&w->fill_plan, 4));
+        w->stage_waves = waves;
+    }
     if (w->stage_recs >= need && w->stage) return TDS_OK;
     dfree(w->stage);
     dfree(w->stage_meta);
@@ -1771,7 +1973,7 @@ int stage_queries(const tds_segments* Q, QueryView* V, hipStream_t s, double** s
 
 DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q, tds_result* out,
                    uint64_t win_lo, uint32_t item_begin, uint32_t item_end, uint32_t* item_count,
-                   uint32_t grid_waves, bool by_order, uint32_t cpl) {
+                   uint32_t grid_waves, bool by_order, uint32_t cpl, bool direct = false) {
     DistArgs A;
     A.cpl = cpl & 0xFFu;
     A.inline_refine = ((cpl >> 8) & 0xFFu) == TDS_REFINE_INLINE ? 1u : 0u;
@@ -1798,6 +2000,18 @@ DistArgs dist_args(const tds_index* idx, const Workspace* w, const QueryView& Q,
     A.item_begin = item_begin;
     A.item_end = item_end;
     A.item_count = item_count;
+    // direct output: chunks of a wave's stage size, the stage buffer as the
+    // scratch for positions past the capacity (W C records, within it)
+    const uint32_t waves = launch_blocks(grid_waves) * kWavesPerBlock;
+    A.direct = (direct && !by_order && win_lo == 0 && waves <= kMaxDirectWaves &&
+                waves <= w->stage_waves && A.stage_cap >= (uint32_t)kWave)
+                   ? 1u
+                   : 0u;
+    A.dir_chunk = A.stage_cap;
+    A.dir_ctr = w->dyn_ctr + (size_t)kXcds * kCtrStride;
+    A.dscratch = w->stage;
+    A.dscratch_cap = (uint64_t)waves * A.stage_cap;
+    A.dlast = w->dlast;
     return A;
 }
 
@@ -1828,6 +2042,17 @@ int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_
     return TDS_OK;
 }
 
+// Direct output: the fill of the holes left by the waves' last reservations.
+int launch_fill(const DistArgs& A, const Workspace* w, uint32_t grid_waves, hipStream_t s) {
+    const uint32_t nw = launch_blocks(grid_waves) * kWavesPerBlock;
+    hipLaunchKernelGGL(k_fill_plan, dim3(1), dim3(1024), 0, s, A.req, A.rc, A.dir_ctr, A.dlast,
+                       nw, A.dir_chunk, w->fill_s, w->fill_d, w->fill_dstart, w->fill_plan);
+    hipLaunchKernelGGL(k_fill_copy, dim3(1024), dim3(256), 0, s, w->fill_plan, w->fill_s,
+                       w->fill_d, w->fill_dstart, nw, A.dir_chunk, A.req, A.out, A.dscratch);
+    TDS_HIP(hipGetLastError());
+    return TDS_OK;
+}
+
 // The whole search for the batch described by w->desc / w->req, as a fixed
 // sequence of fixed-shape launches (capturable in a graph): clear, prepare
 // queries, bucket table, ordering, item table, distance kernel over every
@@ -1835,12 +2060,12 @@ int launch_distance(int prec, const DistArgs& A, uint32_t grid_waves, hipStream_
 int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, size_t q_grid,
                      uint32_t r_cap, int prec, uint32_t chunk, uint32_t grid_waves, uint32_t cpl,
                      tds_result* out, uint32_t* item_count, hipStream_t s, hipEvent_t ev_begin,
-                     hipEvent_t ev_end) {
+                     hipEvent_t ev_end, bool direct = false) {
     const IndexView I = view_of(idx);
     const uint32_t shift = bucket_shift(idx->m);
     const uint32_t nb = bucket_count(idx->m);
     const uint32_t nparts = count_parts(nb);
-    const uint32_t zn = std::max(std::max(nb * nparts, r_cap), kXcds * kCtrStride);
+    const uint32_t zn = std::max(std::max(nb * nparts, r_cap), kCtrSlots * kCtrStride);
     // k_zero also clears the request counters the distance kernel appends with
     hipLaunchKernelGGL(k_zero, dim3(ceil_div(zn, kBlock)), dim3(kBlock), 0, s, w->hdr, w->b_count,
                        w->b_hi, nb, nparts, w->req_ctr, r_cap, w->dyn_ctr);
@@ -1855,10 +2080,10 @@ int enqueue_pipeline(const tds_index* idx, Workspace* w, const QueryView& Q, siz
                        w->qslot, w->b_start, w->b_count, nb, bpp, qblocks, w->qfu, w->qsorted,
                        w->qf, w->binfo, w->item_bucket, w->hdr);
     TDS_HIP(hipGetLastError());
-    return launch_distance(prec,
-                           dist_args(idx, w, Q, out, 0, 0, 0xFFFFFFFFu, item_count, grid_waves,
-                                     false, cpl),
-                           grid_waves, s, ev_begin, ev_end);
+    const DistArgs A = dist_args(idx, w, Q, out, 0, 0, 0xFFFFFFFFu, item_count, grid_waves, false,
+                                 cpl, direct);
+    TDS_TRY(launch_distance(prec, A, grid_waves, s, ev_begin, ev_end));
+    return A.direct ? launch_fill(A, w, grid_waves, s) : TDS_OK;
 }
 
 // Re-runs the distance kernel over work items [i0, i1) keeping result
@@ -1869,7 +2094,7 @@ int enqueue_range(const tds_index* idx, Workspace* w, const QueryView& Q, int pr
                   tds_result* out, uint64_t win_lo, uint32_t i0, uint32_t i1, bool by_order,
                   uint32_t grid_waves, uint32_t cpl, hipStream_t s, hipEvent_t ev_begin,
                   hipEvent_t ev_end) {
-    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, kXcds * kCtrStride), 256)),
+    hipLaunchKernelGGL(k_reset_pass, dim3(ceil_div(std::max(r_cap, kCtrSlots * kCtrStride), 256)),
                        dim3(256), 0, s, w->req_ctr, r_cap, w->dyn_ctr);
     TDS_HIP(hipGetLastError());
     return launch_distance(prec,
@@ -1930,8 +2155,8 @@ int reserve_items(const tds_index* idx, Workspace* w, uint64_t nq, uint32_t chun
 // w->req_host (sent to the device here, with the descriptor), growing the
 // item table and re-running if the bound was too small.
 int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t nreq, int prec,
-              uint32_t chunk, uint32_t grid_waves, uint32_t cpl, tds_result* out, hipStream_t s,
-              tds_stats* st, SearchHeader* h_out) {
+              uint32_t chunk, uint32_t grid_waves, uint32_t cpl, uint32_t output, tds_result* out,
+              hipStream_t s, tds_stats* st, SearchHeader* h_out) {
     uint64_t cap = 0;
     TDS_TRY(reserve_items(idx, w, V.n, chunk, &cap));
     TDS_TRY(ws_reserve_stage(w, grid_waves));
@@ -1940,8 +2165,10 @@ int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t n
         w->desc_host->nreq = nreq;
         w->desc_host->item_cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
         TDS_TRY(ws_upload(w, nreq, s));  // the descriptor and the requests staged by the caller
+        // one request: direct output unless staging is asked for
         TDS_TRY(enqueue_pipeline(idx, w, V, V.n, nreq, prec, chunk, grid_waves, cpl, out,
-                                 w->item_count, s, w->ev0, w->ev1));
+                                 w->item_count, s, w->ev0, w->ev1,
+                                 nreq == 1 && output != TDS_OUTPUT_STAGED));
         TDS_TRY(ws_download(w, nreq, s));
         TDS_HIP(hipStreamSynchronize(s));
         *h_out = *w->hdr_host;
@@ -1971,6 +2198,7 @@ int resolve_config(const tds_search_params* params, PipelineConfig* cfg) {
     cfg->grid_waves = resolve_grid(P.grid_waves);
     cfg->cpl = resolve_tile(P.tile, P.refine, P.deal);
     if (!cfg->cpl) return TDS_E_INVALID;
+    if (P.output > TDS_OUTPUT_STAGED) return TDS_E_INVALID;  // batches always stage
     return TDS_OK;
 }
 
@@ -2069,6 +2297,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
     const uint32_t grid_waves = resolve_grid(P.grid_waves);
     const uint32_t cpl = resolve_tile(P.tile, P.refine, P.deal);
     if (!cpl) return TDS_E_INVALID;
+    if (P.output > TDS_OUTPUT_STAGED) return TDS_E_INVALID;
     const bool dev_out = P.out_on_device != 0;
 
     Workspace* w = acquire(idx);
@@ -2113,7 +2342,7 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
     st.query_segments = nq;
     SearchHeader h{};
     // pass 1: every item, result window [0, dev_cap)
-    TDS_TRY(run_batch(idx, w, V, 1, prec, chunk, grid_waves, cpl, res, s, &st, &h));
+    TDS_TRY(run_batch(idx, w, V, 1, prec, chunk, grid_waves, cpl, P.output, res, s, &st, &h));
     const ReqCounter rc = w->rc_host[0];
     const uint32_t n_items = h.n_items;
     st.active_segments = h.active;
@@ -2221,6 +2450,7 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
     const uint32_t grid_waves = resolve_grid(P.grid_waves);
     const uint32_t cpl = resolve_tile(P.tile, P.refine, P.deal);
     if (!cpl) return TDS_E_INVALID;
+    if (P.output > TDS_OUTPUT_STAGED) return TDS_E_INVALID;
     const bool dev_out = P.out_on_device != 0;
 
     Workspace* w = acquire(idx);
@@ -2248,7 +2478,8 @@ int batch_impl(tds_index* idx, const tds_segments* Q, const tds_request* reqs, u
     tds_stats st{};
     st.query_segments = Q->n;
     SearchHeader h{};
-    TDS_TRY(run_batch(idx, w, V, nreq, prec, chunk, grid_waves, cpl, res, s, &st, &h));
+    TDS_TRY(run_batch(idx, w, V, nreq, prec, chunk, grid_waves, cpl, P.output, res, s, &st,
+                      &h));
     const ReqCounter* rc = w->rc_host;
     int status = TDS_OK;
     uint64_t total = 0;

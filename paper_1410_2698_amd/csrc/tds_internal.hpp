@@ -20,6 +20,9 @@ constexpr int kBlock = 256;             // threads per block of the search kerne
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr uint32_t kXcds = 8;            // accelerator complex dies (own L2 each)
 constexpr uint32_t kCtrStride = 8;       // 64-bit counters 64 bytes apart (own cache lines)
+// counters of the distance kernel: one dynamic item counter per XCD part, and
+// the reservation counter of direct output (the last slot)
+constexpr uint32_t kCtrSlots = kXcds + 1;
 constexpr uint32_t kMaxBins = 65535;
 constexpr uint32_t kMaxBuckets = 65536; // query buckets of one search
 constexpr uint32_t kSpanClasses = 4;    // bin-span classes per first bin
@@ -185,7 +188,15 @@ struct Workspace {
     tds_result* stage = nullptr;
     uint32_t* stage_meta = nullptr;
     size_t stage_recs = 0;
-    unsigned long long* dyn_ctr = nullptr;  // kXcds dynamic item counters, kCtrStride apart
+    unsigned long long* dyn_ctr = nullptr;  // kCtrSlots counters, kCtrStride apart
+    // direct output (one-request searches): each wave's last reservation and
+    // the plan of the pass that fills the holes (sized for stage_waves waves)
+    uint64_t* dlast = nullptr;
+    uint64_t* fill_s = nullptr;      // stage_waves + 2 source prefix sums
+    uint64_t* fill_d = nullptr;      // stage_waves + 1 hole prefix sums
+    uint64_t* fill_dstart = nullptr; // stage_waves hole starts
+    uint64_t* fill_plan = nullptr;   // T, c0, ns, total
+    uint32_t stage_waves = 0;
     SearchHeader* hdr = nullptr;
     SearchHeader* hdr_host = nullptr;  // pinned mirror
     BlockStats* bstats = nullptr;      // kMaxDistBlocks per-workgroup counters

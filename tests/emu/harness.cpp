@@ -155,12 +155,14 @@ int run_search(int argc, char** argv, bool self_join) {
     const uint32_t num_bins = (a < argc) ? (uint32_t)atoi(argv[a++]) : 0u;  // 0: automatic
     const uint32_t refine = (a < argc) ? (uint32_t)atoi(argv[a++]) : 0u;    // TDS_REFINE_*
     const uint32_t tile = (a < argc) ? (uint32_t)atoi(argv[a++]) : 0u;
+    const uint32_t output = (a < argc) ? (uint32_t)atoi(argv[a++]) : 0u;  // TDS_OUTPUT_*
     tds_index* idx = build(D, layout, num_bins);
     tds_search_params p;
     tds_search_params_default(&p);
     p.precision = prec;
     p.refine = refine;
     p.tile = tile;
+    p.output = output;
     p.grid_waves = 64;  // 16 persistent workgroups: fewer idle host threads
     std::vector<tds_result> out(std::max<uint64_t>(cap, 1));
     uint64_t n = 0;

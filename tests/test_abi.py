@@ -43,7 +43,7 @@ def test_binding_covers_every_declared_symbol():
 
 def test_version_and_status_strings():
     lib = _lib.load()
-    assert lib.tds_abi_version() == 3
+    assert lib.tds_abi_version() == 4
     assert lib.tds_status_str(0) == b"TDS_OK"
     assert b"OVERFLOW" in lib.tds_status_str(2)
     assert lib.tds_status_str(12345) == b"unknown tds status"

@@ -30,6 +30,7 @@ RESULT_DTYPE = np.dtype([("q_seg", "<u4"), ("e_seg", "<u4"), ("q_traj", "<u4"), 
 TEMPORAL, SPATIAL = 1, 2  # index layouts (C ABI values)
 FP64, FP32 = 1, 2         # search precisions (C ABI values)
 QUEUED, INLINE = 1, 2     # places of the FP32 refinement (C ABI values)
+DIRECT, STAGED = 1, 2     # output modes (C ABI values)
 
 
 def columns(S):
@@ -82,7 +83,13 @@ def _jobs():
     # the emulated waves, so the dynamic item counters are used as well
     for prec in (FP32, FP64):
         J[f"flush_{prec}"] = ("search", (tiny.D, tiny.D),
-                              [SPATIAL, prec, 250.0, 0.0, 49.0, 600000])
+                              [SPATIAL, prec, 250.0, 0.0, 49.0, 600000, 0, 0, 0, STAGED])
+    # direct output of the same search: chunk reservations kept across
+    # items, and a buffer whose capacity is the exact count (positions past
+    # it go to the scratch buffer and come back in the fill) or less than it
+    for cap in (490000, 489999, 1000):
+        J[f"direct_{cap}"] = ("search", (tiny.D, tiny.D),
+                              [SPATIAL, FP32, 250.0, 0.0, 49.0, cap, 0, 0, 0, DIRECT])
     # the closest-approach refinement inline in the filter walk, at both
     # tiles, on a sparse and a dense search (at d = 250 every time-overlapping
     # pair passes every test)
@@ -222,6 +229,27 @@ def test_search_emulated_inline_refinement(emu, d, tile):
     if d == 250.0:
         assert want.size == len(w.Q) * 100
     same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
+
+
+@pytest.mark.parametrize("cap", [490000, 489999, 1000])
+def test_search_emulated_direct_output(emu, cap):
+    # 490,000 results: at the exact capacity the output is dense and equals
+    # the oracle's set; below it the call overflows and the buffer holds
+    # `cap` distinct results (the holes below the capacity were filled)
+    (st, n, _, reservations), out = result(emu, f"direct_{cap}")
+    w = emu[1]["tiny"]
+    want = oracle.search(w.D, w.D, 250.0, 0.0, 49.0)
+    assert want.size == 490000 and n == want.size and reservations > 0
+    got = np.fromfile(out, dtype=RESULT_DTYPE)
+    if cap >= n:
+        assert st == 0
+        same_records(got, want)
+    else:
+        assert st == 2  # TDS_E_OVERFLOW
+        assert got.size == cap
+        keys = lambda r: set(zip(r["q_seg"].tolist(), r["e_seg"].tolist()))
+        k = keys(got)
+        assert len(k) == cap and k <= keys(want)
 
 
 def test_search_emulated_many_bins(emu):
