@@ -140,10 +140,10 @@ def load_profile(workload, kind):
 # Launch parameters the profiles are taken with (the autotuner's choice for
 # the workload on MI355X; the bench's own tuning picks them again).
 PROFILE_PARAMS = {
-    "galaxy": "num_bins=38,chunk=1024,grid_waves=8192,tile=2,refine=inline,deal=dynamic,"
-              "precision=fp32",
-    "uniform1m": "num_bins=400,chunk=4096,grid_waves=4096,tile=4,refine=queued,deal=static,"
-                 "precision=fp32"}
+    "galaxy": "num_bins=19,chunk=2048,grid_waves=4096,tile=2,refine=inline,deal=dynamic,"
+              "output=direct,precision=fp32",
+    "uniform1m": "num_bins=400,chunk=4096,grid_waves=4096,tile=2,refine=queued,deal=static,"
+                 "output=staged,precision=fp32"}
 
 
 def profile_command(workload, counters):
@@ -646,10 +646,10 @@ def serve_leg(tds, idx, seconds, rate, sweep=(10000.0, 20000.0, 40000.0, 80000.0
 
 
 # Host route threshold of the hybrid serving run: requests whose candidate
-# ranges hold at most this many pairs after the block-box test run on the
-# host (on the uniform1m index nearly every request of the stream: its query
-# trajectories have 5-400 segments, each meeting a few 64-entry blocks).
-HOST_ROUTE_TESTS = 50000
+# ranges hold at most this many pairs run on the host (on the uniform1m index
+# a clipped query segment has about 2,500-5,000 candidates, of which the
+# block boxes leave a few hundred: up to about 100 active segments).
+HOST_ROUTE_TESTS = 500000
 
 LEGS = ("galaxy", "uniform1m", "dense", "tiny", "serve", "self_join", "fsg")
 

@@ -490,12 +490,13 @@ typedef struct tds_server_params {
     uint64_t default_reserve;    /* records reserved per request until known (0 = 1024) */
     uint32_t max_pending;        /* queued requests before submit refuses (0 = 1 << 20) */
     /* Host route (hybrid CPU + GPU serving, 0 = off): a request whose
-       candidate ranges hold at most this many (query, entry) pairs after the
-       block-box test of the spatial layout (all of them with the temporal
-       layout) is searched on 4 host threads over a host copy of the index,
-       with the GPU's filter and canonical evaluation (the same records as on
-       the GPU, bit for bit); the rest go to GPU batches.  The host copy takes
-       about 105 bytes per entry of host memory. */
+       candidate ranges hold at most this many (query, entry) pairs is
+       searched on 4 host threads over a host copy of the index, with the
+       GPU's filter (block boxes of the spatial layout, spheres) and canonical
+       evaluation (the same records as on the GPU, bit for bit), as long as at
+       most 8 such requests wait for those threads; the rest go to GPU batches
+       (so a burst is absorbed by the GPU).  The host copy takes about 105
+       bytes per entry of host memory. */
     uint32_t cpu_route_tests;
     tds_search_params search;    /* precision, chunk, grid (output fields ignored) */
 } tds_server_params;

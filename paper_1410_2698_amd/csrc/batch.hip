@@ -20,8 +20,12 @@
 
 namespace tds {
 
-// Host threads of the serving loop's host route (tds_server_params.cpu_route_tests).
+// Host threads of the serving loop's host route (tds_server_params.cpu_route_tests),
+// and the requests that may wait for them: beyond that a request the cost
+// model sends to the host goes to the GPU batches instead, so that a burst
+// is absorbed by the GPU rather than queued behind the host threads.
 constexpr uint32_t kHostRouteThreads = 4;
+constexpr uint32_t kHostRouteQueue = 2 * kHostRouteThreads;
 
 namespace {
 
@@ -650,10 +654,11 @@ int tds_server_submit(tds_server* S, const tds_segments* Q, double d, double t_s
     t->t1 = t_end;
     t->reserve = reserve ? reserve : S->P.default_reserve;
     // host route: a request with few candidate pairs (the cost model: the
-    // pair tests of its candidate ranges) is searched on the host
+    // pairs of its candidate ranges, which the host search prunes with the
+    // block boxes) is searched on the host
     if (S->host)
-        t->cpu = tds::host_candidates(*S->host, t->q.data(), t->L, d, t_start, t_end) <=
-                 S->P.cpu_route_tests;
+        t->cpu = tds::host_candidates(*S->host, t->q.data(), t->L, t_start, t_end,
+                                      S->P.cpu_route_tests) <= S->P.cpu_route_tests;
     std::unique_lock<std::mutex> lk(S->mu);
     auto queued = [&] { return S->pending.size() + S->cpu_pending.size(); };
     if (queued() >= S->P.max_pending) {
@@ -668,6 +673,7 @@ int tds_server_submit(tds_server* S, const tds_segments* Q, double d, double t_s
     S->tickets[t->id] = t;
     ++S->stats.submitted;
     *ticket = t->id;
+    if (t->cpu && S->cpu_pending.size() >= tds::kHostRouteQueue) t->cpu = false;  // host busy
     if (t->cpu) {
         S->cpu_pending.push_back(t);
         S->cv_cpu.notify_one();

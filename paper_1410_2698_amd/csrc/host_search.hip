@@ -128,25 +128,15 @@ uint64_t host_filter(const HostIndex& h, const HostQuery& hq, F&& f) {
 
 }  // namespace
 
-uint64_t host_candidates(const HostIndex& h, const double* q, uint64_t L, double d, double t0,
-                         double t1) {
+uint64_t host_candidates(const HostIndex& h, const double* q, uint64_t L, double t0, double t1,
+                         uint64_t limit) {
     uint64_t total = 0;
-    for (uint64_t k = 0; k < L; ++k) {
-        HostQuery hq;
-        if (!host_query(h, q, L, k, d, t0, t1, &hq)) continue;
-        // the block-box tests alone: the pair tests they leave
-        const uint32_t b0 = hq.lo >> kBoxShift, b1 = (hq.hi - 1) >> kBoxShift;
-        if (h.bbox.empty()) {
-            total += hq.hi - hq.lo;
-            continue;
-        }
-        for (uint32_t b = b0; b <= b1; ++b) {
-            const BlockBox& x = h.bbox[b];
-            const float box[7] = {x.lx, x.ly, x.lz, x.hx, x.hy, x.hz, x.rmax};
-            if (!box_pass(box, hq.cx, hq.cy, hq.cz, hq.R)) continue;
-            total += std::min<uint64_t>(hq.hi, (uint64_t)(b + 1) << kBoxShift) -
-                     std::max(hq.lo, b << kBoxShift);
-        }
+    for (uint64_t k = 0; k < L && total <= limit; ++k) {
+        const double aq = dmax(q[3 * L + k], t0), bq = dmin(q[7 * L + k], t1);
+        if (!(aq < bq)) continue;
+        uint32_t lo, hi;
+        host_range(h, aq, bq, &lo, &hi);
+        if (lo < hi) total += hi - lo;
     }
     return total;
 }

@@ -419,11 +419,12 @@ struct HostIndex {
 };
 // Copies the index tables to host memory (waits for the device).
 int host_index_load(const tds_index* idx, HostIndex* h);
-// The pair tests a host search of Q (8 arrays of L values, xs .. te, host
-// memory) at distance d makes: over the query segments active in the window,
-// the candidates of their ranges left after the block-box test.
-uint64_t host_candidates(const HostIndex& h, const double* q, uint64_t L, double d, double t0,
-                         double t1);
+// The candidate pairs of Q (8 arrays of L values, xs .. te, host memory) in
+// the window: over its active query segments, the lengths of their candidate
+// ranges (before any spatial pruning); the sum stops growing once it exceeds
+// `limit`.  Two bisections per segment: the serving loop's cost model.
+uint64_t host_candidates(const HostIndex& h, const double* q, uint64_t L, double t0, double t1,
+                         uint64_t limit);
 // The search of Q (validated values) on the host; records in query order.
 void host_search(const HostIndex& h, const double* q, const uint32_t* qtraj, uint64_t L,
                  double d, double t0, double t1, std::vector<tds_result>* out);

@@ -194,7 +194,7 @@ int run_hostsearch(char** argv) {
     std::vector<tds_result> out;
     uint64_t cand = 0;
     if (st == TDS_OK) {
-        cand = tds::host_candidates(h, Qc.col(0), Qc.n, d, t0, t1);
+        cand = tds::host_candidates(h, Qc.col(0), Qc.n, t0, t1, ~0ull);
         tds::host_search(h, Qc.col(0), Q.traj.data(), Qc.n, d, t0, t1, &out);
     }
     write_records(argv[7], out, out.size());
