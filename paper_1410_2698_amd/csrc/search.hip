@@ -1137,22 +1137,24 @@ __device__ __forceinline__ void enqueue(WaveLDS& L, uint64_t m, bool pass, uint3
 __device__ __forceinline__ bool refine32(const QF24& f, const QRef& r, float clx, float cly,
                                          float clz, float vlx, float vly, float vlz, float tl,
                                          float la, float lb, float scl, float svl, float stl) {
+    // sums of products are fused (fmaf): each has at most the rounding error
+    // of the separate multiply and add it replaces
     const float a = fmaxf(f.a32, la), b = fminf(f.b32, lb);
     const float tm = 0.5f * (a + b), h = 0.5f * (b - a);
     const float dq = tm - r.tq, dl = tm - tl;
-    const float dx = (f.cx - clx) + (r.vx * dq - vlx * dl);
-    const float dy = (f.cy - cly) + (r.vy * dq - vly * dl);
-    const float dz = (f.cz - clz) + (r.vz * dq - vlz * dl);
+    const float dx = (f.cx - clx) + fmaf(r.vx, dq, -(vlx * dl));
+    const float dy = (f.cy - cly) + fmaf(r.vy, dq, -(vly * dl));
+    const float dz = (f.cz - clz) + fmaf(r.vz, dq, -(vlz * dl));
     const float wx = r.vx - vlx, wy = r.vy - vly, wz = r.vz - vlz;
-    const float S = (r.sc + scl) + (r.sv + svl) * (r.st + stl);
-    const float R = (r.d + 0x1p-17f * S) * (1.0f + 0x1p-20f);
+    const float S = fmaf(r.sv + svl, r.st + stl, r.sc + scl);
+    const float R = fmaf(0x1p-17f, S, r.d) * (1.0f + 0x1p-20f);
     const float R2 = (R * R) * (1.0f + 0x1p-20f);
     const float dm1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
     const float w1 = fabsf(wx) + fabsf(wy) + fabsf(wz);
-    const float Dm2 = (dx * dx + dy * dy) + dz * dz;
-    const float WW = (wx * wx + wy * wy) + wz * wz;
-    const float DW = (dx * wx + dy * wy) + dz * wz;
-    const float span = dm1 + h * w1;
+    const float Dm2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float WW = fmaf(wz, wz, fmaf(wy, wy, wx * wx));
+    const float DW = fmaf(dz, wz, fmaf(dy, wy, dx * wx));
+    const float span = fmaf(h, w1, dm1);
     const float errA = 0x1p-17f * (span * span);
     // (1)
     const float hw = (h * __builtin_amdgcn_sqrtf(WW + 0x1p-100f)) * (1.0f + 0x1p-18f);
@@ -1160,13 +1162,14 @@ __device__ __forceinline__ bool refine32(const QF24& f, const QRef& r, float clx
     if (Dm2 - errA > (Rh * Rh) * (1.0f + 0x1p-20f)) return false;
     // (2), multiplied through by |W|^2
     const float cross = dm1 * w1;
-    if ((Dm2 * WW - DW * DW) - 0x1p-16f * (cross * cross) > (R2 * WW) * (1.0f + 0x1p-18f))
+    if (fmaf(-DW, DW, Dm2 * WW) - 0x1p-16f * (cross * cross) > (R2 * WW) * (1.0f + 0x1p-18f))
         return false;
     // (3)
-    if (fabsf(DW) > h * WW + 0x1p-17f * (cross + h * (w1 * w1))) {
-        const float ax = dx - h * wx, ay = dy - h * wy, az = dz - h * wz;
-        const float bx = dx + h * wx, by = dy + h * wy, bz = dz + h * wz;
-        const float D0 = (ax * ax + ay * ay) + az * az, D1 = (bx * bx + by * by) + bz * bz;
+    if (fabsf(DW) > fmaf(h, WW, 0x1p-17f * fmaf(h, w1 * w1, cross))) {
+        const float ax = fmaf(-h, wx, dx), ay = fmaf(-h, wy, dy), az = fmaf(-h, wz, dz);
+        const float bx = fmaf(h, wx, dx), by = fmaf(h, wy, dy), bz = fmaf(h, wz, dz);
+        const float D0 = fmaf(az, az, fmaf(ay, ay, ax * ax));
+        const float D1 = fmaf(bz, bz, fmaf(by, by, bx * bx));
         if (fminf(D0, D1) - errA > R2) return false;
     }
     return true;
@@ -1370,6 +1373,7 @@ __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemSta
     const uint32_t code = (cand - S.c0) << 6;  // used in lanes whose candidate is in the chunk
     bool motion = false;
     EntryV32 ev = {0.f, 0.f, 0.f, 0.f};
+    ERef ex = {0.f, 0.f, 0.f};
     while (mk) {
         const uint32_t j = (uint32_t)__builtin_ctzll(mk);
         mk &= mk - 1u;
@@ -1388,13 +1392,12 @@ __device__ __forceinline__ void slot_fp32(WaveLDS& L, const DistArgs& A, ItemSta
                 // lanes outside the chunk load its last entry (they never pass)
                 const uint32_t i = (cand >= S.c0 && cand < S.c1) ? cand : S.c1 - 1u;
                 ev = A.I.ev32[i];
+                ex = eref_of(ecx, ecy, ecz, ev, ets, ete);
             }
             // an unbounded sphere (stored centre 0) passes unrefined
-            if (p && er < INFINITY && q.R < INFINITY) {
-                const ERef ex = eref_of(ecx, ecy, ecz, ev, ets, ete);
+            if (p && er < INFINITY && q.R < INFINITY)
                 p = refine32(q, L.qref[j], ecx, ecy, ecz, ev.vx, ev.vy, ev.vz, ev.tm, ets, ete,
                              ex.sc, ex.sv, ex.st);
-            }
             m = ballot(p);
         }
         if (p) L.queue[S.qn + (uint32_t)__popcll(m & lanemask_lt())] = code | j;
