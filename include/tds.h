@@ -304,6 +304,31 @@ int tds_search(const tds_index* index, const tds_segments* Q, double d,
                tds_stats* stats);
 
 /*
+ * tds_search in two halves, for callers that overlap the search with other
+ * work on the host: tds_search_begin orders the whole search on `stream`
+ * (query preparation, bucket table, distance kernel, and for direct output
+ * the fill pass) and returns without waiting for the device; tds_search_end
+ * waits for it and reports as tds_search does.  The output is device memory
+ * (params->out_on_device must be 1) and Q may be in host memory (copied to
+ * the device before begin returns) or device memory (it must stay valid and
+ * unchanged until end).  No incremental passes: on TDS_E_OVERFLOW `out` holds
+ * an unspecified subset of `capacity` records and *n_out the total.  The
+ * pending search holds a workspace of the index until end; every begin must
+ * be matched by exactly one end (which frees *pending, also on errors), and
+ * the index must outlive it.  Searches begun on different streams run
+ * concurrently.  The rare search whose work items outgrow the table sized
+ * from their bound runs a second time inside end.
+ * Errors (begin): as tds_search, plus TDS_E_INVALID for host output; then
+ * *pending is NULL and nothing is left running.  Errors (end): TDS_E_INVALID
+ * (a NULL handle or invalid Q values found on the device), TDS_E_DEVICE.
+ */
+typedef struct tds_pending tds_pending;
+int tds_search_begin(const tds_index* index, const tds_segments* Q, double d, double t_start,
+                     double t_end, tds_result* out, uint64_t capacity,
+                     const tds_search_params* params, void* stream, tds_pending** pending);
+int tds_search_end(tds_pending* pending, uint64_t* n_out, tds_stats* stats);
+
+/*
  * tds_search for callers that cannot allocate memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * search, records and status codes as tds_search with device output, but

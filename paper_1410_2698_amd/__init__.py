@@ -104,6 +104,23 @@ LAYOUTS = {"default": _lib.TDS_LAYOUT_DEFAULT, "temporal": _lib.TDS_LAYOUT_TEMPO
            "spatial": _lib.TDS_LAYOUT_SPATIAL}
 
 
+class PendingSearch:
+    """A search begun with Index.search_begin; end() waits for it (once)."""
+
+    def __init__(self, lib, handle, segments):
+        self._lib, self._h, self._segments = lib, handle, segments  # keep Q's arrays alive
+
+    def end(self):
+        if self._h is None:
+            raise RuntimeError("tds_search_end: already ended")
+        n = ctypes.c_uint64()
+        st = _lib.tds_stats()
+        status = self._lib.tds_search_end(self._h, ctypes.byref(n), ctypes.byref(st))
+        self._h = None
+        self._segments = None
+        return status, int(n.value), st.as_dict()
+
+
 class Index:
     """Temporal index of an entry-segment database, resident in HBM (Sec. 4.2.1);
     layout "spatial" (the default) also orders every bin by space and keeps a
@@ -183,6 +200,24 @@ class Index:
                                       ctypes.byref(st))
         self.last_stats = st.as_dict()
         return status, int(n.value), self.last_stats
+
+    def search_begin(self, Q, d: float, t_start: float = -math.inf, t_end: float = math.inf, *,
+                     out_ptr: int, capacity: int, precision: str = "fp32", chunk: int = 0,
+                     grid_waves: int = 0, tile: int = 0, refine: str = "default",
+                     deal: str = "default", output: str = "default"):
+        """tds_search_begin into device memory at out_ptr: the search is ordered
+        on the current stream and this returns at once.  Returns a
+        PendingSearch; its end() waits and gives (status, n_total, stats)."""
+        h = _segments(Q)
+        p = _search_params(precision, chunk, grid_waves, tile, refine, deal, output)
+        p.out_on_device = 1
+        handle = ctypes.c_void_p()
+        check(self._lib.tds_search_begin(self._h, ctypes.byref(h.struct), float(d),
+                                         float(t_start), float(t_end), ctypes.c_void_p(out_ptr),
+                                         ctypes.c_uint64(capacity), ctypes.byref(p),
+                                         _current_stream(), ctypes.byref(handle)),
+              "tds_search_begin")
+        return PendingSearch(self._lib, handle, h)
 
     def search_noalloc_raw(self, Q, d: float, t_start: float = -math.inf,
                            t_end: float = math.inf, *, out_ptr: int, capacity: int,

@@ -103,6 +103,12 @@ SIGNATURES = {
                                   ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_uint64,
                                   c_u64_p, ctypes.POINTER(tds_search_params), ctypes.c_void_p,
                                   ctypes.POINTER(tds_stats)]),
+    "tds_search_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments),
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_void_p, ctypes.c_uint64,
+                                        ctypes.POINTER(tds_search_params), ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "tds_search_end": (ctypes.c_int, [ctypes.c_void_p, c_u64_p, ctypes.POINTER(tds_stats)]),
     "tds_search_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(tds_segments),
                                           ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_void_p, ctypes.c_uint64, c_u64_p,

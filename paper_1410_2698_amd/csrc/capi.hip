@@ -86,6 +86,44 @@ int tds_schedule(const tds_index* index, const tds_segments* Q, double t_start, 
                               (hipStream_t)stream);
 }
 
+struct tds_pending {
+    int device;
+    void* impl;  // tds::PendingSearch
+};
+
+int tds_search_begin(const tds_index* index, const tds_segments* Q, double d, double t_start,
+                     double t_end, tds_result* out, uint64_t capacity,
+                     const tds_search_params* params, void* stream, tds_pending** pending) {
+    if (!pending) return TDS_E_INVALID;
+    *pending = nullptr;
+    if (!index || !Q || Q->n == 0) return TDS_E_INVALID;
+    tds_pending* p = new (std::nothrow) tds_pending();
+    if (!p) return TDS_E_NOMEM;
+    p->device = index->device;
+    DeviceGuard g(index->device);
+    if (!g.ok) {
+        delete p;
+        return TDS_E_DEVICE;
+    }
+    const int st = tds::search_begin_impl(const_cast<tds_index*>(index), Q, d, t_start, t_end,
+                                          out, capacity, params, (hipStream_t)stream, &p->impl);
+    if (st != TDS_OK) {
+        delete p;
+        return st;
+    }
+    *pending = p;
+    return TDS_OK;
+}
+
+int tds_search_end(tds_pending* pending, uint64_t* n_out, tds_stats* stats) {
+    if (!pending) return TDS_E_INVALID;
+    if (n_out) *n_out = 0;
+    DeviceGuard g(pending->device);
+    const int st = g.ok ? tds::search_end_impl(pending->impl, n_out, stats) : TDS_E_DEVICE;
+    delete pending;
+    return st;
+}
+
 int tds_search(const tds_index* index, const tds_segments* Q, double d, double t_start,
                double t_end, tds_result* out, uint64_t capacity, uint64_t* n_out,
                const tds_search_params* params, void* stream, tds_stats* stats) {

@@ -2157,6 +2157,44 @@ int reserve_items(const tds_index* idx, Workspace* w, uint64_t nq, uint32_t chun
 // Runs the pipeline once for the batch whose requests the caller staged in
 // w->req_host (sent to the device here, with the descriptor), growing the
 // item table and re-running if the bound was too small.
+// One run of the pipeline for the batch whose requests the caller staged in
+// w->req_host with an item table of `cap` entries: the descriptor and the
+// requests go up, the launches are ordered on `s`, and the header and request
+// counters come back into pinned memory.  Returns without waiting.
+int enqueue_attempt(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t nreq,
+                    int prec, uint32_t chunk, uint32_t grid_waves, uint32_t cpl, uint32_t output,
+                    tds_result* out, hipStream_t s, uint64_t cap) {
+    w->desc_host->nq = V.n;
+    w->desc_host->nreq = nreq;
+    w->desc_host->item_cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
+    TDS_TRY(ws_upload(w, nreq, s));
+    // one request: direct output unless staging is asked for
+    TDS_TRY(enqueue_pipeline(idx, w, V, V.n, nreq, prec, chunk, grid_waves, cpl, out,
+                             w->item_count, s, w->ev0, w->ev1,
+                             nreq == 1 && output != TDS_OUTPUT_STAGED));
+    return ws_download(w, nreq, s);
+}
+
+// After an attempt has completed: its header and kernel time; returns TDS_OK,
+// TDS_E_INVALID, or 1 when the item table was too small (it is then sized
+// exactly for another attempt).
+int finish_attempt(Workspace* w, tds_stats* st, SearchHeader* h_out, uint64_t* cap) {
+    *h_out = *w->hdr_host;
+    float ms = 0.f;
+    TDS_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+    st->kernel_ms += ms;
+    st->passes += 1;
+    if (h_out->err & 1u) return TDS_E_INVALID;
+    if (!(h_out->err & 2u)) return TDS_OK;
+    *cap = h_out->n_items;
+    TDS_TRY(grow(&w->item_bucket, &w->item_bucket_cap, std::max<size_t>(*cap, 1)));
+    TDS_TRY(grow(&w->item_count, &w->item_cap, std::max<size_t>(*cap, 1)));
+    return 1;
+}
+
+// Runs the pipeline once for the batch whose requests the caller staged in
+// w->req_host (sent to the device here, with the descriptor), growing the
+// item table and re-running if the bound was too small.
 int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t nreq, int prec,
               uint32_t chunk, uint32_t grid_waves, uint32_t cpl, uint32_t output, tds_result* out,
               hipStream_t s, tds_stats* st, SearchHeader* h_out) {
@@ -2164,27 +2202,11 @@ int run_batch(const tds_index* idx, Workspace* w, const QueryView& V, uint32_t n
     TDS_TRY(reserve_items(idx, w, V.n, chunk, &cap));
     TDS_TRY(ws_reserve_stage(w, grid_waves));
     for (int attempt = 0; attempt < 2; ++attempt) {
-        w->desc_host->nq = V.n;
-        w->desc_host->nreq = nreq;
-        w->desc_host->item_cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
-        TDS_TRY(ws_upload(w, nreq, s));  // the descriptor and the requests staged by the caller
-        // one request: direct output unless staging is asked for
-        TDS_TRY(enqueue_pipeline(idx, w, V, V.n, nreq, prec, chunk, grid_waves, cpl, out,
-                                 w->item_count, s, w->ev0, w->ev1,
-                                 nreq == 1 && output != TDS_OUTPUT_STAGED));
-        TDS_TRY(ws_download(w, nreq, s));
+        TDS_TRY(enqueue_attempt(idx, w, V, nreq, prec, chunk, grid_waves, cpl, output, out, s,
+                                cap));
         TDS_HIP(hipStreamSynchronize(s));
-        *h_out = *w->hdr_host;
-        float ms = 0.f;
-        TDS_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-        st->kernel_ms += ms;
-        st->passes += 1;
-        if (h_out->err & 1u) return TDS_E_INVALID;
-        if (!(h_out->err & 2u)) return TDS_OK;
-        // the item table was too small: size it exactly and run again
-        cap = h_out->n_items;
-        TDS_TRY(grow(&w->item_bucket, &w->item_bucket_cap, std::max<size_t>(cap, 1)));
-        TDS_TRY(grow(&w->item_count, &w->item_cap, std::max<size_t>(cap, 1)));
+        const int r = finish_attempt(w, st, h_out, &cap);
+        if (r != 1) return r;
     }
     return TDS_E_DEVICE;
 }
@@ -2422,6 +2444,139 @@ int search_core(tds_index* idx, const tds_segments* Q, bool self_join, double d,
     return status;
 }
 }  // namespace
+
+// A search begun on a stream and not yet ended (tds_search_begin): it holds
+// its workspace until tds_search_end.
+struct PendingSearch {
+    tds_index* idx = nullptr;
+    Workspace* w = nullptr;
+    hipStream_t s = nullptr;
+    QueryView V{};
+    tds_result* out = nullptr;
+    uint64_t capacity = 0, cap_items = 0;
+    int prec = 0;
+    uint32_t chunk = 0, grid_waves = 0, cpl = 0, output = 0;
+    hipEvent_t done = nullptr;
+    std::chrono::steady_clock::time_point t0;
+};
+
+int search_begin_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
+                      double t_end, tds_result* out, uint64_t capacity,
+                      const tds_search_params* params, hipStream_t s, void** pending) {
+    const auto t_begin = std::chrono::steady_clock::now();
+    if (!idx || !pending) return TDS_E_INVALID;
+    *pending = nullptr;
+    TDS_TRY(validate_segments_args(Q));
+    if (!valid_window(d, t_start, t_end)) return TDS_E_INVALID;
+    if (capacity > 0 && !out) return TDS_E_INVALID;
+    tds_search_params P;
+    tds_search_params_default(&P);
+    if (params) P = *params;
+    if (!P.out_on_device) return TDS_E_INVALID;  // the output is device memory
+    const int prec = resolve_prec(P.precision);
+    if (prec < 0) return TDS_E_INVALID;
+    const uint32_t cpl = resolve_tile(P.tile, P.refine, P.deal);
+    if (!cpl || P.output > TDS_OUTPUT_STAGED) return TDS_E_INVALID;
+    PendingSearch* ps = new (std::nothrow) PendingSearch();
+    if (!ps) return TDS_E_NOMEM;
+    ps->idx = idx;
+    ps->s = s;
+    ps->out = out;
+    ps->capacity = capacity;
+    ps->prec = prec;
+    ps->chunk = resolve_chunk(prec, P.chunk);
+    ps->grid_waves = resolve_grid(P.grid_waves);
+    ps->cpl = cpl;
+    ps->output = P.output;
+    ps->t0 = t_begin;
+    int st = TDS_OK;
+    do {
+        if (!(ps->w = acquire(idx))) { st = TDS_E_NOMEM; break; }
+        Workspace* w = ps->w;
+        if ((st = ws_reserve(w, Q->n, 1))) break;
+        if ((st = stage_queries(Q, &ps->V, s, &w->qstage, &w->stage_cap, &w->qtraj_stage,
+                                &w->traj_cap, false)))
+            break;
+        Request R{};
+        R.q_begin = 0;
+        R.q_count = Q->n;
+        R.d = d;
+        R.t_start = t_start;
+        R.t_end = t_end;
+        R.out_offset = 0;
+        R.out_capacity = capacity;
+        *w->req_host = R;
+        if ((st = reserve_items(idx, w, Q->n, ps->chunk, &ps->cap_items))) break;
+        if ((st = ws_reserve_stage(w, ps->grid_waves))) break;
+        if (hipEventCreateWithFlags(&ps->done, hipEventDisableTiming) != hipSuccess) {
+            ps->done = nullptr;
+            st = TDS_E_DEVICE;
+            break;
+        }
+        if ((st = enqueue_attempt(idx, w, ps->V, 1, prec, ps->chunk, ps->grid_waves, cpl,
+                                  ps->output, out, s, ps->cap_items)))
+            break;
+        if (hipEventRecord(ps->done, s) != hipSuccess) { st = TDS_E_DEVICE; break; }
+    } while (0);
+    if (st != TDS_OK) {
+        if (ps->done) {
+            (void)hipStreamSynchronize(s);  // nothing of it may still run
+            (void)hipEventDestroy(ps->done);
+        }
+        if (ps->w) release(idx, ps->w);
+        delete ps;
+        return st;
+    }
+    *pending = ps;
+    return TDS_OK;
+}
+
+int search_end_impl(void* pending, uint64_t* n_out, tds_stats* stats) {
+    PendingSearch* ps = static_cast<PendingSearch*>(pending);
+    if (!ps) return TDS_E_INVALID;
+    Workspace* w = ps->w;
+    tds_stats st{};
+    st.query_segments = ps->V.n;
+    SearchHeader h{};
+    int status = TDS_OK;
+    if (hipEventSynchronize(ps->done) != hipSuccess) {
+        status = TDS_E_DEVICE;
+    } else {
+        int r = finish_attempt(w, &st, &h, &ps->cap_items);
+        if (r == 1) {
+            // the item table was too small: the search runs again, sized exactly
+            r = enqueue_attempt(ps->idx, w, ps->V, 1, ps->prec, ps->chunk, ps->grid_waves,
+                                ps->cpl, ps->output, ps->out, ps->s, ps->cap_items);
+            if (r == TDS_OK)
+                r = hipStreamSynchronize(ps->s) == hipSuccess
+                        ? finish_attempt(w, &st, &h, &ps->cap_items)
+                        : TDS_E_DEVICE;
+            if (r == 1) r = TDS_E_DEVICE;
+        }
+        status = r;
+    }
+    if (status == TDS_OK) {
+        const uint64_t total = w->rc_host[0].count;
+        if (n_out) *n_out = total;
+        st.active_segments = h.active;
+        st.work_items = h.n_items;
+        st.candidate_tests = h.tests;
+        st.filter_tests = h.ftests;
+        st.block_tests = h.btests;
+        st.fp64_evals = h.evals;
+        st.stage_flushes = h.flushes;
+        st.results = total;
+        st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                ps->t0)
+                          .count();
+        if (stats) *stats = st;
+        status = total > ps->capacity ? TDS_E_OVERFLOW : TDS_OK;
+    }
+    (void)hipEventDestroy(ps->done);
+    release(ps->idx, w);
+    delete ps;
+    return status;
+}
 
 // Checks that the requests tile [0, nq) in order and their output slices fit.
 int validate_requests(const tds_request* reqs, uint32_t nreq, uint64_t nq, uint64_t out_cap) {

@@ -464,6 +464,12 @@ int enqueue_search(const tds_index* idx, Workspace* w, const double* const* qarr
 int search_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
                 double t_end, tds_result* out, uint64_t capacity, uint64_t* n_out,
                 const tds_search_params* params, hipStream_t stream, tds_stats* stats);
+// tds_search_begin / tds_search_end: the pending search is an opaque object
+// the library allocates in begin and frees in end.
+int search_begin_impl(tds_index* idx, const tds_segments* Q, double d, double t_start,
+                      double t_end, tds_result* out, uint64_t capacity,
+                      const tds_search_params* params, hipStream_t s, void** pending);
+int search_end_impl(void* pending, uint64_t* n_out, tds_stats* stats);
 int self_join_impl(tds_index* idx, double d, double t_start, double t_end, tds_result* out,
                    uint64_t capacity, uint64_t* n_out, const tds_search_params* params,
                    hipStream_t s, tds_stats* stats);
