@@ -78,13 +78,14 @@ def test_every_tile_and_mapping_gives_the_same_records():
     idx.close()
 
 
-@pytest.mark.parametrize("grid_waves", [256, 4096, 8192])
+@pytest.mark.parametrize("grid_waves", [256, 4096, 8192, 20480])
 def test_direct_output_capacities_on_the_device(grid_waves):
     """Direct output into a device buffer: at the exact count the records
     are the staged search's; one short of it (and far short) the call
     overflows and the buffer holds that many distinct results; with room to
     spare the first `count` records are the results.  Many waves end with
-    partly used chunks, so the fill has work at every grid."""
+    partly used chunks, so the fill has work at every grid; a grid of more
+    waves than the fill plan takes (16,384) stages instead, unasked."""
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     w = trajgen.dense(0.05, n_pts=81)
     idx = tds.Index(w.D)
