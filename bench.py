@@ -235,6 +235,10 @@ def roofline(workload, st, launches, n_entries_ranged, nq):
              "algorithmic_bytes_per_launch": int(byts),
              "fp32_flops_per_launch": int(f32), "fp64_flops_per_launch": int(f64),
              "filter_tests_per_s": round(st["filter_tests"] / L / avg_s, 1),
+             # the bandwidth a kernel streaming one 32-B FP32 record per executed
+             # filter test would need (the per-query access model); not bounded
+             # by HBM here, records are reused from registers by 64 queries
+             "filter_test_stream_tb_s": round(32 * st["filter_tests"] / L / avg_s / 1e12, 3),
              "fp64_evals_per_s": round(st["fp64_evals"] / L / avg_s, 1)}
     if traffic:
         views["dram_tb_s"] = round(traffic["bytes_per_launch"] / avg_s / 1e12, 4)
@@ -342,7 +346,13 @@ class SearchLeg:
         self.tuned = dict({"num_bins": 0, "chunk": 0, "grid_waves": 0, "tile": 0,
                            "refine": "default", "deal": "default", "output": "default",
                            "precision": "fp32"}, **(tuned or {}))
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
         self.idx = tds.Index(w.D, num_bins=self.tuned["num_bins"])
+        torch.cuda.synchronize()
+        # index build, host arrays in (upload included): reported apart from
+        # the search, as the paper's response time excludes it
+        self.build_ms = 1e3 * (time.perf_counter() - tb)
         Qt = device_segments(w.Q)
         nq = len(w.Q)
         self.Qb = {k: torch.cat([v] * len(w.ds)) if len(w.ds) > 1 else v for k, v in Qt.items()}
@@ -430,6 +440,7 @@ class SearchLeg:
             "fp64_evals_per_step": acc["fp64_evals"] // steps,
             "fp64_recheck_fraction": round(acc["fp64_evals"] / max(acc["candidate_tests"], 1), 8),
             "stage_flushes_per_step": acc["stage_flushes"] // steps,
+            "index_build_ms": round(self.build_ms, 2),
             "roofline": roofline(w.name, acc, acc["passes"], n_ranged, len(w.Q) * len(w.ds)),
             "fp64_form": fp64,
             "fp32_endpoint_error": {"max_abs": max(e["max_abs"] for e in errs.values()),
