@@ -9,18 +9,33 @@
 //   harness selfjoin D.bin layout prec d t0 t1 cap out.bin        -> "status n ftests"
 //   harness merge recs.bin capacity out.bin                       -> "status n"
 //   harness hostsearch D.bin Q.bin d t0 t1 out.bin                -> "status n candidates"
+//   harness fill seed W C K frac add align prefix                 -> "status count cap T holes R"
 //
 // D.bin / Q.bin: 9 float64 columns (xs ys zs ts xe ye ze te traj), column
 // after column.  recs.bin: tds_result records.  out.bin: the records or
 // intervals written.
+//
+// "fill" runs the direct-output fill pass (k_fill_plan, k_fill_copy) alone on
+// a synthetic reservation pattern: W waves append random runs of 1..64
+// results in chunks of C positions, as the distance kernel's direct output
+// does, in a random interleaving (K runs per wave at most); the capacity is
+// floor(count * frac) + add (rounded down to a multiple of C if align).  It
+// writes prefix.all (every result: id in q_seg, position in e_seg, e_traj 1 if
+// its position was kept in the output or scratch), prefix.before and
+// prefix.after (the first T = min(count, capacity) output records before and
+// after the fill; holes are 0xFFFFFFFF).
+//
+// search.hip is part of this translation unit (not compiled on its own), so
+// that the fill kernels in its anonymous namespace can be launched directly.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
 #include <numeric>
+#include <random>
 #include <vector>
 
-#include "tds_internal.hpp"
+#include "search.hip"
 
 long emu_launches = 0;
 
@@ -203,6 +218,108 @@ int run_hostsearch(char** argv) {
     return 0;
 }
 
+int run_fill(char** argv) {
+    std::mt19937_64 rng(strtoull(argv[2], nullptr, 10));
+    const uint32_t W = (uint32_t)atoi(argv[3]), C = (uint32_t)atoi(argv[4]),
+                   K = (uint32_t)atoi(argv[5]);
+    const double frac = atof(argv[6]);
+    const int64_t add = strtoll(argv[7], nullptr, 10);
+    const bool align = atoi(argv[8]) != 0;
+    const std::string prefix = argv[9];
+    if (W == 0 || W > tds::kMaxDirectWaves || C < 64 || C > 2048 || C % 64) {
+        printf("%d 0 0 0 0 0\n", TDS_E_INVALID);
+        return 0;
+    }
+    // the runs of each wave, then a random interleaving of them
+    std::vector<std::vector<uint32_t>> runs(W);
+    std::vector<uint32_t> order;
+    for (uint32_t w = 0; w < W; ++w) {
+        const uint32_t nr = (uint32_t)(rng() % (K + 1));
+        for (uint32_t r = 0; r < nr; ++r) {
+            runs[w].push_back(1 + (uint32_t)(rng() % 64));
+            order.push_back(w);
+        }
+    }
+    std::shuffle(order.begin(), order.end(), rng);
+    // positions: a wave fills its chunk from the front and reserves the next
+    // chunk from the shared counter when a run does not fit
+    struct Placed {
+        uint64_t id, pos;
+    };
+    std::vector<Placed> placed;
+    std::vector<uint64_t> dpos(W, 0), dend(W, 0);
+    std::vector<size_t> next(W, 0);
+    uint64_t ctr = 0;
+    for (uint32_t w : order) {
+        const uint32_t nhit = runs[w][next[w]++];
+        const uint64_t room = dend[w] - dpos[w];
+        uint64_t b = 0;
+        if (nhit > room) {
+            b = ctr;
+            ctr += C;
+        }
+        for (uint32_t r = 0; r < nhit; ++r) {
+            const uint64_t pos = r < room ? dpos[w] + r : b + (r - room);
+            placed.push_back({placed.size(), pos});
+        }
+        if (nhit > room) {
+            dpos[w] = b + (nhit - room);
+            dend[w] = b + C;
+        } else {
+            dpos[w] += nhit;
+        }
+    }
+    const uint64_t count = placed.size();
+    int64_t capi = (int64_t)std::floor((double)count * frac) + add;
+    if (capi < 0) capi = 0;
+    uint64_t cap = (uint64_t)capi;
+    if (align) cap -= cap % C;
+    const uint64_t scap = (uint64_t)W * C;
+    const uint64_t T = std::min(count, cap);
+    constexpr uint32_t kHole = 0xFFFFFFFFu;
+    tds_result blank{};
+    blank.q_seg = blank.e_seg = kHole;
+    std::vector<tds_result> out(std::max<uint64_t>(cap, 1), blank), scratch(scap, blank);
+    std::vector<tds_result> all(count);
+    for (const Placed& p : placed) {
+        tds_result r{};
+        r.q_seg = (uint32_t)p.id;
+        r.e_seg = (uint32_t)p.pos;
+        r.e_traj = p.pos < cap + scap ? 1u : 0u;
+        all[p.id] = r;
+        r.e_traj = 0;
+        if (p.pos < cap) out[p.pos] = r;
+        else if (p.pos - cap < scap) scratch[p.pos - cap] = r;
+    }
+    std::vector<uint64_t> dlast(W);
+    uint64_t holes = 0;
+    for (uint32_t w = 0; w < W; ++w) {
+        dlast[w] = dend[w] ? ((dend[w] / C - 1) << 16) | (C - (dend[w] - dpos[w])) : ~0ull;
+        if (dend[w] && dpos[w] < T) holes += std::min(dend[w], T) - dpos[w];
+    }
+    write_records((prefix + ".all").c_str(), all, count);
+    write_records((prefix + ".before").c_str(), out, T);
+    // the pass as the library launches it, on buffers of the sizes it
+    // allocates (W + 2, W + 1, W and 4 entries)
+    tds::Request req{};
+    req.q_count = 1;
+    req.out_capacity = cap;
+    tds::ReqCounter rc{count, 0};
+    unsigned long long R = ctr;
+    std::vector<uint64_t> s_pre((size_t)W + 2), d_pre((size_t)W + 1), d_start(W), plan(4);
+    hipLaunchKernelGGL(tds::k_fill_plan, dim3(1), dim3(1024), 0, nullptr, &req, &rc, &R,
+                       dlast.data(), W, C, s_pre.data(), d_pre.data(), d_start.data(),
+                       plan.data());
+    hipLaunchKernelGGL(tds::k_fill_copy, dim3(1024), dim3(256), 0, nullptr, plan.data(),
+                       s_pre.data(), d_pre.data(), d_start.data(), W, C, &req, out.data(),
+                       scratch.data());
+    write_records((prefix + ".after").c_str(), out, T);
+    printf("%d %llu %llu %llu %llu %llu\n", TDS_OK, (unsigned long long)count,
+           (unsigned long long)cap, (unsigned long long)T, (unsigned long long)holes,
+           (unsigned long long)R);
+    return 0;
+}
+
 int run_merge(char** argv) {
     const std::vector<char> raw = read_file(argv[2]);
     const size_t n = raw.size() / sizeof(tds_result);
@@ -227,6 +344,7 @@ int main(int argc, char** argv) {
     if (argc >= 10 && std::string(argv[1]) == "selfjoin") return run_search(argc, argv, true);
     if (argc >= 5 && std::string(argv[1]) == "merge") return run_merge(argv);
     if (argc >= 8 && std::string(argv[1]) == "hostsearch") return run_hostsearch(argv);
+    if (argc >= 10 && std::string(argv[1]) == "fill") return run_fill(argv);
     fprintf(stderr, "usage: harness fsg ... | harness merge ...\n");
     return 2;
 }

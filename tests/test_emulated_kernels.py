@@ -64,6 +64,19 @@ def _merge_degenerate():
     return recs
 
 
+FILL_CASES = {
+    "fill_exact": (1, 64, 64, 6, 1.0, 0, 0),            # capacity = count
+    "fill_more": (2, 64, 128, 6, 1.0, 5000, 0),         # room to spare: holes below count
+    "fill_less_one": (3, 37, 64, 3, 1.0, -1, 0),        # one short, an odd wave count
+    "fill_half": (4, 200, 64, 8, 0.5, 0, 0),            # overflow
+    "fill_aligned": (5, 200, 256, 10, 0.6, 0, 1),       # capacity a multiple of the chunk
+    "fill_big_chunk": (6, 48, 2048, 40, 0.9, 0, 0),     # the largest chunk
+    "fill_zero_cap": (7, 16, 64, 4, 0.0, 0, 0),         # nothing kept
+    "fill_empty": (8, 16, 64, 0, 1.0, 0, 0),            # no results, no reservation
+    "fill_max_waves": (9, 16384, 64, 2, 1.0, 0, 0),     # the most waves of a direct launch
+}
+
+
 def _jobs():
     """Every emulated run: name -> (kind, inputs, arguments after the inputs).
     Kinds "search" and "fsg" take D and Q, "selfjoin" D, "merge" records."""
@@ -106,6 +119,11 @@ def _jobs():
     # the serving loop's host route over a host copy of the index
     J["hostsearch"] = ("hostsearch", (tiny.D, tiny.Q), [30.0, 3.5, 40.25])
     J["hostsearch_all"] = ("hostsearch", (tiny.D, tiny.Q), [250.0, 3.5, 40.25])
+    # the direct output's fill pass alone on synthetic reservation patterns
+    # (seed, waves, chunk, runs per wave at most, capacity = floor(count *
+    # frac) + add, rounded down to a multiple of the chunk if align)
+    for name, args in FILL_CASES.items():
+        J[name] = ("fill", None, list(args))
     J["merge_random"] = ("merge", _merge_random(), [3000])
     J["merge_degenerate"] = ("merge", _merge_degenerate(), [600])
     J["merge_degenerate_cap3"] = ("merge", _merge_degenerate(), [3])
@@ -120,13 +138,14 @@ def _build_harness(out):
     if cxx is None:
         pytest.skip("clang++ not available")
     # host-only build (no GPU code); the canonical evaluation is compiled
-    # without contraction, as for the GPU
+    # without contraction, as for the GPU; search.hip is included by the
+    # harness itself
     cmd = [cxx, "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
            "-ffp-contract=off", "-Wno-unknown-attributes", "-Wno-ignored-attributes",
            "-I", os.path.join(ROOT, "tests", "emu"), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-x", "c++", os.path.join(CSRC, "fsg.hip"), os.path.join(CSRC, "radix_sort.hip"),
            os.path.join(CSRC, "traj_merge.hip"), os.path.join(CSRC, "index_build.hip"),
-           os.path.join(CSRC, "search.hip"), os.path.join(CSRC, "host_search.hip"), "-x", "none",
+           os.path.join(CSRC, "host_search.hip"), "-x", "none",
            os.path.join(ROOT, "tests", "emu", "harness.cpp"), "-o", out, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -139,6 +158,9 @@ def _run_job(harness, d, kind, inputs, args):
     if kind == "merge":
         inputs.astype(RESULT_DTYPE).tofile(os.path.join(d, "recs.bin"))
         argv = [harness, "merge", os.path.join(d, "recs.bin"), *args, out]
+    elif kind == "fill":
+        out = os.path.join(d, "fill")
+        argv = [harness, "fill", *args, out]
     else:
         files = []
         for i, S in enumerate(inputs):
@@ -298,6 +320,42 @@ def test_host_search_emulated(emu, job, d):
     # the evaluation is the kernels' canonical one: endpoints bit for bit
     key = lambda r: np.lexsort((r["e_seg"], r["q_seg"]))
     assert got[key(got)].tobytes() == want[key(want)].tobytes()
+
+
+@pytest.mark.parametrize("name", list(FILL_CASES))
+def test_fill_pass_emulated(emu, name):
+    """The direct output's fill pass on a synthetic reservation pattern: the
+    first T = min(count, capacity) positions must end dense, the results the
+    distance kernel placed below T must stay where they are, and the holes
+    must be filled by the first results past T in position order (those the
+    pass takes), each once."""
+    (st, count, cap, T, holes, R), prefix = result(emu, name)
+    assert st == 0 and T == min(count, cap)
+    allr = np.fromfile(prefix + ".all", dtype=RESULT_DTYPE)
+    before = np.fromfile(prefix + ".before", dtype=RESULT_DTYPE)
+    after = np.fromfile(prefix + ".after", dtype=RESULT_DTYPE)
+    assert allr.size == count and before.size == T and after.size == T
+    assert np.array_equal(allr["q_seg"], np.arange(count))
+    hole = before["q_seg"] == 0xFFFFFFFF
+    assert int(hole.sum()) == holes and R >= count + holes
+    assert not np.any(after["q_seg"] == 0xFFFFFFFF)
+    # every record is one of the results, as it was placed, and appears once
+    assert np.array_equal(after["e_seg"], allr["e_seg"][after["q_seg"]])
+    assert np.unique(after["q_seg"]).size == T
+    assert np.array_equal(after[~hole], before[~hole])
+    pos = allr["e_seg"].astype(np.int64)
+    past = np.sort(pos[pos >= T])[:holes]
+    moved = np.sort(after["e_seg"][hole].astype(np.int64))
+    assert np.array_equal(moved, past)
+    assert np.all(allr["e_traj"][after["q_seg"][hole]] == 1)  # kept in output or scratch
+    if count <= cap:
+        assert np.array_equal(np.sort(after["q_seg"]), np.arange(count))
+    if name == "fill_empty":
+        assert count == 0 and R == 0
+    if name == "fill_zero_cap":
+        assert T == 0 and count > 0
+    if name == "fill_exact":
+        assert count == cap and holes > 0
 
 
 def same_intervals(got, want):
