@@ -61,8 +61,7 @@ PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 # Algorithmic work of the distance kernel, per unit (counted by the kernel):
 # FP32 filter test: 3 sub, 1 mul, 2 FMA (2 flops each), 1 add, 1 mul,
 #   3 compares = 13;
-# (query, 64-entry block) box test: per axis 2 sub + 2 max, then 1 mul,
-#   2 FMA, 1 add, 1 mul, 1 compare = 20;
+# (query, 64-entry block) box test: 2 compares per axis = 6;
 # canonical FP64 membership of one pair: extent 2 min/max + 1 compare + 1 sub,
 #   4 time offsets, 6 position differences of 5, 3 relative velocities, d^2,
 #   C0 and C1 (6 each), A and B (5 each), the vertex clause (3 mul, 1 sub,
@@ -70,7 +69,7 @@ PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 # interval of a result: discriminant 3, sqrt 1, max 1, root numerator 2,
 #   2 divisions + 1 compare, both ends clamped (5 each), order check 1 = 21.
 FLOPS_FILTER = 13
-FLOPS_BOX = 20
+FLOPS_BOX = 6
 FLOPS_EVAL64 = 74
 FLOPS_RESULT64 = 21
 # Bytes the kernel must move, per unit: a result record written (32 B); per

@@ -333,7 +333,7 @@ int tds_search_end(tds_pending* pending, uint64_t* n_out, tds_stats* stats);
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * search, records and status codes as tds_search with device output, but
  * every buffer beyond the caller's inputs and outputs comes from one
- * statically sized device array of 24 MiB per device (held by the library
+ * statically sized device array of 28 MiB per device (held by the library
  * until the process ends; its address is looked up on the first call on a
  * device).  The call allocates no device, host or pinned memory.
  * Requirements beyond tds_search's: Q in device memory (Q->on_device = 1) with

@@ -4,10 +4,10 @@
 // for small, sparse searches, Sec. 5.3-5.5).  It runs the same steps as the
 // GPU search for one query segment: clip to the window, the candidate range
 // E_k of Sec. 4.2.2 from the bin tables, the FP32 filter (block boxes of the
-// spatial layout, then the bounding spheres and time extents: sphere32,
-// box_pass, sphere_pass, the code the kernels use) and the canonical FP64
-// evaluation of every pair it passes (canon.hpp), so its records are
-// bit-identical to the GPU's.
+// spatial layout, then the bounding spheres and time extents: seg_box32,
+// box_overlap, sphere32 and sphere_pass, the code the kernels use) and the
+// canonical FP64 evaluation of every pair it passes (canon.hpp), so its
+// records are bit-identical to the GPU's.
 #include <algorithm>
 #include <cmath>
 
@@ -68,6 +68,7 @@ struct HostQuery {
     QCanon c;
     uint32_t lo, hi;
     float cx, cy, cz, R, a32, b32;
+    float box[6];  // box of the clipped segment grown by d (block culling)
 };
 
 bool host_query(const HostIndex& h, const double* q, uint64_t L, uint64_t k, double d, double t0,
@@ -96,6 +97,7 @@ bool host_query(const HostIndex& h, const double* q, uint64_t L, uint64_t k, dou
     const double pbx = c.x + c.vx * (c.bq - ts), pby = c.y + c.vy * (c.bq - ts),
                  pbz = c.z + c.vz * (c.bq - ts);
     sphere32(pax, pay, paz, pbx, pby, pbz, d, hq->cx, hq->cy, hq->cz, hq->R);
+    seg_box32(pax, pay, paz, pbx, pby, pbz, d, hq->box);
     hq->a32 = f32_rd(c.aq);
     hq->b32 = f32_ru(c.bq);
     return true;
@@ -110,8 +112,8 @@ uint64_t host_filter(const HostIndex& h, const HostQuery& hq, F&& f) {
     for (uint32_t b = b0; b <= b1; ++b) {
         if (!h.bbox.empty()) {
             const BlockBox& x = h.bbox[b];
-            const float box[7] = {x.lx, x.ly, x.lz, x.hx, x.hy, x.hz, x.rmax};
-            if (!box_pass(box, hq.cx, hq.cy, hq.cz, hq.R)) continue;
+            const float box[6] = {x.lx, x.ly, x.lz, x.hx, x.hy, x.hz};
+            if (!box_overlap(box, hq.box)) continue;
         }
         const uint32_t i0 = std::max(hq.lo, b << kBoxShift);
         const uint32_t i1 = std::min<uint64_t>(hq.hi, (uint64_t)(b + 1) << kBoxShift);

@@ -15,8 +15,8 @@
 //   k_bin_scan    running maximum of max t_end over bins, which makes the
 //                 bins overlapping a query one contiguous, bisectable span,
 //                 and the minimum t_start over the bins from j on;
-//   k_block_box   (spatial layout) bounding box of the spheres of every
-//                 aligned block of 64 entries.
+//   k_block_box   (spatial layout) box of the segments of every aligned
+//                 block of 64 entries.
 #include <cmath>
 #include <utility>
 
@@ -243,24 +243,23 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const double* __restrict__ v,
     }
 }
 
-// Bounding box of the FP32 spheres of each aligned block of 64 entries, one
-// wave per block (lanes past n contribute nothing).
-__global__ __launch_bounds__(kBT) void k_block_box(uint64_t n, const EntryF32* __restrict__ e32,
+// Box of each aligned block of 64 entries: the union of the entries' segment
+// boxes (seg_box32 of the end points the canonical evaluation computes from
+// the FP64 record), one wave per block (lanes past n contribute nothing).
+__global__ __launch_bounds__(kBT) void k_block_box(uint64_t n, const EntryF64* __restrict__ e64,
                                                    BlockBox* __restrict__ box, uint32_t nblk) {
     const uint32_t blk = blockIdx.x * (kBT / kWave) + threadIdx.x / kWave;
     if (blk >= nblk) return;
     const uint64_t i = ((uint64_t)blk << kBoxShift) + __lane_id();
-    float v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     if (i < n) {
-        const EntryF32 f = e32[i];
-        v[0] = v[3] = f.cx;
-        v[1] = v[4] = f.cy;
-        v[2] = v[5] = f.cz;
-        v[6] = f.r;
+        const EntryF64 e = e64[i];
+        const double dt = e.te - e.ts;
+        seg_box32(e.x, e.y, e.z, e.x + e.vx * dt, e.y + e.vy * dt, e.z + e.vz * dt, 0.0, v);
     }
     for (int off = kWave / 2; off > 0; off >>= 1) {
         for (int k = 0; k < 3; ++k) v[k] = fminf(v[k], __shfl_xor(v[k], off));
-        for (int k = 3; k < 7; ++k) v[k] = fmaxf(v[k], __shfl_xor(v[k], off));
+        for (int k = 3; k < 6; ++k) v[k] = fmaxf(v[k], __shfl_xor(v[k], off));
     }
     if (__lane_id() == 0) {
         BlockBox b;
@@ -270,8 +269,8 @@ __global__ __launch_bounds__(kBT) void k_block_box(uint64_t n, const EntryF32* _
         b.hx = v[3];
         b.hy = v[4];
         b.hz = v[5];
-        b.rmax = v[6];
-        b.pad = 0.f;
+        b.pad0 = 0.f;
+        b.pad1 = 0.f;
         box[blk] = b;
     }
 }
@@ -478,7 +477,7 @@ int build_impl(const tds_segments* D, const tds_build_params* p, hipStream_t str
                        m);
     if (idx->bbox)
         hipLaunchKernelGGL(k_block_box, dim3(ceil_div(nblk, kBT / kWave)), dim3(kBT), 0, stream, n,
-                           idx->e32, idx->bbox, nblk);
+                           idx->e64, idx->bbox, nblk);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
         destroy_index(idx);
         return TDS_E_DEVICE;

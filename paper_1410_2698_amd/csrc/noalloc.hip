@@ -67,7 +67,7 @@ constexpr Carve carve() {
 }
 
 constexpr Carve kCarve = carve();
-constexpr size_t kScratchBytes = 24ull << 20;  // 24 MiB per device
+constexpr size_t kScratchBytes = 28ull << 20;  // 28 MiB per device
 static_assert(kCarve.total <= kScratchBytes, "scratch layout exceeds the array");
 
 // The search's scratch memory on every device the library runs on (held

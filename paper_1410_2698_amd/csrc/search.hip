@@ -417,6 +417,8 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                                  pbz = p.z + p.vz * (p.bq - ts);
                     QF32 f;
                     sphere32(pax, pay, paz, pbx, pby, pbz, p.d, f.cx, f.cy, f.cz, f.R);
+                    seg_box32(pax, pay, paz, pbx, pby, pbz, p.d, f.box);
+                    f.pad[0] = f.pad[1] = 0.f;
                     f.a32 = __double2float_rd(p.aq);
                     f.b32 = __double2float_ru(p.bq);
                     f.lo = lo;
@@ -1330,9 +1332,9 @@ __device__ __forceinline__ void item_begin(WaveLDS& L, const DistArgs& A, ItemSt
 
 // FP32 filter record of the query segment held by a lane (its QF32 record).
 struct QReg {
-    float cx, cy, cz, R;  // sphere of the clipped segment
-    float a, b;           // clipped window rounded outwards
-    uint32_t lo, hi;      // candidate range
+    float box[6];     // box of the clipped segment grown by d (seg_box32)
+    float a, b;       // clipped window rounded outwards
+    uint32_t lo, hi;  // candidate range
 };
 
 // Value of v in lane j (wave-uniform j): a register read, no memory access.
@@ -1423,13 +1425,15 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
     constexpr uint32_t kStep = kCpl * kWave;  // candidates per tile
     const uint32_t lane = __lane_id();
     const bool has = lane < S.nq;
-    QReg q = {0.f, 0.f, 0.f, 0.f, -INFINITY, INFINITY, 0u, 0u};
+    const bool cull = A.I.bbox != nullptr;
+    // a lane without a query: an empty box (it never passes a block) and an
+    // unbounded window (it never blocks the whole-overlap shortcut)
+    QReg q = {{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY},
+              -INFINITY, INFINITY, 0u, 0u};
     if (has) {
         const QF32 f = A.qf[S.qbase + lane];
-        q.cx = f.cx;
-        q.cy = f.cy;
-        q.cz = f.cz;
-        q.R = f.R;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) q.box[k] = f.box[k];
         q.a = f.a32;
         q.b = f.b32;
         q.lo = f.lo;
@@ -1441,10 +1445,9 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
     const bool all_overlap =
         ballot(((double)q.a < bi.tmin_te) && (bi.tmax_ts < (double)q.b)) == ~0ull;
     const uint64_t has_mask = ballot(has);
-    const bool cull = A.I.bbox != nullptr;
     const uint32_t last_blk = (S.c1 - 1) >> kBoxShift;
     uint32_t wb = 0xFFFFFFFFu;  // first block of the box window held in the lanes
-    float wbox[7];
+    float wbox[6];
     for (uint32_t tile = S.c0 & ~(uint32_t)(kWave - 1); tile < S.c1; tile += kStep) {
         uint32_t cand[kCpl];
         float ecx[kCpl], ecy[kCpl], ecz[kCpl], er[kCpl], ets[kCpl], ete[kCpl];
@@ -1474,7 +1477,6 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
             wbox[3] = bx.hx;
             wbox[4] = bx.hy;
             wbox[5] = bx.hz;
-            wbox[6] = bx.rmax;
         }
 #pragma unroll
         for (int k = 0; k < kCpl; ++k) {
@@ -1487,10 +1489,10 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
             }
             if (cull && mk) {
                 const uint32_t bl = tb + k - wb;
-                float box[7];
+                float box[6];
 #pragma unroll
-                for (int f = 0; f < 7; ++f) box[f] = lane_val(wbox[f], bl);
-                mk &= ballot(box_pass(box, q.cx, q.cy, q.cz, q.R));
+                for (int f = 0; f < 6; ++f) box[f] = lane_val(wbox[f], bl);
+                mk &= ballot(box_overlap(box, q.box));
                 S.btests += S.nq;
             }
             if (!mk) continue;

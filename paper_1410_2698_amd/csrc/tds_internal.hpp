@@ -60,14 +60,14 @@ struct alignas(16) EntryV32 {
 };
 static_assert(sizeof(EntryV32) == 16, "EntryV32 layout");
 
-// Bounding box of the FP32 filter spheres of one aligned block of 64 index
-// entries (spatial layout): every centre lies in [lo, hi] and every radius is
-// at most rmax.  32 bytes: one scalar load.
+// Box of one aligned block of 64 index entries (spatial layout): the union of
+// their segments' boxes (seg_box32), so every position the canonical
+// evaluation computes for an entry of the block lies in [lo, hi], margins
+// included.  32 bytes: one scalar load.
 struct alignas(32) BlockBox {
     float lx, ly, lz;
     float hx, hy, hz;
-    float rmax;
-    float pad;
+    float pad0, pad1;
 };
 static_assert(sizeof(BlockBox) == 32, "BlockBox layout");
 constexpr uint32_t kBoxShift = 6;  // log2 of the entries per box (one wave)
@@ -77,12 +77,14 @@ constexpr uint32_t kBoxShift = 6;  // log2 of the entries per box (one wave)
 // bucket order.  The FP64 data of a query segment is not stored: where it is
 // needed (recheck, plain form) it is derived again from the query arrays by
 // the same operations.
-struct alignas(32) QF32 {
+struct alignas(64) QF32 {
     float cx, cy, cz, R;  // sphere of the clipped segment, R >= r + d + margins
     float a32, b32;       // clipped window rounded outwards
     uint32_t lo, hi;      // candidate range
+    float box[6];         // box of the clipped segment grown by d (seg_box32)
+    float pad[2];
 };
-static_assert(sizeof(QF32) == 32, "QF32 layout");
+static_assert(sizeof(QF32) == 64, "QF32 layout");
 
 // Per-bucket work description, written by the bucket scan (64 bytes: one
 // scalar load in the distance kernel).
@@ -359,21 +361,44 @@ __host__ __device__ inline bool sphere_pass(float cx, float cy, float cz, float 
     return s <= Rr * Rr;
 }
 
-// Bounding-box test of a query sphere (cx, cy, cz, R) against a block box
-// (lx, ly, lz, hx, hy, hz, rmax).  It is the filter's own arithmetic with the
-// centre distance replaced by the distance to the box: per axis the gap
-// fl(lo - c) or fl(c - hi) is at most the filter's |fl(c_l - c)| for every
-// centre c_l in the box (rounding to nearest is monotone and odd), squares,
-// FMAs and fl(R + r) are monotone in their operands, and r <= rmax; so
-// whenever the filter passes a pair of the block, this test passes.
-__host__ __device__ inline bool box_pass(const float (&b)[7], float cx, float cy, float cz,
-                                         float R) {
-    const float gx = fmaxf(fmaxf(b[0] - cx, cx - b[3]), 0.f);
-    const float gy = fmaxf(fmaxf(b[1] - cy, cy - b[4]), 0.f);
-    const float gz = fmaxf(fmaxf(b[2] - cz, cz - b[5]), 0.f);
-    const float s = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
-    const float Rr = R + b[6];
-    return s <= Rr * Rr;
+// Box of the segment from a to b (FP64 end points, as the canonical
+// evaluation computes them), grown on every side by extra + the margin
+// m = 8u(|h|_1 + extra) + 2u|c|_1 + 1e-18 (u = 2^-24, c the midpoint, h half
+// of b - a) and rounded outwards to FP32.  The margin is the one sphere32
+// adds to a radius (with L1 norms, which bound the L2 ones).  For a pair that
+// the canonical evaluation accepts there is a common time at which the two
+// segments' positions lie in their unmargined boxes and are less than d plus
+// both margins apart (the slack the sphere test's radii allow), so the
+// query's box (extra = d) and the entry's box overlap on every axis.  Unlike
+// the sphere test this one spends none of the margin on its own arithmetic
+// (outward rounding, exact comparisons).  Beyond 1e18 the box is the whole
+// space.
+__host__ __device__ inline void seg_box32(double ax, double ay, double az, double bx, double by,
+                                          double bz, double extra, float (&box)[6]) {
+    const double u = 5.9604644775390625e-08;
+    const double cn = fabs(0.5 * (ax + bx)) + fabs(0.5 * (ay + by)) + fabs(0.5 * (az + bz));
+    const double hn = fabs(0.5 * (bx - ax)) + fabs(0.5 * (by - ay)) + fabs(0.5 * (bz - az));
+    const double m = extra + (8.0 * u) * (hn + extra) + (2.0 * u) * cn + 1e-18;
+    if (!(m < 1e18 && cn < 1e18)) {
+        box[0] = box[1] = box[2] = -INFINITY;
+        box[3] = box[4] = box[5] = INFINITY;
+        return;
+    }
+    // the FP64 sum's own rounding (at most 2^-53 of it) moved outwards too
+    const double lo[3] = {fmin(ax, bx) - m, fmin(ay, by) - m, fmin(az, bz) - m};
+    const double hi[3] = {fmax(ax, bx) + m, fmax(ay, by) + m, fmax(az, bz) + m};
+    for (int k = 0; k < 3; ++k) {
+        box[k] = f32_rd(lo[k] - fabs(lo[k]) * 0x1p-50);
+        box[3 + k] = f32_ru(hi[k] + fabs(hi[k]) * 0x1p-50);
+    }
+}
+
+// Block culling: the query's box (seg_box32 of the clipped query segment with
+// extra = d) and a block box (lx, ly, lz, hx, hy, hz) overlap on every axis.
+// Whenever the canonical evaluation accepts a pair of the block, this passes.
+__host__ __device__ inline bool box_overlap(const float (&b)[6], const float (&q)[6]) {
+    return (b[0] <= q[3]) & (q[0] <= b[3]) & (b[1] <= q[4]) & (q[1] <= b[4]) & (b[2] <= q[5]) &
+           (q[2] <= b[5]);
 }
 
 // Stable LSD radix sort of (key, value) pairs on `stream`; keys_bits is the
