@@ -68,7 +68,7 @@ struct HostQuery {
     QCanon c;
     uint32_t lo, hi;
     float cx, cy, cz, R, a32, b32;
-    float box[6];  // box of the clipped segment grown by d (block culling)
+    Box32 box;  // box of the clipped segment grown by d (block culling)
 };
 
 bool host_query(const HostIndex& h, const double* q, uint64_t L, uint64_t k, double d, double t0,
@@ -97,7 +97,7 @@ bool host_query(const HostIndex& h, const double* q, uint64_t L, uint64_t k, dou
     const double pbx = c.x + c.vx * (c.bq - ts), pby = c.y + c.vy * (c.bq - ts),
                  pbz = c.z + c.vz * (c.bq - ts);
     sphere32(pax, pay, paz, pbx, pby, pbz, d, hq->cx, hq->cy, hq->cz, hq->R);
-    seg_box32(pax, pay, paz, pbx, pby, pbz, d, hq->box);
+    hq->box = seg_box32(pax, pay, paz, pbx, pby, pbz, d);
     hq->a32 = f32_rd(c.aq);
     hq->b32 = f32_ru(c.bq);
     return true;
@@ -110,11 +110,7 @@ uint64_t host_filter(const HostIndex& h, const HostQuery& hq, F&& f) {
     uint64_t tests = 0;
     const uint32_t b0 = hq.lo >> kBoxShift, b1 = (hq.hi - 1) >> kBoxShift;
     for (uint32_t b = b0; b <= b1; ++b) {
-        if (!h.bbox.empty()) {
-            const BlockBox& x = h.bbox[b];
-            const float box[6] = {x.lx, x.ly, x.lz, x.hx, x.hy, x.hz};
-            if (!box_overlap(box, hq.box)) continue;
-        }
+        if (!h.bbox.empty() && !box_overlap(h.bbox[b].b, hq.box)) continue;
         const uint32_t i0 = std::max(hq.lo, b << kBoxShift);
         const uint32_t i1 = std::min<uint64_t>(hq.hi, (uint64_t)(b + 1) << kBoxShift);
         tests += i1 - i0;

@@ -251,24 +251,23 @@ __global__ __launch_bounds__(kBT) void k_block_box(uint64_t n, const EntryF64* _
     const uint32_t blk = blockIdx.x * (kBT / kWave) + threadIdx.x / kWave;
     if (blk >= nblk) return;
     const uint64_t i = ((uint64_t)blk << kBoxShift) + __lane_id();
-    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    Box32 v = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     if (i < n) {
         const EntryF64 e = e64[i];
         const double dt = e.te - e.ts;
-        seg_box32(e.x, e.y, e.z, e.x + e.vx * dt, e.y + e.vy * dt, e.z + e.vz * dt, 0.0, v);
+        v = seg_box32(e.x, e.y, e.z, e.x + e.vx * dt, e.y + e.vy * dt, e.z + e.vz * dt, 0.0);
     }
     for (int off = kWave / 2; off > 0; off >>= 1) {
-        for (int k = 0; k < 3; ++k) v[k] = fminf(v[k], __shfl_xor(v[k], off));
-        for (int k = 3; k < 6; ++k) v[k] = fmaxf(v[k], __shfl_xor(v[k], off));
+        v.lx = fminf(v.lx, __shfl_xor(v.lx, off));
+        v.ly = fminf(v.ly, __shfl_xor(v.ly, off));
+        v.lz = fminf(v.lz, __shfl_xor(v.lz, off));
+        v.hx = fmaxf(v.hx, __shfl_xor(v.hx, off));
+        v.hy = fmaxf(v.hy, __shfl_xor(v.hy, off));
+        v.hz = fmaxf(v.hz, __shfl_xor(v.hz, off));
     }
     if (__lane_id() == 0) {
         BlockBox b;
-        b.lx = v[0];
-        b.ly = v[1];
-        b.lz = v[2];
-        b.hx = v[3];
-        b.hy = v[4];
-        b.hz = v[5];
+        b.b = v;
         b.pad0 = 0.f;
         b.pad1 = 0.f;
         box[blk] = b;

@@ -417,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_qprep(QueryView Q, const BatchDesc* 
                                  pbz = p.z + p.vz * (p.bq - ts);
                     QF32 f;
                     sphere32(pax, pay, paz, pbx, pby, pbz, p.d, f.cx, f.cy, f.cz, f.R);
-                    seg_box32(pax, pay, paz, pbx, pby, pbz, p.d, f.box);
+                    f.box = seg_box32(pax, pay, paz, pbx, pby, pbz, p.d);
                     f.pad[0] = f.pad[1] = 0.f;
                     f.a32 = __double2float_rd(p.aq);
                     f.b32 = __double2float_ru(p.bq);
@@ -1332,7 +1332,7 @@ __device__ __forceinline__ void item_begin(WaveLDS& L, const DistArgs& A, ItemSt
 
 // FP32 filter record of the query segment held by a lane (its QF32 record).
 struct QReg {
-    float box[6];     // box of the clipped segment grown by d (seg_box32)
+    Box32 box;        // box of the clipped segment grown by d (seg_box32)
     float a, b;       // clipped window rounded outwards
     uint32_t lo, hi;  // candidate range
 };
@@ -1432,8 +1432,7 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
               -INFINITY, INFINITY, 0u, 0u};
     if (has) {
         const QF32 f = A.qf[S.qbase + lane];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) q.box[k] = f.box[k];
+        q.box = f.box;
         q.a = f.a32;
         q.b = f.b32;
         q.lo = f.lo;
@@ -1447,7 +1446,7 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
     const uint64_t has_mask = ballot(has);
     const uint32_t last_blk = (S.c1 - 1) >> kBoxShift;
     uint32_t wb = 0xFFFFFFFFu;  // first block of the box window held in the lanes
-    float wbox[6];
+    Box32 wbox;
     for (uint32_t tile = S.c0 & ~(uint32_t)(kWave - 1); tile < S.c1; tile += kStep) {
         uint32_t cand[kCpl];
         float ecx[kCpl], ecy[kCpl], ecz[kCpl], er[kCpl], ets[kCpl], ete[kCpl];
@@ -1470,13 +1469,7 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
             // lane l takes the box of block wb + l (the last block of the
             // chunk repeated past the end)
             wb = tb;
-            const BlockBox bx = A.I.bbox[min(wb + lane, last_blk)];
-            wbox[0] = bx.lx;
-            wbox[1] = bx.ly;
-            wbox[2] = bx.lz;
-            wbox[3] = bx.hx;
-            wbox[4] = bx.hy;
-            wbox[5] = bx.hz;
+            wbox = A.I.bbox[min(wb + lane, last_blk)].b;
         }
 #pragma unroll
         for (int k = 0; k < kCpl; ++k) {
@@ -1489,9 +1482,9 @@ __device__ __forceinline__ void scan_chunk_fp32(WaveLDS& L, const DistArgs& A, I
             }
             if (cull && mk) {
                 const uint32_t bl = tb + k - wb;
-                float box[6];
-#pragma unroll
-                for (int f = 0; f < 6; ++f) box[f] = lane_val(wbox[f], bl);
+                const Box32 box = {lane_val(wbox.lx, bl), lane_val(wbox.ly, bl),
+                                   lane_val(wbox.lz, bl), lane_val(wbox.hx, bl),
+                                   lane_val(wbox.hy, bl), lane_val(wbox.hz, bl)};
                 mk &= ballot(box_overlap(box, q.box));
                 S.btests += S.nq;
             }

@@ -64,9 +64,12 @@ static_assert(sizeof(EntryV32) == 16, "EntryV32 layout");
 // their segments' boxes (seg_box32), so every position the canonical
 // evaluation computes for an entry of the block lies in [lo, hi], margins
 // included.  32 bytes: one scalar load.
+struct Box32 {
+    float lx, ly, lz;  // lower corner
+    float hx, hy, hz;  // upper corner
+};
 struct alignas(32) BlockBox {
-    float lx, ly, lz;
-    float hx, hy, hz;
+    Box32 b;
     float pad0, pad1;
 };
 static_assert(sizeof(BlockBox) == 32, "BlockBox layout");
@@ -81,7 +84,7 @@ struct alignas(64) QF32 {
     float cx, cy, cz, R;  // sphere of the clipped segment, R >= r + d + margins
     float a32, b32;       // clipped window rounded outwards
     uint32_t lo, hi;      // candidate range
-    float box[6];         // box of the clipped segment grown by d (seg_box32)
+    Box32 box;            // box of the clipped segment grown by d (seg_box32)
     float pad[2];
 };
 static_assert(sizeof(QF32) == 64, "QF32 layout");
@@ -373,32 +376,32 @@ __host__ __device__ inline bool sphere_pass(float cx, float cy, float cz, float 
 // the sphere test this one spends none of the margin on its own arithmetic
 // (outward rounding, exact comparisons).  Beyond 1e18 the box is the whole
 // space.
-__host__ __device__ inline void seg_box32(double ax, double ay, double az, double bx, double by,
-                                          double bz, double extra, float (&box)[6]) {
+__host__ __device__ inline Box32 seg_box32(double ax, double ay, double az, double bx, double by,
+                                           double bz, double extra) {
     const double u = 5.9604644775390625e-08;
     const double cn = fabs(0.5 * (ax + bx)) + fabs(0.5 * (ay + by)) + fabs(0.5 * (az + bz));
     const double hn = fabs(0.5 * (bx - ax)) + fabs(0.5 * (by - ay)) + fabs(0.5 * (bz - az));
     const double m = extra + (8.0 * u) * (hn + extra) + (2.0 * u) * cn + 1e-18;
-    if (!(m < 1e18 && cn < 1e18)) {
-        box[0] = box[1] = box[2] = -INFINITY;
-        box[3] = box[4] = box[5] = INFINITY;
-        return;
-    }
+    if (!(m < 1e18 && cn < 1e18))
+        return {-INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY};
     // the FP64 sum's own rounding (at most 2^-53 of it) moved outwards too
-    const double lo[3] = {fmin(ax, bx) - m, fmin(ay, by) - m, fmin(az, bz) - m};
-    const double hi[3] = {fmax(ax, bx) + m, fmax(ay, by) + m, fmax(az, bz) + m};
-    for (int k = 0; k < 3; ++k) {
-        box[k] = f32_rd(lo[k] - fabs(lo[k]) * 0x1p-50);
-        box[3 + k] = f32_ru(hi[k] + fabs(hi[k]) * 0x1p-50);
-    }
+    const auto lo = [m](double a, double b) {
+        const double v = fmin(a, b) - m;
+        return f32_rd(v - fabs(v) * 0x1p-50);
+    };
+    const auto hi = [m](double a, double b) {
+        const double v = fmax(a, b) + m;
+        return f32_ru(v + fabs(v) * 0x1p-50);
+    };
+    return {lo(ax, bx), lo(ay, by), lo(az, bz), hi(ax, bx), hi(ay, by), hi(az, bz)};
 }
 
 // Block culling: the query's box (seg_box32 of the clipped query segment with
-// extra = d) and a block box (lx, ly, lz, hx, hy, hz) overlap on every axis.
-// Whenever the canonical evaluation accepts a pair of the block, this passes.
-__host__ __device__ inline bool box_overlap(const float (&b)[6], const float (&q)[6]) {
-    return (b[0] <= q[3]) & (q[0] <= b[3]) & (b[1] <= q[4]) & (q[1] <= b[4]) & (b[2] <= q[5]) &
-           (q[2] <= b[5]);
+// extra = d) and a block box overlap on every axis.  Whenever the canonical
+// evaluation accepts a pair of the block, this passes.
+__host__ __device__ inline bool box_overlap(const Box32& b, const Box32& q) {
+    return (b.lx <= q.hx) & (q.lx <= b.hx) & (b.ly <= q.hy) & (q.ly <= b.hy) & (b.lz <= q.hz) &
+           (q.lz <= b.hz);
 }
 
 // Stable LSD radix sort of (key, value) pairs on `stream`; keys_bits is the

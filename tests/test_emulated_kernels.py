@@ -116,6 +116,14 @@ def _jobs():
     # a result buffer smaller than the result set: the total is reported
     J["overflow"] = ("search", (tiny.D, tiny.Q), [SPATIAL, FP32, 30.0, 0.0, 49.0, 100])
     J["selfjoin"] = ("selfjoin", (tiny04.D,), [SPATIAL, FP32, 4.0, 0.0, 49.0, 200000])
+    # pairs built to pass at d (1 + eps) around coordinates of 1e6, eps down
+    # to 0 (decided by the canonical evaluation's rounding): every filter in
+    # front of it must keep every pair the oracle accepts
+    gD, gQ = trajgen.grazing(660, 77, 0.5, 1e6)
+    for refine, tile in [(QUEUED, 4), (INLINE, 2)]:
+        J[f"graze_{refine}"] = ("search", (gD, gQ),
+                                [SPATIAL, FP32, 0.5, -1e9, 1e9, 100000, 0, refine, tile])
+    J["hostsearch_graze"] = ("hostsearch", (gD, gQ), [0.5, -1e9, 1e9])
     # the serving loop's host route over a host copy of the index
     J["hostsearch"] = ("hostsearch", (tiny.D, tiny.Q), [30.0, 3.5, 40.25])
     J["hostsearch_all"] = ("hostsearch", (tiny.D, tiny.Q), [250.0, 3.5, 40.25])
@@ -127,7 +135,7 @@ def _jobs():
     J["merge_random"] = ("merge", _merge_random(), [3000])
     J["merge_degenerate"] = ("merge", _merge_degenerate(), [600])
     J["merge_degenerate_cap3"] = ("merge", _merge_degenerate(), [3])
-    return J, {"tiny": tiny, "tiny04": tiny04}
+    return J, {"tiny": tiny, "tiny04": tiny04, "graze": (gD, gQ)}
 
 
 def _build_harness(out):
@@ -356,6 +364,20 @@ def test_fill_pass_emulated(emu, name):
         assert T == 0 and count > 0
     if name == "fill_exact":
         assert count == cap and holes > 0
+
+
+@pytest.mark.parametrize("job", ["graze_1", "graze_2", "hostsearch_graze"])
+def test_grazing_pairs_emulated(emu, job):
+    """Grazing pairs (see trajgen.grazing) through the FP32 kernel form with
+    the refinement queued and inline, and through the host route: the same
+    records as the oracle, whose evaluation decides the closest pairs by its
+    FP64 rounding."""
+    (st, n, *_), out = result(emu, job)
+    gD, gQ = emu[1]["graze"]
+    assert st == 0
+    want = oracle.search(gQ, gD, 0.5, -1e9, 1e9)
+    assert want.size > 200 and n == want.size
+    same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
 
 
 def same_intervals(got, want):

@@ -264,6 +264,26 @@ def test_huge_coordinates():
         idx.close()
 
 
+@pytest.mark.parametrize("offset", [0.0, 1e3, 1e6])
+def test_grazing_pairs(offset):
+    """Pairs built to pass at d (1 + eps), eps from 1e-5 down to 0, around
+    coordinates of magnitude `offset`: the closest ones are decided by the
+    FP64 rounding of the canonical evaluation, so every filter in front of it
+    (block boxes, spheres and time extents, the closest-approach refinement,
+    in every kernel form) must keep every pair the oracle accepts."""
+    D, Q = trajgen.grazing(2000, 77, 0.5, offset)
+    want = oracle.search(Q, D, 0.5, -math.inf, math.inf)
+    assert want.size > 600  # about half of the closest pairs and all at eps < 0
+    for layout in ("spatial", "temporal"):
+        idx = build(D, 0, layout)
+        for kw in ({"precision": "fp32", "refine": "queued", "tile": 4},
+                   {"precision": "fp32", "refine": "inline", "tile": 2},
+                   {"precision": "fp32", "refine": "inline", "tile": 4, "output": "staged"},
+                   {"precision": "fp64"}):
+            compare(idx.search(Q, 0.5, **kw), want, f"grazing {offset} {layout} {kw}")
+        idx.close()
+
+
 def test_fp32_and_fp64_forms_bit_identical():
     w = trajgen.dense(0.03, n_pts=41)
     idx = build(w.D)

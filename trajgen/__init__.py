@@ -31,7 +31,7 @@ import dataclasses
 import hashlib
 import math
 import os
-from typing import Dict, List, Optional
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -328,6 +328,58 @@ def merger(n_per_galaxy: int, seed: int, params: MergerParams = MergerParams(),
     times = P.snap_dt * np.arange(P.n_snap, dtype=np.float64)
     ids = np.arange(traj_offset, traj_offset + n, dtype=np.uint32)
     return from_points(snaps, times, ids)
+
+
+# ---------------------------------------------------------------- grazing pairs
+
+GRAZE_EPS = (0.0, 1e-15, -1e-15, 1e-12, -1e-12, 1e-9, -1e-9, 1e-7, -1e-7, 1e-5, -1e-5)
+
+
+def grazing(n: int, seed: int, d: float, offset: float) -> Tuple[Segments, Segments]:
+    """Pairs built to pass at distance d(1 + eps) of each other: entry k and
+    query k, eps cycling through GRAZE_EPS, around a common offset (0 or a
+    large coordinate magnitude, which stresses rounding margins).  Entry k
+    spans [t0, t0 + 1] with a random velocity; query k has the entry's
+    velocity plus w (every 7th w = 0: parallel motion) and at time tau is at
+    the entry's position there plus n d (1 + eps), n a unit vector
+    perpendicular to w, so that the closest approach is at tau (inside the
+    entry's span for most pairs, past its end for every 5th, where the
+    nearest point is an end point).  Query spans are shifted by up to half a
+    unit against their entries.  Pairs are 50 units apart from each other
+    (beyond reach at the d used), so only the built pairs are near."""
+    rng = Rng(seed)
+    k = np.arange(n)
+    t0 = rng.integers(n, 0, 9).astype(np.float64)
+    base = offset + 50.0 * np.stack([k % 37, (k // 37) % 37, k // 1369], 1).astype(np.float64)
+    ve = rng.uniform(3 * n, -3.0, 3.0).reshape(n, 3)
+    w = rng.uniform(3 * n, -2.0, 2.0).reshape(n, 3)
+    w[k % 7 == 0] = 0.0
+    r = rng.normal(3 * n).reshape(n, 3)
+    # n perpendicular to w (any unit vector where w = 0)
+    ww = np.einsum("ij,ij->i", w, w)
+    coef = np.where(ww > 0, np.einsum("ij,ij->i", r, w) / np.where(ww > 0, ww, 1.0), 0.0)
+    nv = r - coef[:, None] * w
+    nv /= np.linalg.norm(nv, axis=1)[:, None]
+    eps = np.array(GRAZE_EPS)[k % len(GRAZE_EPS)]
+    tau = t0 + rng.uniform(n, 0.05, 0.95)
+    tau = np.where(k % 5 == 4, t0 + 1.0 + rng.uniform(n, 0.0, 0.3), tau)
+    sh = rng.uniform(n, -0.5, 0.5)
+    qa, qb = t0 + sh, t0 + sh + 1.0
+    pe0 = base
+    pe1 = base + ve
+    # query position at time t: entry position + n d (1 + eps) + w (t - tau)
+    def entry_at(t):
+        return pe0 + ve * (t - t0)[:, None]
+    def query_at(t):
+        return entry_at(t) + nv * (d * (1.0 + eps))[:, None] + w * (t - tau)[:, None]
+    pq0, pq1 = query_at(qa), query_at(qb)
+    traj = k.astype(np.uint32)
+
+    def seg(p0, p1, a, b):
+        return Segments(xs=p0[:, 0].copy(), ys=p0[:, 1].copy(), zs=p0[:, 2].copy(), ts=a.copy(),
+                        xe=p1[:, 0].copy(), ye=p1[:, 1].copy(), ze=p1[:, 2].copy(), te=b.copy(),
+                        traj=traj.copy())
+    return seg(pe0, pe1, t0, t0 + 1.0), seg(pq0, pq1, qa, qb)
 
 
 # ---------------------------------------------------------------- workloads
