@@ -171,6 +171,11 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
                                "python paper_1410_2698_amd/build.py")
+        # torch (the source of device memory and streams) is loaded first, so
+        # that libtds.so binds to the HIP runtime torch brings; loaded the
+        # other way round, the process holds two HIP runtimes and torch's
+        # streams and memory are not valid in the library's
+        import torch  # noqa: F401
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

@@ -108,3 +108,18 @@ def test_struct_layouts_match_header(tmp_path):
     import paper_1410_2698_amd as tds
     assert int(got["tds_result"]) == tds.RESULT_DTYPE.itemsize == 32
     assert int(got["tds_traj_interval"]) == tds.TRAJ_DTYPE.itemsize == 24
+
+
+def test_binding_loads_one_hip_runtime():
+    """Loaded through the binding first thing in a process, libtds.so must
+    share torch's HIP runtime (one libamdhip64 mapped): with two, torch's
+    streams and device memory are invalid in the library's runtime."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1410_2698_amd import _lib\n"
+            "_lib.load()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n") % ROOT
+    r = subprocess.run(["python3", "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split()[-1] == "1"
