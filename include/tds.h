@@ -532,7 +532,10 @@ typedef struct tds_server_stats {
     uint64_t cpu_routed; /* requests completed by the host route */
 } tds_server_stats;
 
-/* Errors: TDS_E_INVALID, TDS_E_NOMEM, TDS_E_DEVICE.  params may be NULL. */
+/* Creation runs one empty batch on every slot (its graph is captured and its
+ * stream set up before the first request needs it) and returns when they are
+ * done.  Errors: TDS_E_INVALID, TDS_E_NOMEM, TDS_E_DEVICE.  params may be
+ * NULL. */
 int tds_server_create(const tds_index* index, const tds_server_params* params, tds_server** out);
 
 /*

@@ -381,6 +381,30 @@ void finish_ticket(tds_server* S, ServerTicket* t, int status) {
     else ++S->stats.failed;
 }
 
+// One empty batch on a slot before the server takes requests: its graph is
+// captured and instantiated and its stream gets a hardware queue then, not
+// while requests wait (a second slot is first needed only under load, and
+// that first use stalled the requests queued behind it for several ms).
+// The batch is one segment on [0, 1] searched in the window [2, 3]: its
+// clipped extent is empty, so it has no candidates and no results.
+int warm_slot(Batcher& b) {
+    for (int k = 0; k < 8; ++k) b.host_array(k)[0] = (k == 7) ? 1.0 : 0.0;  // ts = 0, te = 1
+    b.host_traj()[0] = 0u;
+    b.mark_host_staged();
+    tds_request r{};
+    r.q_begin = 0;
+    r.q_count = 1;
+    r.d = 0.0;
+    r.t_start = 2.0;
+    r.t_end = 3.0;
+    r.out_offset = 0;
+    r.out_capacity = 0;
+    TDS_TRY(b.launch(1, &r, 1));
+    uint64_t count = 0;
+    bool table_overflow = false;
+    return b.finish(&count, nullptr, &table_overflow);
+}
+
 }  // namespace
 
 }  // namespace tds
@@ -605,6 +629,11 @@ int tds_server_create(const tds_index* index, const tds_server_params* params, t
             return st;
         }
         sl->b.set_copy_all(true);
+        const int wst = tds::warm_slot(sl->b);
+        if (wst != TDS_OK) {
+            delete S;
+            return wst;
+        }
         S->slots.push_back(std::move(sl));
     }
     if (P.cpu_route_tests) {
