@@ -534,8 +534,12 @@ def open_loop(tds, idx, reqs, route=0):
     submitting thread falls behind the arrivals, the second shows it."""
     srv = tds.Server(idx, max_batch_segments=1 << 17, max_batch_requests=2048, slots=2,
                      result_capacity=1 << 21, default_reserve=512, cpu_route_tests=route)
-    for r in reqs[:200]:  # warm-up, not timed
+    # warm-up, not timed: the requests one at a time, then all at once (full
+    # batches on both slots)
+    for r in reqs[:100]:
         srv.wait(srv.submit(r.Q, r.d, r.t_start, r.t_end))
+    for t in [srv.submit(r.Q, r.d, r.t_start, r.t_end) for r in reqs[100:200]]:
+        srv.wait(t)
     reqs = reqs[200:]
     handles = [tds.prepare_segments(r.Q) for r in reqs]  # marshalled before the run
     base = reqs[0].arrival

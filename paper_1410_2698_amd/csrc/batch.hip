@@ -386,7 +386,9 @@ void finish_ticket(tds_server* S, ServerTicket* t, int status) {
 // while requests wait (a second slot is first needed only under load, and
 // that first use stalled the requests queued behind it for several ms).
 // The batch is one segment on [0, 1] searched in the window [2, 3]: its
-// clipped extent is empty, so it has no candidates and no results.
+// clipped extent is empty, so it has no candidates and no results; its
+// one-record output slice makes the launch include the copy of the counted
+// records, as a serving batch's does.
 int warm_slot(Batcher& b) {
     for (int k = 0; k < 8; ++k) b.host_array(k)[0] = (k == 7) ? 1.0 : 0.0;  // ts = 0, te = 1
     b.host_traj()[0] = 0u;
@@ -398,7 +400,7 @@ int warm_slot(Batcher& b) {
     r.t_start = 2.0;
     r.t_end = 3.0;
     r.out_offset = 0;
-    r.out_capacity = 0;
+    r.out_capacity = 1;
     TDS_TRY(b.launch(1, &r, 1));
     uint64_t count = 0;
     bool table_overflow = false;
