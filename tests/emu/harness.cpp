@@ -10,6 +10,7 @@
 //   harness merge recs.bin capacity out.bin                       -> "status n"
 //   harness hostsearch D.bin Q.bin d t0 t1 out.bin                -> "status n candidates"
 //   harness fill seed W C K frac add align prefix                 -> "status count cap T holes R"
+//   harness filtercheck seed n                                    -> "status accepted misses naive"
 //
 // D.bin / Q.bin: 9 float64 columns (xs ys zs ts xe ye ze te traj), column
 // after column.  recs.bin: tds_result records.  out.bin: the records or
@@ -25,9 +26,20 @@
 // prefix.after (the first T = min(count, capacity) output records before and
 // after the fill; holes are 0xFFFFFFFF).
 //
+// "filtercheck" draws n grazing pairs at random scales (coordinates, lengths
+// and d from 1e-3 to 1e9, separations of d (1 + eps) with eps down to 0) and
+// counts the pairs that the canonical evaluation accepts but the FP32
+// filter (sphere32 spheres and sphere_pass, the outward-rounded time
+// extents, seg_box32 boxes and box_overlap, built as the kernels build them)
+// would drop: "misses", which must be 0.  "naive" counts the accepted pairs
+// that boxes without margins (end points rounded to nearest, grown by d in
+// FP32) would drop, which shows that the pairs are close enough to the
+// boundary to matter.
+//
 // search.hip is part of this translation unit (not compiled on its own), so
 // that the fill kernels in its anonymous namespace can be launched directly.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -320,6 +332,98 @@ int run_fill(char** argv) {
     return 0;
 }
 
+int run_filtercheck(char** argv) {
+    using tds::Box32;
+    using tds::QCanon;
+    std::mt19937_64 rng(strtoull(argv[2], nullptr, 10));
+    const uint64_t n = strtoull(argv[3], nullptr, 10);
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+    std::normal_distribution<double> N(0.0, 1.0);
+    const double eps_set[] = {0.0, 1e-15, -1e-15, 1e-12, -1e-12, 1e-9, -1e-9, 1e-6, -1e-6};
+    uint64_t accepted = 0, misses = 0, naive = 0;
+    for (uint64_t k = 0; k < n; ++k) {
+        const double S = std::pow(10.0, -3.0 + 12.0 * U(rng));     // length scale
+        const double off = std::pow(10.0, -3.0 + 12.0 * U(rng));   // coordinate magnitude
+        const double d = S * std::pow(10.0, -3.0 + 4.0 * U(rng));
+        double o[3], ve[3], w[3], nv[3];
+        for (int a = 0; a < 3; ++a) {
+            o[a] = off * (2.0 * U(rng) - 1.0);
+            ve[a] = S * N(rng);
+            w[a] = (k % 5 == 0) ? 0.0 : S * N(rng);
+            nv[a] = N(rng);
+        }
+        // n perpendicular to w, unit length
+        const double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+        const double nw = nv[0] * w[0] + nv[1] * w[1] + nv[2] * w[2];
+        for (int a = 0; a < 3; ++a) nv[a] -= ww > 0 ? nw / ww * w[a] : 0.0;
+        const double nn = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        for (int a = 0; a < 3; ++a) nv[a] /= nn;
+        const double ets = 20.0 * U(rng) - 10.0, ete = ets + std::pow(10.0, -2.0 + 3.0 * U(rng));
+        const double qts = ets + (ete - ets) * (U(rng) - 0.5);
+        const double qte = qts + (ete - ets) * (0.2 + U(rng));
+        const double lo = std::max(ets, qts), hi = std::min(ete, qte);
+        if (!(lo < hi)) continue;
+        const double tau = lo + (hi - lo) * U(rng);
+        const double eps = (k % 10 == 9) ? 1e-3 * (2.0 * U(rng) - 1.0) : eps_set[k % 9];
+        double e0[3], e1[3], q0[3], q1[3];
+        for (int a = 0; a < 3; ++a) {
+            e0[a] = o[a];
+            e1[a] = o[a] + ve[a] * (ete - ets);
+            const double at_tau = o[a] + ve[a] * (tau - ets) + nv[a] * d * (1.0 + eps);
+            q0[a] = at_tau + (ve[a] + w[a]) * (qts - tau);
+            q1[a] = at_tau + (ve[a] + w[a]) * (qte - tau);
+        }
+        // canonical data: velocity = displacement / duration, window unbounded
+        QCanon q;
+        q.x = q0[0];
+        q.y = q0[1];
+        q.z = q0[2];
+        q.vx = (q1[0] - q0[0]) / (qte - qts);
+        q.vy = (q1[1] - q0[1]) / (qte - qts);
+        q.vz = (q1[2] - q0[2]) / (qte - qts);
+        q.ts = qts;
+        q.aq = qts;
+        q.bq = qte;
+        q.d = d;
+        const double edt = ete - ets;
+        const double evx = (e1[0] - e0[0]) / edt, evy = (e1[1] - e0[1]) / edt,
+                     evz = (e1[2] - e0[2]) / edt;
+        double t_lo, t_hi;
+        if (!tds::canon_eval<false>(q, e0[0], e0[1], e0[2], evx, evy, evz, ets, ete, &t_lo, &t_hi))
+            continue;
+        ++accepted;
+        // the FP32 filter as the kernels build it: entry sphere from the data
+        // end points, entry box from the canonical end points, query sphere
+        // and box from the clipped end points
+        float ecx, ecy, ecz, er;
+        tds::sphere32(e0[0], e0[1], e0[2], e1[0], e1[1], e1[2], 0.0, ecx, ecy, ecz, er);
+        const Box32 eb = tds::seg_box32(e0[0], e0[1], e0[2], e0[0] + evx * edt, e0[1] + evy * edt,
+                                   e0[2] + evz * edt, 0.0);
+        const double pa[3] = {q.x + q.vx * (q.aq - q.ts), q.y + q.vy * (q.aq - q.ts),
+                              q.z + q.vz * (q.aq - q.ts)};
+        const double pb[3] = {q.x + q.vx * (q.bq - q.ts), q.y + q.vy * (q.bq - q.ts),
+                              q.z + q.vz * (q.bq - q.ts)};
+        float qcx, qcy, qcz, qR;
+        tds::sphere32(pa[0], pa[1], pa[2], pb[0], pb[1], pb[2], d, qcx, qcy, qcz, qR);
+        const Box32 qb = tds::seg_box32(pa[0], pa[1], pa[2], pb[0], pb[1], pb[2], d);
+        const bool time_ok = tds::f32_rd(q.aq) < tds::f32_ru(ete) && tds::f32_rd(ets) < tds::f32_ru(q.bq);
+        if (!(tds::sphere_pass(qcx, qcy, qcz, qR, ecx, ecy, ecz, er) && time_ok &&
+              tds::box_overlap(eb, qb)))
+            ++misses;
+        const float df = (float)d;
+        const Box32 nb = {(float)std::min(e0[0], e1[0]), (float)std::min(e0[1], e1[1]),
+                          (float)std::min(e0[2], e1[2]), (float)std::max(e0[0], e1[0]),
+                          (float)std::max(e0[1], e1[1]), (float)std::max(e0[2], e1[2])};
+        const Box32 nq = {(float)std::min(pa[0], pb[0]) - df, (float)std::min(pa[1], pb[1]) - df,
+                          (float)std::min(pa[2], pb[2]) - df, (float)std::max(pa[0], pb[0]) + df,
+                          (float)std::max(pa[1], pb[1]) + df, (float)std::max(pa[2], pb[2]) + df};
+        if (!tds::box_overlap(nb, nq)) ++naive;
+    }
+    printf("%d %llu %llu %llu\n", TDS_OK, (unsigned long long)accepted,
+           (unsigned long long)misses, (unsigned long long)naive);
+    return 0;
+}
+
 int run_merge(char** argv) {
     const std::vector<char> raw = read_file(argv[2]);
     const size_t n = raw.size() / sizeof(tds_result);
@@ -345,6 +449,7 @@ int main(int argc, char** argv) {
     if (argc >= 5 && std::string(argv[1]) == "merge") return run_merge(argv);
     if (argc >= 8 && std::string(argv[1]) == "hostsearch") return run_hostsearch(argv);
     if (argc >= 10 && std::string(argv[1]) == "fill") return run_fill(argv);
+    if (argc >= 4 && std::string(argv[1]) == "filtercheck") return run_filtercheck(argv);
     fprintf(stderr, "usage: harness fsg ... | harness merge ...\n");
     return 2;
 }

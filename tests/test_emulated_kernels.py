@@ -132,6 +132,9 @@ def _jobs():
     # frac) + add, rounded down to a multiple of the chunk if align)
     for name, args in FILL_CASES.items():
         J[name] = ("fill", None, list(args))
+    # the FP32 filter against the canonical evaluation on two million grazing
+    # pairs at random scales
+    J["filtercheck"] = ("filtercheck", None, [5, 2000000])
     J["merge_random"] = ("merge", _merge_random(), [3000])
     J["merge_degenerate"] = ("merge", _merge_degenerate(), [600])
     J["merge_degenerate_cap3"] = ("merge", _merge_degenerate(), [3])
@@ -169,6 +172,8 @@ def _run_job(harness, d, kind, inputs, args):
     elif kind == "fill":
         out = os.path.join(d, "fill")
         argv = [harness, "fill", *args, out]
+    elif kind == "filtercheck":
+        argv = [harness, "filtercheck", *args]
     else:
         files = []
         for i, S in enumerate(inputs):
@@ -378,6 +383,21 @@ def test_grazing_pairs_emulated(emu, job):
     want = oracle.search(gQ, gD, 0.5, -1e9, 1e9)
     assert want.size > 200 and n == want.size
     same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
+
+
+def test_filter_keeps_every_accepted_pair(emu):
+    """Two million pairs built to pass at d (1 + eps), eps down to 0, with
+    lengths, coordinate magnitudes and d spread over twelve decades: every
+    pair the canonical FP64 evaluation accepts passes the FP32 sphere test,
+    the outward-rounded time test and the segment-box test, each built from
+    the end points as the kernels build it.  Boxes without the margins and
+    the outward rounding would drop some accepted pairs: the pairs are close
+    enough to the boundary for the margins to matter."""
+    (st, accepted, misses, naive), _ = result(emu, "filtercheck")
+    assert st == 0
+    assert accepted > 500000
+    assert misses == 0
+    assert naive > 0
 
 
 def same_intervals(got, want):
