@@ -309,17 +309,25 @@ inline void dfree(void* p) {
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 // FP64 -> FP32 conversions rounded to nearest, downwards and upwards (host
-// and device code alike).
+// and device code alike): rounded to nearest, then, where that went the
+// wrong way, moved to the adjacent float by stepping its encoding (as an
+// unsigned integer) by one: away from zero for a float on the side of the
+// step, towards zero otherwise, and from zero to the smallest subnormal of
+// the step's sign.  Infinities step to the largest finite float; NaN stays.
 __host__ __device__ inline float f32_rn(double x) { return (float)x; }
+__host__ __device__ inline float f32_step(float f, bool up) {
+    uint32_t b = __builtin_bit_cast(uint32_t, f);
+    if (f == 0.f) b = up ? 0x00000001u : 0x80000001u;
+    else b = ((f > 0.f) == up) ? b + 1u : b - 1u;
+    return __builtin_bit_cast(float, b);
+}
 __host__ __device__ inline float f32_ru(double x) {
-    float f = (float)x;
-    if ((double)f < x) f = nextafterf(f, INFINITY);
-    return f;
+    const float f = (float)x;
+    return (double)f < x ? f32_step(f, true) : f;
 }
 __host__ __device__ inline float f32_rd(double x) {
-    float f = (float)x;
-    if ((double)f > x) f = nextafterf(f, -INFINITY);
-    return f;
+    const float f = (float)x;
+    return (double)f > x ? f32_step(f, false) : f;
 }
 
 // FP32 bounding sphere of the segment from a to b (FP64 end points), used by

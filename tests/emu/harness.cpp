@@ -11,6 +11,7 @@
 //   harness hostsearch D.bin Q.bin d t0 t1 out.bin                -> "status n candidates"
 //   harness fill seed W C K frac add align prefix                 -> "status count cap T holes R"
 //   harness filtercheck seed n                                    -> "status accepted misses naive"
+//   harness cvt in.bin out.bin                                    -> "status n"
 //
 // D.bin / Q.bin: 9 float64 columns (xs ys zs ts xe ye ze te traj), column
 // after column.  recs.bin: tds_result records.  out.bin: the records or
@@ -35,6 +36,9 @@
 // that boxes without margins (end points rounded to nearest, grown by d in
 // FP32) would drop, which shows that the pairs are close enough to the
 // boundary to matter.
+//
+// "cvt" converts the float64 values of in.bin to float32 rounded downwards
+// and upwards (f32_rd, f32_ru) and writes them as pairs.
 //
 // search.hip is part of this translation unit (not compiled on its own), so
 // that the fill kernels in its anonymous namespace can be launched directly.
@@ -424,6 +428,23 @@ int run_filtercheck(char** argv) {
     return 0;
 }
 
+int run_cvt(char** argv) {
+    const std::vector<char> raw = read_file(argv[2]);
+    const size_t n = raw.size() / sizeof(double);
+    std::vector<double> x(n);
+    if (n) std::memcpy(x.data(), raw.data(), n * sizeof(double));
+    std::vector<float> out(2 * n);
+    for (size_t i = 0; i < n; ++i) {
+        out[2 * i] = tds::f32_rd(x[i]);
+        out[2 * i + 1] = tds::f32_ru(x[i]);
+    }
+    FILE* fo = fopen(argv[3], "wb");
+    fwrite(out.data(), sizeof(float), out.size(), fo);
+    fclose(fo);
+    printf("%d %llu\n", TDS_OK, (unsigned long long)n);
+    return 0;
+}
+
 int run_merge(char** argv) {
     const std::vector<char> raw = read_file(argv[2]);
     const size_t n = raw.size() / sizeof(tds_result);
@@ -450,6 +471,7 @@ int main(int argc, char** argv) {
     if (argc >= 8 && std::string(argv[1]) == "hostsearch") return run_hostsearch(argv);
     if (argc >= 10 && std::string(argv[1]) == "fill") return run_fill(argv);
     if (argc >= 4 && std::string(argv[1]) == "filtercheck") return run_filtercheck(argv);
+    if (argc >= 4 && std::string(argv[1]) == "cvt") return run_cvt(argv);
     fprintf(stderr, "usage: harness fsg ... | harness merge ...\n");
     return 2;
 }

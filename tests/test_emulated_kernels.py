@@ -77,6 +77,22 @@ FILL_CASES = {
 }
 
 
+def _cvt_inputs():
+    """Doubles for the directed FP64 -> FP32 conversions: random magnitudes
+    over the whole double range, floats exactly, their neighbours and
+    midpoints, zeros, subnormals, the float range's ends, infinities."""
+    rng = np.random.default_rng(12)
+    x = [rng.standard_normal(20000) * 10.0 ** rng.uniform(-330, 300, 20000)]
+    f = rng.standard_normal(5000).astype(np.float32).astype(np.float64)
+    x += [f, np.nextafter(f, np.inf), np.nextafter(f, -np.inf),
+          (f + np.nextafter(f.astype(np.float32), np.float32(np.inf)).astype(np.float64)) / 2]
+    fl = np.finfo(np.float32)
+    x.append(np.array([0.0, -0.0, 1e-50, -1e-50, 1e-45, -1e-45, 1.4e-45, float(fl.tiny),
+                       -float(fl.tiny), float(fl.max), -float(fl.max), float(fl.max) * 1.0000001,
+                       -float(fl.max) * 1.0000001, 1e300, -1e300, np.inf, -np.inf]))
+    return np.concatenate(x)
+
+
 def _jobs():
     """Every emulated run: name -> (kind, inputs, arguments after the inputs).
     Kinds "search" and "fsg" take D and Q, "selfjoin" D, "merge" records."""
@@ -135,6 +151,7 @@ def _jobs():
     # the FP32 filter against the canonical evaluation on two million grazing
     # pairs at random scales
     J["filtercheck"] = ("filtercheck", None, [5, 2000000])
+    J["cvt"] = ("cvt", _cvt_inputs(), [])
     J["merge_random"] = ("merge", _merge_random(), [3000])
     J["merge_degenerate"] = ("merge", _merge_degenerate(), [600])
     J["merge_degenerate_cap3"] = ("merge", _merge_degenerate(), [3])
@@ -174,6 +191,9 @@ def _run_job(harness, d, kind, inputs, args):
         argv = [harness, "fill", *args, out]
     elif kind == "filtercheck":
         argv = [harness, "filtercheck", *args]
+    elif kind == "cvt":
+        inputs.astype(np.float64).tofile(os.path.join(d, "x.bin"))
+        argv = [harness, "cvt", os.path.join(d, "x.bin"), out]
     else:
         files = []
         for i, S in enumerate(inputs):
@@ -383,6 +403,23 @@ def test_grazing_pairs_emulated(emu, job):
     want = oracle.search(gQ, gD, 0.5, -1e9, 1e9)
     assert want.size > 200 and n == want.size
     same_records(np.fromfile(out, dtype=RESULT_DTYPE), want)
+
+
+def test_directed_conversions(emu):
+    """f32_rd / f32_ru (the outward roundings of the filter's spheres, time
+    extents and boxes) against their definition: the largest float not above
+    x and the smallest float not below it, from numpy's float32 rounding to
+    nearest and one step with nextafter where it went the wrong way."""
+    (st, n), out = result(emu, "cvt")
+    x = _cvt_inputs()
+    assert st == 0 and n == x.size
+    got = np.fromfile(out, dtype=np.float32).reshape(-1, 2)
+    with np.errstate(over="ignore"):  # FLT_MAX steps to infinity, as it should
+        f = x.astype(np.float32)
+        up = np.where(f.astype(np.float64) < x, np.nextafter(f, np.float32(np.inf)), f)
+        dn = np.where(f.astype(np.float64) > x, np.nextafter(f, np.float32(-np.inf)), f)
+    assert np.array_equal(got[:, 0].view(np.uint32), dn.view(np.uint32))
+    assert np.array_equal(got[:, 1].view(np.uint32), up.view(np.uint32))
 
 
 def test_filter_keeps_every_accepted_pair(emu):
