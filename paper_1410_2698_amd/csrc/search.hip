@@ -1612,8 +1612,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const uint32_t b = uniform(A.item_bucket[it]);
         const BucketInfo bi = A.binfo[b];
         const uint32_t local = it - bi.item0;
-        const uint32_t g = local / bi.nch;
-        const uint32_t c = local - g * bi.nch;
+        // chunk-major inside a bucket: the groups of one chunk are adjacent
+        // items, so the waves of an XCD, which work through a contiguous
+        // part of the item list, share the chunk's records in their L2
+        const uint32_t ngr = (bi.count + kWave - 1) / kWave;
+        const uint32_t c = local / ngr;
+        const uint32_t g = local - c * ngr;
         ItemState S;
         S.sbase = sbase;
         S.nq = uniform(min((uint32_t)kWave, bi.count - g * kWave));
