@@ -141,7 +141,7 @@ def load_profile(workload, kind):
 PROFILE_PARAMS = {
     "galaxy": "num_bins=19,chunk=2048,grid_waves=4096,tile=2,refine=inline,deal=dynamic,"
               "output=direct,precision=fp32",
-    "uniform1m": "num_bins=400,chunk=4096,grid_waves=4096,tile=2,refine=queued,deal=static,"
+    "uniform1m": "num_bins=400,chunk=8192,grid_waves=4096,tile=2,refine=queued,deal=static,"
                  "output=staged,precision=fp32"}
 
 
