@@ -49,6 +49,24 @@ __global__ __launch_bounds__(256) void k_copy_counted(const Request* __restrict_
     }
 }
 
+// Host-staged query segments to the device: each thread moves segment i's
+// eight values and trajectory id from the mapped host arrays (array k of
+// either side at k * max_q).  A kernel rather than copy calls, so that
+// queueing a batch makes no copy request of the runtime's (their first uses
+// under load blocked the host for several ms).
+__global__ __launch_bounds__(256) void k_stage_in(const double* __restrict__ hq,
+                                                  const uint32_t* __restrict__ htraj,
+                                                  double* __restrict__ dq,
+                                                  uint32_t* __restrict__ dtraj, uint64_t nq,
+                                                  uint64_t max_q) {
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < nq;
+         i += (uint64_t)gridDim.x * 256) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dq[k * max_q + i] = hq[k * max_q + i];
+        dtraj[i] = htraj[i];
+    }
+}
+
 }  // namespace
 
 
@@ -96,8 +114,10 @@ int Batcher::init(tds_index* idx, uint64_t max_q, uint32_t max_r, uint64_t res_c
     TDS_TRY(dmalloc(&dq_, 8 * max_q));
     TDS_TRY(dmalloc(&dtraj_, max_q));
     TDS_TRY(dmalloc(&dres_, res_cap));
-    TDS_HIP(hipHostMalloc((void**)&hq_, 8 * max_q * sizeof(double), hipHostMallocDefault));
-    TDS_HIP(hipHostMalloc((void**)&htraj_, max_q * sizeof(uint32_t), hipHostMallocDefault));
+    TDS_HIP(hipHostMalloc((void**)&hq_, 8 * max_q * sizeof(double), hipHostMallocMapped));
+    TDS_HIP(hipHostMalloc((void**)&htraj_, max_q * sizeof(uint32_t), hipHostMallocMapped));
+    TDS_HIP(hipHostGetDevicePointer((void**)&hq_dev_, hq_, 0));
+    TDS_HIP(hipHostGetDevicePointer((void**)&htraj_dev_, htraj_, 0));
     hreq_ = w_->req_host;  // the workspace's pinned control block (max_r requests)
     hrc_ = w_->rc_host;
     TDS_HIP(hipHostMalloc((void**)&hres_, res_cap * sizeof(tds_result), hipHostMallocMapped));
@@ -148,11 +168,10 @@ int Batcher::launch(uint64_t nq, const tds_request* reqs, uint32_t nreq) {
     }
     t0_ = std::chrono::steady_clock::now();
     if (!staged_on_device_) {
-        for (int k = 0; k < 8; ++k)
-            TDS_HIP(hipMemcpyAsync(dq_ + k * max_q_, hq_ + k * max_q_, nq * sizeof(double),
-                                   hipMemcpyHostToDevice, stream_));
-        TDS_HIP(hipMemcpyAsync(dtraj_, htraj_, nq * sizeof(uint32_t), hipMemcpyHostToDevice,
-                               stream_));
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>((nq + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_stage_in, dim3(blocks), dim3(256), 0, stream_, hq_dev_, htraj_dev_,
+                           dq_, dtraj_, nq, max_q_);
+        TDS_HIP(hipGetLastError());
     }
     BatchDesc* D = w_->desc_host;
     D->nq = nq;

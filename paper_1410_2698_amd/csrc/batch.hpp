@@ -54,8 +54,10 @@ private:
     double* dq_ = nullptr;
     uint32_t* dtraj_ = nullptr;
     tds_result* dres_ = nullptr;
-    double* hq_ = nullptr;
+    double* hq_ = nullptr;        // mapped pinned host memory: staged query arrays
     uint32_t* htraj_ = nullptr;
+    double* hq_dev_ = nullptr;    // hq_ and htraj_ as the device sees them
+    uint32_t* htraj_dev_ = nullptr;
     Request* hreq_ = nullptr;     // in the workspace's pinned control block
     ReqCounter* hrc_ = nullptr;   // (owned by the workspace)
     tds_result* hres_ = nullptr;
