@@ -145,6 +145,24 @@ PROFILE_PARAMS = {
                  "output=staged,precision=fp32"}
 
 
+def start_space(autotune, workload):
+    """The autotuner's search space with the launch parameters measured best
+    for `workload` (PROFILE_PARAMS) as its starting point, where there are
+    such: its coordinate descent keeps the start unless a neighbour times
+    faster, so a noisy early comparison cannot walk it off to a worse corner
+    of the space (the bin count stays a factor of the automatic one)."""
+    if workload not in PROFILE_PARAMS:
+        return None
+    start = dict(kv.split("=") for kv in PROFILE_PARAMS[workload].split(","))
+    space = {}
+    for knob, values in autotune.SPACE.items():
+        if knob not in start:
+            continue
+        v0 = type(values[0])(start[knob])
+        space[knob] = (v0,) + tuple(v for v in values if v != v0)
+    return space
+
+
 def profile_command(workload, counters):
     return (f"rocprofv3 --pmc {counters} --output-format csv -d gpurun_out/pmc -o p -- "
             f"python3 bench.py --legs {workload} --steps 2 --warmup 1 --no-cpu --no-fp64-form "
@@ -742,7 +760,8 @@ def main():
                 tuned[k] = v if k in ("precision", "refine", "deal", "output") else int(v)
         elif not args.no_tune and name in legs:
             tb = time.perf_counter()
-            best = autotune.tune(w.D, w.Q, w.ds, w.window, cache=None)
+            best = autotune.tune(w.D, w.Q, w.ds, w.window, cache=None,
+                                 space=start_space(autotune, name))
             tuned = {k: best[k] for k in ("num_bins", "chunk", "grid_waves", "tile", "refine",
                                           "deal", "output", "precision")}
             tuned["trials"] = best["trials"]
